@@ -1,0 +1,32 @@
+"""CPU FP64 oracle for recycling BiCGSTAB -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import or run anything in this package.  The product path (the
+HIP library and its Python binding) never routes through it and shares no
+code with it: the only thing both sides consume is the seeded input module
+``workloads``.
+
+Contents (each function cites the passage of the paper it follows):
+
+* ``krylov.bicgstab``   -- van der Vorst's BiCGSTAB (the non-recycling baseline).
+* ``krylov.rbicgstab``  -- Algorithm 2 (RBiCGSTAB), Section 4.
+* ``krylov.rbicg``      -- Algorithm 1 (RBiCG), Section 3, with the cycle store
+                           of Lanczos vectors described in Section 6.2.
+* ``recycle.make_blocks``     -- Algorithm 2 step 1 / eq. (CcheckChat).
+* ``recycle.two_sided_ritz``  -- recycle-space selection (our reading; the
+                                 paper defers it to its reference on RBiCG).
+* ``sequence.run_sequence``   -- the Section 6.2 driver (RBiCG on a matrix
+                                 change, RBiCGSTAB for the other right-hand sides).
+
+Parity status: every function here is pinned by a CPU test (dense LU, SciPy's
+BiCGSTAB, invariants of Theorems 1-2, closed forms); see tests/test_oracle_*.py.
+"""
+from .krylov import (OK, MAXIT, BREAKDOWN_RHO, BREAKDOWN_ALPHA, BREAKDOWN_OMEGA,
+                     NONFINITE, SolveInfo, bicgstab, rbicgstab, rbicg)
+from .recycle import Blocks, make_blocks, empty_blocks, two_sided_ritz
+from .sequence import run_sequence, SequenceResult
+
+__all__ = ["OK", "MAXIT", "BREAKDOWN_RHO", "BREAKDOWN_ALPHA", "BREAKDOWN_OMEGA",
+           "NONFINITE", "SolveInfo", "bicgstab", "rbicgstab", "rbicg", "Blocks",
+           "make_blocks", "empty_blocks", "two_sided_ritz", "run_sequence",
+           "SequenceResult"]

@@ -1,0 +1,400 @@
+"""BiCGSTAB, RBiCGSTAB (Algorithm 2) and RBiCG (Algorithm 1) in plain FP64 -- TEST INFRASTRUCTURE ONLY.
+
+Real arithmetic throughout, so the paper's ``*`` is a transpose and complex
+conjugates of scalars are the scalars themselves (Section 1 notation).
+
+Readings of points the paper leaves open (listed again in the design notes):
+
+* convergence: ``||r_i|| <= rtol * ||b||`` on the recurrence residual; after
+  the final ``x <- x - U x_c`` the true residual ``b - A x`` is checked and,
+  if it is above ``rtol * ||b||``, the solve restarts from that ``x`` (at most
+  ``max_restarts`` times);
+* breakdowns are only detected and reported (the paper assumes they do not
+  happen): an exactly zero ``(rt0, r)``, ``(rt0, q)``, ``(t, t)`` or
+  ``omega``, and any non-finite scalar, is reported; if
+  ``(t, t) = 0`` while ``||s|| <= tol`` the half step ``x + alpha p`` is
+  accepted;
+* RBiCG stops on the primary residual only (the dual system is auxiliary).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from .recycle import Blocks, empty_blocks
+
+OK = 0
+MAXIT = 1
+BREAKDOWN_RHO = 2
+BREAKDOWN_ALPHA = 3
+BREAKDOWN_OMEGA = 4
+NONFINITE = -5
+
+
+def _zero(val: float, a: np.ndarray, b: np.ndarray) -> bool:
+    """Breakdown test of Algorithm 2 step 3 and of the recurrences: an exact zero."""
+    return val == 0.0
+
+
+@dataclass
+class SolveInfo:
+    status: int = OK
+    iters: int = 0                 # iterations of the final (accepted) pass
+    total_iters: int = 0           # summed over restarts
+    matvecs_A: int = 0
+    matvecs_At: int = 0
+    restarts: int = 0
+    rel_res_recur: float = np.nan
+    rel_res_true: float = np.nan
+    res_hist: List[float] = field(default_factory=list)
+    trace: dict = field(default_factory=dict)   # optional per-iteration vectors (tests)
+
+
+def _bad(*vals) -> bool:
+    return any((not np.isfinite(v)) for v in vals)
+
+
+def bicgstab(A, b: np.ndarray, x0: Optional[np.ndarray] = None,
+             shadow: Optional[np.ndarray] = None, rtol: float = 1e-8,
+             max_it: int = 10000, max_restarts: int = 3, record: bool = False):
+    """van der Vorst's BiCGSTAB (the baseline named in Section 1; k = 0 case of Algorithm 2).
+
+    ``shadow`` is the fixed vector ``r^`` of the inner products (defaults to
+    the initial residual).  Returns ``(x, SolveInfo)``.
+    """
+    n = b.shape[0]
+    info = SolveInfo()
+    bnorm = np.linalg.norm(b)
+    if _bad(bnorm):
+        info.status = NONFINITE
+        return np.zeros(n), info
+    tol = rtol * bnorm
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    started_nonzero = x0 is not None and np.any(x != 0)
+    trace = {"r": [], "x": []} if record else {}
+    for attempt in range(max_restarts + 1):
+        if started_nonzero or attempt > 0:
+            r = b - A @ x
+            info.matvecs_A += 1
+        else:
+            r = b.copy()
+        rhat = r.copy() if shadow is None else np.array(shadow, dtype=np.float64)
+        rho_prev = alpha = omega = 1.0
+        p = np.zeros(n)
+        v = np.zeros(n)
+        info.iters = 0
+        status = MAXIT
+        rho = rhat @ r
+        for i in range(1, max_it + 1):
+            if _bad(rho) or _zero(rho, rhat, r):
+                status = NONFINITE if _bad(rho) else BREAKDOWN_RHO
+                break
+            if i == 1:
+                p = r.copy()
+            else:
+                beta = (rho / rho_prev) * (alpha / omega)
+                p = r + beta * (p - omega * v)
+            v = A @ p
+            den = rhat @ v
+            if _bad(den) or _zero(den, rhat, v):
+                status = NONFINITE if _bad(den) else BREAKDOWN_ALPHA
+                break
+            alpha = rho / den
+            s = r - alpha * v
+            t = A @ s
+            info.matvecs_A += 2
+            tt = t @ t
+            info.iters = i
+            if tt == 0.0:
+                if np.linalg.norm(s) <= tol:
+                    x = x + alpha * p
+                    r = s
+                    status = OK
+                else:
+                    status = BREAKDOWN_OMEGA
+                break
+            omega = (t @ s) / tt
+            x = x + alpha * p + omega * s
+            r = s - omega * t
+            rn = np.linalg.norm(r)
+            info.res_hist.append(rn / bnorm)
+            if record:
+                trace["r"].append(r.copy())
+                trace["x"].append(x.copy())
+            if _bad(rn):
+                status = NONFINITE
+                break
+            if rn <= tol:
+                status = OK
+                break
+            if omega == 0.0:
+                status = BREAKDOWN_OMEGA
+                break
+            rho_prev = rho
+            rho = rhat @ r
+        info.total_iters += info.iters
+        info.rel_res_recur = np.linalg.norm(r) / bnorm
+        rt = np.linalg.norm(b - A @ x) / bnorm
+        info.matvecs_A += 1
+        info.rel_res_true = rt
+        info.status = status
+        if status != OK or rt <= rtol or attempt == max_restarts:
+            if status == OK and rt > rtol:
+                info.status = MAXIT
+            break
+        info.restarts += 1
+    info.trace = trace
+    return x, info
+
+
+def rbicgstab(A, blocks: Blocks, b: np.ndarray, x_m1: Optional[np.ndarray] = None,
+              shadow_m1: Optional[np.ndarray] = None, rtol: float = 1e-8,
+              max_it: int = 10000, max_restarts: int = 3, record: bool = False):
+    """Algorithm 2 (RBiCGSTAB), Section 4, in the paper's order and notation.
+
+    ``blocks`` carries ``U``, ``C = A U``, ``Chat = Ct D_c^{-1}`` (step 1) and
+    ``Ct``, ``Ccheck`` for the shadow projection of eq. (minusXR).
+    ``shadow_m1`` is the random ``rt_{-1}`` of step 2 (defaults to ``r_{-1}``).
+    Returns ``(x, SolveInfo)``; ``x`` already includes step 8's ``- U x_c``.
+    """
+    n = b.shape[0]
+    U, C, Chat, Ct, Ccheck = blocks.U, blocks.C, blocks.Chat, blocks.Ct, blocks.Ccheck
+    k = U.shape[1]
+    info = SolveInfo()
+    bnorm = np.linalg.norm(b)
+    if _bad(bnorm):
+        info.status = NONFINITE
+        return np.zeros(n), info
+    tol = rtol * bnorm
+    x = np.zeros(n) if x_m1 is None else np.array(x_m1, dtype=np.float64)
+    started_nonzero = x_m1 is not None and np.any(x != 0)
+    trace = {"r": [], "x": [], "xc": [], "s": [], "q": [], "t": []} if record else {}
+    for attempt in range(max_restarts + 1):
+        # step 2: x_{-1}, r_{-1} = b - A x_{-1}, then eq. (minusXR)
+        if started_nonzero or attempt > 0:
+            r_m1 = b - A @ x
+            info.matvecs_A += 1
+        else:
+            r_m1 = b.copy()
+        rt_m1 = r_m1.copy() if shadow_m1 is None else np.array(shadow_m1, dtype=np.float64)
+        zeta0 = Chat.T @ r_m1
+        x = x + U @ zeta0                       # x_0 = x_{-1} + U Chat^* r_{-1}
+        r = r_m1 - C @ zeta0                    # r_0 = (I - C Chat^*) r_{-1}
+        rt0 = rt_m1 - Ct @ (Ccheck.T @ rt_m1)   # rt_0 = (I - Ct Ccheck^*) rt_{-1}
+        if record:
+            trace["r0"], trace["x0"], trace["rt0"] = r.copy(), x.copy(), rt0.copy()
+        # step 3
+        rho = rt0 @ r
+        status = MAXIT
+        info.iters = 0
+        xc = np.zeros(k)
+        if np.linalg.norm(r) <= tol:
+            status = OK              # r_0 already small: the projection solved it (b in range(C))
+        elif _bad(rho) or _zero(rho, rt0, r):
+            status = NONFINITE if _bad(rho) else BREAKDOWN_RHO
+        else:
+            # step 4
+            beta = omega = 0.0
+            p = np.zeros(n)
+            q = np.zeros(n)
+            # step 6
+            for i in range(1, max_it + 1):
+                p = r + beta * p - beta * omega * q
+                q = A @ p
+                zeta = Chat.T @ q
+                q = q - C @ zeta
+                den = rt0 @ q
+                if _bad(den) or _zero(den, rt0, q):
+                    status = NONFINITE if _bad(den) else BREAKDOWN_ALPHA
+                    break
+                alpha = rho / den
+                s = r - alpha * q
+                t = A @ s
+                gamma = Chat.T @ t
+                t = t - C @ gamma
+                info.matvecs_A += 2
+                info.iters = i
+                tt = t @ t
+                if tt == 0.0:
+                    if np.linalg.norm(s) <= tol:
+                        x = x + alpha * p
+                        xc = xc + alpha * zeta
+                        r = s
+                        status = OK
+                    else:
+                        status = BREAKDOWN_OMEGA
+                    break
+                omega = (s @ t) / tt
+                x = x + alpha * p + omega * s
+                xc = xc + alpha * zeta + omega * gamma
+                r_new = r - alpha * q - omega * t
+                rn = np.linalg.norm(r_new)
+                info.res_hist.append(rn / bnorm)
+                if record:
+                    for key, val in (("r", r_new), ("x", x), ("xc", xc), ("s", s),
+                                     ("q", q), ("t", t)):
+                        trace[key].append(val.copy())
+                if _bad(rn):
+                    status = NONFINITE
+                    r = r_new
+                    break
+                if rn <= tol:
+                    r = r_new
+                    status = OK
+                    break
+                if omega == 0.0:
+                    r = r_new
+                    status = BREAKDOWN_OMEGA
+                    break
+                rho_new = rt0 @ r_new
+                if _zero(rho_new, rt0, r_new):
+                    r = r_new
+                    status = BREAKDOWN_RHO
+                    break
+                beta = (rho_new / rho) * (alpha / omega)
+                rho = rho_new
+                r = r_new
+        # step 8
+        x = x - U @ xc
+        info.total_iters += info.iters
+        info.rel_res_recur = np.linalg.norm(r) / bnorm
+        rt = np.linalg.norm(b - A @ x) / bnorm
+        info.matvecs_A += 1
+        info.rel_res_true = rt
+        info.status = status
+        if status != OK or rt <= rtol or attempt == max_restarts:
+            if status == OK and rt > rtol:
+                info.status = MAXIT
+            break
+        info.restarts += 1
+    info.trace = trace
+    return x, info
+
+
+def rbicg(A, At, blocks: Blocks, b: np.ndarray, bt: Optional[np.ndarray] = None,
+          x_m1: Optional[np.ndarray] = None, xt_m1: Optional[np.ndarray] = None,
+          rtol: float = 1e-8, max_it: int = 10000, s: int = 0,
+          on_cycle: Optional[Callable[[np.ndarray, np.ndarray], None]] = None,
+          record: bool = False):
+    """Algorithm 1 (RBiCG), Section 3, with the Section 6.2 cycle store.
+
+    The dual right-hand side ``bt`` defaults to the vector of all ones (the
+    choice made in Section 6.2).  The Lanczos vectors are the normalised
+    residuals ``r_{i-1}/||r_{i-1}||`` and ``rt_{i-1}/||rt_{i-1}||``; every ``s``
+    iterations (and once more at the end for a partial cycle) they are handed
+    to ``on_cycle(V, Vt)`` and discarded.  Returns ``(x, xt, SolveInfo)``.
+    """
+    n = b.shape[0]
+    U, C, Chat = blocks.U, blocks.C, blocks.Chat
+    Ut, Ct, Ccheck = blocks.Ut, blocks.Ct, blocks.Ccheck
+    k = U.shape[1]
+    info = SolveInfo()
+    if bt is None:
+        bt = np.ones(n)
+    bnorm = np.linalg.norm(b)
+    if _bad(bnorm):
+        info.status = NONFINITE
+        return np.zeros(n), np.zeros(n), info
+    tol = rtol * bnorm
+    x = np.zeros(n) if x_m1 is None else np.array(x_m1, dtype=np.float64)
+    xt = np.zeros(n) if xt_m1 is None else np.array(xt_m1, dtype=np.float64)
+    if np.any(x != 0):
+        r_m1 = b - A @ x
+        info.matvecs_A += 1
+    else:
+        r_m1 = b.copy()
+    if np.any(xt != 0):
+        rt_m1 = bt - At @ xt
+        info.matvecs_At += 1
+    else:
+        rt_m1 = np.array(bt, dtype=np.float64)
+    # step 2: eq. (minusXR)
+    zeta0 = Chat.T @ r_m1
+    x = x + U @ zeta0
+    r = r_m1 - C @ zeta0
+    zt0 = Ccheck.T @ rt_m1
+    xt = xt + Ut @ zt0
+    rt = rt_m1 - Ct @ zt0
+    trace = {"r": [r.copy()], "rt": [rt.copy()]} if record else {}
+    # step 4
+    p = np.zeros(n)
+    pt = np.zeros(n)
+    zc = np.zeros(k)
+    ztc = np.zeros(k)
+    beta = 0.0
+    rho = rt @ r
+    status = MAXIT
+    V, Vt = [], []
+
+    def flush():
+        if on_cycle is not None and V:
+            on_cycle(np.array(V).T, np.array(Vt).T)
+        V.clear()
+        Vt.clear()
+
+    if np.linalg.norm(r) <= tol:
+        status = OK
+    elif _bad(rho) or _zero(rho, rt, r):   # step 3 reports; the caller re-chooses the dual start
+        status = NONFINITE if _bad(rho) else BREAKDOWN_RHO
+    else:
+        for i in range(1, max_it + 1):
+            if s > 0:
+                V.append(r / np.linalg.norm(r))
+                Vt.append(rt / np.linalg.norm(rt))
+            p = r + beta * p
+            pt = rt + beta * pt
+            z = A @ p
+            zt = At @ pt
+            info.matvecs_A += 1
+            info.matvecs_At += 1
+            zeta = Chat.T @ z
+            zetat = Ccheck.T @ zt
+            q = z - C @ zeta
+            qt = zt - Ct @ zetat
+            den = pt @ q
+            info.iters = i
+            if _bad(den) or _zero(den, pt, q):
+                status = NONFINITE if _bad(den) else BREAKDOWN_ALPHA
+                break
+            alpha = rho / den
+            zc = zc + alpha * zeta
+            ztc = ztc + alpha * zetat
+            x = x + alpha * p
+            xt = xt + alpha * pt
+            r = r - alpha * q
+            rt = rt - alpha * qt
+            rn = np.linalg.norm(r)
+            info.res_hist.append(rn / bnorm)
+            if record:
+                trace["r"].append(r.copy())
+                trace["rt"].append(rt.copy())
+            if _bad(rn):
+                status = NONFINITE
+                break
+            if rn <= tol:
+                status = OK
+                break
+            rho_new = rt @ r
+            if _zero(rho_new, rt, r):
+                status = BREAKDOWN_RHO
+                break
+            beta = rho_new / rho
+            rho = rho_new
+            if s > 0 and len(V) == s:
+                flush()
+    if s > 0:
+        flush()
+    # step 7
+    x = x - U @ zc
+    xt = xt - Ut @ ztc
+    info.total_iters = info.iters
+    info.rel_res_recur = np.linalg.norm(r) / bnorm
+    info.rel_res_true = np.linalg.norm(b - A @ x) / bnorm
+    info.matvecs_A += 1
+    if status == OK and info.rel_res_true > rtol:
+        status = MAXIT
+    info.status = status
+    info.trace = trace
+    return x, xt, info

@@ -1,0 +1,121 @@
+"""Sequence driver of Section 6.2 (oracle, FP64) -- TEST INFRASTRUCTURE ONLY.
+
+For each matrix ``A(i)`` (shift-major order of Section 6.1): the first
+right-hand side is solved with RBiCG (Algorithm 1; dual right-hand side of
+all ones), whose Lanczos vectors build or improve the recycle space in
+cycles of ``s`` iterations; every other right-hand side of the same matrix
+is solved with RBiCGSTAB (Algorithm 2) using that space.  The first system
+starts with an empty space.  ``mode="bicgstab"`` runs the non-recycling
+baseline on every system.
+
+Readings: the projection used inside a solve is fixed; the improved space is
+installed (``make_blocks``) after the RBiCG solve ends, and only if that
+solve converged.  Cycle updates combine the space being built with the
+cycle's Lanczos vectors, ``W = [U_new, V_s]``, ``Wt = [Ut_new, Vt_s]``,
+starting from the current space.  ``s=None`` makes the cycle the whole
+RBiCG solve (one update at its end): on these operators short cycles
+discard the small-eigenvalue information (see the design notes).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+from .krylov import OK, bicgstab, rbicg, rbicgstab
+from .recycle import make_blocks, empty_blocks, two_sided_ritz
+
+
+@dataclass
+class SequenceResult:
+    x: List[np.ndarray] = field(default_factory=list)
+    status: List[int] = field(default_factory=list)
+    iters: List[int] = field(default_factory=list)
+    matvecs: List[int] = field(default_factory=list)
+    solver: List[str] = field(default_factory=list)
+    rel_res_true: List[float] = field(default_factory=list)
+    seconds: List[float] = field(default_factory=list)
+    k_used: List[int] = field(default_factory=list)
+
+    @property
+    def total_matvecs(self) -> int:
+        return int(sum(self.matvecs))
+
+
+def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
+                 rtol: float = 1e-8, max_it: int = 20000, systems=None) -> SequenceResult:
+    """Solve the systems of ``seq`` (a ``workloads.ShiftedSequence``) in order.
+
+    ``systems`` limits the run to the first ``systems`` systems (a bounded sample).
+    """
+    k = seq.k if k is None else k
+    if s is None:
+        s = max_it + 1
+    n = seq.n
+    out = SequenceResult()
+    U = np.zeros((n, 0))
+    Ut = np.zeros((n, 0))
+    last = seq.num_systems if systems is None else min(systems, seq.num_systems)
+    cur_shift = -1
+    A = At = None
+    blocks = empty_blocks(n)
+    for idx in range(last):
+        si, j = seq.system(idx)
+        t0 = time.perf_counter()
+        mv = 0
+        if si != cur_shift:
+            Acsr, Atcsr = seq.matrix(si)
+            A, At = Acsr.to_scipy(), Atcsr.to_scipy()
+            cur_shift = si
+            if mode != "bicgstab":
+                blocks = make_blocks(A, At, U, Ut)
+                mv += blocks.matvecs_A + blocks.matvecs_At
+        b = seq.rhs[idx]
+        if mode == "bicgstab":
+            x, info = bicgstab(A, b, shadow=seq.shadows[idx], rtol=rtol, max_it=max_it)
+            mv += info.matvecs_A
+            solver = "bicgstab"
+        elif j == 0:
+            state = {"U": blocks.U, "Ut": blocks.Ut, "mv": 0}
+
+            def on_cycle(V, Vt):
+                W = np.hstack([state["U"], V])
+                Wt = np.hstack([state["Ut"], Vt])
+                Un, Utn, _, m = two_sided_ritz(A, W, Wt, k)
+                state["U"], state["Ut"] = Un, Utn
+                state["mv"] += m
+
+            x, _, info = rbicg(A, At, blocks, b, rtol=rtol, max_it=max_it, s=s,
+                               on_cycle=on_cycle)
+            mv += info.matvecs_A + info.matvecs_At + state["mv"]
+            solver = "rbicg"
+            converged = info.status == OK
+            if not converged:
+                # finish from the RBiCG iterate with RBiCGSTAB on the old space
+                x, info2 = rbicgstab(A, blocks, b, x_m1=x, shadow_m1=seq.shadows[idx],
+                                     rtol=rtol, max_it=max_it)
+                mv += info2.matvecs_A
+                info.iters += info2.total_iters
+                info.status = info2.status
+                info.rel_res_true = info2.rel_res_true
+            if converged:
+                U, Ut = state["U"], state["Ut"]
+                blocks = make_blocks(A, At, U, Ut)
+                U, Ut = blocks.U, blocks.Ut
+                mv += blocks.matvecs_A + blocks.matvecs_At
+        else:
+            x, info = rbicgstab(A, blocks, b, shadow_m1=seq.shadows[idx], rtol=rtol,
+                                max_it=max_it)
+            mv += info.matvecs_A
+            solver = "rbicgstab"
+        out.seconds.append(time.perf_counter() - t0)
+        out.x.append(x)
+        out.status.append(info.status)
+        out.iters.append(info.total_iters if solver != "rbicg" else info.iters)
+        out.matvecs.append(mv)
+        out.solver.append(solver)
+        out.rel_res_true.append(info.rel_res_true)
+        out.k_used.append(blocks.k)
+    return out
