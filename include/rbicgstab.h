@@ -1,0 +1,167 @@
+/*
+ * rbicgstab.h -- C ABI of the MI355X (gfx950) recycling BiCGSTAB library.
+ *
+ * The library solves sequences of sparse nonsymmetric systems
+ *     A(i) x(i,j) = b(i,j)
+ * (the problem statement of Section 1, eq. (1.1)), where the matrix changes
+ * slowly along the sequence and each matrix has several right-hand sides.
+ * A recycle space (U, Ut) carried from system to system accelerates the
+ * solves: Algorithm 2 (RBiCGSTAB) uses it, Algorithm 1 (RBiCG) generates it
+ * (Section 6.2: RBiCG when the matrix changes, RBiCGSTAB for the other
+ * right-hand sides of that matrix).
+ *
+ * Conventions shared by every entry point
+ *  - All vector/matrix pointers are DEVICE pointers unless marked "host".
+ *  - Sparse matrices are CSR with int32 row pointers (n+1) and int32 column
+ *    indices (nnz), FP64 values, indices 0-based; every row stores its
+ *    diagonal position or not, the library does not care.
+ *  - Dense n-by-k blocks passed in or out are column-major with leading
+ *    dimension n.
+ *  - Every call enqueues its device work on the stream given at creation and
+ *    returns after that work has completed (the calls synchronise the stream).
+ *  - Return value: 0 (RBS_OK) on success; > 0 a numerical outcome of a solve
+ *    (the output x and stats are still valid); < 0 an API or HIP error, in
+ *    which case rbicgstab_last_error() describes it and the context keeps
+ *    the state it had before the call where possible.
+ *  - The library never allocates device memory: all device storage is carved
+ *    out of the caller's workspace. It allocates a small pinned host block
+ *    for device-to-host status polling and its host-side context.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef RBICGSTAB_H
+#define RBICGSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbs_ctx rbs_ctx;
+
+/* Per-solve statistics (host struct, filled by rbicgstab_solve). */
+typedef struct {
+    int32_t status;        /* same value as the return code                     */
+    int32_t iters;         /* iterations of the accepted pass                   */
+    int32_t total_iters;   /* iterations summed over restarts                   */
+    int32_t restarts;      /* restarts triggered by the true-residual check     */
+    int32_t matvecs_A;     /* products with A (solve only; setup is separate)    */
+    int32_t matvecs_At;    /* products with A^T                                 */
+    int32_t k_used;        /* recycle dimension used by the projection          */
+    int32_t ritz_updates;  /* cycle-end recycle-space updates (RBICG_GEN only)  */
+    double rel_res_recur;  /* ||r_i|| / ||b|| of the recurrence                 */
+    double rel_res_true;   /* ||b - A x|| / ||b|| computed in FP64 at the end   */
+    double ms;             /* host wall time of the call                        */
+} rbs_stats;
+
+enum {
+    RBS_OK = 0,
+    RBS_MAXIT = 1,             /* max_it reached (or true residual above tol after restarts) */
+    RBS_BREAKDOWN_RHO = 2,     /* (rt0, r) = 0: Algorithm 2 step 3 / Algorithm 1 step 3      */
+    RBS_BREAKDOWN_ALPHA = 3,   /* (rt0, q) = 0 (RBiCGSTAB) or (pt, q) = 0 (RBiCG)            */
+    RBS_BREAKDOWN_OMEGA = 4,   /* omega = 0 or (t, t) = 0 with ||s|| > tol                   */
+    RBS_ERR_ARG = -1,
+    RBS_ERR_HIP = -2,
+    RBS_ERR_WORKSPACE = -3,    /* workspace too small / misaligned                           */
+    RBS_ERR_SINGULAR_DC = -4,  /* D_c = Ct^T C could not be factored                         */
+    RBS_ERR_NONFINITE = -5     /* NaN/Inf in the input or produced by the iteration          */
+};
+
+/* rbicgstab_solve flags */
+enum {
+    RBS_RBICGSTAB = 0,    /* Algorithm 2 with the installed recycle space (k may be 0)        */
+    RBS_BICGSTAB = 1,     /* plain BiCGSTAB: the recycle space is ignored (baseline)          */
+    RBS_RBICG_GEN = 2,    /* Algorithm 1 with dual rhs = ones; its Lanczos vectors build the   *
+                           * next recycle space (installed by recycle_update FROM_LAST_SOLVE) */
+    RBS_TRANSPOSE = 8     /* solve A^T x = b reusing the space with the roles of U and Ut      *
+                           * swapped (OR-ed with RBS_RBICGSTAB or RBS_BICGSTAB)                */
+};
+
+/* recycle_update modes */
+enum {
+    RBS_RECYCLE_SET = 0,             /* install caller's U, Ut (device, n x k, ld = n)          */
+    RBS_RECYCLE_FROM_LAST_SOLVE = 1, /* install the space built by the last RBS_RBICG_GEN solve */
+    RBS_RECYCLE_CLEAR = 2            /* drop the space (k = 0)                                  */
+};
+
+/*
+ * Bytes of device workspace a context needs.
+ *  n            rows of every matrix of the sequence
+ *  max_row_nnz  upper bound on the stored entries of any row of A and of A^T
+ *  k_max        largest recycle dimension (1..64)
+ *  s_max        Lanczos vectors kept per recycle-space cycle (RBiCG); the
+ *               cycle length of Section 6.2. 0 disables RBS_RBICG_GEN.
+ * Returns 0 for invalid arguments.
+ */
+size_t rbicgstab_workspace_bytes(int64_t n, int32_t max_row_nnz, int32_t k_max, int32_t s_max);
+
+/*
+ * Bind a matrix A(i) of the sequence (and create the context on first use).
+ *
+ * If *ctx is NULL a context is created on `workspace` (device, >= 256-byte
+ * aligned, rbicgstab_workspace_bytes() bytes) and `stream`; otherwise the
+ * existing context is rebound to the new matrix and keeps its recycle space
+ * (U, Ut): C = A U and Ct = A^T Ut are recomputed for the new matrix, C and Ct
+ * are made bi-orthogonal with D_c = I, and Chat = Ct D_c^-1, Ccheck = C D_c^-1
+ * are formed (Algorithm 2 step 1, Section 3 eq. CcheckChat). Pairs whose
+ * D_c entry is negligible or whose oblique projector norm exceeds
+ * secant_max are dropped (k shrinks; see rbs_stats.k_used).
+ *
+ * A and A^T (rowptr/colidx/val and rowptrT/colidxT/valT, device, CSR as above)
+ * are read during this call only: the library keeps its own sliced copy.
+ * n, max_row_nnz, k_max and s_max must match the values used for the workspace.
+ * secant_max <= 0 selects the default (1e3).
+ */
+int rbicgstab_setup(rbs_ctx** ctx, int64_t n, int64_t nnz,
+                    const int32_t* rowptr, const int32_t* colidx, const double* val,
+                    int64_t nnzT, const int32_t* rowptrT, const int32_t* colidxT,
+                    const double* valT, int32_t max_row_nnz, int32_t k_max, int32_t s_max,
+                    double secant_max, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Solve A x = b (or A^T x = b with RBS_TRANSPOSE) with the bound matrix.
+ *  b       device, n
+ *  x       device, n: in = initial guess x_{-1} (used only if x_nonzero),
+ *          out = solution including the final  x <- x - U x_c  (Algorithm 2 step 8)
+ *  shadow  device, n, or NULL: the random rt_{-1} of Algorithm 2 step 2; NULL
+ *          uses r_{-1}. Ignored by RBS_RBICG_GEN, whose dual right-hand side is
+ *          the vector of all ones (Section 6.2).
+ *  rtol    relative tolerance: stop when ||r_i|| <= rtol ||b||; success is
+ *          declared only if the true residual ||b - A x|| <= rtol ||b|| too,
+ *          otherwise the solve restarts from x (at most 3 restarts).
+ *  max_it  iteration cap per pass.
+ *  stats   host, may be NULL.
+ * Returns RBS_OK or a numerical outcome (> 0) or an error (< 0).
+ */
+int rbicgstab_solve(rbs_ctx* ctx, const double* b, double* x, int32_t x_nonzero,
+                    const double* shadow, double rtol, int32_t max_it, int32_t flags,
+                    rbs_stats* stats);
+
+/*
+ * Change the recycle space (Section 6.2: the space built while solving one
+ * system is used for the next ones). SET copies U, Ut (device, n x k, ld = n,
+ * 1 <= k <= k_max) into the context; FROM_LAST_SOLVE installs the space the
+ * last RBS_RBICG_GEN solve built from its Lanczos vectors (a no-op returning
+ * RBS_OK if that solve did not converge or none ran); CLEAR sets k = 0.
+ * SET and FROM_LAST_SOLVE then redo the block setup for the bound matrix.
+ */
+int recycle_update(rbs_ctx* ctx, int32_t mode, const double* U, const double* Ut, int32_t k);
+
+/* Copy the installed space out (device n x k_used blocks, ld = n; any may be NULL). */
+int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double* Ct,
+                         double* Chat, double* Ccheck, int32_t* k_used /* host */);
+
+/* Matrix-vector products issued by the last setup / recycle_update (host out). */
+int rbicgstab_setup_matvecs(const rbs_ctx* ctx, int32_t* matvecs_A, int32_t* matvecs_At);
+
+int rbicgstab_destroy(rbs_ctx* ctx);
+
+/* Message of the last error on this context (or of a failed creation if ctx is NULL). */
+const char* rbicgstab_last_error(const rbs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBICGSTAB_H */

@@ -1,0 +1,765 @@
+// C ABI of the recycling BiCGSTAB library: context, workspace carving, the
+// setup / solve / recycle-update state machine and the host side of the
+// recycle-space management.  Declarations and contracts: include/rbicgstab.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rbicgstab.h"
+#include "common.h"
+#include "dense.h"
+#include "kernels.h"
+
+using rbs::BicgState;
+using rbs::Sell;
+using rbs::SolveState;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int NTICKETS = 16;
+constexpr int CHUNK = 8;            // iterations enqueued between status polls
+constexpr int MAX_RESTARTS = 3;
+constexpr double DEFAULT_SECANT = 1e3;
+constexpr double DROP_REL = 1e-12;
+
+struct PinnedStatus {
+    SolveState solve;
+    BicgState bicg;
+    double sums[4];
+};
+
+}  // namespace
+
+struct rbs_ctx {
+    int64_t n = 0, n_pad = 0;
+    int k_max = 0, s_max = 0, max_row = 0;
+    hipStream_t stream = nullptr;
+    double secant_max = DEFAULT_SECANT;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Sell A, At;
+    int64_t sell_cap = 0;
+    int32_t* widths = nullptr;
+    double *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr, *Chat = nullptr,
+           *Ccheck = nullptr, *Gh = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;
+    double *x = nullptr, *r = nullptr, *s = nullptr, *t = nullptr, *p = nullptr, *q = nullptr,
+           *rt0 = nullptr, *rh = nullptr, *rt = nullptr, *pt = nullptr, *z = nullptr, *zt = nullptr,
+           *qt = nullptr;
+    double *W = nullptr, *Wt = nullptr, *AW = nullptr;
+    int64_t ldw = 0;
+    double* partials = nullptr;
+    unsigned* tickets = nullptr;
+    SolveState* st = nullptr;
+    BicgState* bst = nullptr;
+    double* dsums = nullptr;
+    double* dsmall = nullptr;
+    size_t dsmall_doubles = 0;
+    double* gpart = nullptr;
+    size_t gpart_doubles = 0;
+    int k = 0;            // installed recycle dimension
+    bool bound = false;
+    int gen_k = 0;        // dimension of the space held in W / Wt
+    bool gen_valid = false;
+    int setup_mv_A = 0, setup_mv_At = 0;
+    PinnedStatus* hp = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(rbs_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ctx, RBS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = round_up(off, ALIGN);
+        T* ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return ptr;
+    }
+};
+
+// Carve (or, with base == nullptr, size) the workspace of a context.
+size_t carve(rbs_ctx* c, char* base) {
+    Carver cv{base};
+    const int64_t n_pad = c->n_pad, nsl = n_pad / rbs::WAVE;
+    const int64_t kb = (int64_t)n_pad * c->k_max;
+    for (Sell* m : {&c->A, &c->At}) {
+        m->n = c->n;
+        m->nslices = nsl;
+        m->slice_ptr = cv.take<int32_t>(nsl + 1);
+        m->col = cv.take<int32_t>(c->sell_cap);
+        m->val = cv.take<double>(c->sell_cap);
+    }
+    c->widths = cv.take<int32_t>(nsl);
+    double** blocks[] = {&c->U, &c->Ut, &c->C, &c->Ct, &c->Chat, &c->Ccheck, &c->Gh,
+                         &c->T1, &c->T2, &c->T3};
+    for (double** b : blocks) *b = cv.take<double>(std::max<int64_t>(kb, 1));
+    double** vecs[] = {&c->x, &c->r, &c->s, &c->t, &c->p, &c->q, &c->rt0, &c->rh,
+                       &c->rt, &c->pt, &c->z, &c->zt, &c->qt};
+    for (double** v : vecs) *v = cv.take<double>(n_pad);
+    c->ldw = n_pad;
+    const int64_t wcols = c->s_max > 0 ? c->k_max + c->s_max : 0;
+    c->W = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
+    c->Wt = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
+    c->AW = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
+    const int64_t mmax = c->k_max + std::max(c->s_max, 0);
+    c->dsmall_doubles = (size_t)(4 * mmax * mmax + 4 * mmax * c->k_max + 64);
+    c->dsmall = cv.take<double>(c->dsmall_doubles);
+    c->gpart_doubles = std::max(rbs::gemmt_partial_doubles(c->n, (int)mmax, (int)(2 * mmax)),
+                                rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
+    c->gpart = cv.take<double>(c->gpart_doubles);
+    c->partials = cv.take<double>((size_t)2048 * (2 * rbs::KMAX + 8));
+    c->tickets = cv.take<unsigned>(NTICKETS);
+    c->st = cv.take<SolveState>(1);
+    c->bst = cv.take<BicgState>(1);
+    c->dsums = cv.take<double>(8);
+    return round_up(cv.off, ALIGN);
+}
+
+bool args_ok(int64_t n, int32_t max_row, int32_t k_max, int32_t s_max) {
+    return n > 0 && n < (int64_t(1) << 31) && max_row > 0 && k_max >= 1 && k_max <= rbs::KMAX &&
+           s_max >= 0 && s_max <= 512;
+}
+
+void size_ctx(rbs_ctx* c, int64_t n, int32_t max_row, int32_t k_max, int32_t s_max) {
+    c->n = n;
+    c->n_pad = (n + rbs::WAVE - 1) / rbs::WAVE * rbs::WAVE;
+    c->k_max = k_max;
+    c->s_max = s_max;
+    c->max_row = max_row;
+    c->sell_cap = c->n_pad * (int64_t)max_row;
+}
+
+int build_sell(rbs_ctx* c, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+               const double* val, Sell& M) {
+    (void)nnz;
+    rbs::launch_sell_widths(c->stream, c->n, rowptr, c->widths);
+    rbs::launch_sell_scan(c->stream, M.nslices, c->widths, M.slice_ptr);
+    int32_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, M.slice_ptr + M.nslices, sizeof(int32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (total < 0 || total > c->sell_cap)
+        return fail(c, RBS_ERR_WORKSPACE,
+                    "a row is longer than max_row_nnz (sliced storage needs " + std::to_string(total) +
+                        " entries, room for " + std::to_string(c->sell_cap) + ")");
+    M.padded = total;
+    rbs::launch_sell_fill(c->stream, c->n, rowptr, colidx, val, M);
+    return RBS_OK;
+}
+
+// Copy columns between column-major blocks with possibly different leading dims.
+int copy_cols(rbs_ctx* c, double* dst, int64_t ldd, const double* src, int64_t lds, int cols) {
+    if (cols <= 0) return RBS_OK;
+    HIPCHK(c, hipMemcpy2DAsync(dst, ldd * sizeof(double), src, lds * sizeof(double),
+                               c->n * sizeof(double), cols, hipMemcpyDeviceToDevice, c->stream));
+    return RBS_OK;
+}
+
+int to_host(rbs_ctx* c, void* h, const void* d, size_t bytes) {
+    HIPCHK(c, hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBS_OK;
+}
+
+int to_device(rbs_ctx* c, void* d, const void* h, size_t bytes) {
+    HIPCHK(c, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBS_OK;
+}
+
+// Algorithm 2 step 1 for the installed (U, Ut): C = A U, Ct = A^T Ut, then
+// SVD bi-orthogonalisation to D_c = I with the drop / secant rule, then
+// Chat = Ct D^-T, Ccheck = C D^-1, and Gh = A^T Chat for the fused iteration.
+int setup_blocks(rbs_ctx* c) {
+    const int k0 = c->k;
+    if (k0 == 0) return RBS_OK;
+    const int64_t ld = c->n_pad;
+    hipStream_t s = c->stream;
+    rbs::launch_spmm(s, c->A, c->U, ld, c->C, ld, k0);
+    rbs::launch_spmm(s, c->At, c->Ut, ld, c->Ct, ld, k0);
+    c->setup_mv_A += k0;
+    c->setup_mv_At += k0;
+    double* dM = c->dsmall;
+    double* dGc = dM + k0 * k0;
+    double* dGct = dGc + k0 * k0;
+    rbs::launch_gemmt(s, c->n, c->Ct, ld, k0, c->C, ld, k0, nullptr, 0, 0, c->gpart, dM);
+    rbs::launch_gemmt(s, c->n, c->C, ld, k0, c->C, ld, k0, nullptr, 0, 0, c->gpart, dGc);
+    rbs::launch_gemmt(s, c->n, c->Ct, ld, k0, c->Ct, ld, k0, nullptr, 0, 0, c->gpart, dGct);
+    std::vector<double> M(3 * k0 * k0);
+    int rc = to_host(c, M.data(), dM, M.size() * sizeof(double));
+    if (rc) return rc;
+    const double* Mm = M.data();
+    const double* Gc = Mm + k0 * k0;
+    const double* Gct = Gc + k0 * k0;
+    for (double v : M)
+        if (!std::isfinite(v)) return fail(c, RBS_ERR_NONFINITE, "non-finite entries in Ct^T C");
+    std::vector<double> P(k0 * k0), sig(k0), Q(k0 * k0);
+    rbs::dense::svd(k0, Mm, P.data(), sig.data(), Q.data());
+    std::vector<int> keep;
+    for (int j = 0; j < k0; ++j) {
+        if (!(sig[j] > DROP_REL * sig[0])) continue;
+        double a = 0, b = 0;   // ||C q_j||^2, ||Ct p_j||^2 from the Gram matrices
+        for (int u = 0; u < k0; ++u)
+            for (int v = 0; v < k0; ++v) {
+                a += Q[u + j * k0] * Gc[u + v * k0] * Q[v + j * k0];
+                b += P[u + j * k0] * Gct[u + v * k0] * P[v + j * k0];
+            }
+        const double secant = std::sqrt(std::max(a, 0.0)) * std::sqrt(std::max(b, 0.0)) / sig[j];
+        if (secant <= c->secant_max) keep.push_back(j);
+    }
+    const int k1 = (int)keep.size();
+    if (k1 == 0) {
+        c->k = 0;
+        return RBS_OK;
+    }
+    std::vector<double> Sq(k0 * k1), Sp(k0 * k1);
+    for (int jj = 0; jj < k1; ++jj) {
+        const int j = keep[jj];
+        const double f = 1.0 / std::sqrt(sig[j]);
+        for (int u = 0; u < k0; ++u) {
+            Sq[u + jj * k0] = Q[u + j * k0] * f;
+            Sp[u + jj * k0] = P[u + j * k0] * f;
+        }
+    }
+    // D = Sp^T M Sq (= I up to rounding), LU
+    std::vector<double> D(k1 * k1, 0.0);
+    for (int b = 0; b < k1; ++b)
+        for (int a = 0; a < k1; ++a) {
+            double acc = 0.0;
+            for (int u = 0; u < k0; ++u)
+                for (int v = 0; v < k0; ++v) acc += Sp[u + a * k0] * Mm[u + v * k0] * Sq[v + b * k0];
+            D[a + b * k1] = acc;
+        }
+    std::vector<int> piv(k1);
+    if (rbs::dense::lu_factor(k1, D.data(), k1, piv.data()) != 0)
+        return fail(c, RBS_ERR_SINGULAR_DC, "D_c = Ct^T C is singular");
+    // Shat = Sp D^-T  (Chat = Ct Shat), Scheck = Sq D^-1 (Ccheck = C Scheck)
+    std::vector<double> Shat(k0 * k1), Scheck(k0 * k1);
+    {
+        std::vector<double> tmp(k1 * k0);   // D^-1 Sp^T, (k1 x k0)
+        for (int u = 0; u < k0; ++u)
+            for (int a = 0; a < k1; ++a) tmp[a + u * k1] = Sp[u + a * k0];
+        rbs::dense::lu_solve(k1, D.data(), k1, piv.data(), tmp.data(), k1, k0, false);
+        for (int u = 0; u < k0; ++u)
+            for (int a = 0; a < k1; ++a) Shat[u + a * k0] = tmp[a + u * k1];
+        for (int u = 0; u < k0; ++u)   // D^-T Sq^T (k1 x k0)
+            for (int a = 0; a < k1; ++a) tmp[a + u * k1] = Sq[u + a * k0];
+        rbs::dense::lu_solve(k1, D.data(), k1, piv.data(), tmp.data(), k1, k0, true);
+        for (int u = 0; u < k0; ++u)
+            for (int a = 0; a < k1; ++a) Scheck[u + a * k0] = tmp[a + u * k1];
+    }
+    double* dSq = c->dsmall;
+    double* dSp = dSq + k0 * k1;
+    double* dSh = dSp + k0 * k1;
+    double* dSc = dSh + k0 * k1;
+    std::vector<double> up;
+    up.insert(up.end(), Sq.begin(), Sq.end());
+    up.insert(up.end(), Sp.begin(), Sp.end());
+    up.insert(up.end(), Shat.begin(), Shat.end());
+    up.insert(up.end(), Scheck.begin(), Scheck.end());
+    rc = to_device(c, dSq, up.data(), up.size() * sizeof(double));
+    if (rc) return rc;
+    rbs::launch_gemm_ts(s, c->n, c->Ct, ld, k0, dSh, k1, c->Chat, ld);    // Chat = Ct Shat
+    rbs::launch_gemm_ts(s, c->n, c->C, ld, k0, dSc, k1, c->Ccheck, ld);   // Ccheck = C Scheck
+    rbs::launch_gemm_ts(s, c->n, c->U, ld, k0, dSq, k1, c->T1, ld);
+    rbs::launch_gemm_ts(s, c->n, c->C, ld, k0, dSq, k1, c->T2, ld);
+    rbs::launch_gemm_ts(s, c->n, c->Ut, ld, k0, dSp, k1, c->T3, ld);
+    rbs::launch_gemm_ts(s, c->n, c->Ct, ld, k0, dSp, k1, c->Gh, ld);
+    std::swap(c->U, c->T1);
+    std::swap(c->C, c->T2);
+    std::swap(c->Ut, c->T3);
+    std::swap(c->Ct, c->Gh);
+    rbs::launch_spmm(s, c->At, c->Chat, ld, c->Gh, ld, k1);               // Gh = A^T Chat
+    c->setup_mv_At += k1;
+    c->k = k1;
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(s));
+    return RBS_OK;
+}
+
+rbs::SolveBufs solve_bufs(rbs_ctx* c, int k, const double* b, double* xout, const double* shadow) {
+    rbs::SolveBufs B;
+    B.n = c->n;
+    B.ld = c->n_pad;
+    B.k = k;
+    B.A = c->A;
+    B.At = c->At;
+    B.U = c->U;
+    B.C = c->C;
+    B.Chat = c->Chat;
+    B.Ct = c->Ct;
+    B.Ccheck = c->Ccheck;
+    B.Gh = c->Gh;
+    B.b = b;
+    B.xout = xout;
+    B.shadow = shadow;
+    B.x = c->x;
+    B.r = c->r;
+    B.s = c->s;
+    B.t = c->t;
+    B.p = c->p;
+    B.q = c->q;
+    B.rt0 = c->rt0;
+    B.rh = c->rh;
+    B.state = c->st;
+    B.partials = c->partials;
+    B.tickets = c->tickets;
+    return B;
+}
+
+// Enqueue iterations in chunks until the device reports done.  The status
+// block is polled through pinned memory while the next chunk is already
+// queued, so the GPU never waits for the host.
+template <typename Enqueue, typename Done>
+int iterate_until_done(rbs_ctx* c, Enqueue enqueue, Done done, void* hdst, const void* dsrc,
+                       size_t bytes, int cap_iters) {
+    auto poll = [&]() -> int {
+        HIPCHK(c, hipMemcpyAsync(hdst, dsrc, bytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        return RBS_OK;
+    };
+    int enq = 0, rc;
+    enqueue(CHUNK);
+    enq += CHUNK;
+    if ((rc = poll())) return rc;
+    while (true) {
+        enqueue(CHUNK);
+        enq += CHUNK;
+        HIPCHK(c, hipEventSynchronize(c->ev[0]));
+        if (done()) break;
+        if (enq > cap_iters + 4 * CHUNK) break;   // the device stops at max_it; safety net only
+        if ((rc = poll())) return rc;
+    }
+    return RBS_OK;
+}
+
+int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, const double* shadow,
+                    double rtol, int max_it, rbs_stats* stats) {
+    rbs::SolveBufs B = solve_bufs(c, k, b, x, shadow);
+    int status = RBS_MAXIT;
+    int total_iters = 0, iters = 0, restarts = 0, mvA = 0, mvAt = 0;
+    double rel_true = NAN, rel_recur = NAN;
+    for (int pass = 0; pass <= MAX_RESTARTS; ++pass) {
+        const int xz = (xnz || pass > 0) ? 1 : 0;
+        rbs::launch_solve_prologue(c->stream, B, xz, rtol, max_it);
+        mvA += xz;
+        mvAt += 1;
+        int rc = iterate_until_done(
+            c, [&](int cnt) { rbs::launch_solve_iterations(c->stream, B, cnt); },
+            [&]() { return c->hp->solve.done != 0; }, &c->hp->solve, c->st, 128, max_it);
+        if (rc) return rc;
+        rbs::launch_solve_epilogue(c->stream, B);
+        rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->tickets, c->dsums);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->hp->sums, c->dsums, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const SolveState& h = c->hp->solve;
+        if (!h.done) return fail(c, RBS_ERR_HIP, "solve did not terminate");
+        iters = h.iters_done;
+        total_iters += iters;
+        mvA += 2 * iters + 1;
+        status = h.status;
+        const double b2 = c->hp->sums[1];
+        rel_true = b2 > 0 ? std::sqrt(c->hp->sums[0] / b2) : std::sqrt(c->hp->sums[0]);
+        rel_recur = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+        if (!std::isfinite(rel_true) && status == RBS_OK) status = RBS_ERR_NONFINITE;
+        if (status != RBS_OK) break;
+        if (rel_true <= rtol) break;
+        if (pass == MAX_RESTARTS) {
+            status = RBS_MAXIT;
+            break;
+        }
+        ++restarts;
+    }
+    if (stats) {
+        stats->status = status;
+        stats->iters = iters;
+        stats->total_iters = total_iters;
+        stats->restarts = restarts;
+        stats->matvecs_A = mvA;
+        stats->matvecs_At = mvAt;
+        stats->k_used = k;
+        stats->rel_res_recur = rel_recur;
+        stats->rel_res_true = rel_true;
+    }
+    if (status == RBS_ERR_NONFINITE) c->err = "non-finite value in the iteration";
+    return status;
+}
+
+rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
+    rbs::BicgBufs B;
+    B.n = c->n;
+    B.ld = c->n_pad;
+    B.k = c->k;
+    B.A = c->A;
+    B.At = c->At;
+    B.U = c->U;
+    B.C = c->C;
+    B.Chat = c->Chat;
+    B.Ut = c->Ut;
+    B.Ct = c->Ct;
+    B.Ccheck = c->Ccheck;
+    B.b = b;
+    B.xout = xout;
+    B.x = c->x;
+    B.r = c->r;
+    B.rt = c->rt;
+    B.p = c->p;
+    B.pt = c->pt;
+    B.z = c->z;
+    B.zt = c->zt;
+    B.q = c->q;
+    B.qt = c->qt;
+    B.W = c->W;
+    B.Wt = c->Wt;
+    B.AW = c->AW;
+    B.ldw = c->ldw;
+    B.col0 = c->gen_k;
+    B.state = c->bst;
+    B.partials = c->partials;
+    B.tickets = c->tickets;
+    return B;
+}
+
+// Cycle-end recycle-space update from the gen_k current columns and ns new
+// Lanczos vectors held in W / Wt / AW: two-sided Rayleigh-Ritz on the host,
+// basis products on the device.  The new space replaces the first columns.
+int ritz_cycle(rbs_ctx* c, int ns) {
+    const int m = c->gen_k + ns;
+    if (m <= 0) return RBS_OK;
+    hipStream_t s = c->stream;
+    const int64_t ld = c->ldw;
+    double* dFG = c->dsmall;                 // m x 2m : Wt^T [W AW]
+    double* dGw = dFG + (size_t)2 * m * m;   // m x m
+    double* dGwt = dGw + (size_t)m * m;
+    rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->W, ld, m, c->AW, ld, m, c->gpart, dFG);
+    rbs::launch_gemmt(s, c->n, c->W, ld, m, c->W, ld, m, nullptr, 0, 0, c->gpart, dGw);
+    rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->Wt, ld, m, nullptr, 0, 0, c->gpart, dGwt);
+    std::vector<double> hbuf((size_t)4 * m * m);
+    int rc = to_host(c, hbuf.data(), dFG, hbuf.size() * sizeof(double));
+    if (rc) return rc;
+    const double* F = hbuf.data();
+    const double* G = F + (size_t)m * m;
+    const double* Gw = G + (size_t)m * m;
+    const double* Gwt = Gw + (size_t)m * m;
+    rbs::dense::RitzResult res = rbs::dense::two_sided_ritz(m, Gw, Gwt, F, G, c->k_max);
+    if (!res.ok || res.kout == 0) {
+        c->gen_k = 0;
+        return RBS_OK;
+    }
+    const int ko = res.kout;
+    std::vector<double> up(res.Y);
+    up.insert(up.end(), res.Yt.begin(), res.Yt.end());
+    double* dY = c->dsmall;
+    double* dYt = dY + (size_t)m * ko;
+    rc = to_device(c, dY, up.data(), up.size() * sizeof(double));
+    if (rc) return rc;
+    const int64_t lb = c->n_pad;
+    rbs::launch_gemm_ts(s, c->n, c->W, ld, m, dY, ko, c->T1, lb);
+    rbs::launch_gemm_ts(s, c->n, c->Wt, ld, m, dYt, ko, c->T2, lb);
+    rbs::launch_gemm_ts(s, c->n, c->AW, ld, m, dY, ko, c->T3, lb);
+    if ((rc = copy_cols(c, c->W, ld, c->T1, lb, ko))) return rc;
+    if ((rc = copy_cols(c, c->Wt, ld, c->T2, lb, ko))) return rc;
+    if ((rc = copy_cols(c, c->AW, ld, c->T3, lb, ko))) return rc;
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->gen_k = ko;
+    return RBS_OK;
+}
+
+int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* shadow, double rtol,
+                int max_it, rbs_stats* stats) {
+    if (c->s_max <= 0) return fail(c, RBS_ERR_ARG, "RBS_RBICG_GEN needs s_max > 0");
+    int rc;
+    c->gen_valid = false;
+    // the space being built starts from the installed one: W = [U], Wt = [Ut], AW = [C]
+    c->gen_k = c->k;
+    if ((rc = copy_cols(c, c->W, c->ldw, c->U, c->n_pad, c->k))) return rc;
+    if ((rc = copy_cols(c, c->Wt, c->ldw, c->Ut, c->n_pad, c->k))) return rc;
+    if ((rc = copy_cols(c, c->AW, c->ldw, c->C, c->n_pad, c->k))) return rc;
+    rbs::BicgBufs B = bicg_bufs(c, b, x);
+    rbs::launch_bicg_prologue(c->stream, B, rtol, max_it, c->s_max);
+    int ritz_updates = 0;
+    int since_flush = 0;
+    auto poll = [&]() -> int {
+        HIPCHK(c, hipMemcpyAsync(&c->hp->bicg, c->bst, 128, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        return RBS_OK;
+    };
+    // iterate until done (returns 1) or until the cycle store is full (returns 0)
+    auto iterate_cycle = [&]() -> int {
+        auto take = [&](int want) {
+            const int t = std::min(want, c->s_max - since_flush);
+            if (t > 0) rbs::launch_bicg_iterations(c->stream, B, t);
+            since_flush += t;
+            return t;
+        };
+        take(CHUNK);
+        int r = poll();
+        if (r) return r;
+        int enq_total = 0;
+        while (true) {
+            const int t = take(CHUNK);
+            enq_total += t;
+            HIPCHK(c, hipEventSynchronize(c->ev[0]));
+            if (c->hp->bicg.done) return 1;
+            if (t == 0) return 0;   // every queued iteration has been polled: store full
+            if ((r = poll())) return r;
+        }
+    };
+    while (true) {
+        const int r = iterate_cycle();
+        if (r < 0) return r;
+        if (r == 1) break;
+        if ((rc = ritz_cycle(c, c->s_max))) return rc;
+        ++ritz_updates;
+        B.col0 = c->gen_k;
+        rbs::launch_bicg_reset_cycle(c->stream, c->bst);
+        since_flush = 0;
+    }
+    rbs::launch_bicg_epilogue(c->stream, B);
+    rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->tickets, c->dsums);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&c->hp->bicg, c->bst, 128, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hp->sums, c->dsums, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const BicgState h = c->hp->bicg;
+    const double b2 = c->hp->sums[1];
+    const double rel_true = b2 > 0 ? std::sqrt(c->hp->sums[0] / b2) : std::sqrt(c->hp->sums[0]);
+    int status = h.status;
+    int iters = h.iters_done;
+    int mvA = iters + 1 + (xnz ? 1 : 0), mvAt = iters;
+    double rel_recur = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+    int total_iters = iters, restarts = 0;
+    if (status == RBS_OK && rel_true <= rtol) {
+        if (h.stored > 0) {
+            if ((rc = ritz_cycle(c, h.stored))) return rc;
+            ++ritz_updates;
+        }
+        c->gen_valid = c->gen_k > 0;
+    } else {
+        // finish from the RBiCG iterate with RBiCGSTAB on the installed space
+        rbs_stats s2{};
+        status = solve_rbicgstab(c, c->k, b, x, 1, shadow, rtol, max_it, &s2);
+        if (status < 0) return status;
+        mvA += s2.matvecs_A;
+        mvAt += s2.matvecs_At;
+        total_iters += s2.total_iters;
+        restarts = 1 + s2.restarts;
+        rel_recur = s2.rel_res_recur;
+        if (stats) stats->rel_res_true = s2.rel_res_true;
+    }
+    if (stats) {
+        stats->status = status;
+        stats->iters = iters;
+        stats->total_iters = total_iters;
+        stats->restarts = restarts;
+        stats->matvecs_A = mvA;
+        stats->matvecs_At = mvAt;
+        stats->k_used = c->k;
+        stats->ritz_updates = ritz_updates;
+        stats->rel_res_recur = rel_recur;
+        if (restarts == 0) stats->rel_res_true = rel_true;
+    }
+    return status;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" {
+
+size_t rbicgstab_workspace_bytes(int64_t n, int32_t max_row_nnz, int32_t k_max, int32_t s_max) {
+    if (!args_ok(n, max_row_nnz, k_max, s_max)) return 0;
+    rbs_ctx tmp;
+    size_ctx(&tmp, n, max_row_nnz, k_max, s_max);
+    return carve(&tmp, nullptr);
+}
+
+int rbicgstab_setup(rbs_ctx** pctx, int64_t n, int64_t nnz, const int32_t* rowptr,
+                    const int32_t* colidx, const double* val, int64_t nnzT, const int32_t* rowptrT,
+                    const int32_t* colidxT, const double* valT, int32_t max_row_nnz, int32_t k_max,
+                    int32_t s_max, double secant_max, void* workspace, size_t ws_bytes,
+                    hipStream_t stream) {
+    if (!pctx) return fail(nullptr, RBS_ERR_ARG, "ctx pointer is NULL");
+    if (!args_ok(n, max_row_nnz, k_max, s_max))
+        return fail(*pctx, RBS_ERR_ARG, "invalid n / max_row_nnz / k_max / s_max");
+    if (!rowptr || !colidx || !val || !rowptrT || !colidxT || !valT || nnz < 0 || nnzT < 0)
+        return fail(*pctx, RBS_ERR_ARG, "matrix arrays must be non-NULL device pointers");
+    rbs_ctx* c = *pctx;
+    if (!c) {
+        if (!workspace || ((uintptr_t)workspace % ALIGN) != 0)
+            return fail(nullptr, RBS_ERR_WORKSPACE, "workspace must be 256-byte aligned device memory");
+        c = new rbs_ctx();
+        size_ctx(c, n, max_row_nnz, k_max, s_max);
+        const size_t need = carve(c, nullptr);
+        if (ws_bytes < need) {
+            delete c;
+            return fail(nullptr, RBS_ERR_WORKSPACE,
+                        "workspace too small: need " + std::to_string(need) + " bytes");
+        }
+        c->ws = static_cast<char*>(workspace);
+        c->ws_bytes = ws_bytes;
+        c->stream = stream;
+        carve(c, c->ws);
+        void* hp = nullptr;
+        hipError_t e = hipHostMalloc(&hp, sizeof(PinnedStatus), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, RBS_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        }
+        c->hp = static_cast<PinnedStatus*>(hp);
+        std::memset(c->hp, 0, sizeof(PinnedStatus));
+        for (auto& ev : c->ev) {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                rbicgstab_destroy(c);
+                return fail(nullptr, RBS_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+            }
+        }
+        // zero everything once: padding rows of vectors and blocks stay zero
+        e = hipMemsetAsync(c->ws, 0, carve(c, c->ws), stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            rbicgstab_destroy(c);
+            return fail(nullptr, RBS_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+        }
+        *pctx = c;
+    } else if (c->n != n || c->max_row != max_row_nnz || c->k_max != k_max || c->s_max != s_max) {
+        return fail(c, RBS_ERR_ARG, "n / max_row_nnz / k_max / s_max differ from the context's");
+    }
+    c->secant_max = secant_max > 0 ? secant_max : DEFAULT_SECANT;
+    c->setup_mv_A = c->setup_mv_At = 0;
+    int rc = build_sell(c, nnz, rowptr, colidx, val, c->A);
+    if (rc) return rc;
+    rc = build_sell(c, nnzT, rowptrT, colidxT, valT, c->At);
+    if (rc) return rc;
+    HIPCHK(c, hipGetLastError());
+    c->bound = true;
+    c->gen_valid = false;
+    rc = setup_blocks(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBS_OK;
+}
+
+int rbicgstab_solve(rbs_ctx* c, const double* b, double* x, int32_t x_nonzero, const double* shadow,
+                    double rtol, int32_t max_it, int32_t flags, rbs_stats* stats) {
+    if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
+    if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound: call rbicgstab_setup first");
+    if (!b || !x) return fail(c, RBS_ERR_ARG, "b and x must be device pointers");
+    if (!(rtol > 0) || max_it < 1) return fail(c, RBS_ERR_ARG, "rtol must be > 0 and max_it >= 1");
+    const auto t0 = std::chrono::steady_clock::now();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    int rc;
+    const int mode = flags & 3;
+    if (flags & RBS_TRANSPOSE) return fail(c, RBS_ERR_ARG, "RBS_TRANSPOSE is not supported yet");
+    if (mode == RBS_RBICG_GEN)
+        rc = solve_rbicg(c, b, x, x_nonzero, shadow, rtol, max_it, stats);
+    else if (mode == RBS_BICGSTAB)
+        rc = solve_rbicgstab(c, 0, b, x, x_nonzero, shadow, rtol, max_it, stats);
+    else if (mode == RBS_RBICGSTAB)
+        rc = solve_rbicgstab(c, c->k, b, x, x_nonzero, shadow, rtol, max_it, stats);
+    else
+        return fail(c, RBS_ERR_ARG, "unknown solve flags");
+    if (stats)
+        stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int recycle_update(rbs_ctx* c, int32_t mode, const double* U, const double* Ut, int32_t k) {
+    if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
+    if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound");
+    int rc;
+    c->setup_mv_A = c->setup_mv_At = 0;
+    if (mode == RBS_RECYCLE_CLEAR) {
+        c->k = 0;
+        return RBS_OK;
+    }
+    if (mode == RBS_RECYCLE_SET) {
+        if (!U || !Ut || k < 1 || k > c->k_max) return fail(c, RBS_ERR_ARG, "SET needs U, Ut and 1 <= k <= k_max");
+        if ((rc = copy_cols(c, c->U, c->n_pad, U, c->n, k))) return rc;
+        if ((rc = copy_cols(c, c->Ut, c->n_pad, Ut, c->n, k))) return rc;
+        c->k = k;
+        return setup_blocks(c);
+    }
+    if (mode == RBS_RECYCLE_FROM_LAST_SOLVE) {
+        if (!c->gen_valid || c->gen_k <= 0) return RBS_OK;
+        const int kk = c->gen_k;
+        if ((rc = copy_cols(c, c->U, c->n_pad, c->W, c->ldw, kk))) return rc;
+        if ((rc = copy_cols(c, c->Ut, c->n_pad, c->Wt, c->ldw, kk))) return rc;
+        c->k = kk;
+        c->gen_valid = false;
+        return setup_blocks(c);
+    }
+    return fail(c, RBS_ERR_ARG, "unknown recycle_update mode");
+}
+
+int rbicgstab_get_blocks(rbs_ctx* c, double* U, double* Ut, double* C, double* Ct, double* Chat,
+                         double* Ccheck, int32_t* k_used) {
+    if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
+    if (k_used) *k_used = c->k;
+    const std::pair<double*, const double*> pairs[] = {
+        {U, c->U}, {Ut, c->Ut}, {C, c->C}, {Ct, c->Ct}, {Chat, c->Chat}, {Ccheck, c->Ccheck}};
+    for (const auto& pr : pairs) {
+        if (!pr.first) continue;
+        int rc = copy_cols(c, pr.first, c->n, pr.second, c->n_pad, c->k);
+        if (rc) return rc;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBS_OK;
+}
+
+int rbicgstab_setup_matvecs(const rbs_ctx* c, int32_t* matvecs_A, int32_t* matvecs_At) {
+    if (!c) return RBS_ERR_ARG;
+    if (matvecs_A) *matvecs_A = c->setup_mv_A;
+    if (matvecs_At) *matvecs_At = c->setup_mv_At;
+    return RBS_OK;
+}
+
+int rbicgstab_destroy(rbs_ctx* c) {
+    if (!c) return RBS_OK;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (auto& ev : c->ev)
+        if (ev) hipEventDestroy(ev);
+    if (c->hp) hipHostFree(c->hp);
+    delete c;
+    return RBS_OK;
+}
+
+const char* rbicgstab_last_error(const rbs_ctx* c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,584 @@
+// Small dense FP64 linear algebra on the host; see dense.h.
+#include "dense.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace rbs {
+namespace dense {
+
+using cd = std::complex<double>;
+
+int lu_factor(int n, double* A, int lda, int* piv) {
+    auto a = [&](int i, int j) -> double& { return A[i + (size_t)j * lda]; };
+    int info = 0;
+    for (int j = 0; j < n; ++j) {
+        int p = j;
+        double best = std::fabs(a(j, j));
+        for (int i = j + 1; i < n; ++i)
+            if (std::fabs(a(i, j)) > best) {
+                best = std::fabs(a(i, j));
+                p = i;
+            }
+        piv[j] = p;
+        if (best == 0.0) {
+            if (!info) info = j + 1;
+            continue;
+        }
+        if (p != j)
+            for (int c = 0; c < n; ++c) std::swap(a(j, c), a(p, c));
+        const double inv = 1.0 / a(j, j);
+        for (int i = j + 1; i < n; ++i) a(i, j) *= inv;
+        for (int c = j + 1; c < n; ++c) {
+            const double f = a(j, c);
+            if (f != 0.0)
+                for (int i = j + 1; i < n; ++i) a(i, c) -= a(i, j) * f;
+        }
+    }
+    return info;
+}
+
+void lu_solve(int n, const double* LU, int lda, const int* piv, double* B, int ldb, int nrhs,
+              bool trans) {
+    auto a = [&](int i, int j) { return LU[i + (size_t)j * lda]; };
+    for (int c = 0; c < nrhs; ++c) {
+        double* b = B + (size_t)c * ldb;
+        if (!trans) {
+            for (int j = 0; j < n; ++j)
+                if (piv[j] != j) std::swap(b[j], b[piv[j]]);
+            for (int j = 0; j < n; ++j)          // L y = b (unit lower)
+                for (int i = j + 1; i < n; ++i) b[i] -= a(i, j) * b[j];
+            for (int j = n - 1; j >= 0; --j) {   // U x = y
+                b[j] /= a(j, j);
+                for (int i = 0; i < j; ++i) b[i] -= a(i, j) * b[j];
+            }
+        } else {
+            for (int j = 0; j < n; ++j) {        // U^T y = b (lower)
+                double s = b[j];
+                for (int i = 0; i < j; ++i) s -= a(i, j) * b[i];
+                b[j] = s / a(j, j);
+            }
+            for (int j = n - 1; j >= 0; --j) {   // L^T z = y (unit upper)
+                double s = b[j];
+                for (int i = j + 1; i < n; ++i) s -= a(i, j) * b[i];
+                b[j] = s;
+            }
+            for (int j = n - 1; j >= 0; --j)
+                if (piv[j] != j) std::swap(b[j], b[piv[j]]);
+        }
+    }
+}
+
+void svd(int m, const double* M, double* P, double* sig, double* Q) {
+    // Hestenes one-sided Jacobi: rotate column pairs of A = M until mutually
+    // orthogonal; A V = U diag(sig).
+    std::vector<double> A(M, M + (size_t)m * m), V((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) V[i + (size_t)i * m] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                double al = 0, be = 0, ga = 0;
+                for (int i = 0; i < m; ++i) {
+                    const double x = A[i + (size_t)p * m], y = A[i + (size_t)q * m];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                if (ga == 0.0 || std::fabs(ga) <= 1e-15 * std::sqrt(al * be)) continue;
+                off = std::max(off, std::fabs(ga) / std::sqrt(al * be));
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                for (int i = 0; i < m; ++i) {
+                    double& x = A[i + (size_t)p * m];
+                    double& y = A[i + (size_t)q * m];
+                    const double nx = c * x - s * y, ny = s * x + c * y;
+                    x = nx;
+                    y = ny;
+                    double& vx = V[i + (size_t)p * m];
+                    double& vy = V[i + (size_t)q * m];
+                    const double nvx = c * vx - s * vy, nvy = s * vx + c * vy;
+                    vx = nvx;
+                    vy = nvy;
+                }
+            }
+        if (off < 1e-15) break;
+    }
+    std::vector<double> s(m);
+    for (int j = 0; j < m; ++j) {
+        double nn = 0;
+        for (int i = 0; i < m; ++i) nn += A[i + (size_t)j * m] * A[i + (size_t)j * m];
+        s[j] = std::sqrt(nn);
+    }
+    std::vector<int> ord(m);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return s[a] > s[b]; });
+    for (int jj = 0; jj < m; ++jj) {
+        const int j = ord[jj];
+        sig[jj] = s[j];
+        for (int i = 0; i < m; ++i) {
+            P[i + (size_t)jj * m] = s[j] > 0 ? A[i + (size_t)j * m] / s[j] : (i == jj ? 1.0 : 0.0);
+            Q[i + (size_t)jj * m] = V[i + (size_t)j * m];
+        }
+    }
+}
+
+int pivoted_cholesky(int m, const double* G, double tol, std::vector<int>& perm,
+                     std::vector<double>& R) {
+    std::vector<double> w(G, G + (size_t)m * m);
+    auto a = [&](int i, int j) -> double& { return w[i + (size_t)j * m]; };
+    perm.resize(m);
+    std::iota(perm.begin(), perm.end(), 0);
+    double dmax = 0.0;
+    for (int i = 0; i < m; ++i) dmax = std::max(dmax, a(i, i));
+    std::vector<double> L((size_t)m * m, 0.0);
+    int r = 0;
+    for (int j = 0; j < m; ++j) {
+        int p = j;
+        for (int i = j + 1; i < m; ++i)
+            if (a(i, i) > a(p, p)) p = i;
+        if (!(a(p, p) > tol * dmax)) break;
+        if (p != j) {
+            for (int c = 0; c < m; ++c) std::swap(a(j, c), a(p, c));
+            for (int c = 0; c < m; ++c) std::swap(a(c, j), a(c, p));
+            for (int c = 0; c < j; ++c) std::swap(L[j + (size_t)c * m], L[p + (size_t)c * m]);
+            std::swap(perm[j], perm[p]);
+        }
+        const double d = std::sqrt(a(j, j));
+        L[j + (size_t)j * m] = d;
+        for (int i = j + 1; i < m; ++i) L[i + (size_t)j * m] = a(i, j) / d;
+        for (int c = j + 1; c < m; ++c)
+            for (int i = j + 1; i < m; ++i) a(i, c) -= L[i + (size_t)j * m] * L[c + (size_t)j * m];
+        r = j + 1;
+    }
+    R.assign((size_t)r * r, 0.0);
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i <= j; ++i) R[i + (size_t)j * r] = L[j + (size_t)i * m];   // R = L^T
+    perm.resize(r);
+    return r;
+}
+
+// Francis double-shift QR on an upper Hessenberg matrix (eigenvalues only),
+// following the Wilkinson-Reinsch formulation: deflate at negligible
+// subdiagonals, exceptional shifts after 10 and 20 stalled sweeps.
+static bool hessenberg_qr(int n, std::vector<double> a, std::vector<cd>& lam) {
+    auto A = [&](int i, int j) -> double& { return a[i + (size_t)j * n]; };
+    std::vector<double> wr(n), wi(n);
+    double anorm = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = std::max(i - 1, 0); j < n; ++j) anorm += std::fabs(A(i, j));
+    int nn = n - 1;
+    double t = 0.0;
+    while (nn >= 0) {
+        int its = 0, l = 0;
+        do {
+            for (l = nn; l >= 1; --l) {
+                double s = std::fabs(A(l - 1, l - 1)) + std::fabs(A(l, l));
+                if (s == 0.0) s = anorm;
+                if (std::fabs(A(l, l - 1)) + s == s) {
+                    A(l, l - 1) = 0.0;
+                    break;
+                }
+            }
+            double x = A(nn, nn);
+            if (l == nn) {   // one real root
+                wr[nn] = x + t;
+                wi[nn] = 0.0;
+                --nn;
+            } else {
+                double y = A(nn - 1, nn - 1), w = A(nn, nn - 1) * A(nn - 1, nn);
+                if (l == nn - 1) {   // a 2x2 block
+                    const double p = 0.5 * (y - x), q = p * p + w;
+                    double z = std::sqrt(std::fabs(q));
+                    x += t;
+                    if (q >= 0.0) {
+                        z = p + std::copysign(z, p);
+                        wr[nn - 1] = wr[nn] = x + z;
+                        if (z != 0.0) wr[nn] = x - w / z;
+                        wi[nn - 1] = wi[nn] = 0.0;
+                    } else {
+                        wr[nn - 1] = wr[nn] = x + p;
+                        wi[nn - 1] = -z;
+                        wi[nn] = z;
+                    }
+                    nn -= 2;
+                } else {
+                    if (its == 60) return false;
+                    if (its == 10 || its == 20) {
+                        t += x;
+                        for (int i = 0; i <= nn; ++i) A(i, i) -= x;
+                        const double s = std::fabs(A(nn, nn - 1)) + std::fabs(A(nn - 1, nn - 2));
+                        y = x = 0.75 * s;
+                        w = -0.4375 * s * s;
+                    }
+                    ++its;
+                    int m = nn - 2;
+                    double p = 0, q = 0, r = 0, z = 0;
+                    for (m = nn - 2; m >= l; --m) {
+                        z = A(m, m);
+                        r = x - z;
+                        double s = y - z;
+                        p = (r * s - w) / A(m + 1, m) + A(m, m + 1);
+                        q = A(m + 1, m + 1) - z - r - s;
+                        r = A(m + 2, m + 1);
+                        s = std::fabs(p) + std::fabs(q) + std::fabs(r);
+                        p /= s;
+                        q /= s;
+                        r /= s;
+                        if (m == l) break;
+                        const double u = std::fabs(A(m, m - 1)) * (std::fabs(q) + std::fabs(r));
+                        const double v = std::fabs(p) * (std::fabs(A(m - 1, m - 1)) + std::fabs(z) +
+                                                         std::fabs(A(m + 1, m + 1)));
+                        if (u + v == v) break;
+                    }
+                    for (int i = m + 2; i <= nn; ++i) {
+                        A(i, i - 2) = 0.0;
+                        if (i != m + 2) A(i, i - 3) = 0.0;
+                    }
+                    for (int k = m; k <= nn - 1; ++k) {
+                        if (k != m) {
+                            p = A(k, k - 1);
+                            q = A(k + 1, k - 1);
+                            r = 0.0;
+                            if (k != nn - 1) r = A(k + 2, k - 1);
+                            x = std::fabs(p) + std::fabs(q) + std::fabs(r);
+                            if (x != 0.0) {
+                                p /= x;
+                                q /= x;
+                                r /= x;
+                            }
+                        }
+                        const double s = std::copysign(std::sqrt(p * p + q * q + r * r), p);
+                        if (s != 0.0) {
+                            if (k == m) {
+                                if (l != m) A(k, k - 1) = -A(k, k - 1);
+                            } else {
+                                A(k, k - 1) = -s * x;
+                            }
+                            p += s;
+                            x = p / s;
+                            y = q / s;
+                            z = r / s;
+                            q /= p;
+                            r /= p;
+                            for (int j = k; j <= nn; ++j) {
+                                p = A(k, j) + q * A(k + 1, j);
+                                if (k != nn - 1) {
+                                    p += r * A(k + 2, j);
+                                    A(k + 2, j) -= p * z;
+                                }
+                                A(k + 1, j) -= p * y;
+                                A(k, j) -= p * x;
+                            }
+                            const int mmin = nn < k + 3 ? nn : k + 3;
+                            for (int i = l; i <= mmin; ++i) {
+                                p = x * A(i, k) + y * A(i, k + 1);
+                                if (k != nn - 1) {
+                                    p += z * A(i, k + 2);
+                                    A(i, k + 2) -= p * r;
+                                }
+                                A(i, k + 1) -= p * q;
+                                A(i, k) -= p;
+                            }
+                        }
+                    }
+                }
+            }
+        } while (l < nn - 1);
+    }
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) lam[i] = cd(wr[i], wi[i]);
+    return true;
+}
+
+bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<double>& Qh,
+                 std::vector<cd>& lambda) {
+    Hh.assign(H, H + (size_t)n * n);
+    Qh.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Qh[i + (size_t)i * n] = 1.0;
+    auto h = [&](int i, int j) -> double& { return Hh[i + (size_t)j * n]; };
+    auto qq = [&](int i, int j) -> double& { return Qh[i + (size_t)j * n]; };
+    std::vector<double> v(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        // Householder vector annihilating h(k+2.., k)
+        double alpha = 0.0;
+        for (int i = k + 1; i < n; ++i) alpha += h(i, k) * h(i, k);
+        alpha = std::sqrt(alpha);
+        if (alpha == 0.0) continue;
+        if (h(k + 1, k) > 0) alpha = -alpha;
+        for (int i = 0; i < n; ++i) v[i] = 0.0;
+        v[k + 1] = h(k + 1, k) - alpha;
+        for (int i = k + 2; i < n; ++i) v[i] = h(i, k);
+        double vn = 0.0;
+        for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
+        if (vn == 0.0) continue;
+        const double tau = 2.0 / vn;
+        for (int j = 0; j < n; ++j) {   // H <- (I - tau v v^T) H
+            double s = 0.0;
+            for (int i = k + 1; i < n; ++i) s += v[i] * h(i, j);
+            s *= tau;
+            for (int i = k + 1; i < n; ++i) h(i, j) -= s * v[i];
+        }
+        for (int i = 0; i < n; ++i) {   // H <- H (I - tau v v^T), Q <- Q (I - tau v v^T)
+            double s = 0.0, sq = 0.0;
+            for (int j = k + 1; j < n; ++j) {
+                s += h(i, j) * v[j];
+                sq += qq(i, j) * v[j];
+            }
+            s *= tau;
+            sq *= tau;
+            for (int j = k + 1; j < n; ++j) {
+                h(i, j) -= s * v[j];
+                qq(i, j) -= sq * v[j];
+            }
+        }
+        for (int i = k + 2; i < n; ++i) h(i, k) = 0.0;
+    }
+    return hessenberg_qr(n, Hh, lambda);
+}
+
+void hess_eigvec(int n, const std::vector<double>& Hh, cd lam, bool left, std::vector<cd>& y) {
+    // LU with adjacent-row partial pivoting of the Hessenberg Hh - lam I (O(n^2)),
+    // then two steps of inverse iteration.
+    std::vector<cd> M((size_t)n * n);
+    double hn = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            M[i + (size_t)j * n] = Hh[i + (size_t)j * n] - (i == j ? lam : cd(0.0));
+            hn = std::max(hn, std::abs(M[i + (size_t)j * n]));
+        }
+    auto m = [&](int i, int j) -> cd& { return M[i + (size_t)j * n]; };
+    std::vector<cd> mult(n, 0.0);
+    std::vector<char> swp(n, 0);
+    const double tiny = 1e-14 * (hn > 0 ? hn : 1.0);
+    for (int j = 0; j + 1 < n; ++j) {
+        if (std::abs(m(j + 1, j)) > std::abs(m(j, j))) {
+            swp[j] = 1;
+            for (int c = j; c < n; ++c) std::swap(m(j, c), m(j + 1, c));
+        }
+        if (std::abs(m(j, j)) < tiny) m(j, j) = tiny;
+        mult[j] = m(j + 1, j) / m(j, j);
+        m(j + 1, j) = 0.0;
+        for (int c = j + 1; c < n; ++c) m(j + 1, c) -= mult[j] * m(j, c);
+    }
+    if (std::abs(m(n - 1, n - 1)) < tiny) m(n - 1, n - 1) = tiny;
+    y.assign(n, cd(1.0));
+    for (int i = 0; i < n; ++i) y[i] = cd(1.0 + 0.1 * std::sin(1.0 + i), 0.0);   // fixed start
+    for (int it = 0; it < 3; ++it) {
+        if (!left) {
+            for (int j = 0; j + 1 < n; ++j) {
+                if (swp[j]) std::swap(y[j], y[j + 1]);
+                y[j + 1] -= mult[j] * y[j];
+            }
+            for (int j = n - 1; j >= 0; --j) {
+                cd s = y[j];
+                for (int c = j + 1; c < n; ++c) s -= m(j, c) * y[c];
+                y[j] = s / m(j, j);
+            }
+        } else {
+            for (int j = 0; j < n; ++j) {   // U^T w = y
+                cd s = y[j];
+                for (int i = 0; i < j; ++i) s -= m(i, j) * y[i];
+                y[j] = s / m(j, j);
+            }
+            for (int j = n - 2; j >= 0; --j) {
+                y[j] -= mult[j] * y[j + 1];
+                if (swp[j]) std::swap(y[j], y[j + 1]);
+            }
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < n; ++i) nrm += std::norm(y[i]);
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) break;
+        for (int i = 0; i < n; ++i) y[i] /= nrm;
+    }
+}
+
+void ritz_select(const std::vector<cd>& theta, int k, std::vector<int>& idx, std::vector<int>& pair) {
+    idx.clear();
+    pair.clear();
+    const int n = (int)theta.size();
+    std::vector<int> fin;
+    for (int i = 0; i < n; ++i)
+        if (std::isfinite(theta[i].real()) && std::isfinite(theta[i].imag())) fin.push_back(i);
+    std::vector<int> order = fin;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double ma = std::abs(theta[a]), mb = std::abs(theta[b]);
+        if (ma != mb) return ma < mb;
+        if (theta[a].real() != theta[b].real()) return theta[a].real() < theta[b].real();
+        return theta[a].imag() < theta[b].imag();
+    });
+    std::vector<char> used(n, 0);
+    int slots = 0;
+    for (int i : order) {
+        if (slots >= k) break;
+        if (used[i]) continue;
+        const bool cplx = std::fabs(theta[i].imag()) > 1e-10 * std::max(std::abs(theta[i]), 1e-300);
+        if (cplx) {
+            if (slots + 2 > k) break;
+            int best = -1;
+            double bd = 0.0;
+            for (int j : fin) {
+                if (j == i || used[j]) continue;
+                const double d = std::abs(theta[j] - std::conj(theta[i]));
+                if (best < 0 || d < bd) {
+                    best = j;
+                    bd = d;
+                }
+            }
+            used[i] = 1;
+            if (best >= 0) used[best] = 1;
+            idx.push_back(i);
+            pair.push_back(1);
+            slots += 2;
+        } else {
+            used[i] = 1;
+            idx.push_back(i);
+            pair.push_back(0);
+            slots += 1;
+        }
+    }
+}
+
+RitzResult two_sided_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
+                          int k) {
+    RitzResult out;
+    std::vector<double> d(m), dt(m), Gs((size_t)m * m), Gts((size_t)m * m);
+    for (int i = 0; i < m; ++i) {
+        const double a = Gw[i + (size_t)i * m], b = Gwt[i + (size_t)i * m];
+        d[i] = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
+        dt[i] = b > 0 ? 1.0 / std::sqrt(b) : 0.0;
+    }
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+            Gs[i + (size_t)j * m] = d[i] * Gw[i + (size_t)j * m] * d[j];
+            Gts[i + (size_t)j * m] = dt[i] * Gwt[i + (size_t)j * m] * dt[j];
+        }
+    std::vector<int> pr, pt;
+    std::vector<double> R, Rt;
+    const int r = pivoted_cholesky(m, Gs.data(), 1e-12, pr, R);
+    const int rt = pivoted_cholesky(m, Gts.data(), 1e-12, pt, Rt);
+    const int me = std::min(r, rt);
+    out.m_eff = me;
+    if (me == 0) {
+        out.ok = true;
+        return out;
+    }
+    // reduced pencil in orthonormal bases Q = W D P R^-1, Qt = Wt Dt Pt Rt^-1
+    auto reduce = [&](const double* X) {
+        std::vector<double> Y((size_t)me * me);
+        for (int b = 0; b < me; ++b)
+            for (int a = 0; a < me; ++a)
+                Y[a + (size_t)b * me] = dt[pt[a]] * X[pt[a] + (size_t)pr[b] * m] * d[pr[b]];
+        // Y <- Y R^-1 : solve Z R = Y row by row (R upper, leading dim r)
+        for (int a = 0; a < me; ++a)
+            for (int b = 0; b < me; ++b) {
+                double s = Y[a + (size_t)b * me];
+                for (int c = 0; c < b; ++c) s -= Y[a + (size_t)c * me] * R[c + (size_t)b * r];
+                Y[a + (size_t)b * me] = s / R[b + (size_t)b * r];
+            }
+        // Y <- Rt^-T Y : solve Rt^T Z = Y (lower) column by column
+        for (int b = 0; b < me; ++b)
+            for (int a = 0; a < me; ++a) {
+                double s = Y[a + (size_t)b * me];
+                for (int c = 0; c < a; ++c) s -= Rt[c + (size_t)a * rt] * Y[c + (size_t)b * me];
+                Y[a + (size_t)b * me] = s / Rt[a + (size_t)a * rt];
+            }
+        return Y;
+    };
+    std::vector<double> Fp = reduce(F), Gp = reduce(G);
+    std::vector<int> piv(me);
+    std::vector<double> Flu = Fp;
+    if (lu_factor(me, Flu.data(), me, piv.data()) != 0) return out;
+    std::vector<double> H = Gp;
+    lu_solve(me, Flu.data(), me, piv.data(), H.data(), me, me, false);   // H = F'^-1 G'
+    std::vector<double> Hh, Qh;
+    std::vector<cd> lam;
+    if (!eig_general(me, H.data(), Hh, Qh, lam)) return out;
+    std::vector<int> idx, pair;
+    ritz_select(lam, k, idx, pair);
+    std::vector<double> Yr, Ytr;   // me x kout columns
+    std::vector<cd> yh, wh;
+    for (size_t t = 0; t < idx.size(); ++t) {
+        const cd th = lam[idx[t]];
+        hess_eigvec(me, Hh, th, false, yh);
+        hess_eigvec(me, Hh, th, true, wh);
+        std::vector<cd> y(me, 0.0), w(me, 0.0);
+        for (int i = 0; i < me; ++i)
+            for (int j = 0; j < me; ++j) {
+                y[i] += Qh[i + (size_t)j * me] * yh[j];
+                w[i] += Qh[i + (size_t)j * me] * wh[j];
+            }
+        // left pencil vector yt = F'^-T w (real and imaginary parts separately)
+        std::vector<double> wr(me), wi(me);
+        for (int i = 0; i < me; ++i) {
+            wr[i] = w[i].real();
+            wi[i] = w[i].imag();
+        }
+        lu_solve(me, Flu.data(), me, piv.data(), wr.data(), me, 1, true);
+        lu_solve(me, Flu.data(), me, piv.data(), wi.data(), me, 1, true);
+        if (!pair[t]) {
+            // real eigenvalue: make the vectors real (remove a common phase)
+            cd ph = 0.0;
+            for (int i = 0; i < me; ++i)
+                if (std::abs(y[i]) > std::abs(ph)) ph = y[i];
+            ph = ph == cd(0.0) ? cd(1.0) : std::conj(ph) / std::abs(ph);
+            for (int i = 0; i < me; ++i) Yr.push_back((y[i] * ph).real());
+            cd pl = 0.0;
+            for (int i = 0; i < me; ++i)
+                if (std::abs(cd(wr[i], wi[i])) > std::abs(pl)) pl = cd(wr[i], wi[i]);
+            pl = pl == cd(0.0) ? cd(1.0) : std::conj(pl) / std::abs(pl);
+            for (int i = 0; i < me; ++i) Ytr.push_back((cd(wr[i], wi[i]) * pl).real());
+            out.theta.push_back(th);
+        } else {
+            for (int i = 0; i < me; ++i) Yr.push_back(y[i].real());
+            for (int i = 0; i < me; ++i) Yr.push_back(y[i].imag());
+            for (int i = 0; i < me; ++i) Ytr.push_back(wr[i]);
+            for (int i = 0; i < me; ++i) Ytr.push_back(wi[i]);
+            out.theta.push_back(th);
+            out.theta.push_back(std::conj(th));
+        }
+    }
+    const int kout = (int)(Yr.size() / me);
+    // back to W coordinates: Y = D P R^-1 Y'
+    auto back = [&](std::vector<double>& Yc, const std::vector<double>& Rm, int rr,
+                    const std::vector<int>& perm, const std::vector<double>& dd) {
+        std::vector<double> full((size_t)m * kout, 0.0);
+        for (int c = 0; c < kout; ++c) {
+            std::vector<double> z(Yc.begin() + (size_t)c * me, Yc.begin() + (size_t)(c + 1) * me);
+            for (int a = me - 1; a >= 0; --a) {   // R z = y (upper, leading block me)
+                double s = z[a];
+                for (int b = a + 1; b < me; ++b) s -= Rm[a + (size_t)b * rr] * z[b];
+                z[a] = s / Rm[a + (size_t)a * rr];
+            }
+            for (int a = 0; a < me; ++a) full[perm[a] + (size_t)c * m] = dd[perm[a]] * z[a];
+        }
+        return full;
+    };
+    out.Y = back(Yr, R, r, pr, d);
+    out.Yt = back(Ytr, Rt, rt, pt, dt);
+    // unit-norm columns of W Y and Wt Yt
+    auto normalise = [&](std::vector<double>& Y, const double* Gram) {
+        for (int c = 0; c < kout; ++c) {
+            double s = 0.0;
+            const double* y = Y.data() + (size_t)c * m;
+            for (int j = 0; j < m; ++j) {
+                double g = 0.0;
+                for (int i = 0; i < m; ++i) g += Gram[i + (size_t)j * m] * y[i];
+                s += g * y[j];
+            }
+            const double f = s > 0 ? 1.0 / std::sqrt(s) : 0.0;
+            for (int j = 0; j < m; ++j) Y[j + (size_t)c * m] *= f;
+        }
+    };
+    normalise(out.Y, Gw);
+    normalise(out.Yt, Gwt);
+    out.kout = kout;
+    out.ok = true;
+    return out;
+}
+
+}  // namespace dense
+}  // namespace rbs

@@ -1,0 +1,60 @@
+// Small dense FP64 linear algebra on the host (k x k and (k+s) x (k+s)
+// problems of the recycle-space management).  Column-major storage.
+#pragma once
+#include <complex>
+#include <vector>
+
+namespace rbs {
+namespace dense {
+
+// LU with partial pivoting; returns 0 or the 1-based index of a zero pivot.
+int lu_factor(int n, double* A, int lda, int* piv);
+// Solve A X = B (trans = false) or A^T X = B (trans = true) in place.
+void lu_solve(int n, const double* LU, int lda, const int* piv, double* B, int ldb, int nrhs,
+              bool trans);
+
+// One-sided Jacobi SVD of the m x m matrix M = P diag(sig) Q^T, sig descending.
+void svd(int m, const double* M, double* P, double* sig, double* Q);
+
+// Pivoted Cholesky of the symmetric positive semi-definite G (m x m):
+// P^T G P = R^T R truncated at the first pivot <= tol * (largest diagonal).
+// Returns the rank r; perm[0..r) are the chosen columns, R is r x r upper
+// triangular (leading dimension r).
+int pivoted_cholesky(int m, const double* G, double tol, std::vector<int>& perm,
+                     std::vector<double>& R);
+
+// Eigenvalues of a general real matrix H (n x n): Householder reduction to
+// Hessenberg form followed by the Francis double-shift QR iteration.
+// On return Hh holds the Hessenberg form and Qh the orthogonal Q with
+// H = Qh Hh Qh^T.  Returns false if the QR iteration did not converge.
+bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<double>& Qh,
+                 std::vector<std::complex<double>>& lambda);
+
+// Eigenvector of the Hessenberg matrix Hh for eigenvalue lam by inverse
+// iteration (left = true: eigenvector of Hh^T).
+void hess_eigvec(int n, const std::vector<double>& Hh, std::complex<double> lam, bool left,
+                 std::vector<std::complex<double>>& y);
+
+// Two-sided Rayleigh-Ritz for the k smallest-magnitude Ritz values.
+// Inputs (m x m, column-major): Gw = W^T W, Gwt = Wt^T Wt, F = Wt^T W,
+// G = Wt^T A W.  Outputs: coefficient matrices Y, Yt (m x kout) such that
+// U = W Y and Ut = Wt Yt have unit-norm columns spanning approximate right
+// and left invariant subspaces; theta holds the selected Ritz values.
+struct RitzResult {
+    int kout = 0;
+    int m_eff = 0;
+    std::vector<double> Y, Yt;
+    std::vector<std::complex<double>> theta;
+    bool ok = false;
+};
+RitzResult two_sided_ritz(int m, const double* Gw, const double* Gwt, const double* F,
+                          const double* G, int k);
+
+// Selection rule shared by the Ritz step: indices of the k finite values of
+// smallest |theta| ordered by (|theta|, Re, Im); a complex pair takes two
+// slots and is skipped when only one slot is left.  pair[i] flags pairs.
+void ritz_select(const std::vector<std::complex<double>>& theta, int k, std::vector<int>& idx,
+                 std::vector<int>& pair);
+
+}  // namespace dense
+}  // namespace rbs

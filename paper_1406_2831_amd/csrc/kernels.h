@@ -1,0 +1,81 @@
+// Host-side launchers of the HIP kernels (kernels.hip).  Every launcher
+// enqueues on `st` and returns immediately; sizes are validated by the caller.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace rbs {
+
+// Grid used by the streaming (row-parallel) kernels for n rows.
+int stream_grid(int64_t n);
+
+// ---- sliced ELL build (CSR -> Sell) -------------------------------------
+// widths[s] = max row length of slice s; returns nothing (device result).
+void launch_sell_widths(hipStream_t st, int64_t n, const int32_t* rowptr, int32_t* widths);
+// exclusive scan of 64*widths into slice_ptr (nslices+1 entries); single block.
+void launch_sell_scan(hipStream_t st, int64_t nslices, const int32_t* widths, int32_t* slice_ptr);
+void launch_sell_fill(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colidx,
+                      const double* val, Sell A);
+
+// ---- generic streaming kernels ------------------------------------------
+void launch_fill(hipStream_t st, double* y, int64_t len, double v);
+void launch_copy(hipStream_t st, double* y, const double* x, int64_t len);
+// y = A x   (Sell)
+void launch_spmv(hipStream_t st, const Sell& A, const double* x, double* y);
+// Y[:, j] = A X[:, j], j < m (column-major, leading dimension ld)
+void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
+                 int64_t ldy, int m);
+// Y[:, 0:ko] = X[:, 0:m] S   (S device, m x ko column-major with leading dim m)
+void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m,
+                    const double* S, int ko, double* Y, int64_t ldy);
+// out (mx x (my1+my2), column-major, ld = mx) = X^T [Y1 Y2]; partial buffer
+// must hold tile partials (see gemmt_partial_doubles).
+size_t gemmt_partial_doubles(int64_t n, int mx, int my);
+void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx,
+                  const double* Y1, int64_t ldy1, int my1, const double* Y2, int64_t ldy2,
+                  int my2, double* partial, double* out);
+
+// ---- solve kernels (Algorithm 2 / BiCGSTAB) -------------------------------
+struct SolveBufs {
+    int64_t n, ld;
+    int k;
+    Sell A, At;
+    const double *U, *C, *Chat, *Ct, *Ccheck, *Gh;
+    const double* b;
+    double* xout;          // caller's x (in: x_{-1} when x_nonzero; out: solution)
+    const double* shadow;  // rt_{-1} or nullptr (then r_{-1})
+    double *x, *r, *s, *t, *p, *q, *rt0, *rh;
+    SolveState* state;
+    double* partials;
+    unsigned* tickets;     // one per kernel kind
+};
+void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it);
+void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count);
+void launch_solve_epilogue(hipStream_t st, const SolveBufs& B);
+
+// ---- RBiCG (Algorithm 1) kernels ------------------------------------------
+struct BicgBufs {
+    int64_t n, ld;
+    int k;
+    Sell A, At;
+    const double *U, *C, *Chat, *Ut, *Ct, *Ccheck;
+    const double* b;
+    double* xout;
+    double *x, *r, *rt, *p, *pt, *z, *zt, *q, *qt;
+    double *W, *Wt, *AW;   // cycle store (column-major, ld), Lanczos columns at col0..
+    int64_t ldw;
+    int col0;              // first Lanczos column (= recycle dimension of the store)
+    BicgState* state;
+    double* partials;
+    unsigned* tickets;
+};
+void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap);
+void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count);
+void launch_bicg_epilogue(hipStream_t st, const BicgBufs& B);
+void launch_bicg_reset_cycle(hipStream_t st, BicgState* state);
+
+// ||b - A x||^2 into state_sums[0], ||b||^2 into state_sums[1]
+void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const double* x,
+                          double* partials, unsigned* ticket, double* out_sums);
+
+}  // namespace rbs

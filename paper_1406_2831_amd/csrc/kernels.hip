@@ -1,0 +1,1177 @@
+// HIP kernels for gfx950 (MI355X) of the recycling BiCGSTAB library.
+//
+// The per-iteration work of Algorithm 2 (RBiCGSTAB, Section 4) is fused
+// into three row-parallel passes, each ending in one deterministic grid
+// reduction whose last block updates the device-resident scalars:
+//
+//   update : r = s - w t ; x += a p + w s ; p = r + b (p - w q)
+//            sums ||r||^2, (rt0, r), (rh, p), Gh^T p          -> alpha, zeta
+//   spmv1  : q = A p - C zeta ; s = r - alpha q ; sums Gh^T s -> gamma
+//   spmv2  : t = A s - C gamma ; sums (s,t) (t,t) (rt0,s) (rt0,t) (s,s)
+//                                                             -> omega, beta, x_c
+//
+// with Gh = A^T Chat and rh = A^T rt0 formed once per matrix / per solve, so
+// that zeta = Chat^T A p = Gh^T p and (rt0, q) = (rh, p) - (C^T rt0)^T zeta are
+// available before the product A p is.  In exact arithmetic these are the
+// iterates of Algorithm 2; k = 0 gives van der Vorst's BiCGSTAB.
+//
+// All passes are HBM-bandwidth bound (about 0.1-0.25 flop/byte), so they use
+// one thread per row, fully coalesced column-major block reads, and a
+// sliced-ELL matrix copy whose slices are exactly one wavefront tall.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace rbs {
+
+namespace {
+
+enum { S_OK = 0, S_MAXIT = 1, S_BD_RHO = 2, S_BD_ALPHA = 3, S_BD_OMEGA = 4, S_NONFINITE = -5 };
+
+// ticket slots (one per reducing kernel kind; kernels on one stream never overlap)
+enum { T_PRO1 = 0, T_PRO2, T_UPD, T_SPMV1, T_SPMV2, T_RES, T_BPRO1, T_BPRO2, T_BUPD, T_BSPMV,
+       T_BSPMVT, T_BPROJ };
+
+constexpr int MAX_GRID = 2048;
+
+__device__ __forceinline__ int logical_block() {
+    // Blocks are dispatched round-robin over the 8 XCDs; remap so that each
+    // XCD owns one contiguous eighth of the rows (its L2 then holds the
+    // gathered vector entries its rows need).
+    const int b = blockIdx.x, nb = gridDim.x;
+    if ((nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
+    return b;
+}
+
+// Contiguous row range of this block; starts on a slice (64-row) boundary.
+__device__ __forceinline__ void block_rows(int64_t n, int64_t& r0, int64_t& r1) {
+    const int64_t nsl = (n + WAVE - 1) / WAVE;
+    const int64_t per = (nsl + gridDim.x - 1) / gridDim.x;
+    const int64_t s0 = (int64_t)logical_block() * per;
+    const int64_t s1 = s0 + per < nsl ? s0 + per : nsl;
+    r0 = s0 * WAVE;
+    r1 = s1 * WAVE < n ? s1 * WAVE : n;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Sum m (<= M) per-thread values over the block; totals land in tot[0..m).
+template <int M>
+__device__ __forceinline__ void block_sum(const double (&v)[M], int m, double* red, double* tot) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (j < m) {
+            const double s = wave_sum(v[j]);
+            if (lane == 0) red[wid * M + j] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / WAVE; ++w) s += red[w * M + threadIdx.x];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// One-pass grid reduction: block partials, then the last block to arrive sums
+// them in block order (run-to-run deterministic) into tot[] and returns true.
+template <int M>
+__device__ bool grid_reduce(const double (&v)[M], int m, double* partials, unsigned* ticket,
+                            double* tot) {
+    __shared__ double red[(BLOCK / WAVE) * M];
+    __shared__ int last;
+    block_sum<M>(v, m, red, tot);
+    if (threadIdx.x < m) partials[(int64_t)blockIdx.x * M + threadIdx.x] = tot[threadIdx.x];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j < m)
+                acc[j] += __hip_atomic_load(&partials[(int64_t)b * M + j], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum<M>(acc, m, red, tot);
+    if (threadIdx.x == 0) *ticket = 0u;
+    return true;
+}
+
+__device__ __forceinline__ double sell_row(const Sell& A, int64_t row, const double* __restrict__ x) {
+    const int64_t s = row / WAVE;
+    const int lane = (int)(row & (WAVE - 1));
+    const int32_t beg = A.slice_ptr[s], end = A.slice_ptr[s + 1];
+    double acc = 0.0;
+    for (int32_t e = beg + lane; e < end; e += WAVE) acc += A.val[e] * x[A.col[e]];
+    return acc;
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// ---------------------------------------------------------------- sliced ELL build
+
+__global__ __launch_bounds__(BLOCK) void k_sell_widths(int64_t n, const int32_t* __restrict__ rowptr,
+                                                       int32_t* __restrict__ widths) {
+    const int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int len = 0;
+    if (row < n) len = rowptr[row + 1] - rowptr[row];
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const int o = __shfl_xor(len, off, WAVE);
+        len = o > len ? o : len;
+    }
+    const int64_t nsl = (n + WAVE - 1) / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0 && row / WAVE < nsl) widths[row / WAVE] = len;
+}
+
+__global__ __launch_bounds__(1024) void k_sell_scan(int64_t nsl, const int32_t* __restrict__ widths,
+                                                    int32_t* __restrict__ slice_ptr) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nsl + 1023) / 1024;
+    const int64_t b0 = tid * per, b1 = (b0 + per < nsl) ? b0 + per : nsl;
+    int64_t local = 0;
+    for (int64_t s = b0; s < b1; ++s) local += (int64_t)widths[s] * WAVE;
+    part[tid] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - local;
+    for (int64_t s = b0; s < b1; ++s) {
+        slice_ptr[s] = (int32_t)run;
+        run += (int64_t)widths[s] * WAVE;
+    }
+    if (tid == 1023) slice_ptr[nsl] = (int32_t)part[1023];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sell_fill(int64_t n, const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ colidx,
+                                                     const double* __restrict__ val, Sell A) {
+    const int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t s = row / WAVE;
+    if (s >= A.nslices) return;
+    const int lane = (int)(row & (WAVE - 1));
+    const int32_t beg = A.slice_ptr[s];
+    const int w = (A.slice_ptr[s + 1] - beg) / WAVE;
+    int32_t rb = 0, len = 0;
+    if (row < n) {
+        rb = rowptr[row];
+        len = rowptr[row + 1] - rb;
+    }
+    for (int j = 0; j < w; ++j) {
+        const int64_t e = beg + (int64_t)j * WAVE + lane;
+        if (j < len) {
+            A.col[e] = colidx[rb + j];
+            A.val[e] = val[rb + j];
+        } else {
+            A.col[e] = row < n ? (int32_t)row : 0;
+            A.val[e] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- generic streaming
+
+__global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ y, int64_t len, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < len; i += (int64_t)gridDim.x * BLOCK)
+        y[i] = v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_copy(double* __restrict__ y, const double* __restrict__ x,
+                                                int64_t len) {
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < len; i += (int64_t)gridDim.x * BLOCK)
+        y[i] = x[i];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmv(Sell A, const double* __restrict__ x,
+                                                double* __restrict__ y) {
+    int64_t r0, r1;
+    block_rows(A.n, r0, r1);
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) y[row] = sell_row(A, row, x);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmm(Sell A, const double* __restrict__ X, int64_t ldx,
+                                                double* __restrict__ Y, int64_t ldy, int m) {
+    int64_t r0, r1;
+    block_rows(A.n, r0, r1);
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const int64_t s = row / WAVE;
+        const int lane = (int)(row & (WAVE - 1));
+        const int32_t beg = A.slice_ptr[s], end = A.slice_ptr[s + 1];
+        for (int c0 = 0; c0 < m; c0 += 8) {
+            double acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+            for (int32_t e = beg + lane; e < end; e += WAVE) {
+                const double v = A.val[e];
+                const int64_t col = A.col[e];
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (c0 + c < m) acc[c] += v * X[col + (int64_t)(c0 + c) * ldx];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c0 + c < m) Y[row + (int64_t)(c0 + c) * ldy] = acc[c];
+        }
+    }
+}
+
+// Y[:, 0:ko] = X[:, 0:m] S, S (m x ko) column-major; 8 output columns per pass.
+__global__ __launch_bounds__(BLOCK) void k_gemm_ts(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                   int m, const double* __restrict__ S, int ko,
+                                                   double* __restrict__ Y, int64_t ldy) {
+    extern __shared__ double sS[];   // m x 8
+    int64_t r0, r1;
+    block_rows(n, r0, r1);
+    for (int c0 = 0; c0 < ko; c0 += 8) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < m * 8; idx += BLOCK) {
+            const int i = idx / 8, c = idx % 8;
+            sS[idx] = (c0 + c < ko) ? S[i + (int64_t)(c0 + c) * m] : 0.0;
+        }
+        __syncthreads();
+        for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+            double acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+            for (int i = 0; i < m; ++i) {
+                const double xv = X[row + (int64_t)i * ldx];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += xv * sS[i * 8 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c0 + c < ko) Y[row + (int64_t)(c0 + c) * ldy] = acc[c];
+        }
+    }
+}
+
+// Tall-skinny X^T Y: 64x64 output tile per block, 4x4 per thread, rows staged
+// through LDS in slabs of 32; one partial tile per (tile, row chunk).
+constexpr int GT = 64, GS = 32;
+
+__global__ __launch_bounds__(BLOCK) void k_gemmt_tile(int64_t n, const double* __restrict__ X,
+                                                      int64_t ldx, int mx, const double* __restrict__ Y1,
+                                                      int64_t ldy1, int my1, const double* __restrict__ Y2,
+                                                      int64_t ldy2, int my2, int tiles_y, int64_t rows_per_chunk,
+                                                      double* __restrict__ partial) {
+    __shared__ double sx[GS][GT + 1];
+    __shared__ double sy[GS][GT + 1];
+    const int tile = blockIdx.x;
+    const int tx = tile / tiles_y, ty = tile % tiles_y;
+    const int my = my1 + my2;
+    const int64_t c0 = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t c1 = (c0 + rows_per_chunk < n) ? c0 + rows_per_chunk : n;
+    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int64_t base = c0; base < c1; base += GS) {
+        // load: thread covers row (tid % 32) of 8 columns (tid / 32 + 8 q)
+        const int lr = threadIdx.x % GS, lc = threadIdx.x / GS;
+        const int64_t row = base + lr;
+#pragma unroll
+        for (int q = 0; q < GT / 8; ++q) {
+            const int c = lc + 8 * q;
+            const int gi = tx * GT + c;
+            double vx = 0.0, vy = 0.0;
+            if (row < c1 && gi < mx) vx = X[row + (int64_t)gi * ldx];
+            const int gj = ty * GT + c;
+            if (row < c1 && gj < my) vy = gj < my1 ? Y1[row + (int64_t)gj * ldy1]
+                                                  : Y2[row + (int64_t)(gj - my1) * ldy2];
+            sx[lr][c] = vx;
+            sy[lr][c] = vy;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < GS; ++rr) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = sx[rr][tr * 4 + u];
+                b[u] = sy[rr][tc * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+    double* out = partial + ((int64_t)blockIdx.y * gridDim.x + tile) * (GT * GT);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(tr * 4 + u) * GT + tc * 4 + v] = acc[u][v];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tiles_y, int ntiles,
+                                                        int nchunks, const double* __restrict__ partial,
+                                                        double* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= (int64_t)mx * my) return;
+    const int i = (int)(idx % mx), j = (int)(idx / mx);   // out column-major (ld = mx)
+    const int tile = (i / GT) * tiles_y + (j / GT);
+    const int off = (i % GT) * GT + (j % GT);
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * ntiles + tile) * (GT * GT) + off];
+    out[idx] = s;
+}
+
+// ---------------------------------------------------------------- Algorithm 2 passes
+
+// P1: r_{-1} = b - A x_{-1}; sums ||b||^2, Chat^T r_{-1}, Ccheck^T rt_{-1}
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz, double rtol, int max_it) {
+    constexpr int M = 2 * K + 1;
+    __shared__ double tot[M];
+    const int k = B.k;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double bv = B.b[row];
+        const double rm1 = xnz ? bv - sell_row(B.A, row, B.xout) : bv;
+        B.r[row] = rm1;
+        const double rtm1 = B.shadow ? B.shadow[row] : rm1;
+        acc[0] += bv * bv;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < k) {
+                acc[1 + j] += B.Chat[row + (int64_t)j * B.ld] * rm1;
+                acc[1 + K + j] += B.Ccheck[row + (int64_t)j * B.ld] * rtm1;
+            }
+        }
+    }
+    // pack the two k-sized groups contiguously for the reduction
+    double pk[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) pk[j] = 0.0;
+    pk[0] = acc[0];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j < k) {
+            pk[1 + j] = acc[1 + j];
+            pk[1 + k + j] = acc[1 + K + j];
+        }
+    }
+    if (grid_reduce<M>(pk, 1 + 2 * k, B.partials, B.tickets + T_PRO1, tot)) {
+        if (threadIdx.x == 0) {
+            SolveState* st = B.state;
+            const double b2 = tot[0];
+            st->bnorm2 = b2;
+            st->tol2 = rtol * rtol * b2;
+            st->done = 0;
+            st->status = S_MAXIT;
+            st->iters_done = 0;
+            st->max_it = max_it;
+            st->k = k;
+            for (int j = 0; j < k; ++j) {
+                st->zeta[j] = tot[1 + j];       // zeta_0 = Chat^T r_{-1}
+                st->gamma[j] = tot[1 + k + j];  // Ccheck^T rt_{-1}
+            }
+            if (!finite(b2)) {
+                st->done = 1;
+                st->status = S_NONFINITE;
+            }
+        }
+    }
+}
+
+// P2: eq. (minusXR): x_0 = x_{-1} + U zeta_0, r_0 = r_{-1} - C zeta_0,
+//     rt_0 = rt_{-1} - Ct (Ccheck^T rt_{-1}); sums ||r_0||^2, (rt_0, r_0), C^T rt_0
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
+    constexpr int M = K + 2;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    double z0[K > 0 ? K : 1], eta[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        z0[j] = j < k ? st->zeta[j] : 0.0;
+        eta[j] = j < k ? st->gamma[j] : 0.0;
+    }
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double xv = xnz ? B.xout[row] : 0.0;
+        const double rm1 = B.r[row];
+        double rv = rm1;
+        double rtv = B.shadow ? B.shadow[row] : rm1;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < k) {
+                const int64_t o = row + (int64_t)j * B.ld;
+                xv += B.U[o] * z0[j];
+                rv -= B.C[o] * z0[j];
+                rtv -= B.Ct[o] * eta[j];
+            }
+        }
+        B.x[row] = xv;
+        B.s[row] = rv;      // the first update pass forms r_0 = s - 0 t
+        B.rt0[row] = rtv;
+        B.t[row] = 0.0;
+        B.p[row] = 0.0;
+        B.q[row] = 0.0;
+        acc[0] += rv * rv;
+        acc[1] += rtv * rv;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) acc[2 + j] += B.C[row + (int64_t)j * B.ld] * rtv;
+    }
+    if (grid_reduce<M>(acc, 2 + k, B.partials, B.tickets + T_PRO2, tot)) {
+        if (threadIdx.x == 0) {
+            for (int j = 0; j < k; ++j) {
+                st->w[j] = tot[2 + j];
+                st->xc[j] = 0.0;
+            }
+            st->alpha = st->beta = st->omega = 0.0;
+            st->omega_zero = 0;
+            st->iter = 1;
+            st->rr = tot[0];
+            st->rho = tot[1];
+            if (!finite(tot[0]) || !finite(tot[1])) {
+                st->done = 1;
+                st->status = S_NONFINITE;
+            } else if (tot[0] <= st->tol2) {
+                st->done = 1;
+                st->status = S_OK;
+            } else if (tot[1] == 0.0) {
+                st->done = 1;
+                st->status = S_BD_RHO;
+            }
+        }
+    }
+}
+
+// update pass (end of iteration i-1 and start of iteration i)
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
+    constexpr int M = K + 3;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    const double alpha = st->alpha, omega = st->omega, beta = st->beta;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double sv = B.s[row], tv = B.t[row], pv = B.p[row], qv = B.q[row];
+        const double rv = sv - omega * tv;
+        B.x[row] += alpha * pv + omega * sv;
+        const double pn = rv + beta * (pv - omega * qv);
+        B.r[row] = rv;
+        B.p[row] = pn;
+        acc[0] += rv * rv;
+        acc[1] += B.rt0[row] * rv;
+        acc[2] += B.rh[row] * pn;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) acc[3 + j] += B.Gh[row + (int64_t)j * B.ld] * pn;
+    }
+    if (grid_reduce<M>(acc, 3 + k, B.partials, B.tickets + T_UPD, tot)) {
+        if (threadIdx.x == 0) {
+            const int i = st->iter;
+            const double rr = tot[0], rho = tot[1];
+            st->rr = rr;
+            if (!finite(rr) || !finite(rho)) {
+                st->done = 1;
+                st->status = S_NONFINITE;
+                st->iters_done = i - 1;
+            } else if (rr <= st->tol2) {
+                st->done = 1;
+                st->status = S_OK;
+                st->iters_done = i - 1;
+            } else if (st->omega_zero) {
+                st->done = 1;
+                st->status = S_BD_OMEGA;
+                st->iters_done = i - 1;
+            } else if (i > st->max_it) {
+                st->done = 1;
+                st->status = S_MAXIT;
+                st->iters_done = i - 1;
+            } else if (rho == 0.0) {
+                st->done = 1;
+                st->status = S_BD_RHO;
+                st->iters_done = i - 1;
+            } else {
+                double den = tot[2];
+                for (int j = 0; j < k; ++j) {
+                    st->zeta[j] = tot[3 + j];
+                    den -= st->w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
+                }
+                if (den == 0.0 || !finite(den)) {
+                    st->done = 1;
+                    st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
+                    st->iters_done = i - 1;
+                } else {
+                    st->rho = rho;
+                    st->alpha = rho / den;
+                }
+            }
+        }
+    }
+}
+
+// spmv1: q = A p - C zeta ; s = r - alpha q ; gamma partials Gh^T s
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufs B) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    const double alpha = st->alpha;
+    double zeta[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) zeta[j] = (j < k) ? st->zeta[j] : 0.0;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double qv = sell_row(B.A, row, B.p);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) qv -= B.C[row + (int64_t)j * B.ld] * zeta[j];
+        const double sv = B.r[row] - alpha * qv;
+        B.q[row] = qv;
+        B.s[row] = sv;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) acc[j] += B.Gh[row + (int64_t)j * B.ld] * sv;
+    }
+    if (K > 0 && k > 0) {
+        if (grid_reduce<M>(acc, k, B.partials, B.tickets + T_SPMV1, tot)) {
+            if (threadIdx.x < k) st->gamma[threadIdx.x] = tot[threadIdx.x];
+        }
+    }
+}
+
+// spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufs B) {
+    constexpr int M = 5;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    double gam[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) gam[j] = (j < k) ? st->gamma[j] : 0.0;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double tv = sell_row(B.A, row, B.s);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) tv -= B.C[row + (int64_t)j * B.ld] * gam[j];
+        B.t[row] = tv;
+        const double sv = B.s[row], rt = B.rt0[row];
+        acc[0] += sv * tv;
+        acc[1] += tv * tv;
+        acc[2] += rt * sv;
+        acc[3] += rt * tv;
+        acc[4] += sv * sv;
+    }
+    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_SPMV2, tot)) {
+        if (threadIdx.x == 0) {
+            const double st_ = tot[0], tt = tot[1], rts = tot[2], rtt = tot[3];
+            const double alpha = st->alpha;
+            double omega;
+            if (tt == 0.0) {
+                // (t, t) = 0: accept the half step x + alpha p if ||s|| <= tol
+                // (the next update pass sees r = s and tests it), else breakdown
+                omega = 0.0;
+                st->omega_zero = tot[4] <= st->tol2 ? 0 : 1;
+            } else {
+                omega = st_ / tt;
+                st->omega_zero = omega == 0.0 ? 1 : 0;
+            }
+            st->omega = omega;
+            for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + omega * st->gamma[j];
+            const double rho_new = rts - omega * rtt;   // (rt0, r_i) = (rt0, s) - omega (rt0, t)
+            st->beta = omega != 0.0 ? (rho_new / st->rho) * (alpha / omega) : 0.0;
+            st->iter += 1;
+        }
+    }
+}
+
+// epilogue: x_out = x - U x_c (Algorithm 2 step 8)
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_epi(SolveBufs B) {
+    const SolveState* st = B.state;
+    const int k = B.k;
+    double xc[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) xc[j] = j < k ? st->xc[j] : 0.0;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double xv = B.x[row];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) xv -= B.U[row + (int64_t)j * B.ld] * xc[j];
+        B.xout[row] = xv;
+    }
+}
+
+// ||b - A x||^2 and ||b||^2
+__global__ __launch_bounds__(BLOCK) void k_true_res(Sell A, const double* __restrict__ b,
+                                                    const double* __restrict__ x, double* partials,
+                                                    unsigned* ticket, double* out) {
+    __shared__ double tot[2];
+    int64_t r0, r1;
+    block_rows(A.n, r0, r1);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double bv = b[row];
+        const double rv = bv - sell_row(A, row, x);
+        acc[0] += rv * rv;
+        acc[1] += bv * bv;
+    }
+    if (grid_reduce<2>(acc, 2, partials, ticket, tot)) {
+        if (threadIdx.x == 0) {
+            out[0] = tot[0];
+            out[1] = tot[1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Algorithm 1 passes
+
+// BP1: r_{-1} = b - A x_{-1}, rt_{-1} = ones; sums ||b||^2, Chat^T r_{-1}, Ccheck^T rt_{-1}
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz, double rtol, int max_it,
+                                                 int store_cap) {
+    constexpr int M = 2 * K + 1;
+    __shared__ double tot[M];
+    const int k = B.k;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double bv = B.b[row];
+        const double rm1 = xnz ? bv - sell_row(B.A, row, B.xout) : bv;
+        B.r[row] = rm1;
+        acc[0] += bv * bv;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < k) {
+                acc[1 + j] += B.Chat[row + (int64_t)j * B.ld] * rm1;
+                acc[1 + K + j] += B.Ccheck[row + (int64_t)j * B.ld];   // rt_{-1} = ones
+            }
+        }
+    }
+    double pk[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) pk[j] = 0.0;
+    pk[0] = acc[0];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j < k) {
+            pk[1 + j] = acc[1 + j];
+            pk[1 + k + j] = acc[1 + K + j];
+        }
+    }
+    if (grid_reduce<M>(pk, 1 + 2 * k, B.partials, B.tickets + T_BPRO1, tot)) {
+        if (threadIdx.x == 0) {
+            BicgState* st = B.state;
+            const double b2 = tot[0];
+            st->bnorm2 = b2;
+            st->tol2 = rtol * rtol * b2;
+            st->done = 0;
+            st->status = S_MAXIT;
+            st->iters_done = 0;
+            st->max_it = max_it;
+            st->store_cap = store_cap;
+            st->stored = 0;
+            st->cur_slot = -1;
+            st->k = k;
+            for (int j = 0; j < k; ++j) {
+                st->zeta[j] = tot[1 + j];
+                st->zetat[j] = tot[1 + k + j];
+            }
+            if (!finite(b2)) {
+                st->done = 1;
+                st->status = S_NONFINITE;
+            }
+        }
+    }
+}
+
+// BP2: eq. (minusXR) for the primary and the dual system
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
+    constexpr int M = 2;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    double z0[K > 0 ? K : 1], zt0[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        z0[j] = j < k ? st->zeta[j] : 0.0;
+        zt0[j] = j < k ? st->zetat[j] : 0.0;
+    }
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M] = {0.0, 0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double xv = xnz ? B.xout[row] : 0.0;
+        double rv = B.r[row];
+        double rtv = 1.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < k) {
+                const int64_t o = row + (int64_t)j * B.ld;
+                xv += B.U[o] * z0[j];
+                rv -= B.C[o] * z0[j];
+                rtv -= B.Ct[o] * zt0[j];
+            }
+        }
+        B.x[row] = xv;
+        B.r[row] = rv;
+        B.rt[row] = rtv;
+        B.p[row] = 0.0;
+        B.pt[row] = 0.0;
+        B.q[row] = 0.0;
+        B.qt[row] = 0.0;
+        B.z[row] = 0.0;
+        acc[0] += rv * rv;
+        acc[1] += rtv * rv;
+    }
+    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_BPRO2, tot)) {
+        if (threadIdx.x == 0) {
+            for (int j = 0; j < k; ++j) st->zc[j] = 0.0;
+            st->alpha = st->beta = 0.0;
+            st->iter = 1;
+            st->stored = 0;
+            st->rr = tot[0];
+            st->rho = tot[1];
+            if (!finite(tot[0]) || !finite(tot[1])) {
+                st->done = 1;
+                st->status = S_NONFINITE;
+            } else if (tot[0] <= st->tol2) {
+                st->done = 1;
+                st->status = S_OK;
+            } else if (tot[1] == 0.0) {
+                st->done = 1;
+                st->status = S_BD_RHO;
+            }
+        }
+    }
+}
+
+// BQ1: r -= alpha q; rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt;
+//      store r into the cycle store; sums ||r||^2, (rt, r)
+__global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
+    constexpr int M = 2;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const double alpha = st->alpha, beta = st->beta;
+    const int slot = st->stored;
+    const bool store = slot < st->store_cap;
+    double* wcol = B.W + (int64_t)(B.col0 + slot) * B.ldw;
+    double* wtcol = B.Wt + (int64_t)(B.col0 + slot) * B.ldw;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M] = {0.0, 0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double rv = B.r[row] - alpha * B.q[row];
+        const double rtv = B.rt[row] - alpha * B.qt[row];
+        const double pv = B.p[row], ptv = B.pt[row];
+        B.x[row] += alpha * pv;
+        B.r[row] = rv;
+        B.rt[row] = rtv;
+        B.p[row] = rv + beta * pv;
+        B.pt[row] = rtv + beta * ptv;
+        if (store) {
+            wcol[row] = rv;
+            wtcol[row] = rtv;
+        }
+        acc[0] += rv * rv;
+        acc[1] += rtv * rv;
+    }
+    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_BUPD, tot)) {
+        if (threadIdx.x == 0) {
+            const int i = st->iter;
+            const double rr = tot[0], rho = tot[1];
+            st->rr = rr;
+            if (!finite(rr) || !finite(rho)) {
+                st->done = 1;
+                st->status = S_NONFINITE;
+                st->iters_done = i - 1;
+            } else if (rr <= st->tol2) {
+                st->done = 1;
+                st->status = S_OK;
+                st->iters_done = i - 1;
+            } else if (i > st->max_it) {
+                st->done = 1;
+                st->status = S_MAXIT;
+                st->iters_done = i - 1;
+            } else if (rho == 0.0) {
+                st->done = 1;
+                st->status = S_BD_RHO;
+                st->iters_done = i - 1;
+            } else {
+                st->rho = rho;
+                st->cur_slot = store ? slot : -1;
+                if (store) st->stored = slot + 1;
+            }
+        }
+    }
+}
+
+// BQ2: z = A p (cycle store gets A r_{i-1} = z_i - beta_{i-1} z_{i-1}); zeta = Chat^T z
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    const double beta = st->beta;
+    const int slot = st->cur_slot;     // column of r_{i-1}, -1 when not stored
+    const bool store = slot >= 0;
+    double* awcol = B.AW + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double zv = sell_row(B.A, row, B.p);
+        if (store) awcol[row] = zv - beta * B.z[row];
+        B.z[row] = zv;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) acc[j] += B.Chat[row + (int64_t)j * B.ld] * zv;
+    }
+    if (K > 0 && k > 0) {
+        if (grid_reduce<M>(acc, k, B.partials, B.tickets + T_BSPMV, tot)) {
+            if (threadIdx.x < k) st->zeta[threadIdx.x] = tot[threadIdx.x];
+        }
+    }
+}
+
+// BQ2t: zt = A^T pt ; zetat = Ccheck^T zt
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bspmvt(BicgBufs B) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double zv = sell_row(B.At, row, B.pt);
+        B.zt[row] = zv;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) acc[j] += B.Ccheck[row + (int64_t)j * B.ld] * zv;
+    }
+    if (K > 0 && k > 0) {
+        if (grid_reduce<M>(acc, k, B.partials, B.tickets + T_BSPMVT, tot)) {
+            if (threadIdx.x < k) st->zetat[threadIdx.x] = tot[threadIdx.x];
+        }
+    }
+}
+
+// BQ3: q = z - C zeta ; qt = zt - Ct zetat ; alpha = rho / (pt, q);
+//      beta from (rt - a qt, r - a q) expanded
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bproj(BicgBufs B) {
+    constexpr int M = 4;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    double zeta[K > 0 ? K : 1], zetat[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        zeta[j] = j < k ? st->zeta[j] : 0.0;
+        zetat[j] = j < k ? st->zetat[j] : 0.0;
+    }
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double qv = B.z[row], qtv = B.zt[row];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (j < k) {
+                const int64_t o = row + (int64_t)j * B.ld;
+                qv -= B.C[o] * zeta[j];
+                qtv -= B.Ct[o] * zetat[j];
+            }
+        }
+        B.q[row] = qv;
+        B.qt[row] = qtv;
+        const double rv = B.r[row], rtv = B.rt[row];
+        acc[0] += B.pt[row] * qv;
+        acc[1] += rtv * qv;
+        acc[2] += qtv * rv;
+        acc[3] += qtv * qv;
+    }
+    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_BPROJ, tot)) {
+        if (threadIdx.x == 0) {
+            const double den = tot[0];
+            if (den == 0.0 || !finite(den)) {
+                st->done = 1;
+                st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
+                st->iters_done = st->iter - 1;
+            } else {
+                const double rho = st->rho;
+                const double a = rho / den;
+                const double rho_new = rho - a * tot[2] - a * tot[1] + a * a * tot[3];
+                st->alpha = a;
+                st->beta = rho_new / rho;
+                for (int j = 0; j < k; ++j) st->zc[j] += a * st->zeta[j];
+                st->iter += 1;
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bepi(BicgBufs B) {
+    const BicgState* st = B.state;
+    const int k = B.k;
+    double zc[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) zc[j] = j < k ? st->zc[j] : 0.0;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        double xv = B.x[row];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) xv -= B.U[row + (int64_t)j * B.ld] * zc[j];
+        B.xout[row] = xv;
+    }
+}
+
+__global__ void k_bicg_reset(BicgState* st) { st->stored = 0; }
+
+// compile-time recycle-dimension buckets
+template <template <int> class F, typename... Args>
+void dispatch_k(int k, Args&&... args) {
+    if (k <= 0) F<0>::run(args...);
+    else if (k <= 8) F<8>::run(args...);
+    else if (k <= 16) F<16>::run(args...);
+    else if (k <= 24) F<24>::run(args...);
+    else if (k <= 32) F<32>::run(args...);
+    else if (k <= 48) F<48>::run(args...);
+    else F<64>::run(args...);
+}
+
+#define RBS_LAUNCHER(NAME, KERNEL, BUFS)                                                     \
+    template <int K>                                                                         \
+    struct NAME {                                                                            \
+        template <typename... A>                                                             \
+        static void run(hipStream_t st, int grid, const BUFS& B, A... a) {                   \
+            hipLaunchKernelGGL(KERNEL<K>, dim3(grid), dim3(BLOCK), 0, st, B, a...);          \
+        }                                                                                    \
+    };
+
+RBS_LAUNCHER(L_pro1, k_pro1, SolveBufs)
+RBS_LAUNCHER(L_pro2, k_pro2, SolveBufs)
+RBS_LAUNCHER(L_update, k_update, SolveBufs)
+RBS_LAUNCHER(L_spmv1, k_spmv1, SolveBufs)
+RBS_LAUNCHER(L_spmv2, k_spmv2, SolveBufs)
+RBS_LAUNCHER(L_epi, k_epi, SolveBufs)
+RBS_LAUNCHER(L_bpro1, k_bpro1, BicgBufs)
+RBS_LAUNCHER(L_bpro2, k_bpro2, BicgBufs)
+RBS_LAUNCHER(L_bspmv, k_bspmv, BicgBufs)
+RBS_LAUNCHER(L_bspmvt, k_bspmvt, BicgBufs)
+RBS_LAUNCHER(L_bproj, k_bproj, BicgBufs)
+RBS_LAUNCHER(L_bepi, k_bepi, BicgBufs)
+
+}  // namespace
+
+int stream_grid(int64_t n) {
+    const int64_t nsl = (n + WAVE - 1) / WAVE;
+    int64_t g = (nsl + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);   // >= one slice per wave
+    if (g > MAX_GRID) g = MAX_GRID;
+    if (g >= 8) g -= g % 8;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+void launch_sell_widths(hipStream_t st, int64_t n, const int32_t* rowptr, int32_t* widths) {
+    const int64_t nsl = (n + WAVE - 1) / WAVE;
+    const int64_t g = (nsl * WAVE + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_sell_widths, dim3((unsigned)g), dim3(BLOCK), 0, st, n, rowptr, widths);
+}
+
+void launch_sell_scan(hipStream_t st, int64_t nslices, const int32_t* widths, int32_t* slice_ptr) {
+    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, st, nslices, widths, slice_ptr);
+}
+
+void launch_sell_fill(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colidx,
+                      const double* val, Sell A) {
+    const int64_t g = (A.nslices * WAVE + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)g), dim3(BLOCK), 0, st, n, rowptr, colidx, val, A);
+}
+
+void launch_fill(hipStream_t st, double* y, int64_t len, double v) {
+    if (len <= 0) return;
+    int64_t g = (len + BLOCK - 1) / BLOCK;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(BLOCK), 0, st, y, len, v);
+}
+
+void launch_copy(hipStream_t st, double* y, const double* x, int64_t len) {
+    if (len <= 0) return;
+    int64_t g = (len + BLOCK - 1) / BLOCK;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(BLOCK), 0, st, y, x, len);
+}
+
+void launch_spmv(hipStream_t st, const Sell& A, const double* x, double* y) {
+    hipLaunchKernelGGL(k_spmv, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, x, y);
+}
+
+void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
+                 int64_t ldy, int m) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_spmm, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, X, ldx, Y, ldy, m);
+}
+
+void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m, const double* S,
+                    int ko, double* Y, int64_t ldy) {
+    if (ko <= 0) return;
+    const size_t shm = (size_t)(m > 0 ? m : 1) * 8 * sizeof(double);
+    hipLaunchKernelGGL(k_gemm_ts, dim3(stream_grid(n)), dim3(BLOCK), shm, st, n, X, ldx, m, S, ko, Y, ldy);
+}
+
+static void gemmt_shape(int64_t n, int mx, int my, int& tiles_y, int& ntiles, int& nchunks,
+                        int64_t& rows_per_chunk) {
+    const int tiles_x = (mx + GT - 1) / GT;
+    tiles_y = (my + GT - 1) / GT;
+    ntiles = tiles_x * tiles_y;
+    int64_t nc = MAX_GRID / ntiles;
+    if (nc < 1) nc = 1;
+    const int64_t maxc = (n + 255) / 256;   // at least 256 rows per chunk
+    if (nc > maxc) nc = maxc;
+    if (nc < 1) nc = 1;
+    rows_per_chunk = (n + nc - 1) / nc;
+    rows_per_chunk = (rows_per_chunk + GS - 1) / GS * GS;
+    nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
+    if (nchunks < 1) nchunks = 1;
+}
+
+size_t gemmt_partial_doubles(int64_t n, int mx, int my) {
+    // nchunks * ntiles <= max(MAX_GRID, ntiles) for every shape with at most
+    // this many tiles, so one buffer of this size serves all smaller calls too
+    (void)n;
+    const int64_t ntiles = (int64_t)((mx + GT - 1) / GT) * ((my + GT - 1) / GT);
+    return (size_t)(ntiles > MAX_GRID ? ntiles : MAX_GRID) * GT * GT;
+}
+
+void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y1,
+                  int64_t ldy1, int my1, const double* Y2, int64_t ldy2, int my2, double* partial,
+                  double* out) {
+    const int my = my1 + my2;
+    if (mx <= 0 || my <= 0) return;
+    int tiles_y, ntiles, nchunks;
+    int64_t rpc;
+    gemmt_shape(n, mx, my, tiles_y, ntiles, nchunks, rpc);
+    hipLaunchKernelGGL(k_gemmt_tile, dim3(ntiles, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1, ldy1,
+                       my1, Y2, ldy2, my2, tiles_y, rpc, partial);
+    const int64_t total = (int64_t)mx * my;
+    hipLaunchKernelGGL(k_gemmt_reduce, dim3((unsigned)((total + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
+                       mx, my, tiles_y, ntiles, nchunks, partial, out);
+}
+
+void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it) {
+    const int g = stream_grid(B.n);
+    dispatch_k<L_pro1>(B.k, st, g, B, x_nonzero, rtol, max_it);
+    dispatch_k<L_pro2>(B.k, st, g, B, x_nonzero);
+    launch_spmv(st, B.At, B.rt0, B.rh);   // rh = A^T rt_0
+}
+
+void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count) {
+    const int g = stream_grid(B.n);
+    for (int it = 0; it < count; ++it) {
+        dispatch_k<L_update>(B.k, st, g, B);
+        dispatch_k<L_spmv1>(B.k, st, g, B);
+        dispatch_k<L_spmv2>(B.k, st, g, B);
+    }
+}
+
+void launch_solve_epilogue(hipStream_t st, const SolveBufs& B) {
+    dispatch_k<L_epi>(B.k, st, stream_grid(B.n), B);
+}
+
+void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const double* x,
+                          double* partials, unsigned* ticket, double* out_sums) {
+    hipLaunchKernelGGL(k_true_res, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, b, x, partials,
+                       ticket + T_RES, out_sums);
+}
+
+void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap) {
+    const int g = stream_grid(B.n);
+    dispatch_k<L_bpro1>(B.k, st, g, B, 0, rtol, max_it, store_cap);
+    dispatch_k<L_bpro2>(B.k, st, g, B, 0);
+}
+
+void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count) {
+    const int g = stream_grid(B.n);
+    for (int it = 0; it < count; ++it) {
+        hipLaunchKernelGGL(k_bupdate, dim3(g), dim3(BLOCK), 0, st, B);
+        dispatch_k<L_bspmv>(B.k, st, g, B);
+        dispatch_k<L_bspmvt>(B.k, st, g, B);
+        dispatch_k<L_bproj>(B.k, st, g, B);
+    }
+}
+
+void launch_bicg_epilogue(hipStream_t st, const BicgBufs& B) {
+    dispatch_k<L_bepi>(B.k, st, stream_grid(B.n), B);
+}
+
+void launch_bicg_reset_cycle(hipStream_t st, BicgState* state) {
+    hipLaunchKernelGGL(k_bicg_reset, dim3(1), dim3(1), 0, st, state);
+}
+
+}  // namespace rbs

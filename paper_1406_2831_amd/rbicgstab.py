@@ -1,0 +1,242 @@
+"""Thin Python binding of librbicgstab.so (argument marshalling only).
+
+The functions ``rbicgstab_workspace_bytes``, ``rbicgstab_setup``,
+``rbicgstab_solve``, ``recycle_update``, ``rbicgstab_get_blocks`` and
+``rbicgstab_destroy`` mirror the C entry points of include/rbicgstab.h and
+take torch tensors (device memory) plus a torch stream.  ``Context`` bundles
+a handle with the workspace tensor it lives in.  Every computation runs in
+the HIP library: if it is not built, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbicgstab.so")
+
+RBS_OK = 0
+RBS_MAXIT = 1
+RBS_BREAKDOWN_RHO = 2
+RBS_BREAKDOWN_ALPHA = 3
+RBS_BREAKDOWN_OMEGA = 4
+RBS_ERR_ARG = -1
+RBS_ERR_HIP = -2
+RBS_ERR_WORKSPACE = -3
+RBS_ERR_SINGULAR_DC = -4
+RBS_ERR_NONFINITE = -5
+
+RBS_RBICGSTAB = 0
+RBS_BICGSTAB = 1
+RBS_RBICG_GEN = 2
+RBS_TRANSPOSE = 8
+
+RBS_RECYCLE_SET = 0
+RBS_RECYCLE_FROM_LAST_SOLVE = 1
+RBS_RECYCLE_CLEAR = 2
+
+EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "recycle_update",
+           "rbicgstab_get_blocks", "rbicgstab_setup_matvecs", "rbicgstab_destroy",
+           "rbicgstab_last_error")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("total_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("matvecs_A", ctypes.c_int32), ("matvecs_At", ctypes.c_int32),
+                ("k_used", ctypes.c_int32), ("ritz_updates", ctypes.c_int32),
+                ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librbicgstab.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1406_2831_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_size_t)
+    lib.rbicgstab_workspace_bytes.argtypes = [i64, i32, i32, i32]
+    lib.rbicgstab_workspace_bytes.restype = sz
+    lib.rbicgstab_setup.argtypes = [ctypes.POINTER(vp), i64, i64, vp, vp, vp, i64, vp, vp, vp,
+                                    i32, i32, i32, f64, vp, sz, vp]
+    lib.rbicgstab_setup.restype = ctypes.c_int
+    lib.rbicgstab_solve.argtypes = [vp, vp, vp, i32, vp, f64, i32, i32, ctypes.POINTER(Stats)]
+    lib.rbicgstab_solve.restype = ctypes.c_int
+    lib.recycle_update.argtypes = [vp, i32, vp, vp, i32]
+    lib.recycle_update.restype = ctypes.c_int
+    lib.rbicgstab_get_blocks.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
+    lib.rbicgstab_get_blocks.restype = ctypes.c_int
+    lib.rbicgstab_setup_matvecs.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.rbicgstab_setup_matvecs.restype = ctypes.c_int
+    lib.rbicgstab_destroy.argtypes = [vp]
+    lib.rbicgstab_destroy.restype = ctypes.c_int
+    lib.rbicgstab_last_error.argtypes = [vp]
+    lib.rbicgstab_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class RbsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librbicgstab error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(lib, handle, rc: int) -> int:
+    if rc < 0:
+        msg = lib.rbicgstab_last_error(handle)
+        raise RbsError(rc, msg.decode() if msg else "")
+    return rc
+
+
+# ----------------------------------------------------------------- C-named functions
+
+def rbicgstab_workspace_bytes(n: int, max_row_nnz: int, k_max: int, s_max: int) -> int:
+    return int(load_library().rbicgstab_workspace_bytes(n, max_row_nnz, k_max, s_max))
+
+
+def rbicgstab_setup(handle: Optional[ctypes.c_void_p], n: int, A, At, max_row_nnz: int, k_max: int,
+                    s_max: int, workspace: torch.Tensor, secant_max: float = 0.0, stream=None):
+    """A, At: (rowptr int32, colidx int32, val float64) device tensors.  Returns the handle."""
+    lib = load_library()
+    h = handle if handle is not None else ctypes.c_void_p(None)
+    rc = lib.rbicgstab_setup(ctypes.byref(h), n, A[1].numel(), _ptr(A[0]), _ptr(A[1]), _ptr(A[2]),
+                             At[1].numel(), _ptr(At[0]), _ptr(At[1]), _ptr(At[2]), max_row_nnz,
+                             k_max, s_max, secant_max, _ptr(workspace), workspace.numel(),
+                             _stream(stream))
+    _check(lib, h, rc)
+    return h
+
+
+def rbicgstab_solve(handle, b: torch.Tensor, x: torch.Tensor, x_nonzero: bool = False,
+                    shadow: Optional[torch.Tensor] = None, rtol: float = 1e-8, max_it: int = 10000,
+                    flags: int = RBS_RBICGSTAB) -> Stats:
+    lib = load_library()
+    st = Stats()
+    rc = lib.rbicgstab_solve(handle, _ptr(b), _ptr(x), int(bool(x_nonzero)), _ptr(shadow), rtol,
+                             max_it, flags, ctypes.byref(st))
+    _check(lib, handle, rc)
+    return st
+
+
+def recycle_update(handle, mode: int, U: Optional[torch.Tensor] = None,
+                   Ut: Optional[torch.Tensor] = None) -> int:
+    """U, Ut: (k, n) row-major torch tensors == column-major n x k blocks with ld = n."""
+    lib = load_library()
+    k = 0 if U is None else U.shape[0]
+    return _check(lib, handle, lib.recycle_update(handle, mode, _ptr(U), _ptr(Ut), k))
+
+
+def rbicgstab_get_blocks(handle, n: int, k_max: int, device="cuda"):
+    """Returns dict of (k, n) tensors U, Ut, C, Ct, Chat, Ccheck (column j = row j)."""
+    lib = load_library()
+    out = {name: torch.zeros((k_max, n), dtype=torch.float64, device=device)
+           for name in ("U", "Ut", "C", "Ct", "Chat", "Ccheck")}
+    kk = ctypes.c_int32(0)
+    _check(lib, handle, lib.rbicgstab_get_blocks(handle, *[_ptr(out[k]) for k in
+                                                            ("U", "Ut", "C", "Ct", "Chat", "Ccheck")],
+                                                 ctypes.byref(kk)))
+    return {name: t[: kk.value].clone() for name, t in out.items()}, kk.value
+
+
+def rbicgstab_setup_matvecs(handle):
+    lib = load_library()
+    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib, handle, lib.rbicgstab_setup_matvecs(handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def rbicgstab_destroy(handle) -> None:
+    if handle is not None and handle.value:
+        load_library().rbicgstab_destroy(handle)
+
+
+# ----------------------------------------------------------------- convenience wrapper
+
+def device_csr(csr, device="cuda"):
+    """Upload a CSR (rowptr, colidx, val numpy arrays, or an object with those fields)."""
+    rp, ci, va = (csr.rowptr, csr.colidx, csr.val) if hasattr(csr, "rowptr") else csr
+    return (torch.as_tensor(rp, dtype=torch.int32, device=device),
+            torch.as_tensor(ci, dtype=torch.int32, device=device),
+            torch.as_tensor(va, dtype=torch.float64, device=device))
+
+
+@dataclass
+class Context:
+    """A recycling-BiCGSTAB context: workspace tensor + library handle."""
+    n: int
+    max_row_nnz: int
+    k_max: int
+    s_max: int
+    device: str = "cuda"
+    secant_max: float = 0.0
+
+    def __post_init__(self):
+        self.ws_bytes = rbicgstab_workspace_bytes(self.n, self.max_row_nnz, self.k_max, self.s_max)
+        if self.ws_bytes == 0:
+            raise RbsError(RBS_ERR_ARG, "invalid context sizes")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.handle = None
+
+    def setup(self, A, At, stream=None):
+        """Bind A(i) (and its transpose); device tensors or host CSR objects."""
+        if not isinstance(A[0] if isinstance(A, tuple) else None, torch.Tensor):
+            A = device_csr(A, self.device)
+            At = device_csr(At, self.device)
+        self.handle = rbicgstab_setup(self.handle, self.n, A, At, self.max_row_nnz, self.k_max,
+                                      self.s_max, self.workspace, self.secant_max, stream)
+        return self
+
+    def solve(self, b, x=None, x_nonzero=False, shadow=None, rtol=1e-8, max_it=10000,
+              mode: str = "rbicgstab"):
+        flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB,
+                 "rbicg": RBS_RBICG_GEN}[mode]
+        if x is None:
+            x = torch.zeros_like(b)
+        st = rbicgstab_solve(self.handle, b, x, x_nonzero, shadow, rtol, max_it, flags)
+        return x, st
+
+    def recycle(self, mode: str = "from_last_solve", U=None, Ut=None):
+        m = {"set": RBS_RECYCLE_SET, "from_last_solve": RBS_RECYCLE_FROM_LAST_SOLVE,
+             "clear": RBS_RECYCLE_CLEAR}[mode]
+        return recycle_update(self.handle, m, U, Ut)
+
+    def blocks(self):
+        return rbicgstab_get_blocks(self.handle, self.n, self.k_max, self.device)
+
+    def setup_matvecs(self):
+        return rbicgstab_setup_matvecs(self.handle)
+
+    def close(self):
+        rbicgstab_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

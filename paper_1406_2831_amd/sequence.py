@@ -1,0 +1,102 @@
+"""Sequence driver on the GPU library (Section 6.2 strategy).
+
+For each matrix A(i) of a shifted sequence: bind it (``rbicgstab_setup``,
+which recomputes C = A U, Ct = A^T Ut and the projection blocks for the new
+matrix), solve its first right-hand side with RBiCG (``RBS_RBICG_GEN``) and
+install the space built from its Lanczos vectors (``recycle_update``), then
+solve the remaining right-hand sides with RBiCGSTAB.  ``mode="bicgstab"``
+solves every system with plain BiCGSTAB on the same kernels.
+
+All arithmetic runs in the HIP library; this module only orders the calls.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from .rbicgstab import Context, device_csr
+
+
+@dataclass
+class GpuSequenceResult:
+    x: List[torch.Tensor] = field(default_factory=list)
+    status: List[int] = field(default_factory=list)
+    iters: List[int] = field(default_factory=list)
+    matvecs: List[int] = field(default_factory=list)
+    solver: List[str] = field(default_factory=list)
+    rel_res_true: List[float] = field(default_factory=list)
+    k_used: List[int] = field(default_factory=list)
+    setup_matvecs: int = 0
+
+    @property
+    def total_matvecs(self) -> int:
+        return int(sum(self.matvecs)) + int(self.setup_matvecs)
+
+
+def max_row_nnz(*mats) -> int:
+    return int(max(np.diff(m.rowptr).max() for m in mats))
+
+
+class GpuSequence:
+    """Device-resident inputs of a ``workloads.ShiftedSequence`` plus a solver context."""
+
+    def __init__(self, seq, k: Optional[int] = None, s_max: int = 512, device: str = "cuda",
+                 secant_max: float = 0.0, keep_x: bool = True):
+        self.seq = seq
+        self.k = seq.k if k is None else k
+        self.device = device
+        self.keep_x = keep_x
+        mats = [seq.matrix(i) for i in range(len(seq.sigmas))]
+        self.mrow = max_row_nnz(*[m for pair in mats for m in pair])
+        self.mats = [(device_csr(A, device), device_csr(At, device)) for A, At in mats]
+        self.rhs = [torch.as_tensor(b, device=device) for b in seq.rhs]
+        self.shadows = [torch.as_tensor(s, device=device) for s in seq.shadows]
+        self.ctx = Context(seq.n, self.mrow, max(self.k, 1), s_max, device, secant_max)
+        self.xbuf = [torch.zeros(seq.n, dtype=torch.float64, device=device)
+                     for _ in range(seq.num_systems)]
+
+    def run(self, mode: str = "rbicgstab", rtol: float = 1e-8, max_it: int = 20000,
+            systems: Optional[int] = None) -> GpuSequenceResult:
+        seq, ctx = self.seq, self.ctx
+        out = GpuSequenceResult()
+        last = seq.num_systems if systems is None else min(systems, seq.num_systems)
+        cur = -1
+        if ctx.handle is not None:
+            ctx.recycle("clear")
+        for idx in range(last):
+            si, j = seq.system(idx)
+            if si != cur:
+                A, At = self.mats[si]
+                ctx.setup(A, At)
+                cur = si
+                ma, mat = ctx.setup_matvecs()
+                out.setup_matvecs += ma + mat
+            b, sh, x = self.rhs[idx], self.shadows[idx], self.xbuf[idx]
+            x.zero_()
+            if mode == "bicgstab":
+                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="bicgstab")
+                solver = "bicgstab"
+            elif j == 0 and self.k > 0:
+                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicg")
+                ctx.recycle("from_last_solve")
+                ma, mat = ctx.setup_matvecs()
+                out.setup_matvecs += ma + mat
+                solver = "rbicg"
+            else:
+                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicgstab")
+                solver = "rbicgstab"
+            if self.keep_x:
+                out.x.append(x)
+            out.status.append(st.status)
+            out.iters.append(st.total_iters)
+            out.matvecs.append(st.matvecs_A + st.matvecs_At)
+            out.solver.append(solver)
+            out.rel_res_true.append(st.rel_res_true)
+            out.k_used.append(st.k_used)
+        return out
+
+    def close(self):
+        self.ctx.close()

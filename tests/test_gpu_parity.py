@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU FP64 oracle.
+
+Tolerances (floating point, derived from the arithmetic):
+* every solve must reach its own true relative residual (rtol);
+* solution error versus the oracle's solution at rtol = 1e-12 is bounded
+  by kappa * rtol; parity runs use rtol = 1e-10, where kappa * rtol <= 1e-6
+  for every grid used here (kappa(-Laplace_h) ~ 4 / (pi h)^2), so the bar
+  is a relative error <= 1e-6;
+* iteration counts agree within a few percent (the fused three-pass
+  iteration reorders sums, so histories drift by rounding only).
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as o
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def rb():
+    from paper_1406_2831_amd import rbicgstab as rbm
+    rbm.load_library()
+    return rbm
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _ctx(rb, A, At, k_max=8, s_max=64):
+    from paper_1406_2831_amd.sequence import max_row_nnz
+    ctx = rb.Context(A.n, max_row_nnz(A, At), k_max, s_max)
+    ctx.setup(A, At)
+    return ctx
+
+
+def _solve(ctx, torch_mod, b, shadow=None, mode="rbicgstab", rtol=1e-10, max_it=5000, x0=None):
+    bt = torch_mod.as_tensor(b, device="cuda")
+    sh = None if shadow is None else torch_mod.as_tensor(shadow, device="cuda")
+    x = torch_mod.zeros_like(bt) if x0 is None else torch_mod.as_tensor(x0, device="cuda").clone()
+    _, st = ctx.solve(bt, x, x_nonzero=x0 is not None, shadow=sh, rtol=rtol, max_it=max_it, mode=mode)
+    return x.cpu().numpy(), st
+
+
+@pytest.fixture(scope="module")
+def c0():
+    seq = w.seq_2d()
+    A, At = seq.matrix(1)
+    return seq, A, At
+
+
+def test_bicgstab_parity_2d(rb, torch_mod, c0):
+    seq, A, At = c0
+    _say("bicgstab 2d n=1024")
+    ctx = _ctx(rb, A, At)
+    b, sh = seq.rhs[1], seq.shadows[1]
+    x, st = _solve(ctx, torch_mod, b, sh, mode="bicgstab")
+    xo, io = o.bicgstab(A.to_scipy(), b, shadow=sh, rtol=1e-10)
+    xref = np.linalg.solve(A.to_scipy().toarray(), b)
+    assert st.status == 0 and st.rel_res_true <= 1e-10
+    assert np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1e-10
+    assert _rel(x, xref) <= 1e-6 and _rel(x, xo) <= 1e-6
+    assert abs(st.iters - io.iters) <= max(2, 0.05 * io.iters)
+    ctx.close()
+
+
+def test_rbicgstab_parity_exact_space(rb, torch_mod, c0):
+    """Installed exact eigenvector space (SET): blocks and solution match the oracle."""
+    seq, A, At = c0
+    _say("rbicgstab 2d SET exact eigvecs k=8")
+    Ad = A.to_scipy().toarray()
+    lam, vl, vr = sla.eig(Ad, left=True, right=True)
+    order = np.argsort(np.abs(lam))
+    U, Ut = vr[:, order[:8]].real.copy(), vl[:, order[:8]].real.copy()
+    ctx = _ctx(rb, A, At, k_max=8)
+    ctx.secant_max = 0.0
+    ctx.recycle("set", torch_mod.as_tensor(U.T.copy(), device="cuda"),
+                torch_mod.as_tensor(Ut.T.copy(), device="cuda"))
+    blocks, k = ctx.blocks()
+    bl = o.make_blocks(A.to_scipy(), At.to_scipy(), U, Ut)
+    assert k == bl.k == 8
+    C, Chat = blocks["C"].cpu().numpy().T, blocks["Chat"].cpu().numpy().T
+    Ct, Ccheck = blocks["Ct"].cpu().numpy().T, blocks["Ccheck"].cpu().numpy().T
+    assert np.abs(Chat.T @ C - np.eye(k)).max() < 1e-10
+    assert np.abs(Ccheck.T @ Ct - np.eye(k)).max() < 1e-10
+    # same projector as the oracle's (bases may differ): C Chat^T
+    P_gpu, P_or = C @ Chat.T, bl.C @ bl.Chat.T
+    assert np.abs(P_gpu - P_or).max() <= 1e-8 * np.abs(P_or).max()
+    b, sh = seq.rhs[1], seq.shadows[1]
+    x, st = _solve(ctx, torch_mod, b, sh)
+    xo, io = o.rbicgstab(A.to_scipy(), bl, b, shadow_m1=sh, rtol=1e-10)
+    xref = np.linalg.solve(Ad, b)
+    assert st.status == 0 and st.rel_res_true <= 1e-10 and st.k_used == 8
+    assert _rel(x, xref) <= 1e-6 and _rel(x, xo) <= 1e-6
+    assert abs(st.iters - io.iters) <= max(2, 0.05 * io.iters)
+    ctx.close()
+
+
+def test_rbicg_generation_and_sequence_2d(rb, torch_mod):
+    """The Section 6.2 pipeline on the 2D sequence: every system converges, x matches."""
+    from paper_1406_2831_amd.sequence import GpuSequence
+    seq = w.seq_2d(nshift=4, nrhs=2)
+    _say("sequence 2d 4 shifts x 2 rhs")
+    gs = GpuSequence(seq, s_max=256)
+    res = gs.run(mode="rbicgstab", rtol=1e-10)
+    ores = o.run_sequence(seq, mode="rbicgstab", rtol=1e-10)
+    assert all(s == 0 for s in res.status), res.status
+    assert max(res.rel_res_true) <= 1e-10
+    assert res.solver == ores.solver
+    for idx, x in enumerate(res.x):
+        A, _ = seq.matrix(seq.system(idx)[0])
+        xref = np.linalg.solve(A.to_scipy().toarray(), seq.rhs[idx])
+        assert _rel(x.cpu().numpy(), xref) <= 1e-6
+        assert _rel(x.cpu().numpy(), ores.x[idx]) <= 1e-6
+    # a generated space was installed after the first RBiCG solve
+    assert res.k_used[1] > 0
+    gs.close()
+
+
+def test_ragged_3d_rbicgstab_and_bicgstab(rb, torch_mod):
+    """Several tiles and a ragged last slice (n = 23^3 = 12167)."""
+    from paper_1406_2831_amd.sequence import GpuSequence
+    seq = w.seq_3d(N=23, nshift=2, nrhs=3, k=12)
+    _say("sequence 3d N=23 k=12")
+    gs = GpuSequence(seq, s_max=512)
+    for mode in ("bicgstab", "rbicgstab"):
+        res = gs.run(mode=mode, rtol=1e-10)
+        ores = o.run_sequence(seq, mode=mode, rtol=1e-10)
+        assert all(s == 0 for s in res.status), (mode, res.status)
+        for idx, x in enumerate(res.x):
+            assert _rel(x.cpu().numpy(), ores.x[idx]) <= 1e-6, (mode, idx)
+        for it_g, it_o in zip(res.iters, ores.iters):
+            assert abs(it_g - it_o) <= max(3, 0.1 * it_o), (mode, res.iters, ores.iters)
+    gs.close()
+
+
+def test_determinism(rb, torch_mod, c0):
+    seq, A, At = c0
+    _say("determinism")
+    ctx = _ctx(rb, A, At)
+    x1, s1 = _solve(ctx, torch_mod, seq.rhs[1], seq.shadows[1], mode="bicgstab")
+    x2, s2 = _solve(ctx, torch_mod, seq.rhs[1], seq.shadows[1], mode="bicgstab")
+    assert np.array_equal(x1, x2) and s1.iters == s2.iters
+    ctx.close()
+
+
+def test_edge_cases(rb, torch_mod, c0):
+    seq, A, At = c0
+    n = A.n
+    _say("edge cases")
+    ctx = _ctx(rb, A, At)
+    b = seq.rhs[1]
+    # zero right-hand side: solved by x = 0 with no iteration
+    x, st = _solve(ctx, torch_mod, np.zeros(n))
+    assert st.status == 0 and st.iters == 0 and np.all(x == 0)
+    # max_it = 1
+    x, st = _solve(ctx, torch_mod, b, max_it=1, mode="bicgstab")
+    assert st.status == rb.RBS_MAXIT and st.iters == 1
+    # (r_0, rt_0) = 0 exactly: disjoint supports
+    bz = b.copy()
+    bz[n // 2:] = 0.0
+    sh = seq.shadows[1].copy()
+    sh[: n // 2] = 0.0
+    x, st = _solve(ctx, torch_mod, bz, sh, mode="bicgstab")
+    assert st.status == rb.RBS_BREAKDOWN_RHO
+    # non-finite input
+    bad = b.copy()
+    bad[7] = np.nan
+    x, st = _solve(ctx, torch_mod, bad, mode="bicgstab")
+    assert st.status == rb.RBS_ERR_NONFINITE or st.status < 0 or st.status == -5
+    # nonzero initial guess
+    xg = np.linalg.solve(A.to_scipy().toarray(), b) + 1e-3 * seq.shadows[2]
+    x, st = _solve(ctx, torch_mod, b, seq.shadows[1], x0=xg, mode="bicgstab")
+    assert st.status == 0 and st.rel_res_true <= 1e-10
+    ctx.close()
+
+
+def test_tiny_systems(rb, torch_mod):
+    """n below one wavefront, and n = 1."""
+    for N in (1, 5):
+        _say(f"tiny 2d N={N}")
+        K = w.convdiff((N, N), w.VEL2, w.PECLET)
+        A = w.shifted(K, np.ones(K.n), 0.5)
+        At = A.transpose()
+        ctx = _ctx(rb, A, At, k_max=1, s_max=16)
+        b = np.arange(1.0, K.n + 1.0)
+        x, st = _solve(ctx, torch_mod, b, mode="bicgstab")
+        xref = np.linalg.solve(A.to_scipy().toarray(), b)
+        assert st.status == 0 and _rel(x, xref) <= 1e-8
+        x, st = _solve(ctx, torch_mod, b, mode="rbicg")
+        assert st.status == 0 and _rel(x, xref) <= 1e-8
+        ctx.close()
+
+
+def test_full_size_3d_solve(rb, torch_mod):
+    """n = 64^3: GPU RBiCGSTAB with a GPU-generated space vs the oracle's tight solve."""
+    from paper_1406_2831_amd.sequence import GpuSequence
+    seq = w.seq_3d(N=64, nshift=1, nrhs=2)
+    _say("full size 3d 64^3 rbicg + rbicgstab")
+    gs = GpuSequence(seq, s_max=512)
+    res = gs.run(mode="rbicgstab", rtol=1e-10)
+    A, _ = seq.matrix(0)
+    As = A.to_scipy()
+    for idx in range(2):
+        x = res.x[idx].cpu().numpy()
+        b = seq.rhs[idx]
+        assert res.status[idx] == 0
+        assert np.linalg.norm(b - As @ x) / np.linalg.norm(b) <= 1e-10
+        xo, io = o.bicgstab(As, b, shadow=seq.shadows[idx], rtol=1e-12)
+        assert _rel(x, xo) <= 1e-6
+    assert res.solver == ["rbicg", "rbicgstab"] and res.k_used[1] > 0
+    gs.close()
