@@ -1,0 +1,147 @@
+#!/usr/bin/env python
+"""Benchmark: systems solved per second on a shifted convection-diffusion sequence.
+
+Workload: 3D 7-point upwind convection-diffusion, 64^3 grid (n = 262,144),
+A(i) = K + sigma_i M with 5 log-spaced shifts in [1e-2, 1e1] times 4 N(0,1)
+right-hand sides (20 systems), recycle dimension k = 20, true relative
+residual 1e-8.  One step = the whole sequence: per shift the matrix setup
+(sliced copy, C = A U, Ct = A^T Ut, bi-orthogonalisation), RBiCG on the first
+right-hand side with the recycle-space update from its Lanczos vectors, and
+RBiCGSTAB on the other three.  The same sequence is also timed with plain
+BiCGSTAB on the same kernels (the baseline the metric compares against).
+
+Prints one JSON line.  Inputs are generated and uploaded before timing.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(seq, rtol, systems):
+    """The oracle (CPU FP64) on a bounded sample of the same sequence."""
+    import oracle as o
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(p.get("num_threads", 1)) for p in info)
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    res = o.run_sequence(seq, mode="rbicgstab", rtol=rtol, systems=systems)
+    dt = time.perf_counter() - t0
+    return {"value": systems / dt, "unit": "systems/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {systems} systems of the sequence (shift 1: RBiCG + "
+                      f"{systems - 1} RBiCGSTAB), {dt:.1f} s, iterations {res.iters}",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=64, help="grid points per axis")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--k", type=int, default=20)
+    ap.add_argument("--cpu-systems", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-reps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
+              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as w
+    from paper_1406_2831_amd.sequence import GpuSequence
+
+    seq = w.seq_3d(N=args.grid, k=args.k)
+    gs = GpuSequence(seq, s_max=512)
+    nsys = seq.num_systems
+
+    def run(mode):
+        return gs.run(mode=mode, rtol=args.rtol)
+
+    for _ in range(args.warmup):
+        run("rbicgstab")
+        run("bicgstab")
+    timed = {}
+    results = {}
+    for mode in ("rbicgstab", "bicgstab"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            results[mode] = run(mode)
+        torch.cuda.synchronize()
+        timed[mode] = (time.perf_counter() - t0) / args.steps
+    for mode, res in results.items():
+        bad = [s for s in res.status if s != 0]
+        if bad or max(res.rel_res_true) > args.rtol:
+            print(f"{mode}: not every system converged: status {res.status}, "
+                  f"true residuals {res.rel_res_true}", file=sys.stderr)
+            sys.exit(1)
+
+    # live per-kernel timing of the dominant pass (first SpMV + projection)
+    rres = results["rbicgstab"]
+    k_last = int(rres.k_used[-1])
+    ms_spmv1, bytes_spmv1 = gs.ctx.time_pass(1, k_last, args.time_reps)
+    ms_upd, bytes_upd = gs.ctx.time_pass(0, k_last, args.time_reps)
+    ms_spmv2, bytes_spmv2 = gs.ctx.time_pass(2, k_last, args.time_reps)
+    ms_spmv, bytes_spmv = gs.ctx.time_pass(3, 0, args.time_reps)
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
+    achieved = gbs(bytes_spmv1, ms_spmv1)
+
+    out = {
+        "metric": "systems solved/s + SpMV HBM GB/s at rel.res 1e-8, RBiCGSTAB vs BiCGSTAB",
+        "value": nsys / timed["rbicgstab"],
+        "unit": "systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": timed["rbicgstab"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3d 7-point convection-diffusion {args.grid}^3 (n={seq.n}), "
+                               f"5 shifts x 4 rhs = {nsys} systems, k={args.k}, rtol={args.rtol}",
+                   "n": seq.n, "nnz": int(seq.K.nnz), "systems": nsys, "k": args.k},
+        "bicgstab": {"systems_per_s": nsys / timed["bicgstab"],
+                     "ms_per_step": timed["bicgstab"] * 1e3,
+                     "iters": results["bicgstab"].iters,
+                     "matvecs": results["bicgstab"].total_matvecs},
+        "rbicgstab": {"iters": rres.iters, "solver": rres.solver, "k_used": rres.k_used,
+                      "matvecs": rres.total_matvecs,
+                      "max_rel_res_true": max(rres.rel_res_true)},
+        "rbicgstab_over_bicgstab_time": timed["rbicgstab"] / timed["bicgstab"],
+        "spmv_gbs": gbs(bytes_spmv, ms_spmv),
+        "passes": {"update": {"us": ms_upd * 1e3, "gbs": gbs(bytes_upd, ms_upd)},
+                   "spmv1_project": {"us": ms_spmv1 * 1e3, "gbs": achieved},
+                   "spmv2_project": {"us": ms_spmv2 * 1e3, "gbs": gbs(bytes_spmv2, ms_spmv2)},
+                   "spmv": {"us": ms_spmv * 1e3, "gbs": gbs(bytes_spmv, ms_spmv)},
+                   "k": k_last},
+        "roofline": {"bound": "hbm", "kernel": f"k_spmv1<bucket of k={k_last}>",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_spmv1, "us_per_launch": ms_spmv1 * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(seq, args.rtol, args.cpu_systems)
+    gs.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

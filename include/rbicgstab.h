@@ -153,6 +153,20 @@ int recycle_update(rbs_ctx* ctx, int32_t mode, const double* U, const double* Ut
 int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double* Ct,
                          double* Chat, double* Ccheck, int32_t* k_used /* host */);
 
+/*
+ * Time one of the fused per-iteration passes of Algorithm 2 on the bound
+ * matrix with recycle dimension k (0 <= k <= installed k): which = 0 the
+ * update pass, 1 the first SpMV + projection pass, 2 the second SpMV +
+ * projection pass, 3 a plain SpMV.  The pass is launched `reps` times
+ * back to back on the context's stream between two HIP events; *avg_ms
+ * receives the mean duration per launch and *bytes the algorithmic bytes
+ * one launch moves (CSR: 12 bytes per stored entry + 4 per row pointer;
+ * 8 bytes per vector / block entry read or written once).  The context's
+ * solve vectors are used as operands and left in an unspecified state.
+ */
+int rbicgstab_time_pass(rbs_ctx* ctx, int32_t which, int32_t k, int32_t reps, double* avg_ms,
+                        double* bytes);
+
 /* Matrix-vector products issued by the last setup / recycle_update (host out). */
 int rbicgstab_setup_matvecs(const rbs_ctx* ctx, int32_t* matvecs_A, int32_t* matvecs_At);
 

@@ -13,8 +13,9 @@ Contents (each function cites the passage of the paper it follows):
 * ``krylov.rbicg``      -- Algorithm 1 (RBiCG), Section 3, with the cycle store
                            of Lanczos vectors described in Section 6.2.
 * ``recycle.make_blocks``     -- Algorithm 2 step 1 / eq. (CcheckChat).
-* ``recycle.two_sided_ritz``  -- recycle-space selection (our reading; the
-                                 paper defers it to its reference on RBiCG).
+* ``recycle.recycle_space``   -- recycle-space selection (our reading; the
+                                 paper defers it to its reference on RBiCG):
+                                 harmonic right / two-sided left Ritz vectors.
 * ``sequence.run_sequence``   -- the Section 6.2 driver (RBiCG on a matrix
                                  change, RBiCGSTAB for the other right-hand sides).
 
@@ -23,10 +24,12 @@ BiCGSTAB, invariants of Theorems 1-2, closed forms); see tests/test_oracle_*.py.
 """
 from .krylov import (OK, MAXIT, BREAKDOWN_RHO, BREAKDOWN_ALPHA, BREAKDOWN_OMEGA,
                      NONFINITE, SolveInfo, bicgstab, rbicgstab, rbicg)
-from .recycle import Blocks, make_blocks, empty_blocks, two_sided_ritz
+from .recycle import (Blocks, make_blocks, empty_blocks, two_sided_ritz, harmonic_ritz,
+                      recycle_space)
 from .sequence import run_sequence, SequenceResult
 
 __all__ = ["OK", "MAXIT", "BREAKDOWN_RHO", "BREAKDOWN_ALPHA", "BREAKDOWN_OMEGA",
            "NONFINITE", "SolveInfo", "bicgstab", "rbicgstab", "rbicg", "Blocks",
-           "make_blocks", "empty_blocks", "two_sided_ritz", "run_sequence",
+           "make_blocks", "empty_blocks", "two_sided_ritz", "harmonic_ritz", "recycle_space",
+           "run_sequence",
            "SequenceResult"]

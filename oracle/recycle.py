@@ -17,9 +17,14 @@ Readings where the paper defers to other work:
   projected operator ``(I - C Chat^T) A`` ill-conditioned;
 * ``D_c^{-1}``: computed as a full k-by-k LU solve with ``D_c = Ct^T C``
   (identical in exact arithmetic, exact ``Chat^T C = I`` in floating point);
-* the selection of U, Ut (deferred to the RBiCG reference): a two-sided
-  (Petrov-Galerkin) Rayleigh-Ritz projection keeping the k Ritz values of
-  smallest magnitude, see ``two_sided_ritz``.
+* the selection of U, Ut (deferred to the RBiCG reference), see
+  ``recycle_space``: right vectors are harmonic Ritz vectors of A on W (the
+  k smallest-magnitude harmonic Ritz values), left vectors are the left
+  vectors of the two-sided (Petrov-Galerkin) Rayleigh-Ritz projection on
+  (Wt, W) for its k smallest-magnitude Ritz values.  On the convection-
+  diffusion operators two-sided right vectors carry large high-frequency
+  components (relative residuals ~1e2), which makes the C/Ct pairs nearly
+  orthogonal; harmonic right vectors do not.
 """
 from __future__ import annotations
 
@@ -120,6 +125,46 @@ def ritz_select(theta: np.ndarray, k: int, pair_tol: float = 1e-10):
             picks.append((i, False))
             slots += 1
     return picks
+
+
+def _real_basis(Y: np.ndarray, theta: np.ndarray, picks):
+    cols, vals = [], []
+    for i, cplx in picks:
+        if cplx:
+            cols += [Y[:, i].real, Y[:, i].imag]
+            vals += [theta[i], np.conj(theta[i])]
+        else:
+            cols.append(Y[:, i].real)
+            vals.append(theta[i])
+    return cols, vals
+
+
+def harmonic_ritz(A, W: np.ndarray, k: int):
+    """Harmonic Ritz vectors of A on range(W) for the k smallest-magnitude harmonic Ritz values.
+
+    With Q an orthonormal basis of W: solve (AQ)^T (AQ) y = theta (AQ)^T Q y,
+    i.e. the residual A Q y - theta Q y is orthogonal to A Q.  Returns
+    ``(U, theta)`` with unit-norm columns.
+    """
+    Q = _orth(W)
+    AQ = A @ Q
+    theta, Y = sla.eig(AQ.T @ AQ, AQ.T @ Q)
+    cols, vals = _real_basis(Y, theta, ritz_select(theta, k))
+    if not cols:
+        return np.zeros((W.shape[0], 0)), np.zeros(0, dtype=complex)
+    U = Q @ np.array(cols).T
+    return U / np.linalg.norm(U, axis=0), np.array(vals)
+
+
+def recycle_space(A, W: np.ndarray, Wt: np.ndarray, k: int):
+    """The recycle-space update: harmonic right vectors, two-sided left vectors.
+
+    Returns ``(U, Ut, number of products with A)``.
+    """
+    U, _ = harmonic_ritz(A, W, k)
+    _, Ut, _, m = two_sided_ritz(A, W, Wt, k)
+    kk = min(U.shape[1], Ut.shape[1])   # conjugate pairs can make the two counts differ by one
+    return U[:, :kk], Ut[:, :kk], m
 
 
 def two_sided_ritz(A, W: np.ndarray, Wt: np.ndarray, k: int):

@@ -8,7 +8,8 @@ is solved with RBiCGSTAB (Algorithm 2) using that space.  The first system
 starts with an empty space.  ``mode="bicgstab"`` runs the non-recycling
 baseline on every system.
 
-Readings: the projection used inside a solve is fixed; the improved space is
+The space is updated by ``recycle.recycle_space`` (harmonic right, two-sided
+left Ritz vectors).  Readings: the projection used inside a solve is fixed; the improved space is
 installed (``make_blocks``) after the RBiCG solve ends, and only if that
 solve converged.  Cycle updates combine the space being built with the
 cycle's Lanczos vectors, ``W = [U_new, V_s]``, ``Wt = [Ut_new, Vt_s]``,
@@ -25,7 +26,7 @@ from typing import List
 import numpy as np
 
 from .krylov import OK, bicgstab, rbicg, rbicgstab
-from .recycle import make_blocks, empty_blocks, two_sided_ritz
+from .recycle import make_blocks, empty_blocks, recycle_space
 
 
 @dataclass
@@ -83,7 +84,7 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
             def on_cycle(V, Vt):
                 W = np.hstack([state["U"], V])
                 Wt = np.hstack([state["Ut"], Vt])
-                Un, Utn, _, m = two_sided_ritz(A, W, Wt, k)
+                Un, Utn, m = recycle_space(A, W, Wt, k)
                 state["U"], state["Ut"] = Un, Utn
                 state["mv"] += m
 

@@ -68,6 +68,7 @@ struct rbs_ctx {
     int gen_k = 0;        // dimension of the space held in W / Wt
     bool gen_valid = false;
     int setup_mv_A = 0, setup_mv_At = 0;
+    int64_t nnz = 0;
     PinnedStatus* hp = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::string err;
@@ -129,7 +130,7 @@ size_t carve(rbs_ctx* c, char* base) {
     c->Wt = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
     c->AW = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
     const int64_t mmax = c->k_max + std::max(c->s_max, 0);
-    c->dsmall_doubles = (size_t)(4 * mmax * mmax + 4 * mmax * c->k_max + 64);
+    c->dsmall_doubles = (size_t)(6 * mmax * mmax + 4 * mmax * c->k_max + 64);
     c->dsmall = cv.take<double>(c->dsmall_doubles);
     c->gpart_doubles = std::max(rbs::gemmt_partial_doubles(c->n, (int)mmax, (int)(2 * mmax)),
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
@@ -451,27 +452,32 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
 }
 
 // Cycle-end recycle-space update from the gen_k current columns and ns new
-// Lanczos vectors held in W / Wt / AW: two-sided Rayleigh-Ritz on the host,
-// basis products on the device.  The new space replaces the first columns.
+// Lanczos vectors held in W / Wt / AW: Gram matrices on the device, the
+// small harmonic / two-sided Ritz problems on the host, basis products on the
+// device.  The new space replaces the first columns of W, Wt and AW.
 int ritz_cycle(rbs_ctx* c, int ns) {
     const int m = c->gen_k + ns;
     if (m <= 0) return RBS_OK;
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
-    double* dFG = c->dsmall;                 // m x 2m : Wt^T [W AW]
-    double* dGw = dFG + (size_t)2 * m * m;   // m x m
-    double* dGwt = dGw + (size_t)m * m;
+    double* dFG = c->dsmall;                   // m x 2m : Wt^T [W AW]
+    double* dWG = dFG + (size_t)2 * m * m;     // m x 2m : W^T [W AW]
+    double* dG2 = dWG + (size_t)2 * m * m;     // m x m  : (AW)^T AW
+    double* dGwt = dG2 + (size_t)m * m;        // m x m  : Wt^T Wt
     rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->W, ld, m, c->AW, ld, m, c->gpart, dFG);
-    rbs::launch_gemmt(s, c->n, c->W, ld, m, c->W, ld, m, nullptr, 0, 0, c->gpart, dGw);
+    rbs::launch_gemmt(s, c->n, c->W, ld, m, c->W, ld, m, c->AW, ld, m, c->gpart, dWG);
+    rbs::launch_gemmt(s, c->n, c->AW, ld, m, c->AW, ld, m, nullptr, 0, 0, c->gpart, dG2);
     rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->Wt, ld, m, nullptr, 0, 0, c->gpart, dGwt);
-    std::vector<double> hbuf((size_t)4 * m * m);
+    std::vector<double> hbuf((size_t)6 * m * m);
     int rc = to_host(c, hbuf.data(), dFG, hbuf.size() * sizeof(double));
     if (rc) return rc;
     const double* F = hbuf.data();
     const double* G = F + (size_t)m * m;
     const double* Gw = G + (size_t)m * m;
-    const double* Gwt = Gw + (size_t)m * m;
-    rbs::dense::RitzResult res = rbs::dense::two_sided_ritz(m, Gw, Gwt, F, G, c->k_max);
+    const double* F2 = Gw + (size_t)m * m;
+    const double* G2 = F2 + (size_t)m * m;
+    const double* Gwt = G2 + (size_t)m * m;
+    rbs::dense::RitzResult res = rbs::dense::recycle_ritz(m, Gw, Gwt, F, G, G2, F2, c->k_max);
     if (!res.ok || res.kout == 0) {
         c->gen_k = 0;
         return RBS_OK;
@@ -661,6 +667,7 @@ int rbicgstab_setup(rbs_ctx** pctx, int64_t n, int64_t nnz, const int32_t* rowpt
     }
     c->secant_max = secant_max > 0 ? secant_max : DEFAULT_SECANT;
     c->setup_mv_A = c->setup_mv_At = 0;
+    c->nnz = nnz;
     int rc = build_sell(c, nnz, rowptr, colidx, val, c->A);
     if (rc) return rc;
     rc = build_sell(c, nnzT, rowptrT, colidxT, valT, c->At);
@@ -738,6 +745,46 @@ int rbicgstab_get_blocks(rbs_ctx* c, double* U, double* Ut, double* C, double* C
         if (rc) return rc;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBS_OK;
+}
+
+int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, double* avg_ms,
+                        double* bytes) {
+    if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
+    if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound");
+    if (which < 0 || which > 3 || reps < 1 || k < 0 || k > c->k)
+        return fail(c, RBS_ERR_ARG, "which must be 0..3, reps >= 1 and 0 <= k <= k_used");
+    rbs::SolveBufs B = solve_bufs(c, k, c->s, c->x, nullptr);
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    rbs::launch_time_prep(c->stream, c->st);
+    rbs::launch_pass(c->stream, B, which);   // warm-up launch
+    rbs::launch_time_prep(c->stream, c->st);
+    hipEventRecord(e0, c->stream);
+    for (int i = 0; i < reps; ++i) rbs::launch_pass(c->stream, B, which);
+    hipEventRecord(e1, c->stream);
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(c, RBS_ERR_HIP, std::string("timing: ") + hipGetErrorString(e));
+    HIPCHK(c, hipMemcpy(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost));
+    if (c->hp->solve.done) return fail(c, RBS_ERR_NONFINITE, "timing state terminated early");
+    if (avg_ms) *avg_ms = ms / reps;
+    if (bytes) {
+        // algorithmic bytes per launch: CSR (int32 index + fp64 value per stored
+        // entry, int32 row pointer) and every vector / block entry touched once
+        const double n = (double)c->n, nnz = (double)c->nnz, kk = (double)k;
+        const double csr = 12.0 * nnz + 4.0 * (n + 1);
+        double v = 0.0;
+        if (which == 0) v = 80.0 * n + 8.0 * n * kk;
+        else if (which == 1) v = csr + 32.0 * n + 16.0 * n * kk;
+        else if (which == 2) v = csr + 24.0 * n + 8.0 * n * kk;
+        else v = csr + 16.0 * n;
+        *bytes = v;
+    }
     return RBS_OK;
 }
 

@@ -442,139 +442,162 @@ void ritz_select(const std::vector<cd>& theta, int k, std::vector<int>& idx, std
     }
 }
 
-RitzResult two_sided_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
-                          int k) {
-    RitzResult out;
-    std::vector<double> d(m), dt(m), Gs((size_t)m * m), Gts((size_t)m * m);
+namespace {
+
+// Orthonormal-basis factor of a Gram matrix: Q = W D P R^-1 with D the
+// column scaling, P the pivot selection (first r columns), R upper r x r.
+struct Basis {
+    std::vector<double> d, R;
+    std::vector<int> perm;
+    int r = 0;
+};
+
+Basis make_basis(int m, const double* Gram) {
+    Basis b;
+    b.d.resize(m);
     for (int i = 0; i < m; ++i) {
-        const double a = Gw[i + (size_t)i * m], b = Gwt[i + (size_t)i * m];
-        d[i] = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
-        dt[i] = b > 0 ? 1.0 / std::sqrt(b) : 0.0;
+        const double a = Gram[i + (size_t)i * m];
+        b.d[i] = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
     }
+    std::vector<double> Gs((size_t)m * m);
     for (int j = 0; j < m; ++j)
-        for (int i = 0; i < m; ++i) {
-            Gs[i + (size_t)j * m] = d[i] * Gw[i + (size_t)j * m] * d[j];
-            Gts[i + (size_t)j * m] = dt[i] * Gwt[i + (size_t)j * m] * dt[j];
-        }
-    std::vector<int> pr, pt;
-    std::vector<double> R, Rt;
-    const int r = pivoted_cholesky(m, Gs.data(), 1e-12, pr, R);
-    const int rt = pivoted_cholesky(m, Gts.data(), 1e-12, pt, Rt);
-    const int me = std::min(r, rt);
-    out.m_eff = me;
-    if (me == 0) {
-        out.ok = true;
-        return out;
-    }
-    // reduced pencil in orthonormal bases Q = W D P R^-1, Qt = Wt Dt Pt Rt^-1
-    auto reduce = [&](const double* X) {
-        std::vector<double> Y((size_t)me * me);
-        for (int b = 0; b < me; ++b)
-            for (int a = 0; a < me; ++a)
-                Y[a + (size_t)b * me] = dt[pt[a]] * X[pt[a] + (size_t)pr[b] * m] * d[pr[b]];
-        // Y <- Y R^-1 : solve Z R = Y row by row (R upper, leading dim r)
+        for (int i = 0; i < m; ++i) Gs[i + (size_t)j * m] = b.d[i] * Gram[i + (size_t)j * m] * b.d[j];
+    b.r = pivoted_cholesky(m, Gs.data(), 1e-12, b.perm, b.R);
+    return b;
+}
+
+// Ql^T (X) Qr for X = Wl^T Z Wr-type products, me x me.
+std::vector<double> reduce(int m, int me, const double* X, const Basis& L, const Basis& Rt) {
+    std::vector<double> Y((size_t)me * me);
+    for (int b = 0; b < me; ++b)
         for (int a = 0; a < me; ++a)
-            for (int b = 0; b < me; ++b) {
-                double s = Y[a + (size_t)b * me];
-                for (int c = 0; c < b; ++c) s -= Y[a + (size_t)c * me] * R[c + (size_t)b * r];
-                Y[a + (size_t)b * me] = s / R[b + (size_t)b * r];
-            }
-        // Y <- Rt^-T Y : solve Rt^T Z = Y (lower) column by column
-        for (int b = 0; b < me; ++b)
-            for (int a = 0; a < me; ++a) {
-                double s = Y[a + (size_t)b * me];
-                for (int c = 0; c < a; ++c) s -= Rt[c + (size_t)a * rt] * Y[c + (size_t)b * me];
-                Y[a + (size_t)b * me] = s / Rt[a + (size_t)a * rt];
-            }
-        return Y;
-    };
-    std::vector<double> Fp = reduce(F), Gp = reduce(G);
+            Y[a + (size_t)b * me] =
+                L.d[L.perm[a]] * X[L.perm[a] + (size_t)Rt.perm[b] * m] * Rt.d[Rt.perm[b]];
+    for (int a = 0; a < me; ++a)        // Y <- Y Rr^-1
+        for (int b = 0; b < me; ++b) {
+            double s = Y[a + (size_t)b * me];
+            for (int c = 0; c < b; ++c) s -= Y[a + (size_t)c * me] * Rt.R[c + (size_t)b * Rt.r];
+            Y[a + (size_t)b * me] = s / Rt.R[b + (size_t)b * Rt.r];
+        }
+    for (int b = 0; b < me; ++b)        // Y <- Rl^-T Y
+        for (int a = 0; a < me; ++a) {
+            double s = Y[a + (size_t)b * me];
+            for (int c = 0; c < a; ++c) s -= L.R[c + (size_t)a * L.r] * Y[c + (size_t)b * me];
+            Y[a + (size_t)b * me] = s / L.R[a + (size_t)a * L.r];
+        }
+    return Y;
+}
+
+// Map reduced coordinates back to W coordinates (Y = D P R^-1 y) and scale
+// each column to give a unit-norm W Y (Gram = W^T W).
+std::vector<double> back_to_w(int m, int me, int kout, const std::vector<double>& Yc, const Basis& B,
+                              const double* Gram) {
+    std::vector<double> full((size_t)m * kout, 0.0);
+    for (int c = 0; c < kout; ++c) {
+        std::vector<double> z(Yc.begin() + (size_t)c * me, Yc.begin() + (size_t)(c + 1) * me);
+        for (int a = me - 1; a >= 0; --a) {
+            double s = z[a];
+            for (int b = a + 1; b < me; ++b) s -= B.R[a + (size_t)b * B.r] * z[b];
+            z[a] = s / B.R[a + (size_t)a * B.r];
+        }
+        for (int a = 0; a < me; ++a) full[B.perm[a] + (size_t)c * m] = B.d[B.perm[a]] * z[a];
+        double nn = 0.0;
+        const double* y = full.data() + (size_t)c * m;
+        for (int j = 0; j < m; ++j) {
+            double g = 0.0;
+            for (int i = 0; i < m; ++i) g += Gram[i + (size_t)j * m] * y[i];
+            nn += g * y[j];
+        }
+        const double f = nn > 0 ? 1.0 / std::sqrt(nn) : 0.0;
+        for (int j = 0; j < m; ++j) full[j + (size_t)c * m] *= f;
+    }
+    return full;
+}
+
+// Pencil (Gp, Fp) in reduced coordinates: eigenvalues of H = Fp^-1 Gp, the k
+// selected ones, and their right eigenvectors (want_left: left vectors of the
+// pencil, yt^T Gp = theta yt^T Fp) as real columns ([Re, Im] for a pair).
+bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<double>& Fp, int k,
+                    bool want_left, std::vector<double>& cols, std::vector<cd>& theta) {
     std::vector<int> piv(me);
     std::vector<double> Flu = Fp;
-    if (lu_factor(me, Flu.data(), me, piv.data()) != 0) return out;
+    if (lu_factor(me, Flu.data(), me, piv.data()) != 0) return false;
     std::vector<double> H = Gp;
-    lu_solve(me, Flu.data(), me, piv.data(), H.data(), me, me, false);   // H = F'^-1 G'
+    lu_solve(me, Flu.data(), me, piv.data(), H.data(), me, me, false);
     std::vector<double> Hh, Qh;
     std::vector<cd> lam;
-    if (!eig_general(me, H.data(), Hh, Qh, lam)) return out;
+    if (!eig_general(me, H.data(), Hh, Qh, lam)) return false;
     std::vector<int> idx, pair;
     ritz_select(lam, k, idx, pair);
-    std::vector<double> Yr, Ytr;   // me x kout columns
-    std::vector<cd> yh, wh;
+    std::vector<cd> vh;
     for (size_t t = 0; t < idx.size(); ++t) {
         const cd th = lam[idx[t]];
-        hess_eigvec(me, Hh, th, false, yh);
-        hess_eigvec(me, Hh, th, true, wh);
-        std::vector<cd> y(me, 0.0), w(me, 0.0);
+        hess_eigvec(me, Hh, th, want_left, vh);
+        std::vector<cd> v(me, 0.0);
         for (int i = 0; i < me; ++i)
-            for (int j = 0; j < me; ++j) {
-                y[i] += Qh[i + (size_t)j * me] * yh[j];
-                w[i] += Qh[i + (size_t)j * me] * wh[j];
+            for (int j = 0; j < me; ++j) v[i] += Qh[i + (size_t)j * me] * vh[j];
+        if (want_left) {   // pencil left vector = Fp^-T (left vector of H)
+            std::vector<double> vr(me), vi(me);
+            for (int i = 0; i < me; ++i) {
+                vr[i] = v[i].real();
+                vi[i] = v[i].imag();
             }
-        // left pencil vector yt = F'^-T w (real and imaginary parts separately)
-        std::vector<double> wr(me), wi(me);
-        for (int i = 0; i < me; ++i) {
-            wr[i] = w[i].real();
-            wi[i] = w[i].imag();
+            lu_solve(me, Flu.data(), me, piv.data(), vr.data(), me, 1, true);
+            lu_solve(me, Flu.data(), me, piv.data(), vi.data(), me, 1, true);
+            for (int i = 0; i < me; ++i) v[i] = cd(vr[i], vi[i]);
         }
-        lu_solve(me, Flu.data(), me, piv.data(), wr.data(), me, 1, true);
-        lu_solve(me, Flu.data(), me, piv.data(), wi.data(), me, 1, true);
-        if (!pair[t]) {
-            // real eigenvalue: make the vectors real (remove a common phase)
+        if (!pair[t]) {   // real eigenvalue: remove the common phase
             cd ph = 0.0;
             for (int i = 0; i < me; ++i)
-                if (std::abs(y[i]) > std::abs(ph)) ph = y[i];
+                if (std::abs(v[i]) > std::abs(ph)) ph = v[i];
             ph = ph == cd(0.0) ? cd(1.0) : std::conj(ph) / std::abs(ph);
-            for (int i = 0; i < me; ++i) Yr.push_back((y[i] * ph).real());
-            cd pl = 0.0;
-            for (int i = 0; i < me; ++i)
-                if (std::abs(cd(wr[i], wi[i])) > std::abs(pl)) pl = cd(wr[i], wi[i]);
-            pl = pl == cd(0.0) ? cd(1.0) : std::conj(pl) / std::abs(pl);
-            for (int i = 0; i < me; ++i) Ytr.push_back((cd(wr[i], wi[i]) * pl).real());
-            out.theta.push_back(th);
+            for (int i = 0; i < me; ++i) cols.push_back((v[i] * ph).real());
+            theta.push_back(th);
         } else {
-            for (int i = 0; i < me; ++i) Yr.push_back(y[i].real());
-            for (int i = 0; i < me; ++i) Yr.push_back(y[i].imag());
-            for (int i = 0; i < me; ++i) Ytr.push_back(wr[i]);
-            for (int i = 0; i < me; ++i) Ytr.push_back(wi[i]);
-            out.theta.push_back(th);
-            out.theta.push_back(std::conj(th));
+            for (int i = 0; i < me; ++i) cols.push_back(v[i].real());
+            for (int i = 0; i < me; ++i) cols.push_back(v[i].imag());
+            theta.push_back(th);
+            theta.push_back(std::conj(th));
         }
     }
-    const int kout = (int)(Yr.size() / me);
-    // back to W coordinates: Y = D P R^-1 Y'
-    auto back = [&](std::vector<double>& Yc, const std::vector<double>& Rm, int rr,
-                    const std::vector<int>& perm, const std::vector<double>& dd) {
-        std::vector<double> full((size_t)m * kout, 0.0);
-        for (int c = 0; c < kout; ++c) {
-            std::vector<double> z(Yc.begin() + (size_t)c * me, Yc.begin() + (size_t)(c + 1) * me);
-            for (int a = me - 1; a >= 0; --a) {   // R z = y (upper, leading block me)
-                double s = z[a];
-                for (int b = a + 1; b < me; ++b) s -= Rm[a + (size_t)b * rr] * z[b];
-                z[a] = s / Rm[a + (size_t)a * rr];
-            }
-            for (int a = 0; a < me; ++a) full[perm[a] + (size_t)c * m] = dd[perm[a]] * z[a];
-        }
-        return full;
-    };
-    out.Y = back(Yr, R, r, pr, d);
-    out.Yt = back(Ytr, Rt, rt, pt, dt);
-    // unit-norm columns of W Y and Wt Yt
-    auto normalise = [&](std::vector<double>& Y, const double* Gram) {
-        for (int c = 0; c < kout; ++c) {
-            double s = 0.0;
-            const double* y = Y.data() + (size_t)c * m;
-            for (int j = 0; j < m; ++j) {
-                double g = 0.0;
-                for (int i = 0; i < m; ++i) g += Gram[i + (size_t)j * m] * y[i];
-                s += g * y[j];
-            }
-            const double f = s > 0 ? 1.0 / std::sqrt(s) : 0.0;
-            for (int j = 0; j < m; ++j) Y[j + (size_t)c * m] *= f;
-        }
-    };
-    normalise(out.Y, Gw);
-    normalise(out.Yt, Gwt);
+    return true;
+}
+
+}  // namespace
+
+RitzResult recycle_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
+                        const double* G2, const double* F2, int k) {
+    RitzResult out;
+    const Basis bw = make_basis(m, Gw), bwt = make_basis(m, Gwt);
+    // right vectors: harmonic Ritz on W, (AQ)^T (AQ) y = theta (AQ)^T Q y
+    const int mr = bw.r;
+    std::vector<double> Yc, Ytc;
+    std::vector<cd> th_r, th_l;
+    if (mr > 0) {
+        std::vector<double> F2t((size_t)m * m);   // (AW)^T W = F2^T
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) F2t[i + (size_t)j * m] = F2[j + (size_t)i * m];
+        const std::vector<double> A2 = reduce(m, mr, G2, bw, bw);
+        const std::vector<double> B2 = reduce(m, mr, F2t.data(), bw, bw);
+        if (!pencil_vectors(mr, A2, B2, k, false, Yc, th_r)) return out;
+    }
+    // left vectors: two-sided Rayleigh-Ritz on (Wt, W), G y = theta F y
+    const int me = std::min(bw.r, bwt.r);
+    if (me > 0) {
+        Basis bw2 = bw, bwt2 = bwt;
+        const std::vector<double> Gp = reduce(m, me, G, bwt2, bw2);
+        const std::vector<double> Fp = reduce(m, me, F, bwt2, bw2);
+        if (!pencil_vectors(me, Gp, Fp, k, true, Ytc, th_l)) return out;
+    }
+    const int kr = mr > 0 ? (int)(Yc.size() / mr) : 0;
+    const int kl = me > 0 ? (int)(Ytc.size() / me) : 0;
+    const int kout = std::min(kr, kl);
+    out.m_eff = me;
+    if (kout > 0) {
+        out.Y = back_to_w(m, mr, kout, Yc, bw, Gw);
+        out.Yt = back_to_w(m, me, kout, Ytc, bwt, Gwt);
+        out.theta.assign(th_r.begin(), th_r.begin() + kout);
+    }
     out.kout = kout;
     out.ok = true;
     return out;

@@ -35,11 +35,14 @@ bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<do
 void hess_eigvec(int n, const std::vector<double>& Hh, std::complex<double> lam, bool left,
                  std::vector<std::complex<double>>& y);
 
-// Two-sided Rayleigh-Ritz for the k smallest-magnitude Ritz values.
-// Inputs (m x m, column-major): Gw = W^T W, Gwt = Wt^T Wt, F = Wt^T W,
-// G = Wt^T A W.  Outputs: coefficient matrices Y, Yt (m x kout) such that
-// U = W Y and Ut = Wt Yt have unit-norm columns spanning approximate right
-// and left invariant subspaces; theta holds the selected Ritz values.
+// Recycle-space update from the Gram matrices of W (current space + Lanczos
+// vectors), Wt (its dual counterpart) and AW (m x m, column-major):
+//   Gw = W^T W, Gwt = Wt^T Wt, F = Wt^T W, G = Wt^T A W, G2 = (AW)^T (AW),
+//   F2 = W^T (AW).
+// Right vectors: harmonic Ritz vectors of A on W for the k smallest |theta|;
+// left vectors: left vectors of the two-sided projection G y = theta F y for
+// its k smallest |theta|.  Outputs Y, Yt (m x kout) with U = W Y and
+// Ut = Wt Yt of unit-norm columns.
 struct RitzResult {
     int kout = 0;
     int m_eff = 0;
@@ -47,8 +50,8 @@ struct RitzResult {
     std::vector<std::complex<double>> theta;
     bool ok = false;
 };
-RitzResult two_sided_ritz(int m, const double* Gw, const double* Gwt, const double* F,
-                          const double* G, int k);
+RitzResult recycle_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
+                        const double* G2, const double* F2, int k);
 
 // Selection rule shared by the Ritz step: indices of the k finite values of
 // smallest |theta| ordered by (|theta|, Re, Im); a complex pair takes two

@@ -52,6 +52,11 @@ struct SolveBufs {
 void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it);
 void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count);
 void launch_solve_epilogue(hipStream_t st, const SolveBufs& B);
+// Timing support: put the solve state in a non-terminating configuration
+// (done = 0, tolerance below zero, fixed bounded scalars) and launch one of
+// the fused passes (0 update, 1 spmv1, 2 spmv2, 3 plain SpMV y = A x).
+void launch_time_prep(hipStream_t st, SolveState* state);
+void launch_pass(hipStream_t st, const SolveBufs& B, int which);
 
 // ---- RBiCG (Algorithm 1) kernels ------------------------------------------
 struct BicgBufs {

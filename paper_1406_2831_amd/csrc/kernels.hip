@@ -993,6 +993,18 @@ __global__ __launch_bounds__(BLOCK) void k_bepi(BicgBufs B) {
 
 __global__ void k_bicg_reset(BicgState* st) { st->stored = 0; }
 
+__global__ void k_time_prep(SolveState* st) {
+    st->done = 0;
+    st->tol2 = -1.0;
+    st->max_it = 0x7fffffff;
+    st->omega_zero = 0;
+    st->iter = 1;
+    st->alpha = 0.5;
+    st->beta = 0.1;
+    st->omega = 0.2;
+    st->rho = 1.0;
+}
+
 // compile-time recycle-dimension buckets
 template <template <int> class F, typename... Args>
 void dispatch_k(int k, Args&&... args) {
@@ -1138,6 +1150,18 @@ void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count) {
         dispatch_k<L_spmv1>(B.k, st, g, B);
         dispatch_k<L_spmv2>(B.k, st, g, B);
     }
+}
+
+void launch_time_prep(hipStream_t st, SolveState* state) {
+    hipLaunchKernelGGL(k_time_prep, dim3(1), dim3(1), 0, st, state);
+}
+
+void launch_pass(hipStream_t st, const SolveBufs& B, int which) {
+    const int g = stream_grid(B.n);
+    if (which == 0) dispatch_k<L_update>(B.k, st, g, B);
+    else if (which == 1) dispatch_k<L_spmv1>(B.k, st, g, B);
+    else if (which == 2) dispatch_k<L_spmv2>(B.k, st, g, B);
+    else launch_spmv(st, B.A, B.p, B.q);
 }
 
 void launch_solve_epilogue(hipStream_t st, const SolveBufs& B) {

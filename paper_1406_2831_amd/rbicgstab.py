@@ -40,8 +40,8 @@ RBS_RECYCLE_FROM_LAST_SOLVE = 1
 RBS_RECYCLE_CLEAR = 2
 
 EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "recycle_update",
-           "rbicgstab_get_blocks", "rbicgstab_setup_matvecs", "rbicgstab_destroy",
-           "rbicgstab_last_error")
+           "rbicgstab_get_blocks", "rbicgstab_time_pass", "rbicgstab_setup_matvecs",
+           "rbicgstab_destroy", "rbicgstab_last_error")
 
 
 class Stats(ctypes.Structure):
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     lib.recycle_update.restype = ctypes.c_int
     lib.rbicgstab_get_blocks.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
     lib.rbicgstab_get_blocks.restype = ctypes.c_int
+    lib.rbicgstab_time_pass.argtypes = [vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    lib.rbicgstab_time_pass.restype = ctypes.c_int
     lib.rbicgstab_setup_matvecs.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.rbicgstab_setup_matvecs.restype = ctypes.c_int
     lib.rbicgstab_destroy.argtypes = [vp]
@@ -163,6 +165,15 @@ def rbicgstab_get_blocks(handle, n: int, k_max: int, device="cuda"):
     return {name: t[: kk.value].clone() for name, t in out.items()}, kk.value
 
 
+def rbicgstab_time_pass(handle, which: int, k: int, reps: int):
+    """(mean ms per launch, algorithmic bytes per launch) of one fused pass."""
+    lib = load_library()
+    ms, by = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib, handle, lib.rbicgstab_time_pass(handle, which, k, reps, ctypes.byref(ms),
+                                                ctypes.byref(by)))
+    return ms.value, by.value
+
+
 def rbicgstab_setup_matvecs(handle):
     lib = load_library()
     a, b = ctypes.c_int32(0), ctypes.c_int32(0)
@@ -230,6 +241,9 @@ class Context:
 
     def setup_matvecs(self):
         return rbicgstab_setup_matvecs(self.handle)
+
+    def time_pass(self, which: int, k: int, reps: int = 50):
+        return rbicgstab_time_pass(self.handle, which, k, reps)
 
     def close(self):
         rbicgstab_destroy(self.handle)

@@ -1,0 +1,51 @@
+// C wrappers over the library's host dense algebra, built with g++ by the
+// CPU tests only (no GPU): lets NumPy/SciPy check the routines directly.
+#include <cstring>
+#include <vector>
+
+#include "dense.h"
+
+using namespace rbs::dense;
+
+extern "C" {
+
+int shim_lu_solve(int n, const double* A, double* b, int trans) {
+    std::vector<double> lu(A, A + (size_t)n * n);
+    std::vector<int> piv(n);
+    if (lu_factor(n, lu.data(), n, piv.data())) return 1;
+    lu_solve(n, lu.data(), n, piv.data(), b, n, 1, trans != 0);
+    return 0;
+}
+
+void shim_svd(int m, const double* M, double* P, double* sig, double* Q) { svd(m, M, P, sig, Q); }
+
+int shim_eig(int n, const double* H, double* wr, double* wi) {
+    std::vector<double> Hh, Qh;
+    std::vector<std::complex<double>> lam;
+    if (!eig_general(n, H, Hh, Qh, lam)) return 1;
+    for (int i = 0; i < n; ++i) {
+        wr[i] = lam[i].real();
+        wi[i] = lam[i].imag();
+    }
+    return 0;
+}
+
+int shim_pivoted_cholesky(int m, const double* G, double tol, int* perm, double* R) {
+    std::vector<int> p;
+    std::vector<double> r;
+    const int rank = pivoted_cholesky(m, G, tol, p, r);
+    for (int i = 0; i < rank; ++i) perm[i] = p[i];
+    std::memcpy(R, r.data(), sizeof(double) * (size_t)rank * rank);
+    return rank;
+}
+
+int shim_recycle_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
+                      const double* G2, const double* F2, int k, double* Y, double* Yt, double* th_re) {
+    RitzResult r = recycle_ritz(m, Gw, Gwt, F, G, G2, F2, k);
+    if (!r.ok) return -1;
+    std::memcpy(Y, r.Y.data(), sizeof(double) * r.Y.size());
+    std::memcpy(Yt, r.Yt.data(), sizeof(double) * r.Yt.size());
+    for (int i = 0; i < r.kout; ++i) th_re[i] = r.theta[i].real();
+    return r.kout;
+}
+}

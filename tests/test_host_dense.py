@@ -1,0 +1,125 @@
+"""CPU checks of the library's host-side dense algebra (LU, SVD, pivoted
+Cholesky, Hessenberg + Francis QR eigenvalues, recycle-space Ritz step),
+built with g++ from the library's own source into a throwaway shim."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as o
+import workloads as w
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1406_2831_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("shim") / "libdense_shim.so")
+    cmd = [gxx, "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC,
+           os.path.join(ROOT, "tests", "dense_shim.cpp"), os.path.join(CSRC, "dense.cpp"), "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    lib = ctypes.CDLL(out)
+    P = ctypes.POINTER(ctypes.c_double)
+    lib.shim_lu_solve.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+    lib.shim_svd.argtypes = [ctypes.c_int, P, P, P, P]
+    lib.shim_eig.argtypes = [ctypes.c_int, P, P, P]
+    lib.shim_pivoted_cholesky.argtypes = [ctypes.c_int, P, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_int), P]
+    lib.shim_recycle_ritz.argtypes = [ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fortran(a):
+    return np.asfortranarray(a, dtype=np.float64)
+
+
+def test_lu_solve(shim):
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((30, 30))
+    b = rng.standard_normal(30)
+    for trans in (0, 1):
+        x = b.copy()
+        assert shim.shim_lu_solve(30, _p(_fortran(A).ravel(order="F")), _p(x), trans) == 0
+        ref = np.linalg.solve(A.T if trans else A, b)
+        assert np.allclose(x, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_svd(shim):
+    rng = np.random.default_rng(2)
+    M = rng.standard_normal((12, 12))
+    Mf = _fortran(M).ravel(order="F")
+    P, s, Q = np.zeros(144), np.zeros(12), np.zeros(144)
+    shim.shim_svd(12, _p(Mf), _p(P), _p(s), _p(Q))
+    P, Q = P.reshape(12, 12, order="F"), Q.reshape(12, 12, order="F")
+    assert np.allclose(s, np.linalg.svd(M, compute_uv=False), rtol=1e-12)
+    assert np.allclose(P @ np.diag(s) @ Q.T, M, atol=1e-12)
+    assert np.allclose(P.T @ P, np.eye(12), atol=1e-12)
+
+
+def test_pivoted_cholesky_rank(shim):
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((50, 6))
+    X = np.hstack([X, X[:, :2] @ rng.standard_normal((2, 3))])   # rank 6, 9 columns
+    G = _fortran(X.T @ X).ravel(order="F")
+    perm = (ctypes.c_int * 9)()
+    R = np.zeros(81)
+    r = shim.shim_pivoted_cholesky(9, _p(G), 1e-12, perm, _p(R))
+    assert r == 6
+    Rm = R[: r * r].reshape(r, r, order="F")
+    cols = list(perm)[:r]
+    assert np.allclose(Rm.T @ Rm, (X.T @ X)[np.ix_(cols, cols)], rtol=1e-10)
+
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (40, 1), (120, 2)])
+def test_eigenvalues_match_lapack(shim, n, seed):
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((n, n))
+    wr, wi = np.zeros(n), np.zeros(n)
+    assert shim.shim_eig(n, _p(_fortran(H).ravel(order="F")), _p(wr), _p(wi)) == 0
+    got = np.sort_complex(wr + 1j * wi)
+    ref = np.sort_complex(np.linalg.eigvals(H))
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.abs(ref).max()
+
+
+def test_recycle_ritz_vs_oracle(shim):
+    seq = w.seq_2d(nshift=1, nrhs=1)
+    A, At = (m.to_scipy() for m in seq.matrix(0))
+    n = A.shape[0]
+    st = {}
+
+    def cyc(V, Vt):
+        st["V"], st["Vt"] = V, Vt
+
+    o.rbicg(A, At, o.empty_blocks(n), seq.rhs[0], rtol=1e-8, s=100000, on_cycle=cyc)
+    W, Wt = st["V"], st["Vt"]
+    AW = A @ W
+    m, k = W.shape[1], 8
+    mats = [W.T @ W, Wt.T @ Wt, Wt.T @ W, Wt.T @ AW, AW.T @ AW, W.T @ AW]
+    flat = [_fortran(x).ravel(order="F") for x in mats]
+    Y, Yt, th = np.zeros(m * k), np.zeros(m * k), np.zeros(k)
+    kout = shim.shim_recycle_ritz(m, *[_p(f) for f in flat], k, _p(Y), _p(Yt), _p(th))
+    assert kout > 0
+    U = W @ Y[: m * kout].reshape(m, kout, order="F")
+    Ut = Wt @ Yt[: m * kout].reshape(m, kout, order="F")
+    Uo, Uto, _ = o.recycle_space(A, W, Wt, k)
+    assert kout == Uo.shape[1]
+    assert np.allclose(np.linalg.norm(U, axis=0), 1.0, rtol=1e-6)   # normalised through the Gram matrix
+    # same subspaces (near-degenerate boundary values aside: compare the leading half).
+    # The library orthonormalises through Gram matrices (condition number squared),
+    # the oracle through Householder QR, so the angles agree to ~sqrt(eps * cond^2).
+    h = kout // 2
+    cos_r = sla.svdvals(sla.orth(U[:, :h]).T @ sla.orth(Uo))
+    cos_l = sla.svdvals(sla.orth(Ut[:, :h]).T @ sla.orth(Uto))
+    assert cos_r.min() > 1 - 1e-4 and cos_l.min() > 1 - 1e-4

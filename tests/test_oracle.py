@@ -313,3 +313,30 @@ def test_sequence_2d_converges():
         A, _ = seq.matrix(seq.system(idx)[0])
         xd = np.linalg.solve(A.to_scipy().toarray(), seq.rhs[idx])
         assert _rel(x, xd) < 1e-5
+
+
+def test_harmonic_ritz_recovers_planted_vectors(c0, eig_c0):
+    """Exact eigenvectors in W give exact harmonic Ritz pairs (residual orthogonal to A W is zero)."""
+    seq, A, At = c0
+    lam, vl, vr = eig_c0
+    rng = np.random.default_rng(4)
+    pad = vr[:, -40:] @ rng.standard_normal((40, 6))
+    W = np.hstack([vr[:, :5], pad])
+    U, vals = o.harmonic_ritz(A, W, 5)
+    assert np.allclose(np.sort(vals.real), np.sort(lam[:5].real), rtol=1e-9)
+    cosines = sla.svdvals(sla.orth(U).T @ sla.orth(vr[:, :5]))
+    assert cosines.min() > 1 - 1e-9
+    # a right eigenvector's harmonic residual is zero: ||A u - theta u|| ~ 0
+    res = np.linalg.norm(A @ U - U * vals.real, axis=0) / np.abs(vals)
+    assert res.max() < 1e-8
+
+
+def test_recycle_space_reduces_iterations_3d():
+    """Sequence-level property of the update (Section 6.2): RBiCGSTAB with the space
+    from one RBiCG solve needs fewer iterations than BiCGSTAB on the other rhs."""
+    seq = w.seq_3d(N=16, nshift=1, nrhs=3, k=12)
+    res = o.run_sequence(seq, mode="rbicgstab", rtol=1e-8)
+    base = o.run_sequence(seq, mode="bicgstab", rtol=1e-8)
+    assert all(s == o.OK for s in res.status)
+    assert res.k_used[1] >= 8
+    assert sum(res.iters[1:]) < sum(base.iters[1:])
