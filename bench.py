@@ -89,6 +89,7 @@ def main():
         bad = [s for s in res.status if s != 0]
         if bad or max(res.rel_res_true) > args.rtol:
             print(f"{mode}: not every system converged: status {res.status}, "
+                  f"iters {res.iters}, k {res.k_used}, solver {res.solver}, "
                   f"true residuals {res.rel_res_true}", file=sys.stderr)
             sys.exit(1)
 

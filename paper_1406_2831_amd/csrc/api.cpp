@@ -52,7 +52,7 @@ struct rbs_ctx {
     double *x = nullptr, *r = nullptr, *s = nullptr, *t = nullptr, *p = nullptr, *q = nullptr,
            *rt0 = nullptr, *rh = nullptr, *rt = nullptr, *pt = nullptr, *z = nullptr, *zt = nullptr,
            *qt = nullptr;
-    double *W = nullptr, *Wt = nullptr, *AW = nullptr;
+    double *W = nullptr, *Wt = nullptr, *AW = nullptr, *Wtmp = nullptr;
     int64_t ldw = 0;
     double* partials = nullptr;
     unsigned* tickets = nullptr;
@@ -129,6 +129,7 @@ size_t carve(rbs_ctx* c, char* base) {
     c->W = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
     c->Wt = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
     c->AW = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
+    c->Wtmp = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
     const int64_t mmax = c->k_max + std::max(c->s_max, 0);
     c->dsmall_doubles = (size_t)(6 * mmax * mmax + 4 * mmax * c->k_max + 64);
     c->dsmall = cv.take<double>(c->dsmall_doubles);
@@ -451,33 +452,66 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     return B;
 }
 
+// Orthonormalise the first m columns of X in place (pivoted Cholesky-QR,
+// applied twice), applying the same column transform to AX when given.
+// Returns the numerical rank (columns kept), or < 0 on error.
+int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
+    hipStream_t s = c->stream;
+    const int64_t ld = c->ldw;
+    for (int pass = 0; pass < 2 && m > 0; ++pass) {
+        double* dG = c->dsmall;
+        rbs::launch_gemmt(s, c->n, X, ld, m, X, ld, m, nullptr, 0, 0, c->gpart, dG);
+        std::vector<double> G((size_t)m * m);
+        int rc = to_host(c, G.data(), dG, G.size() * sizeof(double));
+        if (rc) return rc;
+        std::vector<double> S;
+        const int r = rbs::dense::orth_factor(m, G.data(), pass == 0 ? 1e-12 : 1e-14, S);
+        if (r == 0) return 0;
+        if ((rc = to_device(c, c->dsmall, S.data(), S.size() * sizeof(double)))) return rc;
+        rbs::launch_gemm_ts(s, c->n, X, ld, m, c->dsmall, r, c->Wtmp, ld);
+        if ((rc = copy_cols(c, X, ld, c->Wtmp, ld, r))) return rc;
+        if (AX) {
+            rbs::launch_gemm_ts(s, c->n, AX, ld, m, c->dsmall, r, c->Wtmp, ld);
+            if ((rc = copy_cols(c, AX, ld, c->Wtmp, ld, r))) return rc;
+        }
+        m = r;
+    }
+    return m;
+}
+
 // Cycle-end recycle-space update from the gen_k current columns and ns new
-// Lanczos vectors held in W / Wt / AW: Gram matrices on the device, the
-// small harmonic / two-sided Ritz problems on the host, basis products on the
-// device.  The new space replaces the first columns of W, Wt and AW.
+// Lanczos vectors held in W / Wt / AW.  W and Wt are first replaced by
+// orthonormal bases of their ranges (AW follows W's transform), so the
+// small problems solved on the host are well conditioned: harmonic Ritz
+// vectors of A on range(W) (right) and the left vectors of the two-sided
+// projection on (Wt, W).  The new space replaces the first columns.
 int ritz_cycle(rbs_ctx* c, int ns) {
     const int m = c->gen_k + ns;
     if (m <= 0) return RBS_OK;
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
-    double* dFG = c->dsmall;                   // m x 2m : Wt^T [W AW]
-    double* dWG = dFG + (size_t)2 * m * m;     // m x 2m : W^T [W AW]
-    double* dG2 = dWG + (size_t)2 * m * m;     // m x m  : (AW)^T AW
-    double* dGwt = dG2 + (size_t)m * m;        // m x m  : Wt^T Wt
-    rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->W, ld, m, c->AW, ld, m, c->gpart, dFG);
-    rbs::launch_gemmt(s, c->n, c->W, ld, m, c->W, ld, m, c->AW, ld, m, c->gpart, dWG);
-    rbs::launch_gemmt(s, c->n, c->AW, ld, m, c->AW, ld, m, nullptr, 0, 0, c->gpart, dG2);
-    rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->Wt, ld, m, nullptr, 0, 0, c->gpart, dGwt);
-    std::vector<double> hbuf((size_t)6 * m * m);
+    const int r = orth_inplace(c, c->W, c->AW, m);
+    if (r < 0) return r;
+    const int rt = orth_inplace(c, c->Wt, nullptr, m);
+    if (rt < 0) return rt;
+    if (r == 0 || rt == 0) {
+        c->gen_k = 0;
+        return RBS_OK;
+    }
+    double* dFG = c->dsmall;                    // rt x 2r : Qt^T [Q AQ]
+    double* dF2 = dFG + (size_t)2 * rt * r;     // r x r   : Q^T AQ
+    double* dG2 = dF2 + (size_t)r * r;          // r x r   : (AQ)^T AQ
+    rbs::launch_gemmt(s, c->n, c->Wt, ld, rt, c->W, ld, r, c->AW, ld, r, c->gpart, dFG);
+    rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
+    rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dG2);
+    std::vector<double> hbuf((size_t)2 * rt * r + 2 * (size_t)r * r);
     int rc = to_host(c, hbuf.data(), dFG, hbuf.size() * sizeof(double));
     if (rc) return rc;
     const double* F = hbuf.data();
-    const double* G = F + (size_t)m * m;
-    const double* Gw = G + (size_t)m * m;
-    const double* F2 = Gw + (size_t)m * m;
-    const double* G2 = F2 + (size_t)m * m;
-    const double* Gwt = G2 + (size_t)m * m;
-    rbs::dense::RitzResult res = rbs::dense::recycle_ritz(m, Gw, Gwt, F, G, G2, F2, c->k_max);
+    const double* G = F + (size_t)rt * r;
+    const double* F2 = G + (size_t)rt * r;
+    const double* G2 = F2 + (size_t)r * r;
+    rbs::dense::RitzResult res = rbs::dense::recycle_ritz_orth(r, rt, F, G, G2, F2, c->k_max);
     if (!res.ok || res.kout == 0) {
         c->gen_k = 0;
         return RBS_OK;
@@ -486,13 +520,12 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     std::vector<double> up(res.Y);
     up.insert(up.end(), res.Yt.begin(), res.Yt.end());
     double* dY = c->dsmall;
-    double* dYt = dY + (size_t)m * ko;
-    rc = to_device(c, dY, up.data(), up.size() * sizeof(double));
-    if (rc) return rc;
+    double* dYt = dY + (size_t)r * ko;
+    if ((rc = to_device(c, dY, up.data(), up.size() * sizeof(double)))) return rc;
     const int64_t lb = c->n_pad;
-    rbs::launch_gemm_ts(s, c->n, c->W, ld, m, dY, ko, c->T1, lb);
-    rbs::launch_gemm_ts(s, c->n, c->Wt, ld, m, dYt, ko, c->T2, lb);
-    rbs::launch_gemm_ts(s, c->n, c->AW, ld, m, dY, ko, c->T3, lb);
+    rbs::launch_gemm_ts(s, c->n, c->W, ld, r, dY, ko, c->T1, lb);
+    rbs::launch_gemm_ts(s, c->n, c->Wt, ld, rt, dYt, ko, c->T2, lb);
+    rbs::launch_gemm_ts(s, c->n, c->AW, ld, r, dY, ko, c->T3, lb);
     if ((rc = copy_cols(c, c->W, ld, c->T1, lb, ko))) return rc;
     if ((rc = copy_cols(c, c->Wt, ld, c->T2, lb, ko))) return rc;
     if ((rc = copy_cols(c, c->AW, ld, c->T3, lb, ko))) return rc;

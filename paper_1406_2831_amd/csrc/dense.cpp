@@ -444,76 +444,6 @@ void ritz_select(const std::vector<cd>& theta, int k, std::vector<int>& idx, std
 
 namespace {
 
-// Orthonormal-basis factor of a Gram matrix: Q = W D P R^-1 with D the
-// column scaling, P the pivot selection (first r columns), R upper r x r.
-struct Basis {
-    std::vector<double> d, R;
-    std::vector<int> perm;
-    int r = 0;
-};
-
-Basis make_basis(int m, const double* Gram) {
-    Basis b;
-    b.d.resize(m);
-    for (int i = 0; i < m; ++i) {
-        const double a = Gram[i + (size_t)i * m];
-        b.d[i] = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
-    }
-    std::vector<double> Gs((size_t)m * m);
-    for (int j = 0; j < m; ++j)
-        for (int i = 0; i < m; ++i) Gs[i + (size_t)j * m] = b.d[i] * Gram[i + (size_t)j * m] * b.d[j];
-    b.r = pivoted_cholesky(m, Gs.data(), 1e-12, b.perm, b.R);
-    return b;
-}
-
-// Ql^T (X) Qr for X = Wl^T Z Wr-type products, me x me.
-std::vector<double> reduce(int m, int me, const double* X, const Basis& L, const Basis& Rt) {
-    std::vector<double> Y((size_t)me * me);
-    for (int b = 0; b < me; ++b)
-        for (int a = 0; a < me; ++a)
-            Y[a + (size_t)b * me] =
-                L.d[L.perm[a]] * X[L.perm[a] + (size_t)Rt.perm[b] * m] * Rt.d[Rt.perm[b]];
-    for (int a = 0; a < me; ++a)        // Y <- Y Rr^-1
-        for (int b = 0; b < me; ++b) {
-            double s = Y[a + (size_t)b * me];
-            for (int c = 0; c < b; ++c) s -= Y[a + (size_t)c * me] * Rt.R[c + (size_t)b * Rt.r];
-            Y[a + (size_t)b * me] = s / Rt.R[b + (size_t)b * Rt.r];
-        }
-    for (int b = 0; b < me; ++b)        // Y <- Rl^-T Y
-        for (int a = 0; a < me; ++a) {
-            double s = Y[a + (size_t)b * me];
-            for (int c = 0; c < a; ++c) s -= L.R[c + (size_t)a * L.r] * Y[c + (size_t)b * me];
-            Y[a + (size_t)b * me] = s / L.R[a + (size_t)a * L.r];
-        }
-    return Y;
-}
-
-// Map reduced coordinates back to W coordinates (Y = D P R^-1 y) and scale
-// each column to give a unit-norm W Y (Gram = W^T W).
-std::vector<double> back_to_w(int m, int me, int kout, const std::vector<double>& Yc, const Basis& B,
-                              const double* Gram) {
-    std::vector<double> full((size_t)m * kout, 0.0);
-    for (int c = 0; c < kout; ++c) {
-        std::vector<double> z(Yc.begin() + (size_t)c * me, Yc.begin() + (size_t)(c + 1) * me);
-        for (int a = me - 1; a >= 0; --a) {
-            double s = z[a];
-            for (int b = a + 1; b < me; ++b) s -= B.R[a + (size_t)b * B.r] * z[b];
-            z[a] = s / B.R[a + (size_t)a * B.r];
-        }
-        for (int a = 0; a < me; ++a) full[B.perm[a] + (size_t)c * m] = B.d[B.perm[a]] * z[a];
-        double nn = 0.0;
-        const double* y = full.data() + (size_t)c * m;
-        for (int j = 0; j < m; ++j) {
-            double g = 0.0;
-            for (int i = 0; i < m; ++i) g += Gram[i + (size_t)j * m] * y[i];
-            nn += g * y[j];
-        }
-        const double f = nn > 0 ? 1.0 / std::sqrt(nn) : 0.0;
-        for (int j = 0; j < m; ++j) full[j + (size_t)c * m] *= f;
-    }
-    return full;
-}
-
 // Pencil (Gp, Fp) in reduced coordinates: eigenvalues of H = Fp^-1 Gp, the k
 // selected ones, and their right eigenvectors (want_left: left vectors of the
 // pencil, yt^T Gp = theta yt^T Fp) as real columns ([Re, Im] for a pair).
@@ -565,42 +495,64 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
 
 }  // namespace
 
-RitzResult recycle_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
-                        const double* G2, const double* F2, int k) {
+RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
+                             const double* F2, int k) {
     RitzResult out;
-    const Basis bw = make_basis(m, Gw), bwt = make_basis(m, Gwt);
-    // right vectors: harmonic Ritz on W, (AQ)^T (AQ) y = theta (AQ)^T Q y
-    const int mr = bw.r;
     std::vector<double> Yc, Ytc;
     std::vector<cd> th_r, th_l;
-    if (mr > 0) {
-        std::vector<double> F2t((size_t)m * m);   // (AW)^T W = F2^T
-        for (int j = 0; j < m; ++j)
-            for (int i = 0; i < m; ++i) F2t[i + (size_t)j * m] = F2[j + (size_t)i * m];
-        const std::vector<double> A2 = reduce(m, mr, G2, bw, bw);
-        const std::vector<double> B2 = reduce(m, mr, F2t.data(), bw, bw);
-        if (!pencil_vectors(mr, A2, B2, k, false, Yc, th_r)) return out;
+    if (r > 0) {   // harmonic: (AQ)^T (AQ) y = theta (AQ)^T Q y, with (AQ)^T Q = F2^T
+        std::vector<double> A2(G2, G2 + (size_t)r * r), B2((size_t)r * r);
+        for (int j = 0; j < r; ++j)
+            for (int i = 0; i < r; ++i) B2[i + (size_t)j * r] = F2[j + (size_t)i * r];
+        if (!pencil_vectors(r, A2, B2, k, false, Yc, th_r)) return out;
     }
-    // left vectors: two-sided Rayleigh-Ritz on (Wt, W), G y = theta F y
-    const int me = std::min(bw.r, bwt.r);
-    if (me > 0) {
-        Basis bw2 = bw, bwt2 = bwt;
-        const std::vector<double> Gp = reduce(m, me, G, bwt2, bw2);
-        const std::vector<double> Fp = reduce(m, me, F, bwt2, bw2);
+    const int me = std::min(r, rt);
+    if (me > 0) {  // two-sided: G y = theta F y on the leading me x me block
+        std::vector<double> Gp((size_t)me * me), Fp((size_t)me * me);
+        for (int j = 0; j < me; ++j)
+            for (int i = 0; i < me; ++i) {
+                Gp[i + (size_t)j * me] = G[i + (size_t)j * rt];
+                Fp[i + (size_t)j * me] = F[i + (size_t)j * rt];
+            }
         if (!pencil_vectors(me, Gp, Fp, k, true, Ytc, th_l)) return out;
     }
-    const int kr = mr > 0 ? (int)(Yc.size() / mr) : 0;
+    const int kr = r > 0 ? (int)(Yc.size() / r) : 0;
     const int kl = me > 0 ? (int)(Ytc.size() / me) : 0;
     const int kout = std::min(kr, kl);
     out.m_eff = me;
-    if (kout > 0) {
-        out.Y = back_to_w(m, mr, kout, Yc, bw, Gw);
-        out.Yt = back_to_w(m, me, kout, Ytc, bwt, Gwt);
-        out.theta.assign(th_r.begin(), th_r.begin() + kout);
+    out.Y.assign((size_t)r * kout, 0.0);
+    out.Yt.assign((size_t)rt * kout, 0.0);
+    for (int c = 0; c < kout; ++c) {   // orthonormal bases: unit coefficient vectors
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < r; ++i) a += Yc[i + (size_t)c * r] * Yc[i + (size_t)c * r];
+        for (int i = 0; i < me; ++i) b += Ytc[i + (size_t)c * me] * Ytc[i + (size_t)c * me];
+        a = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
+        b = b > 0 ? 1.0 / std::sqrt(b) : 0.0;
+        for (int i = 0; i < r; ++i) out.Y[i + (size_t)c * r] = Yc[i + (size_t)c * r] * a;
+        for (int i = 0; i < me; ++i) out.Yt[i + (size_t)c * rt] = Ytc[i + (size_t)c * me] * b;
     }
+    if (kout > 0) out.theta.assign(th_r.begin(), th_r.begin() + kout);
     out.kout = kout;
     out.ok = true;
     return out;
+}
+
+int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S) {
+    std::vector<int> perm;
+    std::vector<double> R;
+    const int r = pivoted_cholesky(m, Gram, tol, perm, R);
+    S.assign((size_t)m * r, 0.0);
+    for (int b = 0; b < r; ++b) {        // column b of R^-1 (upper triangular)
+        std::vector<double> e(r, 0.0);
+        e[b] = 1.0;
+        for (int a = r - 1; a >= 0; --a) {
+            double s = e[a];
+            for (int c = a + 1; c < r; ++c) s -= R[a + (size_t)c * r] * e[c];
+            e[a] = s / R[a + (size_t)a * r];
+        }
+        for (int a = 0; a < r; ++a) S[perm[a] + (size_t)b * m] = e[a];
+    }
+    return r;
 }
 
 }  // namespace dense

@@ -35,14 +35,6 @@ bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<do
 void hess_eigvec(int n, const std::vector<double>& Hh, std::complex<double> lam, bool left,
                  std::vector<std::complex<double>>& y);
 
-// Recycle-space update from the Gram matrices of W (current space + Lanczos
-// vectors), Wt (its dual counterpart) and AW (m x m, column-major):
-//   Gw = W^T W, Gwt = Wt^T Wt, F = Wt^T W, G = Wt^T A W, G2 = (AW)^T (AW),
-//   F2 = W^T (AW).
-// Right vectors: harmonic Ritz vectors of A on W for the k smallest |theta|;
-// left vectors: left vectors of the two-sided projection G y = theta F y for
-// its k smallest |theta|.  Outputs Y, Yt (m x kout) with U = W Y and
-// Ut = Wt Yt of unit-norm columns.
 struct RitzResult {
     int kout = 0;
     int m_eff = 0;
@@ -50,8 +42,20 @@ struct RitzResult {
     std::vector<std::complex<double>> theta;
     bool ok = false;
 };
-RitzResult recycle_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
-                        const double* G2, const double* F2, int k);
+
+// Recycle-space update in orthonormal coordinates: Q (n x r) and Qt (n x rt)
+// have orthonormal columns, F = Qt^T Q, G = Qt^T A Q (rt x r), G2 = (AQ)^T AQ
+// and F2 = Q^T AQ (r x r).  Right vectors: harmonic Ritz vectors of A on
+// range(Q) for the k smallest |theta|; left vectors: left vectors of the
+// two-sided projection G y = theta F y for its k smallest |theta|.
+// Y is r x kout, Yt is rt x kout (unit columns); U = Q Y, Ut = Qt Yt.
+RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
+                             const double* F2, int k);
+
+// Orthonormalising factor of a tall block X from its Gram matrix X^T X
+// (m x m): pivoted Cholesky truncated at tol, S = P R^-1 (m x r) so that
+// X S has orthonormal columns (to rounding times cond^2).  Returns r.
+int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S);
 
 // Selection rule shared by the Ritz step: indices of the k finite values of
 // smallest |theta| ordered by (|theta|, Re, Im); a complex pair takes two

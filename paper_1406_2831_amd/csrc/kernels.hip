@@ -234,32 +234,44 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Sell A, const double* __restrict
     }
 }
 
-// Y[:, 0:ko] = X[:, 0:m] S, S (m x ko) column-major; 8 output columns per pass.
+// Y[:, 0:ko] = X[:, 0:m] S, S (m x ko) column-major.  One thread per row
+// accumulates 32 output columns; S is staged through LDS in 64-row tiles.
+constexpr int GC = 32, GR = 64;
+
 __global__ __launch_bounds__(BLOCK) void k_gemm_ts(int64_t n, const double* __restrict__ X, int64_t ldx,
                                                    int m, const double* __restrict__ S, int ko,
                                                    double* __restrict__ Y, int64_t ldy) {
-    extern __shared__ double sS[];   // m x 8
+    __shared__ double sS[GR][GC];
     int64_t r0, r1;
     block_rows(n, r0, r1);
-    for (int c0 = 0; c0 < ko; c0 += 8) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < m * 8; idx += BLOCK) {
-            const int i = idx / 8, c = idx % 8;
-            sS[idx] = (c0 + c < ko) ? S[i + (int64_t)(c0 + c) * m] : 0.0;
-        }
-        __syncthreads();
-        for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
-            double acc[8];
+    for (int c0 = 0; c0 < ko; c0 += GC) {
+        for (int64_t base = r0; base < r1; base += BLOCK) {
+            const int64_t row = base + threadIdx.x;
+            const bool act = row < r1;
+            double acc[GC];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-            for (int i = 0; i < m; ++i) {
-                const double xv = X[row + (int64_t)i * ldx];
+            for (int c = 0; c < GC; ++c) acc[c] = 0.0;
+            for (int i0 = 0; i0 < m; i0 += GR) {
+                __syncthreads();
+                for (int idx = threadIdx.x; idx < GR * GC; idx += BLOCK) {
+                    const int i = idx / GC, c = idx % GC;
+                    sS[i][c] = (i0 + i < m && c0 + c < ko) ? S[(i0 + i) + (int64_t)(c0 + c) * m] : 0.0;
+                }
+                __syncthreads();
+                if (act) {
+                    const int iend = (m - i0) < GR ? (m - i0) : GR;
+                    for (int i = 0; i < iend; ++i) {
+                        const double xv = X[row + (int64_t)(i0 + i) * ldx];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] += xv * sS[i * 8 + c];
+                        for (int c = 0; c < GC; ++c) acc[c] += xv * sS[i][c];
+                    }
+                }
             }
+            if (act) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (c0 + c < ko) Y[row + (int64_t)(c0 + c) * ldy] = acc[c];
+                for (int c = 0; c < GC; ++c)
+                    if (c0 + c < ko) Y[row + (int64_t)(c0 + c) * ldy] = acc[c];
+            }
         }
     }
 }
@@ -1093,8 +1105,7 @@ void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, do
 void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m, const double* S,
                     int ko, double* Y, int64_t ldy) {
     if (ko <= 0) return;
-    const size_t shm = (size_t)(m > 0 ? m : 1) * 8 * sizeof(double);
-    hipLaunchKernelGGL(k_gemm_ts, dim3(stream_grid(n)), dim3(BLOCK), shm, st, n, X, ldx, m, S, ko, Y, ldy);
+    hipLaunchKernelGGL(k_gemm_ts, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, X, ldx, m, S, ko, Y, ldy);
 }
 
 static void gemmt_shape(int64_t n, int mx, int my, int& tiles_y, int& ntiles, int& nchunks,

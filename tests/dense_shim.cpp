@@ -39,13 +39,19 @@ int shim_pivoted_cholesky(int m, const double* G, double tol, int* perm, double*
     return rank;
 }
 
-int shim_recycle_ritz(int m, const double* Gw, const double* Gwt, const double* F, const double* G,
-                      const double* G2, const double* F2, int k, double* Y, double* Yt, double* th_re) {
-    RitzResult r = recycle_ritz(m, Gw, Gwt, F, G, G2, F2, k);
-    if (!r.ok) return -1;
-    std::memcpy(Y, r.Y.data(), sizeof(double) * r.Y.size());
-    std::memcpy(Yt, r.Yt.data(), sizeof(double) * r.Yt.size());
-    for (int i = 0; i < r.kout; ++i) th_re[i] = r.theta[i].real();
-    return r.kout;
+int shim_orth_factor(int m, const double* G, double tol, double* S) {
+    std::vector<double> v;
+    const int r = orth_factor(m, G, tol, v);
+    std::memcpy(S, v.data(), sizeof(double) * v.size());
+    return r;
+}
+
+int shim_recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
+                           const double* F2, int k, double* Y, double* Yt) {
+    RitzResult res = recycle_ritz_orth(r, rt, F, G, G2, F2, k);
+    if (!res.ok) return -1;
+    std::memcpy(Y, res.Y.data(), sizeof(double) * res.Y.size());
+    std::memcpy(Yt, res.Yt.data(), sizeof(double) * res.Yt.size());
+    return res.kout;
 }
 }

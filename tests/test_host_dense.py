@@ -33,7 +33,8 @@ def shim(tmp_path_factory):
     lib.shim_eig.argtypes = [ctypes.c_int, P, P, P]
     lib.shim_pivoted_cholesky.argtypes = [ctypes.c_int, P, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_int), P]
-    lib.shim_recycle_ritz.argtypes = [ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+    lib.shim_orth_factor.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
+    lib.shim_recycle_ritz_orth.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P]
     return lib
 
 
@@ -93,8 +94,33 @@ def test_eigenvalues_match_lapack(shim, n, seed):
     assert np.max(np.abs(got - ref)) < 1e-9 * np.abs(ref).max()
 
 
+def _orth(shim, X, AX=None):
+    """The library's two-pass pivoted Cholesky-QR, applied the way the API does."""
+    for tol in (1e-12, 1e-14):
+        m = X.shape[1]
+        G = _fortran(X.T @ X).ravel(order="F")
+        S = np.zeros(m * m)
+        r = shim.shim_orth_factor(m, _p(G), tol, _p(S))
+        Sm = S[: m * r].reshape(m, r, order="F")
+        X = X @ Sm
+        if AX is not None:
+            AX = AX @ Sm
+    return X, AX
+
+
+def test_orth_factor_orthonormalises(shim):
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((400, 30)) @ np.diag(np.logspace(0, -5, 30))
+    X = np.hstack([X, X[:, :3]])                      # rank deficient
+    Q, _ = _orth(shim, X)
+    assert Q.shape[1] == 30
+    assert np.abs(Q.T @ Q - np.eye(30)).max() < 1e-12
+    assert sla.subspace_angles(Q, X).max() < 1e-8
+
+
 def test_recycle_ritz_vs_oracle(shim):
-    seq = w.seq_2d(nshift=1, nrhs=1)
+    """Orthonormalise + reduced Ritz (the library's path) reproduces the oracle's space."""
+    seq = w.seq_3d(N=12, nshift=1, nrhs=1, k=10)
     A, At = (m.to_scipy() for m in seq.matrix(0))
     n = A.shape[0]
     st = {}
@@ -102,24 +128,25 @@ def test_recycle_ritz_vs_oracle(shim):
     def cyc(V, Vt):
         st["V"], st["Vt"] = V, Vt
 
-    o.rbicg(A, At, o.empty_blocks(n), seq.rhs[0], rtol=1e-8, s=100000, on_cycle=cyc)
+    o.rbicg(A, At, o.empty_blocks(n), seq.rhs[0], rtol=1e-10, s=100000, on_cycle=cyc)
     W, Wt = st["V"], st["Vt"]
-    AW = A @ W
-    m, k = W.shape[1], 8
-    mats = [W.T @ W, Wt.T @ Wt, Wt.T @ W, Wt.T @ AW, AW.T @ AW, W.T @ AW]
-    flat = [_fortran(x).ravel(order="F") for x in mats]
-    Y, Yt, th = np.zeros(m * k), np.zeros(m * k), np.zeros(k)
-    kout = shim.shim_recycle_ritz(m, *[_p(f) for f in flat], k, _p(Y), _p(Yt), _p(th))
+    k = 10
+    Q, AQ = _orth(shim, W, A @ W)
+    Qt, _ = _orth(shim, Wt)
+    r, rt = Q.shape[1], Qt.shape[1]
+    F = _fortran(Qt.T @ Q).ravel(order="F")
+    G = _fortran(Qt.T @ AQ).ravel(order="F")
+    F2 = _fortran(Q.T @ AQ).ravel(order="F")
+    G2 = _fortran(AQ.T @ AQ).ravel(order="F")
+    Y, Yt = np.zeros(r * k), np.zeros(rt * k)
+    kout = shim.shim_recycle_ritz_orth(r, rt, _p(F), _p(G), _p(G2), _p(F2), k, _p(Y), _p(Yt))
     assert kout > 0
-    U = W @ Y[: m * kout].reshape(m, kout, order="F")
-    Ut = Wt @ Yt[: m * kout].reshape(m, kout, order="F")
+    U = Q @ Y[: r * kout].reshape(r, kout, order="F")
+    Ut = Qt @ Yt[: rt * kout].reshape(rt, kout, order="F")
     Uo, Uto, _ = o.recycle_space(A, W, Wt, k)
     assert kout == Uo.shape[1]
-    assert np.allclose(np.linalg.norm(U, axis=0), 1.0, rtol=1e-6)   # normalised through the Gram matrix
-    # same subspaces (near-degenerate boundary values aside: compare the leading half).
-    # The library orthonormalises through Gram matrices (condition number squared),
-    # the oracle through Householder QR, so the angles agree to ~sqrt(eps * cond^2).
+    assert np.allclose(np.linalg.norm(U, axis=0), 1.0, rtol=1e-10)
+    # same subspaces, away from a possible near-tie at the k boundary: the leading half
     h = kout // 2
-    cos_r = sla.svdvals(sla.orth(U[:, :h]).T @ sla.orth(Uo))
-    cos_l = sla.svdvals(sla.orth(Ut[:, :h]).T @ sla.orth(Uto))
-    assert cos_r.min() > 1 - 1e-4 and cos_l.min() > 1 - 1e-4
+    assert sla.subspace_angles(U[:, :h], Uo).max() < 1e-6
+    assert sla.subspace_angles(Ut[:, :h], Uto).max() < 1e-6
