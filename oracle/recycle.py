@@ -139,14 +139,14 @@ def _real_basis(Y: np.ndarray, theta: np.ndarray, picks):
     return cols, vals
 
 
-def harmonic_ritz(A, W: np.ndarray, k: int):
+def harmonic_ritz(A, W: np.ndarray, k: int, Q=None):
     """Harmonic Ritz vectors of A on range(W) for the k smallest-magnitude harmonic Ritz values.
 
     With Q an orthonormal basis of W: solve (AQ)^T (AQ) y = theta (AQ)^T Q y,
     i.e. the residual A Q y - theta Q y is orthogonal to A Q.  Returns
     ``(U, theta)`` with unit-norm columns.
     """
-    Q = _orth(W)
+    Q = _orth(W) if Q is None else Q
     AQ = A @ Q
     theta, Y = sla.eig(AQ.T @ AQ, AQ.T @ Q)
     cols, vals = _real_basis(Y, theta, ritz_select(theta, k))
@@ -161,13 +161,14 @@ def recycle_space(A, W: np.ndarray, Wt: np.ndarray, k: int):
 
     Returns ``(U, Ut, number of products with A)``.
     """
-    U, _ = harmonic_ritz(A, W, k)
-    _, Ut, _, m = two_sided_ritz(A, W, Wt, k)
+    Q = _orth(W)
+    U, _ = harmonic_ritz(A, W, k, Q=Q)
+    _, Ut, _, m = two_sided_ritz(A, W, Wt, k, Q=Q)
     kk = min(U.shape[1], Ut.shape[1])   # conjugate pairs can make the two counts differ by one
     return U[:, :kk], Ut[:, :kk], m
 
 
-def two_sided_ritz(A, W: np.ndarray, Wt: np.ndarray, k: int):
+def two_sided_ritz(A, W: np.ndarray, Wt: np.ndarray, k: int, Q=None):
     """Approximate right/left invariant subspaces for the k smallest-|theta| Ritz values.
 
     Reading of the paper's deferred selection rule (Sections 5 and 6.2 ask
@@ -177,7 +178,7 @@ def two_sided_ritz(A, W: np.ndarray, Wt: np.ndarray, k: int):
     and return ``U = W Y``, ``Ut = Wt Yt`` (columns scaled to unit norm) and
     the selected Ritz values.  ``A W`` is formed with explicit products.
     """
-    Q = _orth(W)
+    Q = _orth(W) if Q is None else Q
     Qt = _orth(Wt)
     m = min(Q.shape[1], Qt.shape[1])
     Q, Qt = Q[:, :m], Qt[:, :m]

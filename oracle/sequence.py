@@ -13,9 +13,10 @@ left Ritz vectors).  Readings: the projection used inside a solve is fixed; the 
 installed (``make_blocks``) after the RBiCG solve ends, and only if that
 solve converged.  Cycle updates combine the space being built with the
 cycle's Lanczos vectors, ``W = [U_new, V_s]``, ``Wt = [Ut_new, Vt_s]``,
-starting from the current space.  ``s=None`` makes the cycle the whole
-RBiCG solve (one update at its end): on these operators short cycles
-discard the small-eigenvalue information (see the design notes).
+starting from the current space.  ``s=None`` uses cycles of ``S_DEFAULT``
+vectors, long enough to hold a whole RBiCG solve on these workloads (one
+update at its end): short cycles discard the small-eigenvalue information
+on these operators (see the design notes).
 """
 from __future__ import annotations
 
@@ -45,6 +46,9 @@ class SequenceResult:
         return int(sum(self.matvecs))
 
 
+S_DEFAULT = 512   # Lanczos vectors kept per cycle (a whole solve at these sizes)
+
+
 def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
                  rtol: float = 1e-8, max_it: int = 20000, systems=None) -> SequenceResult:
     """Solve the systems of ``seq`` (a ``workloads.ShiftedSequence``) in order.
@@ -53,7 +57,7 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
     """
     k = seq.k if k is None else k
     if s is None:
-        s = max_it + 1
+        s = S_DEFAULT
     n = seq.n
     out = SequenceResult()
     U = np.zeros((n, 0))

@@ -23,7 +23,6 @@ using rbs::SolveState;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int NTICKETS = 16;
 constexpr int CHUNK = 8;            // iterations enqueued between status polls
 constexpr int MAX_RESTARTS = 3;
 constexpr double DEFAULT_SECANT = 1e3;
@@ -55,7 +54,7 @@ struct rbs_ctx {
     double *W = nullptr, *Wt = nullptr, *AW = nullptr, *Wtmp = nullptr;
     int64_t ldw = 0;
     double* partials = nullptr;
-    unsigned* tickets = nullptr;
+    double* partials2 = nullptr;
     SolveState* st = nullptr;
     BicgState* bst = nullptr;
     double* dsums = nullptr;
@@ -137,7 +136,7 @@ size_t carve(rbs_ctx* c, char* base) {
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
     c->gpart = cv.take<double>(c->gpart_doubles);
     c->partials = cv.take<double>((size_t)2048 * (2 * rbs::KMAX + 8));
-    c->tickets = cv.take<unsigned>(NTICKETS);
+    c->partials2 = cv.take<double>((size_t)2048 * (2 * rbs::KMAX + 8));
     c->st = cv.take<SolveState>(1);
     c->bst = cv.take<BicgState>(1);
     c->dsums = cv.take<double>(8);
@@ -332,7 +331,6 @@ rbs::SolveBufs solve_bufs(rbs_ctx* c, int k, const double* b, double* xout, cons
     B.rh = c->rh;
     B.state = c->st;
     B.partials = c->partials;
-    B.tickets = c->tickets;
     return B;
 }
 
@@ -378,7 +376,7 @@ int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, cons
             [&]() { return c->hp->solve.done != 0; }, &c->hp->solve, c->st, 128, max_it);
         if (rc) return rc;
         rbs::launch_solve_epilogue(c->stream, B);
-        rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->tickets, c->dsums);
+        rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->dsums);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hp->sums, c->dsums, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -448,7 +446,7 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     B.col0 = c->gen_k;
     B.state = c->bst;
     B.partials = c->partials;
-    B.tickets = c->tickets;
+    B.partials2 = c->partials2;
     return B;
 }
 
@@ -586,7 +584,7 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
         since_flush = 0;
     }
     rbs::launch_bicg_epilogue(c->stream, B);
-    rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->tickets, c->dsums);
+    rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->dsums);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(&c->hp->bicg, c->bst, 128, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->hp->sums, c->dsums, 2 * sizeof(double), hipMemcpyDeviceToHost,

@@ -538,9 +538,19 @@ RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, co
 }
 
 int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S) {
+    // unit-diagonal scaling first, so the rank test sees angles between
+    // columns rather than their lengths (stored Lanczos vectors are raw
+    // residuals whose norms span many orders of magnitude)
+    std::vector<double> d(m), Gs((size_t)m * m);
+    for (int i = 0; i < m; ++i) {
+        const double g = Gram[i + (size_t)i * m];
+        d[i] = g > 0 ? 1.0 / std::sqrt(g) : 0.0;
+    }
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) Gs[i + (size_t)j * m] = d[i] * Gram[i + (size_t)j * m] * d[j];
     std::vector<int> perm;
     std::vector<double> R;
-    const int r = pivoted_cholesky(m, Gram, tol, perm, R);
+    const int r = pivoted_cholesky(m, Gs.data(), tol, perm, R);
     S.assign((size_t)m * r, 0.0);
     for (int b = 0; b < r; ++b) {        // column b of R^-1 (upper triangular)
         std::vector<double> e(r, 0.0);
@@ -550,7 +560,7 @@ int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S) {
             for (int c = a + 1; c < r; ++c) s -= R[a + (size_t)c * r] * e[c];
             e[a] = s / R[a + (size_t)a * r];
         }
-        for (int a = 0; a < r; ++a) S[perm[a] + (size_t)b * m] = e[a];
+        for (int a = 0; a < r; ++a) S[perm[a] + (size_t)b * m] = d[perm[a]] * e[a];
     }
     return r;
 }

@@ -53,8 +53,9 @@ RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, co
                              const double* F2, int k);
 
 // Orthonormalising factor of a tall block X from its Gram matrix X^T X
-// (m x m): pivoted Cholesky truncated at tol, S = P R^-1 (m x r) so that
-// X S has orthonormal columns (to rounding times cond^2).  Returns r.
+// (m x m): columns scaled to unit norm (D), pivoted Cholesky of D G D
+// truncated at tol, S = D P R^-1 (m x r) so that X S has orthonormal
+// columns (to rounding times cond^2).  Returns r.
 int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S);
 
 // Selection rule shared by the Ritz step: indices of the k finite values of

@@ -46,8 +46,7 @@ struct SolveBufs {
     const double* shadow;  // rt_{-1} or nullptr (then r_{-1})
     double *x, *r, *s, *t, *p, *q, *rt0, *rh;
     SolveState* state;
-    double* partials;
-    unsigned* tickets;     // one per kernel kind
+    double* partials;      // per-block partial sums (grid x (2 KMAX + 8))
 };
 void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it);
 void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count);
@@ -71,8 +70,8 @@ struct BicgBufs {
     int64_t ldw;
     int col0;              // first Lanczos column (= recycle dimension of the store)
     BicgState* state;
-    double* partials;
-    unsigned* tickets;
+    double* partials;      // per-block partial sums
+    double* partials2;     // second buffer (the A^T product's sums)
 };
 void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap);
 void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count);
@@ -81,6 +80,6 @@ void launch_bicg_reset_cycle(hipStream_t st, BicgState* state);
 
 // ||b - A x||^2 into state_sums[0], ||b||^2 into state_sums[1]
 void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const double* x,
-                          double* partials, unsigned* ticket, double* out_sums);
+                          double* partials, double* out_sums);
 
 }  // namespace rbs

@@ -1,8 +1,9 @@
 // HIP kernels for gfx950 (MI355X) of the recycling BiCGSTAB library.
 //
 // The per-iteration work of Algorithm 2 (RBiCGSTAB, Section 4) is fused
-// into three row-parallel passes, each ending in one deterministic grid
-// reduction whose last block updates the device-resident scalars:
+// into three row-parallel passes; each writes per-block partial sums and a
+// one-block finalize kernel reduces them in fixed order (run-to-run
+// deterministic) and updates the device-resident scalars:
 //
 //   update : r = s - w t ; x += a p + w s ; p = r + b (p - w q)
 //            sums ||r||^2, (rt0, r), (rh, p), Gh^T p          -> alpha, zeta
@@ -28,10 +29,6 @@ namespace rbs {
 namespace {
 
 enum { S_OK = 0, S_MAXIT = 1, S_BD_RHO = 2, S_BD_ALPHA = 3, S_BD_OMEGA = 4, S_NONFINITE = -5 };
-
-// ticket slots (one per reducing kernel kind; kernels on one stream never overlap)
-enum { T_PRO1 = 0, T_PRO2, T_UPD, T_SPMV1, T_SPMV2, T_RES, T_BPRO1, T_BPRO2, T_BUPD, T_BSPMV,
-       T_BSPMVT, T_BPROJ };
 
 constexpr int MAX_GRID = 2048;
 
@@ -81,34 +78,32 @@ __device__ __forceinline__ void block_sum(const double (&v)[M], int m, double* r
     __syncthreads();
 }
 
-// One-pass grid reduction: block partials, then the last block to arrive sums
-// them in block order (run-to-run deterministic) into tot[] and returns true.
+// Block partial of m (<= M) sums, written to partials[block][0..m) with
+// plain stores; the kernel boundary makes them visible to the finalize
+// kernel, so no device-scope fence (an L2 write-back on this chip) is needed.
 template <int M>
-__device__ bool grid_reduce(const double (&v)[M], int m, double* partials, unsigned* ticket,
-                            double* tot) {
+__device__ __forceinline__ void block_partial(const double (&v)[M], int m, double* partials) {
     __shared__ double red[(BLOCK / WAVE) * M];
-    __shared__ int last;
+    __shared__ double tot[M];
     block_sum<M>(v, m, red, tot);
     if (threadIdx.x < m) partials[(int64_t)blockIdx.x * M + threadIdx.x] = tot[threadIdx.x];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// Finalize side (one block): sum the nb block partials in block order, so
+// the result is the same on every run.
+template <int M>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nb, int m,
+                                                double* tot) {
+    __shared__ double red[(BLOCK / WAVE) * M];
     double acc[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) {
+    for (int b = threadIdx.x; b < nb; b += BLOCK) {
 #pragma unroll
         for (int j = 0; j < M; ++j)
-            if (j < m)
-                acc[j] += __hip_atomic_load(&partials[(int64_t)b * M + j], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+            if (j < m) acc[j] += partials[(int64_t)b * M + j];
     }
     block_sum<M>(acc, m, red, tot);
-    if (threadIdx.x == 0) *ticket = 0u;
-    return true;
 }
 
 __device__ __forceinline__ double sell_row(const Sell& A, int64_t row, const double* __restrict__ x) {
@@ -351,12 +346,14 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tile
 }
 
 // ---------------------------------------------------------------- Algorithm 2 passes
+//
+// Every reducing pass writes one partial row per block; the matching *_fin
+// kernel (a single block) sums them in block order and updates the scalars.
 
 // P1: r_{-1} = b - A x_{-1}; sums ||b||^2, Chat^T r_{-1}, Ccheck^T rt_{-1}
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz, double rtol, int max_it) {
+__global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz) {
     constexpr int M = 2 * K + 1;
-    __shared__ double tot[M];
     const int k = B.k;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
@@ -377,37 +374,32 @@ __global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz, double rto
             }
         }
     }
-    // pack the two k-sized groups contiguously for the reduction
-    double pk[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) pk[j] = 0.0;
-    pk[0] = acc[0];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j < k) {
-            pk[1 + j] = acc[1 + j];
-            pk[1 + k + j] = acc[1 + K + j];
+    block_partial<M>(acc, M, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_pro1_fin(SolveBufs B, int nb, double rtol, int max_it) {
+    constexpr int M = 2 * K + 1;
+    __shared__ double tot[M];
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        SolveState* st = B.state;
+        const double b2 = tot[0];
+        st->bnorm2 = b2;
+        st->tol2 = rtol * rtol * b2;
+        st->done = 0;
+        st->status = S_MAXIT;
+        st->iters_done = 0;
+        st->max_it = max_it;
+        st->k = k;
+        for (int j = 0; j < k; ++j) {
+            st->zeta[j] = tot[1 + j];       // zeta_0 = Chat^T r_{-1}
+            st->gamma[j] = tot[1 + K + j];  // Ccheck^T rt_{-1}
         }
-    }
-    if (grid_reduce<M>(pk, 1 + 2 * k, B.partials, B.tickets + T_PRO1, tot)) {
-        if (threadIdx.x == 0) {
-            SolveState* st = B.state;
-            const double b2 = tot[0];
-            st->bnorm2 = b2;
-            st->tol2 = rtol * rtol * b2;
-            st->done = 0;
-            st->status = S_MAXIT;
-            st->iters_done = 0;
-            st->max_it = max_it;
-            st->k = k;
-            for (int j = 0; j < k; ++j) {
-                st->zeta[j] = tot[1 + j];       // zeta_0 = Chat^T r_{-1}
-                st->gamma[j] = tot[1 + k + j];  // Ccheck^T rt_{-1}
-            }
-            if (!finite(b2)) {
-                st->done = 1;
-                st->status = S_NONFINITE;
-            }
+        if (!finite(b2)) {
+            st->done = 1;
+            st->status = S_NONFINITE;
         }
     }
 }
@@ -417,7 +409,6 @@ __global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz, double rto
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
     constexpr int M = K + 2;
-    __shared__ double tot[M];
     SolveState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -458,27 +449,36 @@ __global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
         for (int j = 0; j < K; ++j)
             if (j < k) acc[2 + j] += B.C[row + (int64_t)j * B.ld] * rtv;
     }
-    if (grid_reduce<M>(acc, 2 + k, B.partials, B.tickets + T_PRO2, tot)) {
-        if (threadIdx.x == 0) {
-            for (int j = 0; j < k; ++j) {
-                st->w[j] = tot[2 + j];
-                st->xc[j] = 0.0;
-            }
-            st->alpha = st->beta = st->omega = 0.0;
-            st->omega_zero = 0;
-            st->iter = 1;
-            st->rr = tot[0];
-            st->rho = tot[1];
-            if (!finite(tot[0]) || !finite(tot[1])) {
-                st->done = 1;
-                st->status = S_NONFINITE;
-            } else if (tot[0] <= st->tol2) {
-                st->done = 1;
-                st->status = S_OK;
-            } else if (tot[1] == 0.0) {
-                st->done = 1;
-                st->status = S_BD_RHO;
-            }
+    block_partial<M>(acc, M, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufs B, int nb) {
+    constexpr int M = K + 2;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < k; ++j) {
+            st->w[j] = tot[2 + j];
+            st->xc[j] = 0.0;
+        }
+        st->alpha = st->beta = st->omega = 0.0;
+        st->omega_zero = 0;
+        st->iter = 1;
+        st->rr = tot[0];
+        st->rho = tot[1];
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            st->done = 1;
+            st->status = S_NONFINITE;
+        } else if (tot[0] <= st->tol2) {
+            st->done = 1;
+            st->status = S_OK;
+        } else if (tot[1] == 0.0) {
+            st->done = 1;
+            st->status = S_BD_RHO;
         }
     }
 }
@@ -487,7 +487,6 @@ __global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
     constexpr int M = K + 3;
-    __shared__ double tot[M];
     SolveState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -511,45 +510,54 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
         for (int j = 0; j < K; ++j)
             if (j < k) acc[3 + j] += B.Gh[row + (int64_t)j * B.ld] * pn;
     }
-    if (grid_reduce<M>(acc, 3 + k, B.partials, B.tickets + T_UPD, tot)) {
-        if (threadIdx.x == 0) {
-            const int i = st->iter;
-            const double rr = tot[0], rho = tot[1];
-            st->rr = rr;
-            if (!finite(rr) || !finite(rho)) {
+    block_partial<M>(acc, M, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufs B, int nb) {
+    constexpr int M = K + 3;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        const int i = st->iter;
+        const double rr = tot[0], rho = tot[1];
+        st->rr = rr;
+        if (!finite(rr) || !finite(rho)) {
+            st->done = 1;
+            st->status = S_NONFINITE;
+            st->iters_done = i - 1;
+        } else if (rr <= st->tol2) {
+            st->done = 1;
+            st->status = S_OK;
+            st->iters_done = i - 1;
+        } else if (st->omega_zero) {
+            st->done = 1;
+            st->status = S_BD_OMEGA;
+            st->iters_done = i - 1;
+        } else if (i > st->max_it) {
+            st->done = 1;
+            st->status = S_MAXIT;
+            st->iters_done = i - 1;
+        } else if (rho == 0.0) {
+            st->done = 1;
+            st->status = S_BD_RHO;
+            st->iters_done = i - 1;
+        } else {
+            double den = tot[2];
+            for (int j = 0; j < k; ++j) {
+                st->zeta[j] = tot[3 + j];
+                den -= st->w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
+            }
+            if (den == 0.0 || !finite(den)) {
                 st->done = 1;
-                st->status = S_NONFINITE;
-                st->iters_done = i - 1;
-            } else if (rr <= st->tol2) {
-                st->done = 1;
-                st->status = S_OK;
-                st->iters_done = i - 1;
-            } else if (st->omega_zero) {
-                st->done = 1;
-                st->status = S_BD_OMEGA;
-                st->iters_done = i - 1;
-            } else if (i > st->max_it) {
-                st->done = 1;
-                st->status = S_MAXIT;
-                st->iters_done = i - 1;
-            } else if (rho == 0.0) {
-                st->done = 1;
-                st->status = S_BD_RHO;
+                st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
                 st->iters_done = i - 1;
             } else {
-                double den = tot[2];
-                for (int j = 0; j < k; ++j) {
-                    st->zeta[j] = tot[3 + j];
-                    den -= st->w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
-                }
-                if (den == 0.0 || !finite(den)) {
-                    st->done = 1;
-                    st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
-                    st->iters_done = i - 1;
-                } else {
-                    st->rho = rho;
-                    st->alpha = rho / den;
-                }
+                st->rho = rho;
+                st->alpha = rho / den;
             }
         }
     }
@@ -559,7 +567,6 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufs B) {
     constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
     SolveState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -584,18 +591,24 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufs B) {
         for (int j = 0; j < K; ++j)
             if (j < k) acc[j] += B.Gh[row + (int64_t)j * B.ld] * sv;
     }
-    if (K > 0 && k > 0) {
-        if (grid_reduce<M>(acc, k, B.partials, B.tickets + T_SPMV1, tot)) {
-            if (threadIdx.x < k) st->gamma[threadIdx.x] = tot[threadIdx.x];
-        }
-    }
+    if (K > 0) block_partial<M>(acc, M, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv1_fin(SolveBufs B, int nb) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x < k) st->gamma[threadIdx.x] = tot[threadIdx.x];
 }
 
 // spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufs B) {
     constexpr int M = 5;
-    __shared__ double tot[M];
     SolveState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -618,26 +631,34 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufs B) {
         acc[3] += rt * tv;
         acc[4] += sv * sv;
     }
-    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_SPMV2, tot)) {
-        if (threadIdx.x == 0) {
-            const double st_ = tot[0], tt = tot[1], rts = tot[2], rtt = tot[3];
-            const double alpha = st->alpha;
-            double omega;
-            if (tt == 0.0) {
-                // (t, t) = 0: accept the half step x + alpha p if ||s|| <= tol
-                // (the next update pass sees r = s and tests it), else breakdown
-                omega = 0.0;
-                st->omega_zero = tot[4] <= st->tol2 ? 0 : 1;
-            } else {
-                omega = st_ / tt;
-                st->omega_zero = omega == 0.0 ? 1 : 0;
-            }
-            st->omega = omega;
-            for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + omega * st->gamma[j];
-            const double rho_new = rts - omega * rtt;   // (rt0, r_i) = (rt0, s) - omega (rt0, t)
-            st->beta = omega != 0.0 ? (rho_new / st->rho) * (alpha / omega) : 0.0;
-            st->iter += 1;
+    block_partial<M>(acc, M, B.partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmv2_fin(SolveBufs B, int nb) {
+    constexpr int M = 5;
+    __shared__ double tot[M];
+    SolveState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        const double st_ = tot[0], tt = tot[1], rts = tot[2], rtt = tot[3];
+        const double alpha = st->alpha;
+        double omega;
+        if (tt == 0.0) {
+            // (t, t) = 0: accept the half step x + alpha p if ||s|| <= tol
+            // (the next update pass sees r = s and tests it), else breakdown
+            omega = 0.0;
+            st->omega_zero = tot[4] <= st->tol2 ? 0 : 1;
+        } else {
+            omega = st_ / tt;
+            st->omega_zero = omega == 0.0 ? 1 : 0;
         }
+        st->omega = omega;
+        for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + omega * st->gamma[j];
+        const double rho_new = rts - omega * rtt;   // (rt0, r_i) = (rt0, s) - omega (rt0, t)
+        st->beta = omega != 0.0 ? (rho_new / st->rho) * (alpha / omega) : 0.0;
+        st->iter += 1;
     }
 }
 
@@ -662,9 +683,7 @@ __global__ __launch_bounds__(BLOCK) void k_epi(SolveBufs B) {
 
 // ||b - A x||^2 and ||b||^2
 __global__ __launch_bounds__(BLOCK) void k_true_res(Sell A, const double* __restrict__ b,
-                                                    const double* __restrict__ x, double* partials,
-                                                    unsigned* ticket, double* out) {
-    __shared__ double tot[2];
+                                                    const double* __restrict__ x, double* partials) {
     int64_t r0, r1;
     block_rows(A.n, r0, r1);
     double acc[2] = {0.0, 0.0};
@@ -674,11 +693,15 @@ __global__ __launch_bounds__(BLOCK) void k_true_res(Sell A, const double* __rest
         acc[0] += rv * rv;
         acc[1] += bv * bv;
     }
-    if (grid_reduce<2>(acc, 2, partials, ticket, tot)) {
-        if (threadIdx.x == 0) {
-            out[0] = tot[0];
-            out[1] = tot[1];
-        }
+    block_partial<2>(acc, 2, partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, int nb, double* out) {
+    __shared__ double tot[2];
+    reduce_partials<2>(partials, nb, 2, tot);
+    if (threadIdx.x == 0) {
+        out[0] = tot[0];
+        out[1] = tot[1];
     }
 }
 
@@ -686,10 +709,8 @@ __global__ __launch_bounds__(BLOCK) void k_true_res(Sell A, const double* __rest
 
 // BP1: r_{-1} = b - A x_{-1}, rt_{-1} = ones; sums ||b||^2, Chat^T r_{-1}, Ccheck^T rt_{-1}
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz, double rtol, int max_it,
-                                                 int store_cap) {
+__global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz) {
     constexpr int M = 2 * K + 1;
-    __shared__ double tot[M];
     const int k = B.k;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
@@ -709,39 +730,36 @@ __global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz, double rto
             }
         }
     }
-    double pk[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) pk[j] = 0.0;
-    pk[0] = acc[0];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j < k) {
-            pk[1 + j] = acc[1 + j];
-            pk[1 + k + j] = acc[1 + K + j];
+    block_partial<M>(acc, M, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bpro1_fin(BicgBufs B, int nb, double rtol, int max_it,
+                                                     int store_cap) {
+    constexpr int M = 2 * K + 1;
+    __shared__ double tot[M];
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        BicgState* st = B.state;
+        const double b2 = tot[0];
+        st->bnorm2 = b2;
+        st->tol2 = rtol * rtol * b2;
+        st->done = 0;
+        st->status = S_MAXIT;
+        st->iters_done = 0;
+        st->max_it = max_it;
+        st->store_cap = store_cap;
+        st->stored = 0;
+        st->cur_slot = -1;
+        st->k = k;
+        for (int j = 0; j < k; ++j) {
+            st->zeta[j] = tot[1 + j];
+            st->zetat[j] = tot[1 + K + j];
         }
-    }
-    if (grid_reduce<M>(pk, 1 + 2 * k, B.partials, B.tickets + T_BPRO1, tot)) {
-        if (threadIdx.x == 0) {
-            BicgState* st = B.state;
-            const double b2 = tot[0];
-            st->bnorm2 = b2;
-            st->tol2 = rtol * rtol * b2;
-            st->done = 0;
-            st->status = S_MAXIT;
-            st->iters_done = 0;
-            st->max_it = max_it;
-            st->store_cap = store_cap;
-            st->stored = 0;
-            st->cur_slot = -1;
-            st->k = k;
-            for (int j = 0; j < k; ++j) {
-                st->zeta[j] = tot[1 + j];
-                st->zetat[j] = tot[1 + k + j];
-            }
-            if (!finite(b2)) {
-                st->done = 1;
-                st->status = S_NONFINITE;
-            }
+        if (!finite(b2)) {
+            st->done = 1;
+            st->status = S_NONFINITE;
         }
     }
 }
@@ -750,7 +768,6 @@ __global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz, double rto
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
     constexpr int M = 2;
-    __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -787,40 +804,47 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
         acc[0] += rv * rv;
         acc[1] += rtv * rv;
     }
-    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_BPRO2, tot)) {
-        if (threadIdx.x == 0) {
-            for (int j = 0; j < k; ++j) st->zc[j] = 0.0;
-            st->alpha = st->beta = 0.0;
-            st->iter = 1;
-            st->stored = 0;
-            st->rr = tot[0];
-            st->rho = tot[1];
-            if (!finite(tot[0]) || !finite(tot[1])) {
-                st->done = 1;
-                st->status = S_NONFINITE;
-            } else if (tot[0] <= st->tol2) {
-                st->done = 1;
-                st->status = S_OK;
-            } else if (tot[1] == 0.0) {
-                st->done = 1;
-                st->status = S_BD_RHO;
-            }
+    block_partial<M>(acc, M, B.partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
+    constexpr int M = 2;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < k; ++j) st->zc[j] = 0.0;
+        st->alpha = st->beta = 0.0;
+        st->iter = 1;
+        st->stored = 0;
+        st->rr = tot[0];
+        st->rho = tot[1];
+        if (!finite(tot[0]) || !finite(tot[1])) {
+            st->done = 1;
+            st->status = S_NONFINITE;
+        } else if (tot[0] <= st->tol2) {
+            st->done = 1;
+            st->status = S_OK;
+        } else if (tot[1] == 0.0) {
+            st->done = 1;
+            st->status = S_BD_RHO;
         }
     }
 }
 
 // BQ1: r -= alpha q; rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt;
-//      store r into the cycle store; sums ||r||^2, (rt, r)
+//      store r, rt into the cycle store; sums ||r||^2, (rt, r)
 __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
     constexpr int M = 2;
-    __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
     const double alpha = st->alpha, beta = st->beta;
     const int slot = st->stored;
     const bool store = slot < st->store_cap;
-    double* wcol = B.W + (int64_t)(B.col0 + slot) * B.ldw;
-    double* wtcol = B.Wt + (int64_t)(B.col0 + slot) * B.ldw;
+    double* wcol = B.W + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
+    double* wtcol = B.Wt + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     double acc[M] = {0.0, 0.0};
@@ -840,32 +864,41 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
         acc[0] += rv * rv;
         acc[1] += rtv * rv;
     }
-    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_BUPD, tot)) {
-        if (threadIdx.x == 0) {
-            const int i = st->iter;
-            const double rr = tot[0], rho = tot[1];
-            st->rr = rr;
-            if (!finite(rr) || !finite(rho)) {
-                st->done = 1;
-                st->status = S_NONFINITE;
-                st->iters_done = i - 1;
-            } else if (rr <= st->tol2) {
-                st->done = 1;
-                st->status = S_OK;
-                st->iters_done = i - 1;
-            } else if (i > st->max_it) {
-                st->done = 1;
-                st->status = S_MAXIT;
-                st->iters_done = i - 1;
-            } else if (rho == 0.0) {
-                st->done = 1;
-                st->status = S_BD_RHO;
-                st->iters_done = i - 1;
-            } else {
-                st->rho = rho;
-                st->cur_slot = store ? slot : -1;
-                if (store) st->stored = slot + 1;
-            }
+    block_partial<M>(acc, M, B.partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_bupdate_fin(BicgBufs B, int nb) {
+    constexpr int M = 2;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        const int i = st->iter;
+        const int slot = st->stored;
+        const bool store = slot < st->store_cap;
+        const double rr = tot[0], rho = tot[1];
+        st->rr = rr;
+        if (!finite(rr) || !finite(rho)) {
+            st->done = 1;
+            st->status = S_NONFINITE;
+            st->iters_done = i - 1;
+        } else if (rr <= st->tol2) {
+            st->done = 1;
+            st->status = S_OK;
+            st->iters_done = i - 1;
+        } else if (i > st->max_it) {
+            st->done = 1;
+            st->status = S_MAXIT;
+            st->iters_done = i - 1;
+        } else if (rho == 0.0) {
+            st->done = 1;
+            st->status = S_BD_RHO;
+            st->iters_done = i - 1;
+        } else {
+            st->rho = rho;
+            st->cur_slot = store ? slot : -1;
+            if (store) st->stored = slot + 1;
         }
     }
 }
@@ -874,7 +907,6 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
     constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -895,18 +927,23 @@ __global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
         for (int j = 0; j < K; ++j)
             if (j < k) acc[j] += B.Chat[row + (int64_t)j * B.ld] * zv;
     }
-    if (K > 0 && k > 0) {
-        if (grid_reduce<M>(acc, k, B.partials, B.tickets + T_BSPMV, tot)) {
-            if (threadIdx.x < k) st->zeta[threadIdx.x] = tot[threadIdx.x];
-        }
-    }
+    if (K > 0) block_partial<M>(acc, M, B.partials);
 }
 
-// BQ2t: zt = A^T pt ; zetat = Ccheck^T zt
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bspmv_fin(BicgBufs B, int nb) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x < B.k) st->zeta[threadIdx.x] = tot[threadIdx.x];
+}
+
+// BQ2t: zt = A^T pt ; zetat = Ccheck^T zt  (partials go to the second half of the buffer)
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bspmvt(BicgBufs B) {
     constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -922,11 +959,17 @@ __global__ __launch_bounds__(BLOCK) void k_bspmvt(BicgBufs B) {
         for (int j = 0; j < K; ++j)
             if (j < k) acc[j] += B.Ccheck[row + (int64_t)j * B.ld] * zv;
     }
-    if (K > 0 && k > 0) {
-        if (grid_reduce<M>(acc, k, B.partials, B.tickets + T_BSPMVT, tot)) {
-            if (threadIdx.x < k) st->zetat[threadIdx.x] = tot[threadIdx.x];
-        }
-    }
+    if (K > 0) block_partial<M>(acc, M, B.partials2);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_bspmvt_fin(BicgBufs B, int nb) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    reduce_partials<M>(B.partials2, nb, M, tot);
+    if (threadIdx.x < B.k) st->zetat[threadIdx.x] = tot[threadIdx.x];
 }
 
 // BQ3: q = z - C zeta ; qt = zt - Ct zetat ; alpha = rho / (pt, q);
@@ -934,7 +977,6 @@ __global__ __launch_bounds__(BLOCK) void k_bspmvt(BicgBufs B) {
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bproj(BicgBufs B) {
     constexpr int M = 4;
-    __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -965,22 +1007,30 @@ __global__ __launch_bounds__(BLOCK) void k_bproj(BicgBufs B) {
         acc[2] += qtv * rv;
         acc[3] += qtv * qv;
     }
-    if (grid_reduce<M>(acc, M, B.partials, B.tickets + T_BPROJ, tot)) {
-        if (threadIdx.x == 0) {
-            const double den = tot[0];
-            if (den == 0.0 || !finite(den)) {
-                st->done = 1;
-                st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
-                st->iters_done = st->iter - 1;
-            } else {
-                const double rho = st->rho;
-                const double a = rho / den;
-                const double rho_new = rho - a * tot[2] - a * tot[1] + a * a * tot[3];
-                st->alpha = a;
-                st->beta = rho_new / rho;
-                for (int j = 0; j < k; ++j) st->zc[j] += a * st->zeta[j];
-                st->iter += 1;
-            }
+    block_partial<M>(acc, M, B.partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_bproj_fin(BicgBufs B, int nb) {
+    constexpr int M = 4;
+    __shared__ double tot[M];
+    BicgState* st = B.state;
+    if (st->done) return;
+    const int k = B.k;
+    reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x == 0) {
+        const double den = tot[0];
+        if (den == 0.0 || !finite(den)) {
+            st->done = 1;
+            st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
+            st->iters_done = st->iter - 1;
+        } else {
+            const double rho = st->rho;
+            const double a = rho / den;
+            const double rho_new = rho - a * tot[2] - a * tot[1] + a * a * tot[3];
+            st->alpha = a;
+            st->beta = rho_new / rho;
+            for (int j = 0; j < k; ++j) st->zc[j] += a * st->zeta[j];
+            st->iter += 1;
         }
     }
 }
@@ -1029,27 +1079,35 @@ void dispatch_k(int k, Args&&... args) {
     else F<64>::run(args...);
 }
 
-#define RBS_LAUNCHER(NAME, KERNEL, BUFS)                                                     \
+#define RBS_LAUNCHER(NAME, KERNEL, BUFS, GRID_IS_ONE)                                      \
     template <int K>                                                                         \
     struct NAME {                                                                            \
         template <typename... A>                                                             \
         static void run(hipStream_t st, int grid, const BUFS& B, A... a) {                   \
-            hipLaunchKernelGGL(KERNEL<K>, dim3(grid), dim3(BLOCK), 0, st, B, a...);          \
+            hipLaunchKernelGGL(KERNEL<K>, dim3(GRID_IS_ONE ? 1 : grid), dim3(BLOCK), 0, st, B, \
+                               a...);                                                        \
         }                                                                                    \
     };
 
-RBS_LAUNCHER(L_pro1, k_pro1, SolveBufs)
-RBS_LAUNCHER(L_pro2, k_pro2, SolveBufs)
-RBS_LAUNCHER(L_update, k_update, SolveBufs)
-RBS_LAUNCHER(L_spmv1, k_spmv1, SolveBufs)
-RBS_LAUNCHER(L_spmv2, k_spmv2, SolveBufs)
-RBS_LAUNCHER(L_epi, k_epi, SolveBufs)
-RBS_LAUNCHER(L_bpro1, k_bpro1, BicgBufs)
-RBS_LAUNCHER(L_bpro2, k_bpro2, BicgBufs)
-RBS_LAUNCHER(L_bspmv, k_bspmv, BicgBufs)
-RBS_LAUNCHER(L_bspmvt, k_bspmvt, BicgBufs)
-RBS_LAUNCHER(L_bproj, k_bproj, BicgBufs)
-RBS_LAUNCHER(L_bepi, k_bepi, BicgBufs)
+RBS_LAUNCHER(L_pro1, k_pro1, SolveBufs, false)
+RBS_LAUNCHER(L_pro1_fin, k_pro1_fin, SolveBufs, true)
+RBS_LAUNCHER(L_pro2, k_pro2, SolveBufs, false)
+RBS_LAUNCHER(L_pro2_fin, k_pro2_fin, SolveBufs, true)
+RBS_LAUNCHER(L_update, k_update, SolveBufs, false)
+RBS_LAUNCHER(L_update_fin, k_update_fin, SolveBufs, true)
+RBS_LAUNCHER(L_spmv1, k_spmv1, SolveBufs, false)
+RBS_LAUNCHER(L_spmv1_fin, k_spmv1_fin, SolveBufs, true)
+RBS_LAUNCHER(L_spmv2, k_spmv2, SolveBufs, false)
+RBS_LAUNCHER(L_epi, k_epi, SolveBufs, false)
+RBS_LAUNCHER(L_bpro1, k_bpro1, BicgBufs, false)
+RBS_LAUNCHER(L_bpro1_fin, k_bpro1_fin, BicgBufs, true)
+RBS_LAUNCHER(L_bpro2, k_bpro2, BicgBufs, false)
+RBS_LAUNCHER(L_bspmv, k_bspmv, BicgBufs, false)
+RBS_LAUNCHER(L_bspmv_fin, k_bspmv_fin, BicgBufs, true)
+RBS_LAUNCHER(L_bspmvt, k_bspmvt, BicgBufs, false)
+RBS_LAUNCHER(L_bspmvt_fin, k_bspmvt_fin, BicgBufs, true)
+RBS_LAUNCHER(L_bproj, k_bproj, BicgBufs, false)
+RBS_LAUNCHER(L_bepi, k_bepi, BicgBufs, false)
 
 }  // namespace
 
@@ -1149,8 +1207,10 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
 
 void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it) {
     const int g = stream_grid(B.n);
-    dispatch_k<L_pro1>(B.k, st, g, B, x_nonzero, rtol, max_it);
+    dispatch_k<L_pro1>(B.k, st, g, B, x_nonzero);
+    dispatch_k<L_pro1_fin>(B.k, st, g, B, g, rtol, max_it);
     dispatch_k<L_pro2>(B.k, st, g, B, x_nonzero);
+    dispatch_k<L_pro2_fin>(B.k, st, g, B, g);
     launch_spmv(st, B.At, B.rt0, B.rh);   // rh = A^T rt_0
 }
 
@@ -1158,8 +1218,11 @@ void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
         dispatch_k<L_update>(B.k, st, g, B);
+        dispatch_k<L_update_fin>(B.k, st, g, B, g);
         dispatch_k<L_spmv1>(B.k, st, g, B);
+        if (B.k > 0) dispatch_k<L_spmv1_fin>(B.k, st, g, B, g);
         dispatch_k<L_spmv2>(B.k, st, g, B);
+        hipLaunchKernelGGL(k_spmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
     }
 }
 
@@ -1169,10 +1232,18 @@ void launch_time_prep(hipStream_t st, SolveState* state) {
 
 void launch_pass(hipStream_t st, const SolveBufs& B, int which) {
     const int g = stream_grid(B.n);
-    if (which == 0) dispatch_k<L_update>(B.k, st, g, B);
-    else if (which == 1) dispatch_k<L_spmv1>(B.k, st, g, B);
-    else if (which == 2) dispatch_k<L_spmv2>(B.k, st, g, B);
-    else launch_spmv(st, B.A, B.p, B.q);
+    if (which == 0) {
+        dispatch_k<L_update>(B.k, st, g, B);
+        dispatch_k<L_update_fin>(B.k, st, g, B, g);
+    } else if (which == 1) {
+        dispatch_k<L_spmv1>(B.k, st, g, B);
+        if (B.k > 0) dispatch_k<L_spmv1_fin>(B.k, st, g, B, g);
+    } else if (which == 2) {
+        dispatch_k<L_spmv2>(B.k, st, g, B);
+        hipLaunchKernelGGL(k_spmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
+    } else {
+        launch_spmv(st, B.A, B.p, B.q);
+    }
 }
 
 void launch_solve_epilogue(hipStream_t st, const SolveBufs& B) {
@@ -1180,24 +1251,33 @@ void launch_solve_epilogue(hipStream_t st, const SolveBufs& B) {
 }
 
 void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const double* x,
-                          double* partials, unsigned* ticket, double* out_sums) {
-    hipLaunchKernelGGL(k_true_res, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, b, x, partials,
-                       ticket + T_RES, out_sums);
+                          double* partials, double* out_sums) {
+    const int g = stream_grid(A.n);
+    hipLaunchKernelGGL(k_true_res, dim3(g), dim3(BLOCK), 0, st, A, b, x, partials);
+    hipLaunchKernelGGL(k_true_res_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sums);
 }
 
 void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap) {
     const int g = stream_grid(B.n);
-    dispatch_k<L_bpro1>(B.k, st, g, B, 0, rtol, max_it, store_cap);
+    dispatch_k<L_bpro1>(B.k, st, g, B, 0);
+    dispatch_k<L_bpro1_fin>(B.k, st, g, B, g, rtol, max_it, store_cap);
     dispatch_k<L_bpro2>(B.k, st, g, B, 0);
+    hipLaunchKernelGGL(k_bpro2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
 }
 
 void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
         hipLaunchKernelGGL(k_bupdate, dim3(g), dim3(BLOCK), 0, st, B);
+        hipLaunchKernelGGL(k_bupdate_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
         dispatch_k<L_bspmv>(B.k, st, g, B);
         dispatch_k<L_bspmvt>(B.k, st, g, B);
+        if (B.k > 0) {
+            dispatch_k<L_bspmv_fin>(B.k, st, g, B, g);
+            dispatch_k<L_bspmvt_fin>(B.k, st, g, B, g);
+        }
         dispatch_k<L_bproj>(B.k, st, g, B);
+        hipLaunchKernelGGL(k_bproj_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
     }
 }
 

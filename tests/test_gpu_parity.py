@@ -246,3 +246,33 @@ def test_full_size_3d_solve(rb, torch_mod):
         assert _rel(x, xo) <= 1e-6
     assert res.solver == ["rbicg", "rbicgstab"] and res.k_used[1] > 0
     gs.close()
+
+
+def test_generated_space_matches_oracle(rb, torch_mod):
+    """RBiCG on the GPU + its recycle update (Lanczos store, orthonormalisation,
+    harmonic / two-sided Ritz) spans the oracle's space: principal angles ~ 0."""
+    from paper_1406_2831_amd.sequence import max_row_nnz
+    seq = w.seq_2d(nshift=1, nrhs=1)
+    A, At = seq.matrix(0)
+    As, Ats = A.to_scipy(), At.to_scipy()
+    _say("generated space vs oracle (2d)")
+    ctx = rb.Context(A.n, max_row_nnz(A, At), 8, 256, secant_max=1e30)
+    ctx.setup(A, At)
+    x, st = _solve(ctx, torch_mod, seq.rhs[0], mode="rbicg")
+    assert st.status == 0 and st.ritz_updates == 1
+    ctx.recycle("from_last_solve")
+    bl, k = ctx.blocks()
+    st_ = {}
+
+    def cyc(V, Vt):
+        st_["V"], st_["Vt"] = V, Vt
+
+    xo, _, io = o.rbicg(As, Ats, o.empty_blocks(A.n), seq.rhs[0], rtol=1e-10, s=100000, on_cycle=cyc)
+    assert abs(st.iters - io.iters) <= 2
+    Uo, Uto, _ = o.recycle_space(As, st_["V"], st_["Vt"], 8)
+    blo = o.make_blocks(As, Ats, Uo, Uto, secant_max=1e30)
+    assert k == blo.k
+    U, Ut = bl["U"].cpu().numpy().T, bl["Ut"].cpu().numpy().T
+    assert sla.subspace_angles(U, blo.U).max() < 1e-6
+    assert sla.subspace_angles(Ut, blo.Ut).max() < 1e-6
+    ctx.close()

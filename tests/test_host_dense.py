@@ -110,7 +110,8 @@ def _orth(shim, X, AX=None):
 
 def test_orth_factor_orthonormalises(shim):
     rng = np.random.default_rng(7)
-    X = rng.standard_normal((400, 30)) @ np.diag(np.logspace(0, -5, 30))
+    # column norms over ten orders of magnitude, like raw residual vectors
+    X = rng.standard_normal((400, 30)) @ np.diag(np.logspace(0, -10, 30))
     X = np.hstack([X, X[:, :3]])                      # rank deficient
     Q, _ = _orth(shim, X)
     assert Q.shape[1] == 30
@@ -130,6 +131,9 @@ def test_recycle_ritz_vs_oracle(shim):
 
     o.rbicg(A, At, o.empty_blocks(n), seq.rhs[0], rtol=1e-10, s=100000, on_cycle=cyc)
     W, Wt = st["V"], st["Vt"]
+    # the library stores raw residuals: rescale the columns like them
+    scale = np.logspace(0, -9, W.shape[1])
+    W, Wt = W * scale, Wt * scale[::-1]
     k = 10
     Q, AQ = _orth(shim, W, A @ W)
     Qt, _ = _orth(shim, Wt)
