@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--cpu-systems", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-reps", type=int, default=100)
+    ap.add_argument("--secant-max", type=float, default=0.0,
+                    help="oblique-projector cap of the recycle setup (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
@@ -67,7 +69,7 @@ def main():
     from paper_1406_2831_amd.sequence import GpuSequence
 
     seq = w.seq_3d(N=args.grid, k=args.k)
-    gs = GpuSequence(seq, s_max=512)
+    gs = GpuSequence(seq, s_max=512, secant_max=args.secant_max)
     nsys = seq.num_systems
 
     def run(mode):

@@ -112,7 +112,7 @@ size_t rbicgstab_workspace_bytes(int64_t n, int32_t max_row_nnz, int32_t k_max, 
  * A and A^T (rowptr/colidx/val and rowptrT/colidxT/valT, device, CSR as above)
  * are read during this call only: the library keeps its own sliced copy.
  * n, max_row_nnz, k_max and s_max must match the values used for the workspace.
- * secant_max <= 0 selects the default (1e3).
+ * secant_max <= 0 selects the default (1e2).
  */
 int rbicgstab_setup(rbs_ctx** ctx, int64_t n, int64_t nnz,
                     const int32_t* rowptr, const int32_t* colidx, const double* val,

@@ -58,7 +58,7 @@ def empty_blocks(n: int) -> Blocks:
 
 
 def make_blocks(A, At, U: np.ndarray, Ut: np.ndarray, drop: float = 1e-12,
-                secant_max: float = 1e3) -> Blocks:
+                secant_max: float = 1e2) -> Blocks:
     """Algorithm 2 step 1 with the bi-orthogonalisation reading described above."""
     n = A.shape[0]
     if U.shape[1] == 0:

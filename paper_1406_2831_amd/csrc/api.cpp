@@ -25,7 +25,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int CHUNK = 8;            // iterations enqueued between status polls
 constexpr int MAX_RESTARTS = 3;
-constexpr double DEFAULT_SECANT = 1e3;
+constexpr double DEFAULT_SECANT = 1e2;
 constexpr double DROP_REL = 1e-12;
 
 struct PinnedStatus {
@@ -135,8 +135,8 @@ size_t carve(rbs_ctx* c, char* base) {
     c->gpart_doubles = std::max(rbs::gemmt_partial_doubles(c->n, (int)mmax, (int)(2 * mmax)),
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
     c->gpart = cv.take<double>(c->gpart_doubles);
-    c->partials = cv.take<double>((size_t)2048 * (2 * rbs::KMAX + 8));
-    c->partials2 = cv.take<double>((size_t)2048 * (2 * rbs::KMAX + 8));
+    c->partials = cv.take<double>((size_t)1024 * (2 * rbs::KMAX + 8));
+    c->partials2 = cv.take<double>((size_t)1024 * (2 * rbs::KMAX + 8));
     c->st = cv.take<SolveState>(1);
     c->bst = cv.take<BicgState>(1);
     c->dsums = cv.take<double>(8);

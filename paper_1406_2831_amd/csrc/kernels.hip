@@ -30,7 +30,8 @@ namespace {
 
 enum { S_OK = 0, S_MAXIT = 1, S_BD_RHO = 2, S_BD_ALPHA = 3, S_BD_OMEGA = 4, S_NONFINITE = -5 };
 
-constexpr int MAX_GRID = 2048;
+constexpr int MAX_GRID = 1024;   // streaming-kernel grid cap (rows per thread grow past it)
+
 
 __device__ __forceinline__ int logical_block() {
     // Blocks are dispatched round-robin over the 8 XCDs; remap so that each
@@ -95,27 +96,71 @@ template <int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nb, int m,
                                                 double* tot) {
     __shared__ double red[(BLOCK / WAVE) * M];
+    constexpr int RPT = MAX_GRID / BLOCK;
     double acc[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BLOCK) {
+    if constexpr (M <= 24) {
+        // all of a thread's partial rows are requested before any is summed
+        // (one memory round trip), then added in block order
+        double v[RPT][M];
 #pragma unroll
-        for (int j = 0; j < M; ++j)
-            if (j < m) acc[j] += partials[(int64_t)b * M + j];
+        for (int q = 0; q < RPT; ++q) {
+            const int b = threadIdx.x + q * BLOCK;
+#pragma unroll
+            for (int j = 0; j < M; ++j) v[q][j] = (b < nb && j < m) ? partials[(int64_t)b * M + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int j = 0; j < M; ++j) acc[j] += v[q][j];
+    } else {
+        for (int b = threadIdx.x; b < nb; b += BLOCK) {
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j < m) acc[j] += partials[(int64_t)b * M + j];
+        }
     }
     block_sum<M>(acc, m, red, tot);
 }
 
+// Row product of the sliced matrix.  Entries are fetched eight at a time
+// with clamped (always valid) indices and zero weights past the slice
+// width, so a wave has eight index/value loads and then eight gathers in
+// flight instead of one dependent chain per entry.
+constexpr int SPMV_BATCH = 8;
+
 __device__ __forceinline__ double sell_row(const Sell& A, int64_t row, const double* __restrict__ x) {
     const int64_t s = row / WAVE;
     const int lane = (int)(row & (WAVE - 1));
-    const int32_t beg = A.slice_ptr[s], end = A.slice_ptr[s + 1];
+    const int32_t beg = A.slice_ptr[s];
+    const int w = (A.slice_ptr[s + 1] - beg) / WAVE;
     double acc = 0.0;
-    for (int32_t e = beg + lane; e < end; e += WAVE) acc += A.val[e] * x[A.col[e]];
+    for (int j0 = 0; j0 < w; j0 += SPMV_BATCH) {
+        int32_t c[SPMV_BATCH];
+        double v[SPMV_BATCH];
+#pragma unroll
+        for (int u = 0; u < SPMV_BATCH; ++u) {
+            const int j = (j0 + u < w) ? j0 + u : w - 1;
+            const int32_t e = beg + j * WAVE + lane;
+            c[u] = A.col[e];
+            v[u] = (j0 + u < w) ? A.val[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SPMV_BATCH; ++u) acc += v[u] * x[c[u]];
+    }
     return acc;
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Offset of block column j for a kernel compiled for K >= k columns.  Past
+// the live k columns the index is clamped to column k-1 (a cached re-read)
+// and the caller's coefficient for that column is zero, so the column loop
+// has no branches and all its loads can be in flight together.
+__device__ __forceinline__ int64_t col_off(int j, int k, int64_t ld) {
+    return (int64_t)(j < k ? j : k - 1) * ld;
+}
 
 // ---------------------------------------------------------------- sliced ELL build
 
@@ -279,11 +324,12 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_tile(int64_t n, const double* _
                                                       int64_t ldx, int mx, const double* __restrict__ Y1,
                                                       int64_t ldy1, int my1, const double* __restrict__ Y2,
                                                       int64_t ldy2, int my2, int tiles_y, int64_t rows_per_chunk,
-                                                      double* __restrict__ partial) {
+                                                      int symmetric, double* __restrict__ partial) {
     __shared__ double sx[GS][GT + 1];
     __shared__ double sy[GS][GT + 1];
     const int tile = blockIdx.x;
     const int tx = tile / tiles_y, ty = tile % tiles_y;
+    if (symmetric && tx > ty) return;   // X^T X: the reduce kernel mirrors the upper tiles
     const int my = my1 + my2;
     const int64_t c0 = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t c1 = (c0 + rows_per_chunk < n) ? c0 + rows_per_chunk : n;
@@ -333,11 +379,17 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_tile(int64_t n, const double* _
 }
 
 __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tiles_y, int ntiles,
-                                                        int nchunks, const double* __restrict__ partial,
+                                                        int nchunks, int symmetric,
+                                                        const double* __restrict__ partial,
                                                         double* __restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= (int64_t)mx * my) return;
-    const int i = (int)(idx % mx), j = (int)(idx / mx);   // out column-major (ld = mx)
+    int i = (int)(idx % mx), j = (int)(idx / mx);   // out column-major (ld = mx)
+    if (symmetric && i / GT > j / GT) {
+        const int t = i;
+        i = j;
+        j = t;
+    }
     const int tile = (i / GT) * tiles_y + (j / GT);
     const int off = (i % GT) * GT + (j % GT);
     double s = 0.0;
@@ -368,10 +420,9 @@ __global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz) {
         acc[0] += bv * bv;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (j < k) {
-                acc[1 + j] += B.Chat[row + (int64_t)j * B.ld] * rm1;
-                acc[1 + K + j] += B.Ccheck[row + (int64_t)j * B.ld] * rtm1;
-            }
+            const int64_t o = row + col_off(j, k, B.ld);
+            acc[1 + j] += B.Chat[o] * rm1;
+            acc[1 + K + j] += B.Ccheck[o] * rtm1;
         }
     }
     block_partial<M>(acc, M, B.partials);
@@ -430,12 +481,10 @@ __global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
         double rtv = B.shadow ? B.shadow[row] : rm1;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (j < k) {
-                const int64_t o = row + (int64_t)j * B.ld;
-                xv += B.U[o] * z0[j];
-                rv -= B.C[o] * z0[j];
-                rtv -= B.Ct[o] * eta[j];
-            }
+            const int64_t o = row + col_off(j, k, B.ld);
+            xv += B.U[o] * z0[j];
+            rv -= B.C[o] * z0[j];
+            rtv -= B.Ct[o] * eta[j];
         }
         B.x[row] = xv;
         B.s[row] = rv;      // the first update pass forms r_0 = s - 0 t
@@ -446,8 +495,7 @@ __global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
         acc[0] += rv * rv;
         acc[1] += rtv * rv;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) acc[2 + j] += B.C[row + (int64_t)j * B.ld] * rtv;
+        for (int j = 0; j < K; ++j) acc[2 + j] += B.C[row + col_off(j, k, B.ld)] * rtv;
     }
     block_partial<M>(acc, M, B.partials);
 }
@@ -507,8 +555,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
         acc[1] += B.rt0[row] * rv;
         acc[2] += B.rh[row] * pn;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) acc[3 + j] += B.Gh[row + (int64_t)j * B.ld] * pn;
+        for (int j = 0; j < K; ++j) acc[3 + j] += B.Gh[row + col_off(j, k, B.ld)] * pn;
     }
     block_partial<M>(acc, M, B.partials);
 }
@@ -582,14 +629,12 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufs B) {
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         double qv = sell_row(B.A, row, B.p);
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) qv -= B.C[row + (int64_t)j * B.ld] * zeta[j];
+        for (int j = 0; j < K; ++j) qv -= B.C[row + col_off(j, k, B.ld)] * zeta[j];
         const double sv = B.r[row] - alpha * qv;
         B.q[row] = qv;
         B.s[row] = sv;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) acc[j] += B.Gh[row + (int64_t)j * B.ld] * sv;
+        for (int j = 0; j < K; ++j) acc[j] += B.Gh[row + col_off(j, k, B.ld)] * sv;
     }
     if (K > 0) block_partial<M>(acc, M, B.partials);
 }
@@ -621,8 +666,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufs B) {
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         double tv = sell_row(B.A, row, B.s);
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) tv -= B.C[row + (int64_t)j * B.ld] * gam[j];
+        for (int j = 0; j < K; ++j) tv -= B.C[row + col_off(j, k, B.ld)] * gam[j];
         B.t[row] = tv;
         const double sv = B.s[row], rt = B.rt0[row];
         acc[0] += sv * tv;
@@ -675,8 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_epi(SolveBufs B) {
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         double xv = B.x[row];
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) xv -= B.U[row + (int64_t)j * B.ld] * xc[j];
+        for (int j = 0; j < K; ++j) xv -= B.U[row + col_off(j, k, B.ld)] * xc[j];
         B.xout[row] = xv;
     }
 }
@@ -724,10 +767,9 @@ __global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz) {
         acc[0] += bv * bv;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (j < k) {
-                acc[1 + j] += B.Chat[row + (int64_t)j * B.ld] * rm1;
-                acc[1 + K + j] += B.Ccheck[row + (int64_t)j * B.ld];   // rt_{-1} = ones
-            }
+            const int64_t o = row + col_off(j, k, B.ld);
+            acc[1 + j] += B.Chat[o] * rm1;
+            acc[1 + K + j] += B.Ccheck[o];   // rt_{-1} = ones
         }
     }
     block_partial<M>(acc, M, B.partials);
@@ -786,12 +828,10 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
         double rtv = 1.0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (j < k) {
-                const int64_t o = row + (int64_t)j * B.ld;
-                xv += B.U[o] * z0[j];
-                rv -= B.C[o] * z0[j];
-                rtv -= B.Ct[o] * zt0[j];
-            }
+            const int64_t o = row + col_off(j, k, B.ld);
+            xv += B.U[o] * z0[j];
+            rv -= B.C[o] * z0[j];
+            rtv -= B.Ct[o] * zt0[j];
         }
         B.x[row] = xv;
         B.r[row] = rv;
@@ -924,8 +964,7 @@ __global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
         if (store) awcol[row] = zv - beta * B.z[row];
         B.z[row] = zv;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) acc[j] += B.Chat[row + (int64_t)j * B.ld] * zv;
+        for (int j = 0; j < K; ++j) acc[j] += B.Chat[row + col_off(j, k, B.ld)] * zv;
     }
     if (K > 0) block_partial<M>(acc, M, B.partials);
 }
@@ -956,8 +995,7 @@ __global__ __launch_bounds__(BLOCK) void k_bspmvt(BicgBufs B) {
         const double zv = sell_row(B.At, row, B.pt);
         B.zt[row] = zv;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) acc[j] += B.Ccheck[row + (int64_t)j * B.ld] * zv;
+        for (int j = 0; j < K; ++j) acc[j] += B.Ccheck[row + col_off(j, k, B.ld)] * zv;
     }
     if (K > 0) block_partial<M>(acc, M, B.partials2);
 }
@@ -993,11 +1031,9 @@ __global__ __launch_bounds__(BLOCK) void k_bproj(BicgBufs B) {
         double qv = B.z[row], qtv = B.zt[row];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            if (j < k) {
-                const int64_t o = row + (int64_t)j * B.ld;
-                qv -= B.C[o] * zeta[j];
-                qtv -= B.Ct[o] * zetat[j];
-            }
+            const int64_t o = row + col_off(j, k, B.ld);
+            qv -= B.C[o] * zeta[j];
+            qtv -= B.Ct[o] * zetat[j];
         }
         B.q[row] = qv;
         B.qt[row] = qtv;
@@ -1047,8 +1083,7 @@ __global__ __launch_bounds__(BLOCK) void k_bepi(BicgBufs B) {
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         double xv = B.x[row];
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j < k) xv -= B.U[row + (int64_t)j * B.ld] * zc[j];
+        for (int j = 0; j < K; ++j) xv -= B.U[row + col_off(j, k, B.ld)] * zc[j];
         B.xout[row] = xv;
     }
 }
@@ -1068,14 +1103,22 @@ __global__ void k_time_prep(SolveState* st) {
 }
 
 // compile-time recycle-dimension buckets
+// compile-time recycle-dimension buckets (kernels read K >= k columns, the
+// surplus as cached duplicates of the last one)
 template <template <int> class F, typename... Args>
 void dispatch_k(int k, Args&&... args) {
     if (k <= 0) F<0>::run(args...);
+    else if (k <= 4) F<4>::run(args...);
     else if (k <= 8) F<8>::run(args...);
+    else if (k <= 12) F<12>::run(args...);
     else if (k <= 16) F<16>::run(args...);
+    else if (k <= 20) F<20>::run(args...);
     else if (k <= 24) F<24>::run(args...);
+    else if (k <= 28) F<28>::run(args...);
     else if (k <= 32) F<32>::run(args...);
+    else if (k <= 40) F<40>::run(args...);
     else if (k <= 48) F<48>::run(args...);
+    else if (k <= 56) F<56>::run(args...);
     else F<64>::run(args...);
 }
 
@@ -1198,11 +1241,12 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
     int tiles_y, ntiles, nchunks;
     int64_t rpc;
     gemmt_shape(n, mx, my, tiles_y, ntiles, nchunks, rpc);
+    const int sym = (X == Y1 && my2 == 0 && mx == my1 && ldx == ldy1) ? 1 : 0;
     hipLaunchKernelGGL(k_gemmt_tile, dim3(ntiles, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1, ldy1,
-                       my1, Y2, ldy2, my2, tiles_y, rpc, partial);
+                       my1, Y2, ldy2, my2, tiles_y, rpc, sym, partial);
     const int64_t total = (int64_t)mx * my;
     hipLaunchKernelGGL(k_gemmt_reduce, dim3((unsigned)((total + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
-                       mx, my, tiles_y, ntiles, nchunks, partial, out);
+                       mx, my, tiles_y, ntiles, nchunks, sym, partial, out);
 }
 
 void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it) {
