@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--cpu-systems", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-reps", type=int, default=100)
+    ap.add_argument("--calib-copy-mib", type=int, default=256,
+                    help="size of the known-size copy used to calibrate HBM counters (0: skip)")
     ap.add_argument("--secant-max", type=float, default=0.0,
                     help="oblique-projector cap of the recycle setup (0: library default)")
     args = ap.parse_args()
@@ -144,6 +146,16 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_spmv1, "us_per_launch": ms_spmv1 * 1e3},
     }
+    # a plain device-to-device copy of known size (outside the timed region):
+    # the reference the HBM counters of a profiled run are calibrated with
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * nel * 8
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seq, args.rtol, args.cpu_systems)
     gs.close()

@@ -154,10 +154,11 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
                          double* Chat, double* Ccheck, int32_t* k_used /* host */);
 
 /*
- * Time one of the fused per-iteration passes of Algorithm 2 on the bound
- * matrix with recycle dimension k (0 <= k <= installed k): which = 0 the
- * update pass, 1 the first SpMV + projection pass, 2 the second SpMV +
- * projection pass, 3 a plain SpMV.  The pass is launched `reps` times
+ * Time the main kernel of one of the fused per-iteration passes of
+ * Algorithm 2 on the bound matrix with recycle dimension k (0 <= k <=
+ * installed k): which = 0 the update pass, 1 the first SpMV + projection
+ * pass, 2 the second SpMV + projection pass (their one-block finalize
+ * kernels are not included), 3 a plain SpMV.  The pass is launched `reps` times
  * back to back on the context's stream between two HIP events; *avg_ms
  * receives the mean duration per launch and *bytes the algorithmic bytes
  * one launch moves (CSR: 12 bytes per stored entry + 4 per row pointer;

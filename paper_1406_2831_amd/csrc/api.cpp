@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -76,6 +77,14 @@ struct rbs_ctx {
 namespace {
 
 thread_local std::string g_create_error;
+
+bool trace_enabled() {
+    static const bool on = [] {
+        const char* v = std::getenv("RBS_TRACE");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
 
 int fail(rbs_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -486,6 +495,7 @@ int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
 int ritz_cycle(rbs_ctx* c, int ns) {
     const int m = c->gen_k + ns;
     if (m <= 0) return RBS_OK;
+    const auto t_start = std::chrono::steady_clock::now();
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
     const int r = orth_inplace(c, c->W, c->AW, m);
@@ -509,7 +519,15 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     const double* G = F + (size_t)rt * r;
     const double* F2 = G + (size_t)rt * r;
     const double* G2 = F2 + (size_t)r * r;
+    const auto t_host = std::chrono::steady_clock::now();
     rbs::dense::RitzResult res = rbs::dense::recycle_ritz_orth(r, rt, F, G, G2, F2, c->k_max);
+    if (trace_enabled()) {
+        const auto t_end = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[rbs] ritz m=%d r=%d rt=%d k=%d: device+copies %.2f ms, host eig %.2f ms\n",
+                     m, r, rt, res.kout,
+                     std::chrono::duration<double, std::milli>(t_host - t_start).count(),
+                     std::chrono::duration<double, std::milli>(t_end - t_host).count());
+    }
     if (!res.ok || res.kout == 0) {
         c->gen_k = 0;
         return RBS_OK;

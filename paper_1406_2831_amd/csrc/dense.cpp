@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 namespace rbs {
 namespace dense {
@@ -500,13 +501,17 @@ RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, co
     RitzResult out;
     std::vector<double> Yc, Ytc;
     std::vector<cd> th_r, th_l;
-    if (r > 0) {   // harmonic: (AQ)^T (AQ) y = theta (AQ)^T Q y, with (AQ)^T Q = F2^T
+    bool ok_r = true, ok_l = true;
+    const int me = std::min(r, rt);
+    // the two small eigenproblems are independent: solve them on two threads
+    std::thread right([&]() {
+        if (r == 0) return;
+        // harmonic: (AQ)^T (AQ) y = theta (AQ)^T Q y, with (AQ)^T Q = F2^T
         std::vector<double> A2(G2, G2 + (size_t)r * r), B2((size_t)r * r);
         for (int j = 0; j < r; ++j)
             for (int i = 0; i < r; ++i) B2[i + (size_t)j * r] = F2[j + (size_t)i * r];
-        if (!pencil_vectors(r, A2, B2, k, false, Yc, th_r)) return out;
-    }
-    const int me = std::min(r, rt);
+        ok_r = pencil_vectors(r, A2, B2, k, false, Yc, th_r);
+    });
     if (me > 0) {  // two-sided: G y = theta F y on the leading me x me block
         std::vector<double> Gp((size_t)me * me), Fp((size_t)me * me);
         for (int j = 0; j < me; ++j)
@@ -514,8 +519,10 @@ RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, co
                 Gp[i + (size_t)j * me] = G[i + (size_t)j * rt];
                 Fp[i + (size_t)j * me] = F[i + (size_t)j * rt];
             }
-        if (!pencil_vectors(me, Gp, Fp, k, true, Ytc, th_l)) return out;
+        ok_l = pencil_vectors(me, Gp, Fp, k, true, Ytc, th_l);
     }
+    right.join();
+    if (!ok_r || !ok_l) return out;
     const int kr = r > 0 ? (int)(Yc.size() / r) : 0;
     const int kl = me > 0 ? (int)(Ytc.size() / me) : 0;
     const int kout = std::min(kr, kl);

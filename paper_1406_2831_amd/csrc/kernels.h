@@ -46,14 +46,15 @@ struct SolveBufs {
     const double* shadow;  // rt_{-1} or nullptr (then r_{-1})
     double *x, *r, *s, *t, *p, *q, *rt0, *rh;
     SolveState* state;
-    double* partials;      // per-block partial sums (grid x (2 KMAX + 8))
+    double* partials;      // per-block partial sums, value-major ((2 KMAX + 8) x 1024)
 };
 void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it);
 void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count);
 void launch_solve_epilogue(hipStream_t st, const SolveBufs& B);
 // Timing support: put the solve state in a non-terminating configuration
-// (done = 0, tolerance below zero, fixed bounded scalars) and launch one of
-// the fused passes (0 update, 1 spmv1, 2 spmv2, 3 plain SpMV y = A x).
+// (done = 0, tolerance below zero, fixed bounded scalars) and launch the
+// main kernel of one of the fused passes (0 update, 1 spmv1, 2 spmv2; their
+// one-block finalize kernels are not launched) or 3, a plain SpMV y = A x.
 void launch_time_prep(hipStream_t st, SolveState* state);
 void launch_pass(hipStream_t st, const SolveBufs& B, int which);
 

@@ -79,19 +79,21 @@ __device__ __forceinline__ void block_sum(const double (&v)[M], int m, double* r
     __syncthreads();
 }
 
-// Block partial of m (<= M) sums, written to partials[block][0..m) with
-// plain stores; the kernel boundary makes them visible to the finalize
-// kernel, so no device-scope fence (an L2 write-back on this chip) is needed.
+// Block partial of m (<= M) sums, stored value-major (partials[j][block],
+// row stride MAX_GRID) with plain stores; the kernel boundary makes them
+// visible to the finalize kernel, so no device-scope fence (an L2
+// write-back on this chip) is needed.
 template <int M>
 __device__ __forceinline__ void block_partial(const double (&v)[M], int m, double* partials) {
     __shared__ double red[(BLOCK / WAVE) * M];
     __shared__ double tot[M];
     block_sum<M>(v, m, red, tot);
-    if (threadIdx.x < m) partials[(int64_t)blockIdx.x * M + threadIdx.x] = tot[threadIdx.x];
+    if (threadIdx.x < m) partials[(int64_t)threadIdx.x * MAX_GRID + blockIdx.x] = tot[threadIdx.x];
 }
 
 // Finalize side (one block): sum the nb block partials in block order, so
-// the result is the same on every run.
+// the result is the same on every run.  Consecutive threads read
+// consecutive blocks' partials (coalesced), all rows in one round trip.
 template <int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nb, int m,
                                                 double* tot) {
@@ -99,27 +101,16 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
     constexpr int RPT = MAX_GRID / BLOCK;
     double acc[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    if constexpr (M <= 24) {
-        // all of a thread's partial rows are requested before any is summed
-        // (one memory round trip), then added in block order
-        double v[RPT][M];
+    for (int j = 0; j < M; ++j) {
+        double v[RPT];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int b = threadIdx.x + q * BLOCK;
-#pragma unroll
-            for (int j = 0; j < M; ++j) v[q][j] = (b < nb && j < m) ? partials[(int64_t)b * M + j] : 0.0;
+            v[q] = b < nb ? partials[(int64_t)j * MAX_GRID + b] : 0.0;
         }
+        acc[j] = 0.0;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q)
-#pragma unroll
-            for (int j = 0; j < M; ++j) acc[j] += v[q][j];
-    } else {
-        for (int b = threadIdx.x; b < nb; b += BLOCK) {
-#pragma unroll
-            for (int j = 0; j < M; ++j)
-                if (j < m) acc[j] += partials[(int64_t)b * M + j];
-        }
+        for (int q = 0; q < RPT; ++q) acc[j] += v[q];
     }
     block_sum<M>(acc, m, red, tot);
 }
@@ -1276,18 +1267,10 @@ void launch_time_prep(hipStream_t st, SolveState* state) {
 
 void launch_pass(hipStream_t st, const SolveBufs& B, int which) {
     const int g = stream_grid(B.n);
-    if (which == 0) {
-        dispatch_k<L_update>(B.k, st, g, B);
-        dispatch_k<L_update_fin>(B.k, st, g, B, g);
-    } else if (which == 1) {
-        dispatch_k<L_spmv1>(B.k, st, g, B);
-        if (B.k > 0) dispatch_k<L_spmv1_fin>(B.k, st, g, B, g);
-    } else if (which == 2) {
-        dispatch_k<L_spmv2>(B.k, st, g, B);
-        hipLaunchKernelGGL(k_spmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
-    } else {
-        launch_spmv(st, B.A, B.p, B.q);
-    }
+    if (which == 0) dispatch_k<L_update>(B.k, st, g, B);
+    else if (which == 1) dispatch_k<L_spmv1>(B.k, st, g, B);
+    else if (which == 2) dispatch_k<L_spmv2>(B.k, st, g, B);
+    else launch_spmv(st, B.A, B.p, B.q);
 }
 
 void launch_solve_epilogue(hipStream_t st, const SolveBufs& B) {

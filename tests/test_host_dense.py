@@ -23,7 +23,7 @@ def shim(tmp_path_factory):
     if gxx is None:
         pytest.skip("g++ not available")
     out = str(tmp_path_factory.mktemp("shim") / "libdense_shim.so")
-    cmd = [gxx, "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC,
+    cmd = [gxx, "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-I", CSRC,
            os.path.join(ROOT, "tests", "dense_shim.cpp"), os.path.join(CSRC, "dense.cpp"), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     lib = ctypes.CDLL(out)
