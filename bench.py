@@ -23,6 +23,36 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+K_BUCKETS = (0, 4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64)
+
+
+def k_bucket(k):
+    """Template instantiation (recycle-dimension bucket) the library launches for k."""
+    return next(b for b in K_BUCKETS if b >= k)
+
+
+def counter_traffic(kernel):
+    """Calibrated HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summaries in profiles/, or None when there is no
+    summary for it or the kernel source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1406_2831_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                key, sep, val = line.partition(":")
+                if sep and key.strip() in ("kernel", "kernels_hip_sha256", "fetch_kib_per_dispatch",
+                                           "write_kib_per_dispatch", "fetch_scale", "write_scale"):
+                    kv[key.strip()] = val.strip()
+        if kv.get("kernel") != kernel or kv.get("kernels_hip_sha256") != digest:
+            continue
+        return 1024.0 * (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+                         + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]))
+    return None
 
 
 def cpu_baseline(seq, rtol, systems):
@@ -110,6 +140,8 @@ def main():
     ms_spmv, bytes_spmv = passes["spmv"]
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
     achieved = gbs(bytes_spmv1, ms_spmv1)
+    dom_kernel = f"k_spmv1<{k_bucket(k_last)}>"
+    traffic = counter_traffic(dom_kernel)
 
     out = {
         "metric": "systems solved/s + SpMV HBM GB/s at rel.res 1e-8, RBiCGSTAB vs BiCGSTAB",
@@ -141,9 +173,9 @@ def main():
                    "spmv2_project": {"us": ms_spmv2 * 1e3, "gbs": gbs(bytes_spmv2, ms_spmv2)},
                    "spmv": {"us": ms_spmv * 1e3, "gbs": gbs(bytes_spmv, ms_spmv)},
                    "k": k_last},
-        "roofline": {"bound": "hbm", "kernel": f"k_spmv1<bucket of k={k_last}>",
+        "roofline": {"bound": "hbm", "kernel": dom_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": bytes_spmv1, "us_per_launch": ms_spmv1 * 1e3},
     }
     # a plain device-to-device copy of known size (outside the timed region):

@@ -52,28 +52,29 @@ __device__ __forceinline__ void block_rows(int64_t n, int64_t& r0, int64_t& r1) 
     r1 = s1 * WAVE < n ? s1 * WAVE : n;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
-}
 
 // Sum m (<= M) per-thread values over the block; totals land in tot[0..m).
+// The butterfly steps run over all m values at once, so each step issues m
+// independent cross-lane exchanges and waits once (not once per value).
+// w is consumed (overwritten with the wave sums).
 template <int M>
-__device__ __forceinline__ void block_sum(const double (&v)[M], int m, double* red, double* tot) {
+__device__ __forceinline__ void block_sum(double (&w)[M], int m, double* red, double* tot) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        if (j < m) {
-            const double s = wave_sum(v[j]);
-            if (lane == 0) red[wid * M + j] = s;
-        }
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) w[j] += __shfl_xor(w[j], off, WAVE);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j < m) red[wid * M + j] = w[j];
     }
     __syncthreads();
     if (threadIdx.x < m) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < BLOCK / WAVE; ++w) s += red[w * M + threadIdx.x];
+        for (int q = 0; q < BLOCK / WAVE; ++q) s += red[q * M + threadIdx.x];
         tot[threadIdx.x] = s;
     }
     __syncthreads();
@@ -84,35 +85,48 @@ __device__ __forceinline__ void block_sum(const double (&v)[M], int m, double* r
 // visible to the finalize kernel, so no device-scope fence (an L2
 // write-back on this chip) is needed.
 template <int M>
-__device__ __forceinline__ void block_partial(const double (&v)[M], int m, double* partials) {
+__device__ __forceinline__ void block_partial(double (&v)[M], int m, double* partials) {
     __shared__ double red[(BLOCK / WAVE) * M];
     __shared__ double tot[M];
     block_sum<M>(v, m, red, tot);
     if (threadIdx.x < m) partials[(int64_t)threadIdx.x * MAX_GRID + blockIdx.x] = tot[threadIdx.x];
 }
 
-// Finalize side (one block): sum the nb block partials in block order, so
-// the result is the same on every run.  Consecutive threads read
-// consecutive blocks' partials (coalesced), all rows in one round trip.
+// Finalize side (one block): sum the nb block partials of M values in block
+// order, so the result is the same on every run.  Consecutive threads read
+// consecutive blocks' partials (coalesced).  The loads are unconditional
+// (every row holds MAX_GRID slots) and entries past nb are masked by a
+// select, so a chunk of FIN_CHUNK values costs one memory round trip.
+constexpr int FIN_CHUNK = 16;
+
 template <int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nb, int m,
                                                 double* tot) {
-    __shared__ double red[(BLOCK / WAVE) * M];
     constexpr int RPT = MAX_GRID / BLOCK;
-    double acc[M];
+    constexpr int MC = M < FIN_CHUNK ? M : FIN_CHUNK;
+    __shared__ double red[(BLOCK / WAVE) * MC];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        double v[RPT];
+    for (int c0 = 0; c0 < M; c0 += MC) {
+        double v[MC][RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int b = threadIdx.x + q * BLOCK;
-            v[q] = b < nb ? partials[(int64_t)j * MAX_GRID + b] : 0.0;
+        for (int j = 0; j < MC; ++j) {
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int b = threadIdx.x + q * BLOCK;
+                const double t = c0 + j < M ? partials[(int64_t)(c0 + j) * MAX_GRID + b] : 0.0;
+                v[j][q] = b < nb ? t : 0.0;
+            }
         }
-        acc[j] = 0.0;
+        double acc[MC];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) acc[j] += v[q];
+        for (int j = 0; j < MC; ++j) {
+            acc[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) acc[j] += v[j][q];
+        }
+        const int mc = m - c0 < MC ? m - c0 : MC;
+        block_sum<MC>(acc, mc, red, tot + c0);
     }
-    block_sum<M>(acc, m, red, tot);
 }
 
 // Row product of the sliced matrix.  Entries are fetched eight at a time
