@@ -76,7 +76,10 @@ enum {
     RBS_RBICG_GEN = 2,    /* Algorithm 1 with dual rhs = ones; its Lanczos vectors build the   *
                            * next recycle space (installed by recycle_update FROM_LAST_SOLVE) */
     RBS_TRANSPOSE = 8     /* solve A^T x = b reusing the space with the roles of U and Ut      *
-                           * swapped (OR-ed with RBS_RBICGSTAB or RBS_BICGSTAB)                */
+                           * swapped (OR-ed with RBS_RBICGSTAB or RBS_BICGSTAB): for A^T the   *
+                           * right space is Ut, C' = A^T Ut = Ct, Chat' = Ccheck and          *
+                           * Ccheck' = Chat, so no new setup is needed (one extra block        *
+                           * A Ccheck is formed on the first transposed solve per matrix)      */
 };
 
 /* recycle_update modes */
@@ -132,7 +135,8 @@ int rbicgstab_setup(rbs_ctx** ctx, int64_t n, int64_t nnz,
  *          declared only if the true residual ||b - A x|| <= rtol ||b|| too,
  *          otherwise the solve restarts from x (at most 3 restarts).
  *  max_it  iteration cap per pass.
- *  stats   host, may be NULL.
+ *  stats   host, may be NULL.  With RBS_TRANSPOSE, matvecs_A / matvecs_At
+ *          still count products with A and with A^T respectively.
  * Returns RBS_OK or a numerical outcome (> 0) or an error (< 0).
  */
 int rbicgstab_solve(rbs_ctx* ctx, const double* b, double* x, int32_t x_nonzero,
@@ -167,6 +171,35 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  */
 int rbicgstab_time_pass(rbs_ctx* ctx, int32_t which, int32_t k, int32_t reps, double* avg_ms,
                         double* bytes);
+
+/*
+ * Adjoint gradients for the parametrised matrices A(sigma) = K + sigma M of
+ * Section 6.1 (M diagonal) and a loss L = c^T x with A x = b.  Given x and the
+ * adjoint solution lambda of A^T lambda = c (rbicgstab_solve with
+ * RBS_TRANSPOSE), dL/db = lambda, and this call forms
+ *     grad_val[e] = dL/dA_ij = -lambda_i x_j  for every stored entry e = (i, j)
+ *     *grad_sigma = dL/dsigma = -sum_i lambda_i m_i x_i        (0 if mdiag NULL)
+ * rowptr (n+1) / colidx (nnz): CSR pattern of A (device, int32); lambda, x,
+ * mdiag: device, n; grad_val: device, nnz (the gradient with respect to the
+ * values of K, which share A's pattern); grad_sigma: host, may be NULL.
+ * Uses the context's stream and scratch; returns when done.
+ */
+int rbicgstab_adjoint_grads(rbs_ctx* ctx, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* colidx, const double* lambda, const double* x,
+                            const double* mdiag, double* grad_val, double* grad_sigma);
+
+/*
+ * Values of A(sigma) = K + sigma M on a fixed pattern (Section 6.1's
+ * parametrised family): val = kval, then val[diag_pos[i]] += sigma mdiag[i].
+ * With perm_t non-NULL also valT[e] = val[perm_t[e]] (the values of A^T in
+ * its own CSR order).  kval, val: device, nnz; diag_pos, perm_t: device int64
+ * (n and nnz); mdiag: device, n.  Needs no context (it prepares the values a
+ * later rbicgstab_setup binds); runs on `stream` and returns when done.
+ * Errors are reported through rbicgstab_last_error(NULL).
+ */
+int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const int64_t* diag_pos,
+                             const double* mdiag, double sigma, const int64_t* perm_t, double* val,
+                             double* valT, hipStream_t stream);
 
 /* Matrix-vector products issued by the last setup / recycle_update (host out). */
 int rbicgstab_setup_matvecs(const rbs_ctx* ctx, int32_t* matvecs_A, int32_t* matvecs_At);

@@ -18,18 +18,22 @@ Contents (each function cites the passage of the paper it follows):
                                  harmonic right / two-sided left Ritz vectors.
 * ``sequence.run_sequence``   -- the Section 6.2 driver (RBiCG on a matrix
                                  change, RBiCGSTAB for the other right-hand sides).
+* ``adjoint.adjoint_solve``   -- A^T lambda = c by Algorithm 2 with the swapped
+                                 recycle space; ``adjoint.gradients`` -- dL/db,
+                                 dL/dsigma, dL/dK for A(sigma) = K + sigma M.
 
 Parity status: every function here is pinned by a CPU test (dense LU, SciPy's
-BiCGSTAB, invariants of Theorems 1-2, closed forms); see tests/test_oracle_*.py.
+BiCGSTAB, invariants of Theorems 1-2, closed forms, finite differences of
+dense solves); see tests/test_oracle*.py.
 """
 from .krylov import (OK, MAXIT, BREAKDOWN_RHO, BREAKDOWN_ALPHA, BREAKDOWN_OMEGA,
                      NONFINITE, SolveInfo, bicgstab, rbicgstab, rbicg)
 from .recycle import (Blocks, make_blocks, empty_blocks, two_sided_ritz, harmonic_ritz,
                       recycle_space)
 from .sequence import run_sequence, SequenceResult
+from .adjoint import adjoint_solve, gradients, transposed_blocks
 
 __all__ = ["OK", "MAXIT", "BREAKDOWN_RHO", "BREAKDOWN_ALPHA", "BREAKDOWN_OMEGA",
            "NONFINITE", "SolveInfo", "bicgstab", "rbicgstab", "rbicg", "Blocks",
            "make_blocks", "empty_blocks", "two_sided_ritz", "harmonic_ritz", "recycle_space",
-           "run_sequence",
-           "SequenceResult"]
+           "run_sequence", "SequenceResult", "adjoint_solve", "gradients", "transposed_blocks"]

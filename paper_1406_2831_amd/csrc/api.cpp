@@ -39,6 +39,7 @@ struct PinnedStatus {
 
 struct rbs_ctx {
     int64_t n = 0, n_pad = 0;
+    int64_t ld = 0;   // leading dimension of every n-row block; also the vector stride
     int k_max = 0, s_max = 0, max_row = 0;
     hipStream_t stream = nullptr;
     double secant_max = DEFAULT_SECANT;
@@ -49,6 +50,8 @@ struct rbs_ctx {
     int32_t* widths = nullptr;
     double *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr, *Chat = nullptr,
            *Ccheck = nullptr, *Gh = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;
+    double* GhT = nullptr;   // A Ccheck: the Gh block of the transposed system
+    bool ght_valid = false;
     double *x = nullptr, *r = nullptr, *s = nullptr, *t = nullptr, *p = nullptr, *q = nullptr,
            *rt0 = nullptr, *rh = nullptr, *rt = nullptr, *pt = nullptr, *z = nullptr, *zt = nullptr,
            *qt = nullptr;
@@ -116,8 +119,8 @@ struct Carver {
 // Carve (or, with base == nullptr, size) the workspace of a context.
 size_t carve(rbs_ctx* c, char* base) {
     Carver cv{base};
-    const int64_t n_pad = c->n_pad, nsl = n_pad / rbs::WAVE;
-    const int64_t kb = (int64_t)n_pad * c->k_max;
+    const int64_t n_pad = c->n_pad, nsl = n_pad / rbs::WAVE, ld = c->ld;
+    const int64_t kb = ld * c->k_max;
     for (Sell* m : {&c->A, &c->At}) {
         m->n = c->n;
         m->nslices = nsl;
@@ -127,17 +130,17 @@ size_t carve(rbs_ctx* c, char* base) {
     }
     c->widths = cv.take<int32_t>(nsl);
     double** blocks[] = {&c->U, &c->Ut, &c->C, &c->Ct, &c->Chat, &c->Ccheck, &c->Gh,
-                         &c->T1, &c->T2, &c->T3};
+                         &c->T1, &c->T2, &c->T3, &c->GhT};
     for (double** b : blocks) *b = cv.take<double>(std::max<int64_t>(kb, 1));
     double** vecs[] = {&c->x, &c->r, &c->s, &c->t, &c->p, &c->q, &c->rt0, &c->rh,
                        &c->rt, &c->pt, &c->z, &c->zt, &c->qt};
-    for (double** v : vecs) *v = cv.take<double>(n_pad);
-    c->ldw = n_pad;
+    for (double** v : vecs) *v = cv.take<double>(ld);
+    c->ldw = ld;
     const int64_t wcols = c->s_max > 0 ? c->k_max + c->s_max : 0;
-    c->W = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
-    c->Wt = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
-    c->AW = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
-    c->Wtmp = cv.take<double>(std::max<int64_t>(n_pad * wcols, 1));
+    c->W = cv.take<double>(std::max<int64_t>(ld * wcols, 1));
+    c->Wt = cv.take<double>(std::max<int64_t>(ld * wcols, 1));
+    c->AW = cv.take<double>(std::max<int64_t>(ld * wcols, 1));
+    c->Wtmp = cv.take<double>(std::max<int64_t>(ld * wcols, 1));
     const int64_t mmax = c->k_max + std::max(c->s_max, 0);
     c->dsmall_doubles = (size_t)(6 * mmax * mmax + 4 * mmax * c->k_max + 64);
     c->dsmall = cv.take<double>(c->dsmall_doubles);
@@ -160,6 +163,7 @@ bool args_ok(int64_t n, int32_t max_row, int32_t k_max, int32_t s_max) {
 void size_ctx(rbs_ctx* c, int64_t n, int32_t max_row, int32_t k_max, int32_t s_max) {
     c->n = n;
     c->n_pad = (n + rbs::WAVE - 1) / rbs::WAVE * rbs::WAVE;
+    c->ld = c->n_pad;
     c->k_max = k_max;
     c->s_max = s_max;
     c->max_row = max_row;
@@ -208,9 +212,10 @@ int to_device(rbs_ctx* c, void* d, const void* h, size_t bytes) {
 // SVD bi-orthogonalisation to D_c = I with the drop / secant rule, then
 // Chat = Ct D^-T, Ccheck = C D^-1, and Gh = A^T Chat for the fused iteration.
 int setup_blocks(rbs_ctx* c) {
+    c->ght_valid = false;
     const int k0 = c->k;
     if (k0 == 0) return RBS_OK;
-    const int64_t ld = c->n_pad;
+    const int64_t ld = c->ld;
     hipStream_t s = c->stream;
     rbs::launch_spmm(s, c->A, c->U, ld, c->C, ld, k0);
     rbs::launch_spmm(s, c->At, c->Ut, ld, c->Ct, ld, k0);
@@ -314,19 +319,23 @@ int setup_blocks(rbs_ctx* c) {
     return RBS_OK;
 }
 
-rbs::SolveBufs solve_bufs(rbs_ctx* c, int k, const double* b, double* xout, const double* shadow) {
+// Buffers of one solve.  transpose = true solves A^T x = b with the blocks
+// of A's recycle space swapped (the transposed system's right space is Ut,
+// C' = A^T Ut = Ct, Chat' = Ccheck, Ccheck' = Chat, and Gh' = A Ccheck).
+rbs::SolveBufs solve_bufs(rbs_ctx* c, int k, const double* b, double* xout, const double* shadow,
+                          bool transpose = false) {
     rbs::SolveBufs B;
     B.n = c->n;
-    B.ld = c->n_pad;
+    B.ld = c->ld;
     B.k = k;
-    B.A = c->A;
-    B.At = c->At;
-    B.U = c->U;
-    B.C = c->C;
-    B.Chat = c->Chat;
-    B.Ct = c->Ct;
-    B.Ccheck = c->Ccheck;
-    B.Gh = c->Gh;
+    B.A = transpose ? c->At : c->A;
+    B.At = transpose ? c->A : c->At;
+    B.U = transpose ? c->Ut : c->U;
+    B.C = transpose ? c->Ct : c->C;
+    B.Chat = transpose ? c->Ccheck : c->Chat;
+    B.Ct = transpose ? c->C : c->Ct;
+    B.Ccheck = transpose ? c->Chat : c->Ccheck;
+    B.Gh = transpose ? c->GhT : c->Gh;
     B.b = b;
     B.xout = xout;
     B.shadow = shadow;
@@ -370,10 +379,17 @@ int iterate_until_done(rbs_ctx* c, Enqueue enqueue, Done done, void* hdst, const
 }
 
 int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, const double* shadow,
-                    double rtol, int max_it, rbs_stats* stats) {
-    rbs::SolveBufs B = solve_bufs(c, k, b, x, shadow);
+                    double rtol, int max_it, rbs_stats* stats, bool transpose = false) {
     int status = RBS_MAXIT;
     int total_iters = 0, iters = 0, restarts = 0, mvA = 0, mvAt = 0;
+    if (transpose && k > 0 && !c->ght_valid) {
+        // Gh of the transposed system: (A^T)^T Chat' = A Ccheck, once per matrix
+        rbs::launch_spmm(c->stream, c->A, c->Ccheck, c->ld, c->GhT, c->ld, k);
+        HIPCHK(c, hipGetLastError());
+        c->ght_valid = true;
+        mvAt += k;   // counted in the operator's own column, swapped back below
+    }
+    rbs::SolveBufs B = solve_bufs(c, k, b, x, shadow, transpose);
     double rel_true = NAN, rel_recur = NAN;
     for (int pass = 0; pass <= MAX_RESTARTS; ++pass) {
         const int xz = (xnz || pass > 0) ? 1 : 0;
@@ -385,7 +401,7 @@ int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, cons
             [&]() { return c->hp->solve.done != 0; }, &c->hp->solve, c->st, 128, max_it);
         if (rc) return rc;
         rbs::launch_solve_epilogue(c->stream, B);
-        rbs::launch_true_residual(c->stream, c->A, b, x, c->partials, c->dsums);
+        rbs::launch_true_residual(c->stream, B.A, b, x, c->partials, c->dsums);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hp->sums, c->dsums, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -414,8 +430,9 @@ int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, cons
         stats->iters = iters;
         stats->total_iters = total_iters;
         stats->restarts = restarts;
-        stats->matvecs_A = mvA;
-        stats->matvecs_At = mvAt;
+        // mvA counts products with the solve's operator; report them per matrix
+        stats->matvecs_A = transpose ? mvAt : mvA;
+        stats->matvecs_At = transpose ? mvA : mvAt;
         stats->k_used = k;
         stats->rel_res_recur = rel_recur;
         stats->rel_res_true = rel_true;
@@ -427,7 +444,7 @@ int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, cons
 rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     rbs::BicgBufs B;
     B.n = c->n;
-    B.ld = c->n_pad;
+    B.ld = c->ld;
     B.k = c->k;
     B.A = c->A;
     B.At = c->At;
@@ -538,7 +555,7 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     double* dY = c->dsmall;
     double* dYt = dY + (size_t)r * ko;
     if ((rc = to_device(c, dY, up.data(), up.size() * sizeof(double)))) return rc;
-    const int64_t lb = c->n_pad;
+    const int64_t lb = c->ld;
     rbs::launch_gemm_ts(s, c->n, c->W, ld, r, dY, ko, c->T1, lb);
     rbs::launch_gemm_ts(s, c->n, c->Wt, ld, rt, dYt, ko, c->T2, lb);
     rbs::launch_gemm_ts(s, c->n, c->AW, ld, r, dY, ko, c->T3, lb);
@@ -558,9 +575,9 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
     c->gen_valid = false;
     // the space being built starts from the installed one: W = [U], Wt = [Ut], AW = [C]
     c->gen_k = c->k;
-    if ((rc = copy_cols(c, c->W, c->ldw, c->U, c->n_pad, c->k))) return rc;
-    if ((rc = copy_cols(c, c->Wt, c->ldw, c->Ut, c->n_pad, c->k))) return rc;
-    if ((rc = copy_cols(c, c->AW, c->ldw, c->C, c->n_pad, c->k))) return rc;
+    if ((rc = copy_cols(c, c->W, c->ldw, c->U, c->ld, c->k))) return rc;
+    if ((rc = copy_cols(c, c->Wt, c->ldw, c->Ut, c->ld, c->k))) return rc;
+    if ((rc = copy_cols(c, c->AW, c->ldw, c->C, c->ld, c->k))) return rc;
     rbs::BicgBufs B = bicg_bufs(c, b, x);
     rbs::launch_bicg_prologue(c->stream, B, rtol, max_it, c->s_max);
     int ritz_updates = 0;
@@ -740,13 +757,16 @@ int rbicgstab_solve(rbs_ctx* c, const double* b, double* x, int32_t x_nonzero, c
     if (stats) std::memset(stats, 0, sizeof(*stats));
     int rc;
     const int mode = flags & 3;
-    if (flags & RBS_TRANSPOSE) return fail(c, RBS_ERR_ARG, "RBS_TRANSPOSE is not supported yet");
+    const bool tr = (flags & RBS_TRANSPOSE) != 0;
+    if (flags & ~(3 | RBS_TRANSPOSE)) return fail(c, RBS_ERR_ARG, "unknown solve flags");
+    if (tr && mode == RBS_RBICG_GEN)
+        return fail(c, RBS_ERR_ARG, "RBS_TRANSPOSE applies to RBS_RBICGSTAB and RBS_BICGSTAB only");
     if (mode == RBS_RBICG_GEN)
         rc = solve_rbicg(c, b, x, x_nonzero, shadow, rtol, max_it, stats);
     else if (mode == RBS_BICGSTAB)
-        rc = solve_rbicgstab(c, 0, b, x, x_nonzero, shadow, rtol, max_it, stats);
+        rc = solve_rbicgstab(c, 0, b, x, x_nonzero, shadow, rtol, max_it, stats, tr);
     else if (mode == RBS_RBICGSTAB)
-        rc = solve_rbicgstab(c, c->k, b, x, x_nonzero, shadow, rtol, max_it, stats);
+        rc = solve_rbicgstab(c, c->k, b, x, x_nonzero, shadow, rtol, max_it, stats, tr);
     else
         return fail(c, RBS_ERR_ARG, "unknown solve flags");
     if (stats)
@@ -765,16 +785,16 @@ int recycle_update(rbs_ctx* c, int32_t mode, const double* U, const double* Ut, 
     }
     if (mode == RBS_RECYCLE_SET) {
         if (!U || !Ut || k < 1 || k > c->k_max) return fail(c, RBS_ERR_ARG, "SET needs U, Ut and 1 <= k <= k_max");
-        if ((rc = copy_cols(c, c->U, c->n_pad, U, c->n, k))) return rc;
-        if ((rc = copy_cols(c, c->Ut, c->n_pad, Ut, c->n, k))) return rc;
+        if ((rc = copy_cols(c, c->U, c->ld, U, c->n, k))) return rc;
+        if ((rc = copy_cols(c, c->Ut, c->ld, Ut, c->n, k))) return rc;
         c->k = k;
         return setup_blocks(c);
     }
     if (mode == RBS_RECYCLE_FROM_LAST_SOLVE) {
         if (!c->gen_valid || c->gen_k <= 0) return RBS_OK;
         const int kk = c->gen_k;
-        if ((rc = copy_cols(c, c->U, c->n_pad, c->W, c->ldw, kk))) return rc;
-        if ((rc = copy_cols(c, c->Ut, c->n_pad, c->Wt, c->ldw, kk))) return rc;
+        if ((rc = copy_cols(c, c->U, c->ld, c->W, c->ldw, kk))) return rc;
+        if ((rc = copy_cols(c, c->Ut, c->ld, c->Wt, c->ldw, kk))) return rc;
         c->k = kk;
         c->gen_valid = false;
         return setup_blocks(c);
@@ -790,7 +810,7 @@ int rbicgstab_get_blocks(rbs_ctx* c, double* U, double* Ut, double* C, double* C
         {U, c->U}, {Ut, c->Ut}, {C, c->C}, {Ct, c->Ct}, {Chat, c->Chat}, {Ccheck, c->Ccheck}};
     for (const auto& pr : pairs) {
         if (!pr.first) continue;
-        int rc = copy_cols(c, pr.first, c->n, pr.second, c->n_pad, c->k);
+        int rc = copy_cols(c, pr.first, c->n, pr.second, c->ld, c->k);
         if (rc) return rc;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -834,6 +854,37 @@ int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, doub
         else v = csr + 16.0 * n;
         *bytes = v;
     }
+    return RBS_OK;
+}
+
+int rbicgstab_adjoint_grads(rbs_ctx* c, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                            const double* lambda, const double* x, const double* mdiag,
+                            double* grad_val, double* grad_sigma) {
+    if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
+    if (!c->ws) return fail(c, RBS_ERR_ARG, "context has no workspace");
+    if (nnz < 0 || !rowptr || !colidx || !grad_val || !lambda || !x)
+        return fail(c, RBS_ERR_ARG, "rowptr, colidx, grad_val, lambda and x are required");
+    rbs::launch_adjoint_grads(c->stream, c->n, rowptr, colidx, lambda, x, mdiag, grad_val,
+                              c->partials, c->dsums);
+    HIPCHK(c, hipGetLastError());
+    double gs = 0.0;
+    int rc = to_host(c, &gs, c->dsums, sizeof(double));
+    if (rc) return rc;
+    if (grad_sigma) *grad_sigma = mdiag ? gs : 0.0;
+    return RBS_OK;
+}
+
+int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const int64_t* diag_pos,
+                             const double* mdiag, double sigma, const int64_t* perm_t, double* val,
+                             double* valT, hipStream_t stream) {
+    if (n < 1 || nnz < n || !kval || !diag_pos || !mdiag || !val || (perm_t && !valT) ||
+        !std::isfinite(sigma))
+        return fail(nullptr, RBS_ERR_ARG,
+                    "n >= 1, nnz >= n, kval, diag_pos, mdiag, val (and valT with perm_t) are required");
+    rbs::launch_shifted_values(stream, n, nnz, kval, diag_pos, mdiag, sigma, perm_t, val, valT);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(nullptr, RBS_ERR_HIP, hipGetErrorString(e));
     return RBS_OK;
 }
 

@@ -82,5 +82,14 @@ void launch_bicg_reset_cycle(hipStream_t st, BicgState* state);
 // ||b - A x||^2 into state_sums[0], ||b||^2 into state_sums[1]
 void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const double* x,
                           double* partials, double* out_sums);
+// Adjoint gradients for A(sigma) = K + sigma M: grad[e] = -lam[row(e)] x[col(e)]
+// over the CSR pattern, *out_sigma (device) = -sum_i lam_i m_i x_i (mdiag may be null).
+void launch_adjoint_grads(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colidx,
+                          const double* lam, const double* x, const double* mdiag, double* grad,
+                          double* partials, double* out_sigma);
+// val = kval with sigma * mdiag added on the diagonal entries; valT[e] = val[perm_t[e]].
+void launch_shifted_values(hipStream_t st, int64_t n, int64_t nnz, const double* kval,
+                           const int64_t* diag_pos, const double* mdiag, double sigma,
+                           const int64_t* perm_t, double* val, double* valT);
 
 }  // namespace rbs

@@ -753,6 +753,58 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
     }
 }
 
+// ---------------------------------------------------------------- adjoint support
+// For the parametrised family A(sigma) = K + sigma M (M diagonal; the form of
+// the parametric systems of Section 6.1) and a loss L = c^T x with A x = b:
+// A^T lambda = c gives dL/dA_ij = -lambda_i x_j on the stored entries and
+// dL/dsigma = -sum_i lambda_i m_i x_i.
+
+__global__ __launch_bounds__(BLOCK) void k_adjoint_grads(int64_t n, const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colidx,
+                                                         const double* __restrict__ lam,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ mdiag,
+                                                         double* __restrict__ grad, double* partials) {
+    int64_t r0, r1;
+    block_rows(n, r0, r1);
+    double acc[1] = {0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double l = lam[row];
+        const int32_t e1 = rowptr[row + 1];
+        for (int32_t e = rowptr[row]; e < e1; ++e) grad[e] = -l * x[colidx[e]];
+        if (mdiag) acc[0] += l * mdiag[row] * x[row];
+    }
+    block_partial<1>(acc, 1, partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adjoint_grads_fin(const double* partials, int nb,
+                                                             double* out) {
+    __shared__ double tot[1];
+    reduce_partials<1>(partials, nb, 1, tot);
+    if (threadIdx.x == 0) out[0] = -tot[0];
+}
+
+// val = kval + sigma M on the diagonal entries (diag_pos[i] indexes row i's
+// diagonal in the CSR arrays)
+__global__ __launch_bounds__(BLOCK) void k_shift_diag(int64_t n, const int64_t* __restrict__ diag_pos,
+                                                      const double* __restrict__ kval,
+                                                      const double* __restrict__ mdiag,
+                                                      double sigma, double* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) {
+        const int64_t e = diag_pos[i];
+        val[e] = kval[e] + sigma * mdiag[i];
+    }
+}
+
+// out[e] = in[perm[e]] (values of the transpose from a fixed pattern map)
+__global__ __launch_bounds__(BLOCK) void k_gather(int64_t m, const int64_t* __restrict__ perm,
+                                                  const double* __restrict__ in,
+                                                  double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (e < m) out[e] = in[perm[e]];
+}
+
 // ---------------------------------------------------------------- Algorithm 1 passes
 
 // BP1: r_{-1} = b - A x_{-1}, rt_{-1} = ones; sums ||b||^2, Chat^T r_{-1}, Ccheck^T rt_{-1}
@@ -1296,6 +1348,27 @@ void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const 
     const int g = stream_grid(A.n);
     hipLaunchKernelGGL(k_true_res, dim3(g), dim3(BLOCK), 0, st, A, b, x, partials);
     hipLaunchKernelGGL(k_true_res_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sums);
+}
+
+void launch_adjoint_grads(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colidx,
+                          const double* lam, const double* x, const double* mdiag, double* grad,
+                          double* partials, double* out_sigma) {
+    const int g = stream_grid(n);
+    hipLaunchKernelGGL(k_adjoint_grads, dim3(g), dim3(BLOCK), 0, st, n, rowptr, colidx, lam, x, mdiag,
+                       grad, partials);
+    hipLaunchKernelGGL(k_adjoint_grads_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sigma);
+}
+
+void launch_shifted_values(hipStream_t st, int64_t n, int64_t nnz, const double* kval,
+                           const int64_t* diag_pos, const double* mdiag, double sigma,
+                           const int64_t* perm_t, double* val, double* valT) {
+    if (nnz <= 0) return;
+    hipMemcpyAsync(val, kval, nnz * sizeof(double), hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_shift_diag, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, n,
+                       diag_pos, kval, mdiag, sigma, val);
+    if (perm_t && valT)
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)((nnz + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, nnz,
+                           perm_t, val, valT);
 }
 
 void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap) {

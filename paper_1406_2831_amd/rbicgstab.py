@@ -41,7 +41,8 @@ RBS_RECYCLE_CLEAR = 2
 
 EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "recycle_update",
            "rbicgstab_get_blocks", "rbicgstab_time_pass", "rbicgstab_setup_matvecs",
-           "rbicgstab_destroy", "rbicgstab_last_error")
+           "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_destroy",
+           "rbicgstab_last_error")
 
 
 class Stats(ctypes.Structure):
@@ -82,6 +83,10 @@ def load_library(path: str = LIB_PATH):
     lib.rbicgstab_get_blocks.restype = ctypes.c_int
     lib.rbicgstab_time_pass.argtypes = [vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
     lib.rbicgstab_time_pass.restype = ctypes.c_int
+    lib.rbicgstab_adjoint_grads.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(f64)]
+    lib.rbicgstab_adjoint_grads.restype = ctypes.c_int
+    lib.rbicgstab_shifted_values.argtypes = [i64, i64, vp, vp, vp, f64, vp, vp, vp, vp]
+    lib.rbicgstab_shifted_values.restype = ctypes.c_int
     lib.rbicgstab_setup_matvecs.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.rbicgstab_setup_matvecs.restype = ctypes.c_int
     lib.rbicgstab_destroy.argtypes = [vp]
@@ -174,6 +179,28 @@ def rbicgstab_time_pass(handle, which: int, k: int, reps: int):
     return ms.value, by.value
 
 
+def rbicgstab_adjoint_grads(handle, rowptr: torch.Tensor, colidx: torch.Tensor, lam: torch.Tensor,
+                            x: torch.Tensor, mdiag: Optional[torch.Tensor], grad_val: torch.Tensor):
+    """Fills grad_val (device, nnz) and returns dL/dsigma (host float)."""
+    lib = load_library()
+    gs = ctypes.c_double(0)
+    _check(lib, handle, lib.rbicgstab_adjoint_grads(handle, colidx.numel(), _ptr(rowptr), _ptr(colidx),
+                                                    _ptr(lam), _ptr(x), _ptr(mdiag), _ptr(grad_val),
+                                                    ctypes.byref(gs)))
+    return gs.value
+
+
+def rbicgstab_shifted_values(kval: torch.Tensor, diag_pos: torch.Tensor, mdiag: torch.Tensor,
+                             sigma: float, perm_t: Optional[torch.Tensor], val: torch.Tensor,
+                             valT: Optional[torch.Tensor], stream=None) -> None:
+    """val = kval + sigma * mdiag on the diagonal entries; valT = val[perm_t] (device)."""
+    lib = load_library()
+    _check(lib, None, lib.rbicgstab_shifted_values(mdiag.numel(), kval.numel(), _ptr(kval),
+                                                   _ptr(diag_pos), _ptr(mdiag), float(sigma),
+                                                   _ptr(perm_t), _ptr(val), _ptr(valT),
+                                                   _stream(stream)))
+
+
 def rbicgstab_setup_matvecs(handle):
     lib = load_library()
     a, b = ctypes.c_int32(0), ctypes.c_int32(0)
@@ -223,9 +250,9 @@ class Context:
         return self
 
     def solve(self, b, x=None, x_nonzero=False, shadow=None, rtol=1e-8, max_it=10000,
-              mode: str = "rbicgstab"):
+              mode: str = "rbicgstab", transpose: bool = False):
         flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB,
-                 "rbicg": RBS_RBICG_GEN}[mode]
+                 "rbicg": RBS_RBICG_GEN}[mode] | (RBS_TRANSPOSE if transpose else 0)
         if x is None:
             x = torch.zeros_like(b)
         st = rbicgstab_solve(self.handle, b, x, x_nonzero, shadow, rtol, max_it, flags)
@@ -241,6 +268,13 @@ class Context:
 
     def setup_matvecs(self):
         return rbicgstab_setup_matvecs(self.handle)
+
+    def adjoint_grads(self, rowptr, colidx, lam, x, mdiag=None, grad_val=None):
+        if grad_val is None:
+            grad_val = torch.empty(colidx.numel(), dtype=torch.float64, device=lam.device)
+        gs = rbicgstab_adjoint_grads(self.handle, rowptr, colidx, lam, x, mdiag, grad_val)
+        return grad_val, gs
+
 
     def time_pass(self, which: int, k: int, reps: int = 50):
         return rbicgstab_time_pass(self.handle, which, k, reps)
