@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,7 @@ struct rbs_ctx {
     int32_t* widths = nullptr;
     double *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr, *Chat = nullptr,
            *Ccheck = nullptr, *Gh = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;
+    int ritz_mv = 0;         // products with A spent by Ritz steps of the current RBiCG solve
     double* GhT = nullptr;   // A Ccheck: the Gh block of the transposed system
     bool ght_valid = false;
     double *x = nullptr, *r = nullptr, *s = nullptr, *t = nullptr, *p = nullptr, *q = nullptr,
@@ -467,7 +469,6 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     B.qt = c->qt;
     B.W = c->W;
     B.Wt = c->Wt;
-    B.AW = c->AW;
     B.ldw = c->ldw;
     B.col0 = c->gen_k;
     B.state = c->bst;
@@ -479,6 +480,14 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
 // Orthonormalise the first m columns of X in place (pivoted Cholesky-QR,
 // applied twice), applying the same column transform to AX when given.
 // Returns the numerical rank (columns kept), or < 0 on error.
+// X (n x m, ld = ldw) <- an orthonormal basis of its range, AX <- AX S with
+// the same transform.  Shifted Cholesky QR: a first pass on the column-scaled
+// Gram matrix plus the shift 11 (n m + m (m+1)) u ||D G D|| (||D G D|| <= m)
+// makes X S well conditioned whatever cond(X) is (the stored Lanczos vectors
+// lose bi-orthogonality and are far from orthogonal), and a second, unshifted
+// pass makes it orthonormal.  No direction is dropped except zero columns, so
+// the basis spans the whole stored Krylov space.  Pivoted, truncated Cholesky
+// is the fallback if a pass breaks down.  Returns the rank kept.
 int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
@@ -489,7 +498,11 @@ int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
         int rc = to_host(c, G.data(), dG, G.size() * sizeof(double));
         if (rc) return rc;
         std::vector<double> S;
-        const int r = rbs::dense::orth_factor(m, G.data(), pass == 0 ? 1e-12 : 1e-14, S);
+        const double eps = std::numeric_limits<double>::epsilon();
+        const double shift =
+            pass == 0 ? 11.0 * ((double)c->n * m + (double)m * (m + 1)) * eps * m : 0.0;
+        int r = rbs::dense::orth_factor_chol(m, G.data(), shift, S);
+        if (r < 0) r = rbs::dense::orth_factor(m, G.data(), pass == 0 ? 1e-12 : 1e-14, S);
         if (r == 0) return 0;
         if ((rc = to_device(c, c->dsmall, S.data(), S.size() * sizeof(double)))) return rc;
         rbs::launch_gemm_ts(s, c->n, X, ld, m, c->dsmall, r, c->Wtmp, ld);
@@ -515,6 +528,11 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
+    // A W by explicit products (the Lanczos recurrences give it only up to a
+    // cancellation that grows with ||p|| / ||r||, which perturbs the Ritz
+    // vectors of clustered values)
+    rbs::launch_spmm(s, c->A, c->W, ld, c->AW, ld, m);
+    c->ritz_mv += m;
     const int r = orth_inplace(c, c->W, c->AW, m);
     if (r < 0) return r;
     const int rt = orth_inplace(c, c->Wt, nullptr, m);
@@ -558,10 +576,8 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     const int64_t lb = c->ld;
     rbs::launch_gemm_ts(s, c->n, c->W, ld, r, dY, ko, c->T1, lb);
     rbs::launch_gemm_ts(s, c->n, c->Wt, ld, rt, dYt, ko, c->T2, lb);
-    rbs::launch_gemm_ts(s, c->n, c->AW, ld, r, dY, ko, c->T3, lb);
     if ((rc = copy_cols(c, c->W, ld, c->T1, lb, ko))) return rc;
     if ((rc = copy_cols(c, c->Wt, ld, c->T2, lb, ko))) return rc;
-    if ((rc = copy_cols(c, c->AW, ld, c->T3, lb, ko))) return rc;
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(s));
     c->gen_k = ko;
@@ -573,11 +589,11 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
     if (c->s_max <= 0) return fail(c, RBS_ERR_ARG, "RBS_RBICG_GEN needs s_max > 0");
     int rc;
     c->gen_valid = false;
-    // the space being built starts from the installed one: W = [U], Wt = [Ut], AW = [C]
+    c->ritz_mv = 0;
+    // the space being built starts from the installed one: W = [U], Wt = [Ut]
     c->gen_k = c->k;
     if ((rc = copy_cols(c, c->W, c->ldw, c->U, c->ld, c->k))) return rc;
     if ((rc = copy_cols(c, c->Wt, c->ldw, c->Ut, c->ld, c->k))) return rc;
-    if ((rc = copy_cols(c, c->AW, c->ldw, c->C, c->ld, c->k))) return rc;
     rbs::BicgBufs B = bicg_bufs(c, b, x);
     rbs::launch_bicg_prologue(c->stream, B, rtol, max_it, c->s_max);
     int ritz_updates = 0;
@@ -651,6 +667,7 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
         rel_recur = s2.rel_res_recur;
         if (stats) stats->rel_res_true = s2.rel_res_true;
     }
+    mvA += c->ritz_mv;
     if (stats) {
         stats->status = status;
         stats->iters = iters;

@@ -299,43 +299,53 @@ bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<do
     Hh.assign(H, H + (size_t)n * n);
     Qh.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) Qh[i + (size_t)i * n] = 1.0;
-    auto h = [&](int i, int j) -> double& { return Hh[i + (size_t)j * n]; };
-    auto qq = [&](int i, int j) -> double& { return Qh[i + (size_t)j * n]; };
-    std::vector<double> v(n);
+    double* hp = Hh.data();
+    double* qp = Qh.data();
+    std::vector<double> v(n), w(n), wq(n);
     for (int k = 0; k + 2 < n; ++k) {
-        // Householder vector annihilating h(k+2.., k)
+        // Householder vector v (zero above k+1) annihilating H(k+2.., k)
+        double* hk = hp + (size_t)k * n;
         double alpha = 0.0;
-        for (int i = k + 1; i < n; ++i) alpha += h(i, k) * h(i, k);
+        for (int i = k + 1; i < n; ++i) alpha += hk[i] * hk[i];
         alpha = std::sqrt(alpha);
         if (alpha == 0.0) continue;
-        if (h(k + 1, k) > 0) alpha = -alpha;
-        for (int i = 0; i < n; ++i) v[i] = 0.0;
-        v[k + 1] = h(k + 1, k) - alpha;
-        for (int i = k + 2; i < n; ++i) v[i] = h(i, k);
+        if (hk[k + 1] > 0) alpha = -alpha;
+        v[k + 1] = hk[k + 1] - alpha;
+        for (int i = k + 2; i < n; ++i) v[i] = hk[i];
         double vn = 0.0;
         for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
         if (vn == 0.0) continue;
         const double tau = 2.0 / vn;
-        for (int j = 0; j < n; ++j) {   // H <- (I - tau v v^T) H
+        // H <- (I - tau v v^T) H: one dot and one update per column (contiguous)
+        for (int j = 0; j < n; ++j) {
+            double* hj = hp + (size_t)j * n;
             double s = 0.0;
-            for (int i = k + 1; i < n; ++i) s += v[i] * h(i, j);
+            for (int i = k + 1; i < n; ++i) s += v[i] * hj[i];
             s *= tau;
-            for (int i = k + 1; i < n; ++i) h(i, j) -= s * v[i];
+            for (int i = k + 1; i < n; ++i) hj[i] -= s * v[i];
         }
-        for (int i = 0; i < n; ++i) {   // H <- H (I - tau v v^T), Q <- Q (I - tau v v^T)
-            double s = 0.0, sq = 0.0;
-            for (int j = k + 1; j < n; ++j) {
-                s += h(i, j) * v[j];
-                sq += qq(i, j) * v[j];
-            }
-            s *= tau;
-            sq *= tau;
-            for (int j = k + 1; j < n; ++j) {
-                h(i, j) -= s * v[j];
-                qq(i, j) -= sq * v[j];
+        // H <- H (I - tau v v^T), Q <- Q (I - tau v v^T): w = H v, wq = Q v
+        // accumulated column by column, then rank-one updates of columns k+1..
+        for (int i = 0; i < n; ++i) w[i] = wq[i] = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const double vj = v[j];
+            const double* hj = hp + (size_t)j * n;
+            const double* qj = qp + (size_t)j * n;
+            for (int i = 0; i < n; ++i) {
+                w[i] += hj[i] * vj;
+                wq[i] += qj[i] * vj;
             }
         }
-        for (int i = k + 2; i < n; ++i) h(i, k) = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const double tv = tau * v[j];
+            double* hj = hp + (size_t)j * n;
+            double* qj = qp + (size_t)j * n;
+            for (int i = 0; i < n; ++i) {
+                hj[i] -= w[i] * tv;
+                qj[i] -= wq[i] * tv;
+            }
+        }
+        for (int i = k + 2; i < n; ++i) hk[i] = 0.0;
     }
     return hessenberg_qr(n, Hh, lambda);
 }
@@ -542,6 +552,49 @@ RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, co
     out.kout = kout;
     out.ok = true;
     return out;
+}
+
+int orth_factor_chol(int m, const double* Gram, double shift, std::vector<double>& S) {
+    // columns scaled to unit norm; zero columns are left out (their rows of S
+    // stay zero), the others keep their order
+    std::vector<double> d(m);
+    std::vector<int> idx;
+    for (int i = 0; i < m; ++i) {
+        const double g = Gram[i + (size_t)i * m];
+        if (!std::isfinite(g)) return -1;
+        d[i] = g > 0 ? 1.0 / std::sqrt(g) : 0.0;
+        if (g > 0) idx.push_back(i);
+    }
+    const int r = (int)idx.size();
+    std::vector<double> R((size_t)r * r, 0.0);   // upper triangular, R^T R = D G D + shift I
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i <= j; ++i)
+            R[i + (size_t)j * r] = d[idx[i]] * Gram[idx[i] + (size_t)idx[j] * m] * d[idx[j]] +
+                                   (i == j ? shift : 0.0);
+    for (int j = 0; j < r; ++j) {   // right-looking Cholesky on the upper triangle
+        const double pv = R[j + (size_t)j * r];
+        if (!(pv > 0.0) || !std::isfinite(pv)) return -1;
+        const double rj = std::sqrt(pv);
+        R[j + (size_t)j * r] = rj;
+        for (int c = j + 1; c < r; ++c) R[j + (size_t)c * r] /= rj;
+        for (int c = j + 1; c < r; ++c) {
+            const double a = R[j + (size_t)c * r];
+            for (int i = j + 1; i <= c; ++i) R[i + (size_t)c * r] -= R[j + (size_t)i * r] * a;
+        }
+    }
+    S.assign((size_t)m * r, 0.0);
+    std::vector<double> e(r);
+    for (int b = 0; b < r; ++b) {   // column b of R^-1
+        std::fill(e.begin(), e.end(), 0.0);
+        e[b] = 1.0;
+        for (int a = b; a >= 0; --a) {
+            double s = e[a];
+            for (int c = a + 1; c <= b; ++c) s -= R[a + (size_t)c * r] * e[c];
+            e[a] = s / R[a + (size_t)a * r];
+        }
+        for (int a = 0; a <= b; ++a) S[idx[a] + (size_t)b * m] = d[idx[a]] * e[a];
+    }
+    return r;
 }
 
 int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S) {

@@ -58,6 +58,15 @@ RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, co
 // columns (to rounding times cond^2).  Returns r.
 int orth_factor(int m, const double* Gram, double tol, std::vector<double>& S);
 
+// Orthonormalising factor without pivoting or truncation: columns scaled to
+// unit norm (D), Cholesky R^T R = D G D + shift I, S = D R^-1 (m x r, r the
+// number of nonzero columns, kept in order).  With the shift of shifted
+// Cholesky QR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, 2020) the
+// factorisation succeeds for any conditioning and X S is well conditioned;
+// a second pass with shift 0 then makes it orthonormal.  Returns r, or -1 if
+// the factorisation breaks down (only possible with shift 0).
+int orth_factor_chol(int m, const double* Gram, double shift, std::vector<double>& S);
+
 // Selection rule shared by the Ritz step: indices of the k finite values of
 // smallest |theta| ordered by (|theta|, Re, Im); a complex pair takes two
 // slots and is skipped when only one slot is left.  pair[i] flags pairs.

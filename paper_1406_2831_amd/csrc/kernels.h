@@ -67,7 +67,7 @@ struct BicgBufs {
     const double* b;
     double* xout;
     double *x, *r, *rt, *p, *pt, *z, *zt, *q, *qt;
-    double *W, *Wt, *AW;   // cycle store (column-major, ld), Lanczos columns at col0..
+    double *W, *Wt;        // cycle store (column-major, ld), Lanczos columns at col0..
     int64_t ldw;
     int col0;              // first Lanczos column (= recycle dimension of the store)
     BicgState* state;

@@ -1007,10 +1007,6 @@ __global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
     BicgState* st = B.state;
     if (st->done) return;
     const int k = B.k;
-    const double beta = st->beta;
-    const int slot = st->cur_slot;     // column of r_{i-1}, -1 when not stored
-    const bool store = slot >= 0;
-    double* awcol = B.AW + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     double acc[M];
@@ -1018,7 +1014,6 @@ __global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         const double zv = sell_row(B.A, row, B.p);
-        if (store) awcol[row] = zv - beta * B.z[row];
         B.z[row] = zv;
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] += B.Chat[row + col_off(j, k, B.ld)] * zv;

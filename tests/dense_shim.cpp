@@ -46,6 +46,13 @@ int shim_orth_factor(int m, const double* G, double tol, double* S) {
     return r;
 }
 
+int shim_orth_factor_chol(int m, const double* G, double shift, double* S) {
+    std::vector<double> v;
+    const int r = orth_factor_chol(m, G, shift, v);
+    if (r > 0) std::memcpy(S, v.data(), sizeof(double) * v.size());
+    return r;
+}
+
 int shim_recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
                            const double* F2, int k, double* Y, double* Yt) {
     RitzResult res = recycle_ritz_orth(r, rt, F, G, G2, F2, k);

@@ -34,6 +34,7 @@ def shim(tmp_path_factory):
     lib.shim_pivoted_cholesky.argtypes = [ctypes.c_int, P, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_int), P]
     lib.shim_orth_factor.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
+    lib.shim_orth_factor_chol.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
     lib.shim_recycle_ritz_orth.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P]
     return lib
 
@@ -95,12 +96,18 @@ def test_eigenvalues_match_lapack(shim, n, seed):
 
 
 def _orth(shim, X, AX=None):
-    """The library's two-pass pivoted Cholesky-QR, applied the way the API does."""
-    for tol in (1e-12, 1e-14):
+    """The library's orthonormalisation applied the way the API does: shifted
+    Cholesky QR (shift 11 (n m + m (m+1)) u m on the column-scaled Gram
+    matrix), then an unshifted pass; pivoted truncated Cholesky as fallback."""
+    n = X.shape[0]
+    for p in range(2):
         m = X.shape[1]
         G = _fortran(X.T @ X).ravel(order="F")
         S = np.zeros(m * m)
-        r = shim.shim_orth_factor(m, _p(G), tol, _p(S))
+        shift = 11.0 * (n * m + m * (m + 1)) * np.finfo(float).eps * m if p == 0 else 0.0
+        r = shim.shim_orth_factor_chol(m, _p(G), shift, _p(S))
+        if r < 0:
+            r = shim.shim_orth_factor(m, _p(G), 1e-12 if p == 0 else 1e-14, _p(S))
         Sm = S[: m * r].reshape(m, r, order="F")
         X = X @ Sm
         if AX is not None:
@@ -112,11 +119,44 @@ def test_orth_factor_orthonormalises(shim):
     rng = np.random.default_rng(7)
     # column norms over ten orders of magnitude, like raw residual vectors
     X = rng.standard_normal((400, 30)) @ np.diag(np.logspace(0, -10, 30))
-    X = np.hstack([X, X[:, :3]])                      # rank deficient
+    S = np.zeros(30 * 30)
+    G = _fortran(X.T @ X).ravel(order="F")
+    r = shim.shim_orth_factor(30, _p(G), 1e-12, _p(S))   # the pivoted fallback
+    Q = X @ S[: 30 * r].reshape(30, r, order="F")
+    assert r == 30 and np.abs(Q.T @ Q - np.eye(30)).max() < 1e-8
     Q, _ = _orth(shim, X)
     assert Q.shape[1] == 30
     assert np.abs(Q.T @ Q - np.eye(30)).max() < 1e-12
     assert sla.subspace_angles(Q, X).max() < 1e-8
+
+
+def test_shifted_cholesky_qr_keeps_ill_conditioned_directions(shim):
+    """A Krylov-like basis with cond > 1e10: the shifted pass keeps every
+    direction (each column of X lies in range(Q) to rounding) where the
+    pivoted truncated factor drops some; a zero column is left out.  Two
+    passes leave Q only roughly orthonormal at this conditioning, which the
+    Ritz step does not need (its pencils do not depend on the basis)."""
+    rng = np.random.default_rng(9)
+    n, m = 3000, 60
+    d = np.linspace(1.0, 2.0, n)
+    X = np.empty((n, m))
+    v = rng.standard_normal(n)
+    for j in range(m):   # power-like sequence with a little noise: nearly dependent columns
+        v = d * v
+        v /= np.linalg.norm(v)
+        X[:, j] = v + 1e-12 * rng.standard_normal(n)
+    X[:, 17] = 0.0
+    cond = np.linalg.cond(np.delete(X, 17, axis=1))
+    assert cond > 1e10
+    Q, _ = _orth(shim, X)
+    assert Q.shape[1] == m - 1
+    assert np.abs(Q.T @ Q - np.eye(m - 1)).max() < 1e-2
+    assert np.linalg.cond(Q) < 1.1
+    Qo, _ = np.linalg.qr(Q)
+    assert np.linalg.norm(X - Qo @ (Qo.T @ X)) < 1e-12 * np.linalg.norm(X)
+    S = np.zeros(m * m)
+    G = _fortran(X.T @ X).ravel(order="F")
+    assert shim.shim_orth_factor(m, _p(G), 1e-12, _p(S)) < m - 1
 
 
 def test_recycle_ritz_vs_oracle(shim):
