@@ -11,6 +11,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rbicgstab.h"
@@ -491,8 +492,15 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
 int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
+    const int m0 = m;
+    // device scratch: Gram | S0 | S1 | S0 S1 (each at most mmax^2 doubles)
+    const size_t mm = (size_t)(c->k_max + std::max(c->s_max, 0)) * (c->k_max + std::max(c->s_max, 0));
+    double* dG = c->dsmall;
+    double* dS[2] = {c->dsmall + mm, c->dsmall + 2 * mm};
+    double* dStot = c->dsmall + 3 * mm;
+    int mpass[2] = {0, 0}, rpass[2] = {0, 0};
+    int npass = 0;
     for (int pass = 0; pass < 2 && m > 0; ++pass) {
-        double* dG = c->dsmall;
         rbs::launch_gemmt(s, c->n, X, ld, m, X, ld, m, nullptr, 0, 0, c->gpart, dG);
         std::vector<double> G((size_t)m * m);
         int rc = to_host(c, G.data(), dG, G.size() * sizeof(double));
@@ -504,14 +512,23 @@ int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
         int r = rbs::dense::orth_factor_chol(m, G.data(), shift, S);
         if (r < 0) r = rbs::dense::orth_factor(m, G.data(), pass == 0 ? 1e-12 : 1e-14, S);
         if (r == 0) return 0;
-        if ((rc = to_device(c, c->dsmall, S.data(), S.size() * sizeof(double)))) return rc;
-        rbs::launch_gemm_ts(s, c->n, X, ld, m, c->dsmall, r, c->Wtmp, ld);
+        if ((rc = to_device(c, dS[pass], S.data(), S.size() * sizeof(double)))) return rc;
+        rbs::launch_gemm_ts(s, c->n, X, ld, m, dS[pass], r, c->Wtmp, ld);
         if ((rc = copy_cols(c, X, ld, c->Wtmp, ld, r))) return rc;
-        if (AX) {
-            rbs::launch_gemm_ts(s, c->n, AX, ld, m, c->dsmall, r, c->Wtmp, ld);
-            if ((rc = copy_cols(c, AX, ld, c->Wtmp, ld, r))) return rc;
-        }
+        mpass[pass] = m;
+        rpass[pass] = r;
+        npass = pass + 1;
         m = r;
+    }
+    if (AX && m > 0) {   // AX needs only the product of the transforms: one pass over it
+        const double* T = dS[0];
+        if (npass == 2) {
+            rbs::launch_gemm_ts(s, m0, dS[0], m0, mpass[1], dS[1], rpass[1], dStot, m0);
+            T = dStot;
+        }
+        rbs::launch_gemm_ts(s, c->n, AX, ld, m0, T, m, c->Wtmp, ld);
+        int rc = copy_cols(c, AX, ld, c->Wtmp, ld, m);
+        if (rc) return rc;
     }
     return m;
 }
@@ -535,33 +552,52 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     c->ritz_mv += m;
     const int r = orth_inplace(c, c->W, c->AW, m);
     if (r < 0) return r;
+    if (r == 0) {
+        c->gen_k = 0;
+        return RBS_OK;
+    }
+    // right (harmonic) pencil inputs first; its host eigenproblem then runs on
+    // a worker thread while the device orthonormalises Wt and forms Qt^T [Q AQ]
+    double* dF2 = c->dsmall;                    // r x r : Q^T AQ
+    double* dG2 = dF2 + (size_t)r * r;          // r x r : (AQ)^T AQ
+    rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
+    rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dG2);
+    std::vector<double> h2((size_t)2 * r * r);
+    int rc = to_host(c, h2.data(), dF2, h2.size() * sizeof(double));
+    if (rc) return rc;
+    const double* F2 = h2.data();
+    const double* G2 = F2 + (size_t)r * r;
+    const auto t_host = std::chrono::steady_clock::now();
+    rbs::dense::PencilResult right, left;
+    std::thread worker([&]() { right = rbs::dense::ritz_right_harmonic(r, G2, F2, c->k_max); });
+    struct Joiner {
+        std::thread& t;
+        ~Joiner() {
+            if (t.joinable()) t.join();
+        }
+    } joiner{worker};
     const int rt = orth_inplace(c, c->Wt, nullptr, m);
     if (rt < 0) return rt;
-    if (r == 0 || rt == 0) {
+    if (rt == 0) {
         c->gen_k = 0;
         return RBS_OK;
     }
     double* dFG = c->dsmall;                    // rt x 2r : Qt^T [Q AQ]
-    double* dF2 = dFG + (size_t)2 * rt * r;     // r x r   : Q^T AQ
-    double* dG2 = dF2 + (size_t)r * r;          // r x r   : (AQ)^T AQ
     rbs::launch_gemmt(s, c->n, c->Wt, ld, rt, c->W, ld, r, c->AW, ld, r, c->gpart, dFG);
-    rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
-    rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dG2);
-    std::vector<double> hbuf((size_t)2 * rt * r + 2 * (size_t)r * r);
-    int rc = to_host(c, hbuf.data(), dFG, hbuf.size() * sizeof(double));
-    if (rc) return rc;
-    const double* F = hbuf.data();
-    const double* G = F + (size_t)rt * r;
-    const double* F2 = G + (size_t)rt * r;
-    const double* G2 = F2 + (size_t)r * r;
-    const auto t_host = std::chrono::steady_clock::now();
-    rbs::dense::RitzResult res = rbs::dense::recycle_ritz_orth(r, rt, F, G, G2, F2, c->k_max);
+    std::vector<double> hFG((size_t)2 * rt * r);
+    if ((rc = to_host(c, hFG.data(), dFG, hFG.size() * sizeof(double)))) return rc;
+    const auto t_left = std::chrono::steady_clock::now();
+    left = rbs::dense::ritz_left_two_sided(r, rt, hFG.data(), hFG.data() + (size_t)rt * r, c->k_max);
+    worker.join();
+    rbs::dense::RitzResult res = rbs::dense::ritz_combine(r, rt, right, left);
     if (trace_enabled()) {
         const auto t_end = std::chrono::steady_clock::now();
-        std::fprintf(stderr, "[rbs] ritz m=%d r=%d rt=%d k=%d: device+copies %.2f ms, host eig %.2f ms\n",
-                     m, r, rt, res.kout,
-                     std::chrono::duration<double, std::milli>(t_host - t_start).count(),
-                     std::chrono::duration<double, std::milli>(t_end - t_host).count());
+        auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+        std::fprintf(stderr,
+                     "[rbs] ritz m=%d r=%d rt=%d k=%d: to right pencil %.2f ms, Wt side (overlapped) "
+                     "%.2f ms, left pencil + join %.2f ms, total %.2f ms\n",
+                     m, r, rt, res.kout, ms(t_start, t_host), ms(t_host, t_left), ms(t_left, t_end),
+                     ms(t_start, t_end));
     }
     if (!res.ok || res.kout == 0) {
         c->gen_k = 0;

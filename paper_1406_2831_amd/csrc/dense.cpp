@@ -506,52 +506,71 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
 
 }  // namespace
 
-RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
-                             const double* F2, int k) {
-    RitzResult out;
-    std::vector<double> Yc, Ytc;
-    std::vector<cd> th_r, th_l;
-    bool ok_r = true, ok_l = true;
-    const int me = std::min(r, rt);
-    // the two small eigenproblems are independent: solve them on two threads
-    std::thread right([&]() {
-        if (r == 0) return;
-        // harmonic: (AQ)^T (AQ) y = theta (AQ)^T Q y, with (AQ)^T Q = F2^T
-        std::vector<double> A2(G2, G2 + (size_t)r * r), B2((size_t)r * r);
-        for (int j = 0; j < r; ++j)
-            for (int i = 0; i < r; ++i) B2[i + (size_t)j * r] = F2[j + (size_t)i * r];
-        ok_r = pencil_vectors(r, A2, B2, k, false, Yc, th_r);
-    });
-    if (me > 0) {  // two-sided: G y = theta F y on the leading me x me block
-        std::vector<double> Gp((size_t)me * me), Fp((size_t)me * me);
-        for (int j = 0; j < me; ++j)
-            for (int i = 0; i < me; ++i) {
-                Gp[i + (size_t)j * me] = G[i + (size_t)j * rt];
-                Fp[i + (size_t)j * me] = F[i + (size_t)j * rt];
-            }
-        ok_l = pencil_vectors(me, Gp, Fp, k, true, Ytc, th_l);
+PencilResult ritz_right_harmonic(int r, const double* G2, const double* F2, int k) {
+    // harmonic: (AQ)^T (AQ) y = theta (AQ)^T Q y, with (AQ)^T Q = F2^T
+    PencilResult out;
+    if (r == 0) {
+        out.ok = true;
+        return out;
     }
-    right.join();
-    if (!ok_r || !ok_l) return out;
-    const int kr = r > 0 ? (int)(Yc.size() / r) : 0;
-    const int kl = me > 0 ? (int)(Ytc.size() / me) : 0;
+    std::vector<double> A2(G2, G2 + (size_t)r * r), B2((size_t)r * r);
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i < r; ++i) B2[i + (size_t)j * r] = F2[j + (size_t)i * r];
+    out.ok = pencil_vectors(r, A2, B2, k, false, out.cols, out.theta);
+    return out;
+}
+
+PencilResult ritz_left_two_sided(int r, int rt, const double* F, const double* G, int k) {
+    // two-sided: G y = theta F y on the leading me x me block; left vectors
+    PencilResult out;
+    const int me = std::min(r, rt);
+    if (me == 0) {
+        out.ok = true;
+        return out;
+    }
+    std::vector<double> Gp((size_t)me * me), Fp((size_t)me * me);
+    for (int j = 0; j < me; ++j)
+        for (int i = 0; i < me; ++i) {
+            Gp[i + (size_t)j * me] = G[i + (size_t)j * rt];
+            Fp[i + (size_t)j * me] = F[i + (size_t)j * rt];
+        }
+    out.ok = pencil_vectors(me, Gp, Fp, k, true, out.cols, out.theta);
+    return out;
+}
+
+RitzResult ritz_combine(int r, int rt, const PencilResult& right, const PencilResult& left) {
+    RitzResult out;
+    if (!right.ok || !left.ok) return out;
+    const int me = std::min(r, rt);
+    const int kr = r > 0 ? (int)(right.cols.size() / r) : 0;
+    const int kl = me > 0 ? (int)(left.cols.size() / me) : 0;
     const int kout = std::min(kr, kl);
     out.m_eff = me;
     out.Y.assign((size_t)r * kout, 0.0);
     out.Yt.assign((size_t)rt * kout, 0.0);
     for (int c = 0; c < kout; ++c) {   // orthonormal bases: unit coefficient vectors
         double a = 0.0, b = 0.0;
-        for (int i = 0; i < r; ++i) a += Yc[i + (size_t)c * r] * Yc[i + (size_t)c * r];
-        for (int i = 0; i < me; ++i) b += Ytc[i + (size_t)c * me] * Ytc[i + (size_t)c * me];
+        for (int i = 0; i < r; ++i) a += right.cols[i + (size_t)c * r] * right.cols[i + (size_t)c * r];
+        for (int i = 0; i < me; ++i) b += left.cols[i + (size_t)c * me] * left.cols[i + (size_t)c * me];
         a = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
         b = b > 0 ? 1.0 / std::sqrt(b) : 0.0;
-        for (int i = 0; i < r; ++i) out.Y[i + (size_t)c * r] = Yc[i + (size_t)c * r] * a;
-        for (int i = 0; i < me; ++i) out.Yt[i + (size_t)c * rt] = Ytc[i + (size_t)c * me] * b;
+        for (int i = 0; i < r; ++i) out.Y[i + (size_t)c * r] = right.cols[i + (size_t)c * r] * a;
+        for (int i = 0; i < me; ++i) out.Yt[i + (size_t)c * rt] = left.cols[i + (size_t)c * me] * b;
     }
-    if (kout > 0) out.theta.assign(th_r.begin(), th_r.begin() + kout);
+    if (kout > 0) out.theta.assign(right.theta.begin(), right.theta.begin() + kout);
     out.kout = kout;
     out.ok = true;
     return out;
+}
+
+RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
+                             const double* F2, int k) {
+    // the two small eigenproblems are independent: solve them on two threads
+    PencilResult right, left;
+    std::thread tr([&]() { right = ritz_right_harmonic(r, G2, F2, k); });
+    left = ritz_left_two_sided(r, rt, F, G, k);
+    tr.join();
+    return ritz_combine(r, rt, right, left);
 }
 
 int orth_factor_chol(int m, const double* Gram, double shift, std::vector<double>& S) {

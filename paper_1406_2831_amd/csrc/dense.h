@@ -52,6 +52,18 @@ struct RitzResult {
 RitzResult recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
                              const double* F2, int k);
 
+// The two halves of recycle_ritz_orth, for callers that overlap them with
+// device work: the right (harmonic) pencil needs only G2, F2; the left
+// (two-sided) pencil only F, G.  cols holds the selected real vectors.
+struct PencilResult {
+    std::vector<double> cols;
+    std::vector<std::complex<double>> theta;
+    bool ok = false;
+};
+PencilResult ritz_right_harmonic(int r, const double* G2, const double* F2, int k);
+PencilResult ritz_left_two_sided(int r, int rt, const double* F, const double* G, int k);
+RitzResult ritz_combine(int r, int rt, const PencilResult& right, const PencilResult& left);
+
 // Orthonormalising factor of a tall block X from its Gram matrix X^T X
 // (m x m): columns scaled to unit norm (D), pivoted Cholesky of D G D
 // truncated at tol, S = D P R^-1 (m x r) so that X S has orthonormal

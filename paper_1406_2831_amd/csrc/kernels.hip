@@ -383,23 +383,120 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_tile(int64_t n, const double* _
         for (int v = 0; v < 4; ++v) out[(tr * 4 + u) * GT + tc * 4 + v] = acc[u][v];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tiles_y, int ntiles,
-                                                        int nchunks, int symmetric,
+// Sum the row-chunk partial tiles of X^T Y into out (column-major, ld = mx).
+// Partial tile `slot` of chunk c sits at partial[(c * stride + slot) T^2]:
+// slot = tx * tiles_y + ty (stride = all tiles), or with `tri` the index of
+// (tx, ty), tx <= ty, in the row-by-row upper triangle (stride = its size).
+// Symmetric products mirror the upper tiles.
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tiles_y, int stride,
+                                                        int nchunks, int symmetric, int tri,
                                                         const double* __restrict__ partial,
                                                         double* __restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= (int64_t)mx * my) return;
-    int i = (int)(idx % mx), j = (int)(idx / mx);   // out column-major (ld = mx)
-    if (symmetric && i / GT > j / GT) {
+    // consecutive threads take consecutive j: their partial loads are contiguous
+    int i = (int)(idx / my), j = (int)(idx % my);
+    double* dst = out + i + (int64_t)j * mx;
+    if (symmetric && i / T > j / T) {
         const int t = i;
         i = j;
         j = t;
     }
-    const int tile = (i / GT) * tiles_y + (j / GT);
-    const int off = (i % GT) * GT + (j % GT);
+    const int ti = i / T, tj = j / T;
+    const int slot = tri ? ti * tiles_y - ti * (ti - 1) / 2 + (tj - ti) : ti * tiles_y + tj;
+    const int off = (i % T) * T + (j % T);
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * ntiles + tile) * (GT * GT) + off];
-    out[idx] = s;
+    for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * stride + slot) * (T * T) + off];
+    *dst = s;
+}
+
+// Tall-skinny X^T Y on the matrix cores: a 128 x 128 output tile per block,
+// each of the 4 waves owns a 64 x 64 quarter as 4 x 4 tiles of
+// v_mfma_f64_16x16x4 (operand lanes: A(i, kk) and B(kk, j) from lane
+// i + 16 kk / j + 16 kk; result element (i, j) of a 16 x 16 tile in lane
+// j + 16 (i % 4), register i / 4).  Rows are staged through LDS in slabs of
+// 16 (row-major in LDS, so an operand read is 16 consecutive doubles per
+// lane group; the row stride is padded so the two half-waves of a read hit
+// disjoint banks).  Symmetric products launch only tiles with tx <= ty.
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int MT = 128, MR = 16, MSTRIDE = MT + 16;
+
+__global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* __restrict__ X,
+                                                      int64_t ldx, int mx, const double* __restrict__ Y1,
+                                                      int64_t ldy1, int my1, const double* __restrict__ Y2,
+                                                      int64_t ldy2, int my2, int tiles_y,
+                                                      int64_t rows_per_chunk, int symmetric,
+                                                      double* __restrict__ partial) {
+    __shared__ double sx[MR * MSTRIDE];
+    __shared__ double sy[MR * MSTRIDE];
+    int tx, ty;
+    if (symmetric) {   // blockIdx.x enumerates the upper triangle row by row
+        int b = blockIdx.x;
+        tx = 0;
+        while (b >= tiles_y - tx) {
+            b -= tiles_y - tx;
+            ++tx;
+        }
+        ty = tx + b;
+    } else {
+        tx = blockIdx.x / tiles_y;
+        ty = blockIdx.x % tiles_y;
+    }
+    const int my = my1 + my2;
+    const int64_t c0 = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t c1 = (c0 + rows_per_chunk < n) ? c0 + rows_per_chunk : n;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int wi = w >> 1, wj = w & 1;
+    const int lr = threadIdx.x & 15, lc = threadIdx.x >> 4;   // load: row lr of columns lc + 16 q
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t base = c0; base < c1; base += MR) {
+        const int64_t row = base + lr;
+        const bool rok = row < c1;
+#pragma unroll
+        for (int q = 0; q < MT / 16; ++q) {
+            const int c = lc + 16 * q;
+            const int gi = tx * MT + c, gj = ty * MT + c;
+            double vx = 0.0, vy = 0.0;
+            if (rok && gi < mx) vx = X[row + (int64_t)gi * ldx];
+            if (rok && gj < my)
+                vy = gj < my1 ? Y1[row + (int64_t)gj * ldy1] : Y2[row + (int64_t)(gj - my1) * ldy2];
+            sx[lr * MSTRIDE + c] = vx;
+            sy[lr * MSTRIDE + c] = vy;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < MR / 4; ++ks) {
+            const int r = ks * 4 + (lane >> 4);
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = sx[r * MSTRIDE + wi * 64 + t * 16 + (lane & 15)];
+                b[t] = sy[r * MSTRIDE + wj * 64 + t * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int it = 0; it < 4; ++it)
+#pragma unroll
+                for (int jt = 0; jt < 4; ++jt)
+                    acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[it], b[jt], acc[it][jt], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* out = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (MT * MT);
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i = wi * 64 + it * 16 + (lane >> 4) + 4 * rr;
+                const int j = wj * 64 + jt * 16 + (lane & 15);
+                out[i * MT + j] = acc[it][jt][rr];
+            }
 }
 
 // ---------------------------------------------------------------- Algorithm 2 passes
@@ -1261,28 +1358,40 @@ void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int
     hipLaunchKernelGGL(k_gemm_ts, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, X, ldx, m, S, ko, Y, ldy);
 }
 
-static void gemmt_shape(int64_t n, int mx, int my, int& tiles_y, int& ntiles, int& nchunks,
+// Tiling of X^T Y (mx x my) with T x T output tiles: `launched` blocks per row
+// chunk (all tiles, or the upper triangle when symmetric), and as many row
+// chunks as keep the grid near `grid_cap` blocks with >= 256 rows each.
+static void gemmt_shape(int64_t n, int mx, int my, int T, int rows_mult, int grid_cap, bool sym,
+                        int& tiles_y, int& ntiles, int& launched, int& nchunks,
                         int64_t& rows_per_chunk) {
-    const int tiles_x = (mx + GT - 1) / GT;
-    tiles_y = (my + GT - 1) / GT;
+    const int tiles_x = (mx + T - 1) / T;
+    tiles_y = (my + T - 1) / T;
     ntiles = tiles_x * tiles_y;
-    int64_t nc = MAX_GRID / ntiles;
+    launched = sym ? tiles_x * (tiles_x + 1) / 2 : ntiles;
+    int64_t nc = grid_cap / launched;
     if (nc < 1) nc = 1;
-    const int64_t maxc = (n + 255) / 256;   // at least 256 rows per chunk
+    const int64_t maxc = (n + 255) / 256;
     if (nc > maxc) nc = maxc;
     if (nc < 1) nc = 1;
     rows_per_chunk = (n + nc - 1) / nc;
-    rows_per_chunk = (rows_per_chunk + GS - 1) / GS * GS;
+    rows_per_chunk = (rows_per_chunk + rows_mult - 1) / rows_mult * rows_mult;
     nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
     if (nchunks < 1) nchunks = 1;
 }
 
+// the matrix-core kernel pays off once the output spans more than one 64-wide tile
+constexpr int MFMA_MIN_DIM = 65;
+constexpr int MFMA_GRID = 512;
+
 size_t gemmt_partial_doubles(int64_t n, int mx, int my) {
-    // nchunks * ntiles <= max(MAX_GRID, ntiles) for every shape with at most
-    // this many tiles, so one buffer of this size serves all smaller calls too
+    // chunks * tiles <= max(grid cap, tiles) for every shape with at most this
+    // many tiles, so one buffer of this size serves all smaller calls too
     (void)n;
-    const int64_t ntiles = (int64_t)((mx + GT - 1) / GT) * ((my + GT - 1) / GT);
-    return (size_t)(ntiles > MAX_GRID ? ntiles : MAX_GRID) * GT * GT;
+    const int64_t t64 = (int64_t)((mx + GT - 1) / GT) * ((my + GT - 1) / GT);
+    const int64_t t128 = (int64_t)((mx + MT - 1) / MT) * ((my + MT - 1) / MT);
+    const int64_t a = (t64 > MAX_GRID ? t64 : MAX_GRID) * GT * GT;
+    const int64_t b = (t128 > MFMA_GRID ? t128 : MFMA_GRID) * MT * MT;
+    return (size_t)(a > b ? a : b);
 }
 
 void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y1,
@@ -1290,15 +1399,24 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
                   double* out) {
     const int my = my1 + my2;
     if (mx <= 0 || my <= 0) return;
-    int tiles_y, ntiles, nchunks;
+    int tiles_y, ntiles, launched, nchunks;
     int64_t rpc;
-    gemmt_shape(n, mx, my, tiles_y, ntiles, nchunks, rpc);
-    const int sym = (X == Y1 && my2 == 0 && mx == my1 && ldx == ldy1) ? 1 : 0;
-    hipLaunchKernelGGL(k_gemmt_tile, dim3(ntiles, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1, ldy1,
-                       my1, Y2, ldy2, my2, tiles_y, rpc, sym, partial);
+    const bool sym = X == Y1 && my2 == 0 && mx == my1 && ldx == ldy1;
     const int64_t total = (int64_t)mx * my;
-    hipLaunchKernelGGL(k_gemmt_reduce, dim3((unsigned)((total + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
-                       mx, my, tiles_y, ntiles, nchunks, sym, partial, out);
+    const unsigned rgrid = (unsigned)((total + BLOCK - 1) / BLOCK);
+    if (mx >= MFMA_MIN_DIM || my >= MFMA_MIN_DIM) {
+        gemmt_shape(n, mx, my, MT, MR, MFMA_GRID, sym, tiles_y, ntiles, launched, nchunks, rpc);
+        hipLaunchKernelGGL(k_gemmt_mfma, dim3(launched, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1,
+                           ldy1, my1, Y2, ldy2, my2, tiles_y, rpc, sym ? 1 : 0, partial);
+        hipLaunchKernelGGL(k_gemmt_reduce<MT>, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, tiles_y, launched,
+                           nchunks, sym ? 1 : 0, sym ? 1 : 0, partial, out);
+    } else {
+        gemmt_shape(n, mx, my, GT, GS, MAX_GRID, false, tiles_y, ntiles, launched, nchunks, rpc);
+        hipLaunchKernelGGL(k_gemmt_tile, dim3(ntiles, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1,
+                           ldy1, my1, Y2, ldy2, my2, tiles_y, rpc, sym ? 1 : 0, partial);
+        hipLaunchKernelGGL(k_gemmt_reduce<GT>, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, tiles_y, ntiles,
+                           nchunks, sym ? 1 : 0, 0, partial, out);
+    }
 }
 
 void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it) {
