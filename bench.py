@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--time-reps", type=int, default=100)
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of the known-size copy used to calibrate HBM counters (0: skip)")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32-storage / FP64-refinement runs (reported beside the FP64 line)")
     ap.add_argument("--secant-max", type=float, default=0.0,
                     help="oblique-projector cap of the recycle setup (0: library default)")
     args = ap.parse_args()
@@ -104,8 +106,8 @@ def main():
     gs = GpuSequence(seq, s_max=512, secant_max=args.secant_max)
     nsys = seq.num_systems
 
-    def run(mode):
-        return gs.run(mode=mode, rtol=args.rtol)
+    def run(mode, precision="fp64"):
+        return gs.run(mode=mode, rtol=args.rtol, precision=precision)
 
     for _ in range(args.warmup):
         run("rbicgstab")
@@ -113,24 +115,39 @@ def main():
     timed = {}
     results = {}
     passes = {}
-    for mode in ("rbicgstab", "bicgstab"):
+    x64 = None
+    modes = [("rbicgstab", "fp64"), ("bicgstab", "fp64")]
+    if not args.no_fp32:
+        modes += [("rbicgstab", "fp32_ir"), ("bicgstab", "fp32_ir")]
+    for mode, prec in modes:
+        key = mode if prec == "fp64" else f"{mode}_fp32_ir"
+        if prec != "fp64" and args.warmup:
+            run(mode, prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            results[mode] = run(mode)
+            results[key] = run(mode, prec)
         torch.cuda.synchronize()
-        timed[mode] = (time.perf_counter() - t0) / args.steps
-        res = results[mode]
+        timed[key] = (time.perf_counter() - t0) / args.steps
+        res = results[key]
         if any(s != 0 for s in res.status) or max(res.rel_res_true) > args.rtol:
-            print(f"{mode}: not every system converged: status {res.status}, "
+            print(f"{key}: not every system converged: status {res.status}, "
                   f"iters {res.iters}, k {res.k_used}, solver {res.solver}, "
                   f"true residuals {res.rel_res_true}", file=sys.stderr)
             sys.exit(1)
-        if mode == "rbicgstab":
+        if key == "rbicgstab":
+            x64 = [x.clone() for x in res.x]
+        elif prec == "fp32_ir":
+            # error of each FP32-storage result against the FP64 pipeline's
+            res.err_vs_fp64 = [float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
+                               for x, xr in zip(res.x, x64)]
+        if key == "rbicgstab":
             # live per-kernel timing of the fused passes at the installed space's k
             k_last = int(res.k_used[-1])
             for name, which, kk in (("spmv1_project", 1, k_last), ("update", 0, k_last),
-                                    ("spmv2_project", 2, k_last), ("spmv", 3, 0)):
+                                    ("spmv2_project", 2, k_last), ("spmv", 3, 0),
+                                    ("spmv1_project_fp32", 5, k_last), ("update_fp32", 4, k_last),
+                                    ("spmv2_project_fp32", 6, k_last), ("spmv_fp32", 7, 0)):
                 passes[name] = gs.ctx.time_pass(which, kk, args.time_reps)
 
     rres = results["rbicgstab"]
@@ -168,11 +185,8 @@ def main():
                       "max_rel_res_true": max(rres.rel_res_true)},
         "rbicgstab_over_bicgstab_time": timed["rbicgstab"] / timed["bicgstab"],
         "spmv_gbs": gbs(bytes_spmv, ms_spmv),
-        "passes": {"update": {"us": ms_upd * 1e3, "gbs": gbs(bytes_upd, ms_upd)},
-                   "spmv1_project": {"us": ms_spmv1 * 1e3, "gbs": achieved},
-                   "spmv2_project": {"us": ms_spmv2 * 1e3, "gbs": gbs(bytes_spmv2, ms_spmv2)},
-                   "spmv": {"us": ms_spmv * 1e3, "gbs": gbs(bytes_spmv, ms_spmv)},
-                   "k": k_last},
+        "passes": dict({name: {"us": ms * 1e3, "gbs": gbs(by, ms)} for name, (ms, by) in passes.items()},
+                       k=k_last),
         "roofline": {"bound": "hbm", "kernel": dom_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -180,6 +194,17 @@ def main():
     }
     # a plain device-to-device copy of known size (outside the timed region):
     # the reference the HBM counters of a profiled run are calibrated with
+    if not args.no_fp32:
+        r32, b32 = results["rbicgstab_fp32_ir"], results["bicgstab_fp32_ir"]
+        out["fp32_ir"] = {
+            "rbicgstab_systems_per_s": nsys / timed["rbicgstab_fp32_ir"],
+            "rbicgstab_ms_per_step": timed["rbicgstab_fp32_ir"] * 1e3,
+            "bicgstab_systems_per_s": nsys / timed["bicgstab_fp32_ir"],
+            "bicgstab_ms_per_step": timed["bicgstab_fp32_ir"] * 1e3,
+            "rbicgstab_inner_iters": r32.iters, "bicgstab_inner_iters": b32.iters,
+            "rbicgstab_matvecs": r32.total_matvecs, "bicgstab_matvecs": b32.total_matvecs,
+            "max_rel_res_true_fp64": max(max(r32.rel_res_true), max(b32.rel_res_true)),
+            "rbicgstab_err_vs_fp64": r32.err_vs_fp64, "bicgstab_err_vs_fp64": b32.err_vs_fp64}
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")

@@ -54,6 +54,8 @@ typedef struct {
     double rel_res_recur;  /* ||r_i|| / ||b|| of the recurrence                 */
     double rel_res_true;   /* ||b - A x|| / ||b|| computed in FP64 at the end   */
     double ms;             /* host wall time of the call                        */
+    int32_t ir_steps;      /* outer refinement steps (RBS_FP32_IR only)         */
+    int32_t reserved;
 } rbs_stats;
 
 enum {
@@ -75,6 +77,14 @@ enum {
     RBS_BICGSTAB = 1,     /* plain BiCGSTAB: the recycle space is ignored (baseline)          */
     RBS_RBICG_GEN = 2,    /* Algorithm 1 with dual rhs = ones; its Lanczos vectors build the   *
                            * next recycle space (installed by recycle_update FROM_LAST_SOLVE) */
+    RBS_FP32_IR = 16,     /* FP32 storage + FP64 iterative refinement (OR-ed with RBS_RBICGSTAB *
+                           * or RBS_BICGSTAB): the residual b - A x is formed in FP64 with the  *
+                           * FP64 matrix; each correction A d = r / ||r|| is solved with FP32    *
+                           * vectors, matrix values and recycle blocks (FP64 sums and scalars)  *
+                           * to a relative residual 1e-5 (or what is still missing); x += ||r|| d *
+                           * in FP64; at most 10 outer steps.  The recycle space itself (D_c    *
+                           * solve, Ritz step) stays FP64.  stats.iters = inner iterations,     *
+                           * stats.ir_steps = outer steps, stats.rel_res_true = FP64 residual.  */
     RBS_TRANSPOSE = 8     /* solve A^T x = b reusing the space with the roles of U and Ut      *
                            * swapped (OR-ed with RBS_RBICGSTAB or RBS_BICGSTAB): for A^T the   *
                            * right space is Ut, C' = A^T Ut = Ct, Chat' = Ccheck and          *
@@ -162,11 +172,12 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  * Algorithm 2 on the bound matrix with recycle dimension k (0 <= k <=
  * installed k): which = 0 the update pass, 1 the first SpMV + projection
  * pass, 2 the second SpMV + projection pass (their one-block finalize
- * kernels are not included), 3 a plain SpMV.  The pass is launched `reps` times
+ * kernels are not included), 3 a plain SpMV; which = 4..7 the same passes
+ * with the FP32 storage of RBS_FP32_IR (4-byte values and vector entries).  The pass is launched `reps` times
  * back to back on the context's stream between two HIP events; *avg_ms
  * receives the mean duration per launch and *bytes the algorithmic bytes
  * one launch moves (CSR: 12 bytes per stored entry + 4 per row pointer;
- * 8 bytes per vector / block entry read or written once).  The context's
+ * 8 bytes per vector / block entry read or written once; 8 and 4 for FP32).  The context's
  * solve vectors are used as operands and left in an unspecified state.
  */
 int rbicgstab_time_pass(rbs_ctx* ctx, int32_t which, int32_t k, int32_t reps, double* avg_ms,

@@ -53,6 +53,16 @@ struct rbs_ctx {
     double *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr, *Chat = nullptr,
            *Ccheck = nullptr, *Gh = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;
     int ritz_mv = 0;         // products with A spent by Ritz steps of the current RBiCG solve
+    // FP32 storage for the inner solves of iterative refinement (RBS_FP32_IR):
+    // value copies of A, A^T (sharing their slices and columns), of the blocks,
+    // and a float vector set; refreshed lazily after every setup
+    rbs::SellF Af, Atf;
+    float *Uf = nullptr, *Cf = nullptr, *Chatf = nullptr, *Ctf = nullptr, *Ccheckf = nullptr,
+          *Ghf = nullptr;
+    float *xf = nullptr, *rf = nullptr, *sf = nullptr, *tf = nullptr, *pf = nullptr, *qf = nullptr,
+          *rt0f = nullptr, *rhf = nullptr, *bf = nullptr, *df = nullptr, *shf = nullptr;
+    double* r64 = nullptr;   // FP64 residual of the refinement loop
+    bool f32_valid = false;
     double* GhT = nullptr;   // A Ccheck: the Gh block of the transposed system
     bool ght_valid = false;
     double *x = nullptr, *r = nullptr, *s = nullptr, *t = nullptr, *p = nullptr, *q = nullptr,
@@ -132,6 +142,17 @@ size_t carve(rbs_ctx* c, char* base) {
         m->val = cv.take<double>(c->sell_cap);
     }
     c->widths = cv.take<int32_t>(nsl);
+    for (rbs::SellF* m : {&c->Af, &c->Atf}) {
+        m->n = c->n;
+        m->nslices = nsl;
+        m->val = cv.take<float>(c->sell_cap);
+    }
+    for (float** b : {&c->Uf, &c->Cf, &c->Chatf, &c->Ctf, &c->Ccheckf, &c->Ghf})
+        *b = cv.take<float>(std::max<int64_t>(kb, 1));
+    for (float** v : {&c->xf, &c->rf, &c->sf, &c->tf, &c->pf, &c->qf, &c->rt0f, &c->rhf, &c->bf, &c->df,
+                      &c->shf})
+        *v = cv.take<float>(ld);
+    c->r64 = cv.take<double>(ld);
     double** blocks[] = {&c->U, &c->Ut, &c->C, &c->Ct, &c->Chat, &c->Ccheck, &c->Gh,
                          &c->T1, &c->T2, &c->T3, &c->GhT};
     for (double** b : blocks) *b = cv.take<double>(std::max<int64_t>(kb, 1));
@@ -216,6 +237,7 @@ int to_device(rbs_ctx* c, void* d, const void* h, size_t bytes) {
 // Chat = Ct D^-T, Ccheck = C D^-1, and Gh = A^T Chat for the fused iteration.
 int setup_blocks(rbs_ctx* c) {
     c->ght_valid = false;
+    c->f32_valid = false;
     const int k0 = c->k;
     if (k0 == 0) return RBS_OK;
     const int64_t ld = c->ld;
@@ -441,6 +463,144 @@ int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, cons
         stats->rel_res_true = rel_true;
     }
     if (status == RBS_ERR_NONFINITE) c->err = "non-finite value in the iteration";
+    return status;
+}
+
+// ---------------------------------------------------------------- FP32 storage + FP64 refinement
+
+constexpr int MAX_IR_STEPS = 10;
+constexpr double INNER_RTOL = 1e-5;   // residual reduction asked of one FP32 inner solve
+
+// FP32 copies of the matrix values and of the installed blocks
+int ensure_f32(rbs_ctx* c) {
+    if (c->f32_valid) return RBS_OK;
+    hipStream_t s = c->stream;
+    for (auto pr : {std::make_pair(&c->A, &c->Af), std::make_pair(&c->At, &c->Atf)}) {
+        rbs::Sell& d = *pr.first;
+        rbs::SellF& f = *pr.second;
+        f.n = d.n;
+        f.nslices = d.nslices;
+        f.padded = d.padded;
+        f.slice_ptr = d.slice_ptr;
+        f.col = d.col;
+        rbs::launch_to_float(s, d.padded, d.val, 1.0, f.val);
+    }
+    const int64_t kb = c->ld * (int64_t)c->k;
+    if (kb > 0) {
+        const std::pair<const double*, float*> blocks[] = {{c->U, c->Uf},       {c->C, c->Cf},
+                                                           {c->Chat, c->Chatf}, {c->Ct, c->Ctf},
+                                                           {c->Ccheck, c->Ccheckf}, {c->Gh, c->Ghf}};
+        for (const auto& pr : blocks) rbs::launch_to_float(s, kb, pr.first, 1.0, pr.second);
+    }
+    HIPCHK(c, hipGetLastError());
+    c->f32_valid = true;
+    return RBS_OK;
+}
+
+rbs::SolveBufsF solve_bufs_f32(rbs_ctx* c, int k, bool with_shadow) {
+    rbs::SolveBufsF B;
+    B.n = c->n;
+    B.ld = c->ld;
+    B.k = k;
+    B.A = c->Af;
+    B.At = c->Atf;
+    B.U = c->Uf;
+    B.C = c->Cf;
+    B.Chat = c->Chatf;
+    B.Ct = c->Ctf;
+    B.Ccheck = c->Ccheckf;
+    B.Gh = c->Ghf;
+    B.b = c->bf;
+    B.xout = c->df;
+    B.shadow = with_shadow ? c->shf : nullptr;
+    B.x = c->xf;
+    B.r = c->rf;
+    B.s = c->sf;
+    B.t = c->tf;
+    B.p = c->pf;
+    B.q = c->qf;
+    B.rt0 = c->rt0f;
+    B.rh = c->rhf;
+    B.state = c->st;
+    B.partials = c->partials;
+    return B;
+}
+
+// Iterative refinement (the FP32-storage mode): the outer loop forms the
+// residual r = b - A x in FP64 with the FP64 matrix, solves A d = r / ||r||
+// by RBiCGSTAB (or BiCGSTAB) with FP32 vectors, matrix and blocks (sums and
+// scalars in FP64) to a relative residual INNER_RTOL, and updates x += ||r|| d
+// in FP64, until the FP64 residual meets rtol.
+int solve_ir(rbs_ctx* c, int k, const double* b, double* x, int xnz, const double* shadow,
+             double rtol, int max_it, rbs_stats* stats) {
+    int rc = ensure_f32(c);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    if (!xnz) rbs::launch_fill(s, x, c->n, 0.0);
+    if (shadow) rbs::launch_to_float(s, c->n, shadow, 1.0, c->shf);
+    rbs::SolveBufsF B = solve_bufs_f32(c, k, shadow != nullptr);
+    int status = RBS_MAXIT, total_iters = 0, steps = 0, mvA = 0, mvAt = 0;
+    double rel = NAN, rel_inner = NAN;
+    for (int outer = 0;; ++outer) {
+        rbs::launch_residual(s, c->A, b, x, c->r64, c->partials, c->dsums);
+        HIPCHK(c, hipGetLastError());
+        if ((rc = to_host(c, c->hp->sums, c->dsums, 2 * sizeof(double)))) return rc;
+        ++mvA;
+        const double rr = c->hp->sums[0], bb = c->hp->sums[1];
+        rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        if (!std::isfinite(rel)) {
+            status = RBS_ERR_NONFINITE;
+            break;
+        }
+        if (rel <= rtol) {
+            status = RBS_OK;
+            break;
+        }
+        if (outer == MAX_IR_STEPS || total_iters >= max_it) {
+            status = RBS_MAXIT;
+            break;
+        }
+        const double rn = std::sqrt(rr);
+        rbs::launch_to_float(s, c->n, c->r64, 1.0 / rn, c->bf);
+        // ask for what is still missing, but no less than FP32 storage can give
+        const double want = std::max(INNER_RTOL, 0.5 * rtol / rel);
+        rbs::launch_solve_prologue(s, B, 0, want, max_it - total_iters);
+        mvAt += 1;
+        rc = iterate_until_done(
+            c, [&](int cnt) { rbs::launch_solve_iterations(s, B, cnt); },
+            [&]() { return c->hp->solve.done != 0; }, &c->hp->solve, c->st, 128, max_it);
+        if (rc) return rc;
+        rbs::launch_solve_epilogue(s, B);
+        rbs::launch_add_float(s, c->n, x, c->df, rn);
+        HIPCHK(c, hipGetLastError());
+        if ((rc = to_host(c, &c->hp->solve, c->st, 128))) return rc;
+        const SolveState& h = c->hp->solve;
+        total_iters += h.iters_done;
+        mvA += 2 * h.iters_done;
+        ++steps;
+        rel_inner = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+        if (h.status == RBS_ERR_NONFINITE) {
+            status = RBS_ERR_NONFINITE;
+            break;
+        }
+        if (h.status != RBS_OK && h.status != RBS_MAXIT && h.iters_done == 0) {
+            status = h.status;   // breakdown before any progress: refinement cannot continue
+            break;
+        }
+    }
+    if (stats) {
+        stats->status = status;
+        stats->iters = total_iters;
+        stats->total_iters = total_iters;
+        stats->restarts = 0;
+        stats->matvecs_A = mvA;
+        stats->matvecs_At = mvAt;
+        stats->k_used = k;
+        stats->rel_res_recur = rel_inner;
+        stats->rel_res_true = rel;
+        stats->ir_steps = steps;
+    }
+    if (status == RBS_ERR_NONFINITE) c->err = "non-finite value in the refinement";
     return status;
 }
 
@@ -794,6 +954,7 @@ int rbicgstab_setup(rbs_ctx** pctx, int64_t n, int64_t nnz, const int32_t* rowpt
     HIPCHK(c, hipGetLastError());
     c->bound = true;
     c->gen_valid = false;
+    c->f32_valid = false;
     rc = setup_blocks(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -811,10 +972,15 @@ int rbicgstab_solve(rbs_ctx* c, const double* b, double* x, int32_t x_nonzero, c
     int rc;
     const int mode = flags & 3;
     const bool tr = (flags & RBS_TRANSPOSE) != 0;
-    if (flags & ~(3 | RBS_TRANSPOSE)) return fail(c, RBS_ERR_ARG, "unknown solve flags");
+    const bool ir = (flags & RBS_FP32_IR) != 0;
+    if (flags & ~(3 | RBS_TRANSPOSE | RBS_FP32_IR)) return fail(c, RBS_ERR_ARG, "unknown solve flags");
     if (tr && mode == RBS_RBICG_GEN)
         return fail(c, RBS_ERR_ARG, "RBS_TRANSPOSE applies to RBS_RBICGSTAB and RBS_BICGSTAB only");
-    if (mode == RBS_RBICG_GEN)
+    if (ir && (tr || mode == RBS_RBICG_GEN || mode == 3))
+        return fail(c, RBS_ERR_ARG, "RBS_FP32_IR applies to untransposed RBS_RBICGSTAB / RBS_BICGSTAB");
+    if (ir)
+        rc = solve_ir(c, mode == RBS_BICGSTAB ? 0 : c->k, b, x, x_nonzero, shadow, rtol, max_it, stats);
+    else if (mode == RBS_RBICG_GEN)
         rc = solve_rbicg(c, b, x, x_nonzero, shadow, rtol, max_it, stats);
     else if (mode == RBS_BICGSTAB)
         rc = solve_rbicgstab(c, 0, b, x, x_nonzero, shadow, rtol, max_it, stats, tr);
@@ -874,17 +1040,28 @@ int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, doub
                         double* bytes) {
     if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
     if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound");
-    if (which < 0 || which > 3 || reps < 1 || k < 0 || k > c->k)
-        return fail(c, RBS_ERR_ARG, "which must be 0..3, reps >= 1 and 0 <= k <= k_used");
+    if (which < 0 || which > 7 || reps < 1 || k < 0 || k > c->k)
+        return fail(c, RBS_ERR_ARG, "which must be 0..7, reps >= 1 and 0 <= k <= k_used");
+    const bool f32 = which >= 4;
+    const int pass = which & 3;
+    if (f32) {
+        int rc = ensure_f32(c);
+        if (rc) return rc;
+    }
     rbs::SolveBufs B = solve_bufs(c, k, c->s, c->x, nullptr);
+    rbs::SolveBufsF Bf = solve_bufs_f32(c, k, false);
+    auto launch = [&]() {
+        if (f32) rbs::launch_pass(c->stream, Bf, pass);
+        else rbs::launch_pass(c->stream, B, pass);
+    };
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     rbs::launch_time_prep(c->stream, c->st);
-    rbs::launch_pass(c->stream, B, which);   // warm-up launch
+    launch();   // warm-up launch
     rbs::launch_time_prep(c->stream, c->st);
     hipEventRecord(e0, c->stream);
-    for (int i = 0; i < reps; ++i) rbs::launch_pass(c->stream, B, which);
+    for (int i = 0; i < reps; ++i) launch();
     hipEventRecord(e1, c->stream);
     hipError_t e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -896,15 +1073,16 @@ int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, doub
     if (c->hp->solve.done) return fail(c, RBS_ERR_NONFINITE, "timing state terminated early");
     if (avg_ms) *avg_ms = ms / reps;
     if (bytes) {
-        // algorithmic bytes per launch: CSR (int32 index + fp64 value per stored
+        // algorithmic bytes per launch: CSR (int32 index + value per stored
         // entry, int32 row pointer) and every vector / block entry touched once
         const double n = (double)c->n, nnz = (double)c->nnz, kk = (double)k;
-        const double csr = 12.0 * nnz + 4.0 * (n + 1);
+        const double w = f32 ? 4.0 : 8.0;   // bytes per value
+        const double csr = (4.0 + w) * nnz + 4.0 * (n + 1);
         double v = 0.0;
-        if (which == 0) v = 80.0 * n + 8.0 * n * kk;
-        else if (which == 1) v = csr + 32.0 * n + 16.0 * n * kk;
-        else if (which == 2) v = csr + 24.0 * n + 8.0 * n * kk;
-        else v = csr + 16.0 * n;
+        if (pass == 0) v = 10.0 * w * n + w * n * kk;
+        else if (pass == 1) v = csr + 4.0 * w * n + 2.0 * w * n * kk;
+        else if (pass == 2) v = csr + 3.0 * w * n + w * n * kk;
+        else v = csr + 2.0 * w * n;
         *bytes = v;
     }
     return RBS_OK;

@@ -14,14 +14,18 @@ constexpr int MAX_SUMS = KMAX + 8;
 // row 64 s + l sits at slice_ptr[s] + 64 j + l.  Rows shorter than the
 // slice width are padded with (col = row, val = 0).  One wave reads one
 // slice, so every load is a fully coalesced 64-lane access.
-struct Sell {
+template <typename T>
+struct SellT {
     int64_t n = 0;
     int64_t nslices = 0;
     int64_t padded = 0;        // stored entries including padding
     int32_t* slice_ptr = nullptr;  // nslices + 1 (entry offsets; multiples of 64)
     int32_t* col = nullptr;
-    double* val = nullptr;
+    T* val = nullptr;
 };
+using Sell = SellT<double>;
+// FP32 copy of a matrix: same slices and column indices, values rounded to float
+using SellF = SellT<float>;
 
 // Device-resident scalars of one solve.  Written by the last block of each
 // fused kernel (deterministic fixed-order reductions), read by the next

@@ -22,6 +22,7 @@ void launch_fill(hipStream_t st, double* y, int64_t len, double v);
 void launch_copy(hipStream_t st, double* y, const double* x, int64_t len);
 // y = A x   (Sell)
 void launch_spmv(hipStream_t st, const Sell& A, const double* x, double* y);
+void launch_spmv(hipStream_t st, const SellF& A, const float* x, float* y);
 // Y[:, j] = A X[:, j], j < m (column-major, leading dimension ld)
 void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
                  int64_t ldy, int m);
@@ -36,27 +37,45 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
                   int my2, double* partial, double* out);
 
 // ---- solve kernels (Algorithm 2 / BiCGSTAB) -------------------------------
-struct SolveBufs {
+// T is the storage type of the vectors, blocks and matrix values of one solve:
+// double, or float for the FP32-storage inner solves of iterative refinement
+// (reductions and the scalar state stay FP64 either way).
+template <typename T>
+struct SolveBufsT {
     int64_t n, ld;
     int k;
-    Sell A, At;
-    const double *U, *C, *Chat, *Ct, *Ccheck, *Gh;
-    const double* b;
-    double* xout;          // caller's x (in: x_{-1} when x_nonzero; out: solution)
-    const double* shadow;  // rt_{-1} or nullptr (then r_{-1})
-    double *x, *r, *s, *t, *p, *q, *rt0, *rh;
+    SellT<T> A, At;
+    const T *U, *C, *Chat, *Ct, *Ccheck, *Gh;
+    const T* b;
+    T* xout;               // caller's x (in: x_{-1} when x_nonzero; out: solution)
+    const T* shadow;       // rt_{-1} or nullptr (then r_{-1})
+    T *x, *r, *s, *t, *p, *q, *rt0, *rh;
     SolveState* state;
     double* partials;      // per-block partial sums, value-major ((2 KMAX + 8) x 1024)
 };
-void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it);
-void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count);
-void launch_solve_epilogue(hipStream_t st, const SolveBufs& B);
+using SolveBufs = SolveBufsT<double>;
+using SolveBufsF = SolveBufsT<float>;
+template <typename T>
+void launch_solve_prologue(hipStream_t st, const SolveBufsT<T>& B, int x_nonzero, double rtol,
+                           int max_it);
+template <typename T>
+void launch_solve_iterations(hipStream_t st, const SolveBufsT<T>& B, int count);
+template <typename T>
+void launch_solve_epilogue(hipStream_t st, const SolveBufsT<T>& B);
 // Timing support: put the solve state in a non-terminating configuration
 // (done = 0, tolerance below zero, fixed bounded scalars) and launch the
 // main kernel of one of the fused passes (0 update, 1 spmv1, 2 spmv2; their
 // one-block finalize kernels are not launched) or 3, a plain SpMV y = A x.
 void launch_time_prep(hipStream_t st, SolveState* state);
-void launch_pass(hipStream_t st, const SolveBufs& B, int which);
+template <typename T>
+void launch_pass(hipStream_t st, const SolveBufsT<T>& B, int which);
+// y (float) = x (double) rounded, scaled by `scale`
+void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y);
+// x += scale * d  (x double, d float)
+void launch_add_float(hipStream_t st, int64_t n, double* x, const float* d, double scale);
+// r = b - A x (FP64); out_sums[0] = ||r||^2, out_sums[1] = ||b||^2
+void launch_residual(hipStream_t st, const Sell& A, const double* b, const double* x, double* r,
+                     double* partials, double* out_sums);
 
 // ---- RBiCG (Algorithm 1) kernels ------------------------------------------
 struct BicgBufs {

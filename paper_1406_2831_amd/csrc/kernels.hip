@@ -135,21 +135,22 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
 // flight instead of one dependent chain per entry.
 constexpr int SPMV_BATCH = 8;
 
-__device__ __forceinline__ double sell_row(const Sell& A, int64_t row, const double* __restrict__ x) {
+template <typename T>
+__device__ __forceinline__ T sell_row(const SellT<T>& A, int64_t row, const T* __restrict__ x) {
     const int64_t s = row / WAVE;
     const int lane = (int)(row & (WAVE - 1));
     const int32_t beg = A.slice_ptr[s];
     const int w = (A.slice_ptr[s + 1] - beg) / WAVE;
-    double acc = 0.0;
+    T acc = 0;
     for (int j0 = 0; j0 < w; j0 += SPMV_BATCH) {
         int32_t c[SPMV_BATCH];
-        double v[SPMV_BATCH];
+        T v[SPMV_BATCH];
 #pragma unroll
         for (int u = 0; u < SPMV_BATCH; ++u) {
             const int j = (j0 + u < w) ? j0 + u : w - 1;
             const int32_t e = beg + j * WAVE + lane;
             c[u] = A.col[e];
-            v[u] = (j0 + u < w) ? A.val[e] : 0.0;
+            v[u] = (j0 + u < w) ? A.val[e] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < SPMV_BATCH; ++u) acc += v[u] * x[c[u]];
@@ -246,8 +247,9 @@ __global__ __launch_bounds__(BLOCK) void k_copy(double* __restrict__ y, const do
         y[i] = x[i];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_spmv(Sell A, const double* __restrict__ x,
-                                                double* __restrict__ y) {
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_spmv(SellT<T> A, const T* __restrict__ x,
+                                                T* __restrict__ y) {
     int64_t r0, r1;
     block_rows(A.n, r0, r1);
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) y[row] = sell_row(A, row, x);
@@ -505,8 +507,8 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
 // kernel (a single block) sums them in block order and updates the scalars.
 
 // P1: r_{-1} = b - A x_{-1}; sums ||b||^2, Chat^T r_{-1}, Ccheck^T rt_{-1}
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufsT<T> B, int xnz) {
     constexpr int M = 2 * K + 1;
     const int k = B.k;
     int64_t r0, r1;
@@ -530,8 +532,8 @@ __global__ __launch_bounds__(BLOCK) void k_pro1(SolveBufs B, int xnz) {
     block_partial<M>(acc, M, B.partials);
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_pro1_fin(SolveBufs B, int nb, double rtol, int max_it) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_pro1_fin(SolveBufsT<T> B, int nb, double rtol, int max_it) {
     constexpr int M = 2 * K + 1;
     __shared__ double tot[M];
     const int k = B.k;
@@ -559,8 +561,8 @@ __global__ __launch_bounds__(BLOCK) void k_pro1_fin(SolveBufs B, int nb, double 
 
 // P2: eq. (minusXR): x_0 = x_{-1} + U zeta_0, r_0 = r_{-1} - C zeta_0,
 //     rt_0 = rt_{-1} - Ct (Ccheck^T rt_{-1}); sums ||r_0||^2, (rt_0, r_0), C^T rt_0
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufsT<T> B, int xnz) {
     constexpr int M = K + 2;
     SolveState* st = B.state;
     if (st->done) return;
@@ -602,8 +604,8 @@ __global__ __launch_bounds__(BLOCK) void k_pro2(SolveBufs B, int xnz) {
     block_partial<M>(acc, M, B.partials);
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufs B, int nb) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufsT<T> B, int nb) {
     constexpr int M = K + 2;
     __shared__ double tot[M];
     SolveState* st = B.state;
@@ -634,8 +636,8 @@ __global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufs B, int nb) {
 }
 
 // update pass (end of iteration i-1 and start of iteration i)
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B) {
     constexpr int M = K + 3;
     SolveState* st = B.state;
     if (st->done) return;
@@ -662,8 +664,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufs B) {
     block_partial<M>(acc, M, B.partials);
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufs B, int nb) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufsT<T> B, int nb) {
     constexpr int M = K + 3;
     __shared__ double tot[M];
     SolveState* st = B.state;
@@ -713,8 +715,8 @@ __global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufs B, int nb) {
 }
 
 // spmv1: q = A p - C zeta ; s = r - alpha q ; gamma partials Gh^T s
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufs B) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B) {
     constexpr int M = K > 0 ? K : 1;
     SolveState* st = B.state;
     if (st->done) return;
@@ -741,8 +743,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufs B) {
     if (K > 0) block_partial<M>(acc, M, B.partials);
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv1_fin(SolveBufs B, int nb) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv1_fin(SolveBufsT<T> B, int nb) {
     constexpr int M = K > 0 ? K : 1;
     __shared__ double tot[M];
     SolveState* st = B.state;
@@ -753,8 +755,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1_fin(SolveBufs B, int nb) {
 }
 
 // spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufs B) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B) {
     constexpr int M = 5;
     SolveState* st = B.state;
     if (st->done) return;
@@ -780,7 +782,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufs B) {
     block_partial<M>(acc, M, B.partials);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_spmv2_fin(SolveBufs B, int nb) {
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_spmv2_fin(SolveBufsT<T> B, int nb) {
     constexpr int M = 5;
     __shared__ double tot[M];
     SolveState* st = B.state;
@@ -809,8 +812,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2_fin(SolveBufs B, int nb) {
 }
 
 // epilogue: x_out = x - U x_c (Algorithm 2 step 8)
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_epi(SolveBufs B) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_epi(SolveBufsT<T> B) {
     const SolveState* st = B.state;
     const int k = B.k;
     double xc[K > 0 ? K : 1];
@@ -848,6 +851,37 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
         out[0] = tot[0];
         out[1] = tot[1];
     }
+}
+
+// ---------------------------------------------------------------- iterative refinement support
+
+__global__ __launch_bounds__(BLOCK) void k_to_float(int64_t n, const double* __restrict__ x,
+                                                    double scale, float* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        y[i] = (float)(x[i] * scale);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_add_float(int64_t n, double* __restrict__ x,
+                                                     const float* __restrict__ d, double scale) {
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        x[i] += scale * (double)d[i];
+}
+
+// r = b - A x in FP64 with ||r||^2 and ||b||^2 (block partials)
+__global__ __launch_bounds__(BLOCK) void k_residual(Sell A, const double* __restrict__ b,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ r, double* partials) {
+    int64_t r0, r1;
+    block_rows(A.n, r0, r1);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+        const double bv = b[row];
+        const double rv = bv - sell_row(A, row, x);
+        r[row] = rv;
+        acc[0] += rv * rv;
+        acc[1] += bv * bv;
+    }
+    block_partial<2>(acc, 2, partials);
 }
 
 // ---------------------------------------------------------------- adjoint support
@@ -1281,16 +1315,27 @@ void dispatch_k(int k, Args&&... args) {
         }                                                                                    \
     };
 
-RBS_LAUNCHER(L_pro1, k_pro1, SolveBufs, false)
-RBS_LAUNCHER(L_pro1_fin, k_pro1_fin, SolveBufs, true)
-RBS_LAUNCHER(L_pro2, k_pro2, SolveBufs, false)
-RBS_LAUNCHER(L_pro2_fin, k_pro2_fin, SolveBufs, true)
-RBS_LAUNCHER(L_update, k_update, SolveBufs, false)
-RBS_LAUNCHER(L_update_fin, k_update_fin, SolveBufs, true)
-RBS_LAUNCHER(L_spmv1, k_spmv1, SolveBufs, false)
-RBS_LAUNCHER(L_spmv1_fin, k_spmv1_fin, SolveBufs, true)
-RBS_LAUNCHER(L_spmv2, k_spmv2, SolveBufs, false)
-RBS_LAUNCHER(L_epi, k_epi, SolveBufs, false)
+// the same for kernels templated on the storage type T of SolveBufsT<T>
+#define RBS_LAUNCHER_T(NAME, KERNEL, GRID_IS_ONE)                                          \
+    template <int K>                                                                         \
+    struct NAME {                                                                            \
+        template <typename T, typename... A>                                                 \
+        static void run(hipStream_t st, int grid, const SolveBufsT<T>& B, A... a) {          \
+            hipLaunchKernelGGL((KERNEL<T, K>), dim3(GRID_IS_ONE ? 1 : grid), dim3(BLOCK), 0, st, \
+                               B, a...);                                                     \
+        }                                                                                    \
+    };
+
+RBS_LAUNCHER_T(L_pro1, k_pro1, false)
+RBS_LAUNCHER_T(L_pro1_fin, k_pro1_fin, true)
+RBS_LAUNCHER_T(L_pro2, k_pro2, false)
+RBS_LAUNCHER_T(L_pro2_fin, k_pro2_fin, true)
+RBS_LAUNCHER_T(L_update, k_update, false)
+RBS_LAUNCHER_T(L_update_fin, k_update_fin, true)
+RBS_LAUNCHER_T(L_spmv1, k_spmv1, false)
+RBS_LAUNCHER_T(L_spmv1_fin, k_spmv1_fin, true)
+RBS_LAUNCHER_T(L_spmv2, k_spmv2, false)
+RBS_LAUNCHER_T(L_epi, k_epi, false)
 RBS_LAUNCHER(L_bpro1, k_bpro1, BicgBufs, false)
 RBS_LAUNCHER(L_bpro1_fin, k_bpro1_fin, BicgBufs, true)
 RBS_LAUNCHER(L_bpro2, k_bpro2, BicgBufs, false)
@@ -1343,7 +1388,10 @@ void launch_copy(hipStream_t st, double* y, const double* x, int64_t len) {
 }
 
 void launch_spmv(hipStream_t st, const Sell& A, const double* x, double* y) {
-    hipLaunchKernelGGL(k_spmv, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, x, y);
+    hipLaunchKernelGGL(k_spmv<double>, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, x, y);
+}
+void launch_spmv(hipStream_t st, const SellF& A, const float* x, float* y) {
+    hipLaunchKernelGGL(k_spmv<float>, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, x, y);
 }
 
 void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
@@ -1419,7 +1467,9 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
     }
 }
 
-void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, double rtol, int max_it) {
+template <typename T>
+void launch_solve_prologue(hipStream_t st, const SolveBufsT<T>& B, int x_nonzero, double rtol,
+                           int max_it) {
     const int g = stream_grid(B.n);
     dispatch_k<L_pro1>(B.k, st, g, B, x_nonzero);
     dispatch_k<L_pro1_fin>(B.k, st, g, B, g, rtol, max_it);
@@ -1428,7 +1478,8 @@ void launch_solve_prologue(hipStream_t st, const SolveBufs& B, int x_nonzero, do
     launch_spmv(st, B.At, B.rt0, B.rh);   // rh = A^T rt_0
 }
 
-void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count) {
+template <typename T>
+void launch_solve_iterations(hipStream_t st, const SolveBufsT<T>& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
         dispatch_k<L_update>(B.k, st, g, B);
@@ -1436,7 +1487,7 @@ void launch_solve_iterations(hipStream_t st, const SolveBufs& B, int count) {
         dispatch_k<L_spmv1>(B.k, st, g, B);
         if (B.k > 0) dispatch_k<L_spmv1_fin>(B.k, st, g, B, g);
         dispatch_k<L_spmv2>(B.k, st, g, B);
-        hipLaunchKernelGGL(k_spmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
+        hipLaunchKernelGGL(k_spmv2_fin<T>, dim3(1), dim3(BLOCK), 0, st, B, g);
     }
 }
 
@@ -1444,7 +1495,8 @@ void launch_time_prep(hipStream_t st, SolveState* state) {
     hipLaunchKernelGGL(k_time_prep, dim3(1), dim3(1), 0, st, state);
 }
 
-void launch_pass(hipStream_t st, const SolveBufs& B, int which) {
+template <typename T>
+void launch_pass(hipStream_t st, const SolveBufsT<T>& B, int which) {
     const int g = stream_grid(B.n);
     if (which == 0) dispatch_k<L_update>(B.k, st, g, B);
     else if (which == 1) dispatch_k<L_spmv1>(B.k, st, g, B);
@@ -1452,7 +1504,8 @@ void launch_pass(hipStream_t st, const SolveBufs& B, int which) {
     else launch_spmv(st, B.A, B.p, B.q);
 }
 
-void launch_solve_epilogue(hipStream_t st, const SolveBufs& B) {
+template <typename T>
+void launch_solve_epilogue(hipStream_t st, const SolveBufsT<T>& B) {
     dispatch_k<L_epi>(B.k, st, stream_grid(B.n), B);
 }
 
@@ -1460,6 +1513,21 @@ void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const 
                           double* partials, double* out_sums) {
     const int g = stream_grid(A.n);
     hipLaunchKernelGGL(k_true_res, dim3(g), dim3(BLOCK), 0, st, A, b, x, partials);
+    hipLaunchKernelGGL(k_true_res_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sums);
+}
+
+void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y) {
+    hipLaunchKernelGGL(k_to_float, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, x, scale, y);
+}
+
+void launch_add_float(hipStream_t st, int64_t n, double* x, const float* d, double scale) {
+    hipLaunchKernelGGL(k_add_float, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, x, d, scale);
+}
+
+void launch_residual(hipStream_t st, const Sell& A, const double* b, const double* x, double* r,
+                     double* partials, double* out_sums) {
+    const int g = stream_grid(A.n);
+    hipLaunchKernelGGL(k_residual, dim3(g), dim3(BLOCK), 0, st, A, b, x, r, partials);
     hipLaunchKernelGGL(k_true_res_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sums);
 }
 
@@ -1515,5 +1583,15 @@ void launch_bicg_epilogue(hipStream_t st, const BicgBufs& B) {
 void launch_bicg_reset_cycle(hipStream_t st, BicgState* state) {
     hipLaunchKernelGGL(k_bicg_reset, dim3(1), dim3(1), 0, st, state);
 }
+
+// the solve launchers for the two storage types
+template void launch_solve_prologue<double>(hipStream_t, const SolveBufsT<double>&, int, double, int);
+template void launch_solve_prologue<float>(hipStream_t, const SolveBufsT<float>&, int, double, int);
+template void launch_solve_iterations<double>(hipStream_t, const SolveBufsT<double>&, int);
+template void launch_solve_iterations<float>(hipStream_t, const SolveBufsT<float>&, int);
+template void launch_solve_epilogue<double>(hipStream_t, const SolveBufsT<double>&);
+template void launch_solve_epilogue<float>(hipStream_t, const SolveBufsT<float>&);
+template void launch_pass<double>(hipStream_t, const SolveBufsT<double>&, int);
+template void launch_pass<float>(hipStream_t, const SolveBufsT<float>&, int);
 
 }  // namespace rbs

@@ -34,6 +34,7 @@ RBS_RBICGSTAB = 0
 RBS_BICGSTAB = 1
 RBS_RBICG_GEN = 2
 RBS_TRANSPOSE = 8
+RBS_FP32_IR = 16
 
 RBS_RECYCLE_SET = 0
 RBS_RECYCLE_FROM_LAST_SOLVE = 1
@@ -51,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("matvecs_A", ctypes.c_int32), ("matvecs_At", ctypes.c_int32),
                 ("k_used", ctypes.c_int32), ("ritz_updates", ctypes.c_int32),
                 ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("ir_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -250,9 +251,11 @@ class Context:
         return self
 
     def solve(self, b, x=None, x_nonzero=False, shadow=None, rtol=1e-8, max_it=10000,
-              mode: str = "rbicgstab", transpose: bool = False):
+              mode: str = "rbicgstab", transpose: bool = False, precision: str = "fp64"):
+        """precision: "fp64", or "fp32_ir" (FP32 storage under FP64 iterative refinement)."""
         flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB,
                  "rbicg": RBS_RBICG_GEN}[mode] | (RBS_TRANSPOSE if transpose else 0)
+        flags |= {"fp64": 0, "fp32_ir": RBS_FP32_IR}[precision]
         if x is None:
             x = torch.zeros_like(b)
         st = rbicgstab_solve(self.handle, b, x, x_nonzero, shadow, rtol, max_it, flags)

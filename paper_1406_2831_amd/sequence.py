@@ -59,7 +59,9 @@ class GpuSequence:
                      for _ in range(seq.num_systems)]
 
     def run(self, mode: str = "rbicgstab", rtol: float = 1e-8, max_it: int = 20000,
-            systems: Optional[int] = None) -> GpuSequenceResult:
+            systems: Optional[int] = None, precision: str = "fp64") -> GpuSequenceResult:
+        """precision applies to the RBiCGSTAB / BiCGSTAB solves ("fp64" or
+        "fp32_ir"); RBiCG and the recycle-space update always run in FP64."""
         seq, ctx = self.seq, self.ctx
         out = GpuSequenceResult()
         last = seq.num_systems if systems is None else min(systems, seq.num_systems)
@@ -77,7 +79,8 @@ class GpuSequence:
             b, sh, x = self.rhs[idx], self.shadows[idx], self.xbuf[idx]
             x.zero_()
             if mode == "bicgstab":
-                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="bicgstab")
+                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="bicgstab",
+                                  precision=precision)
                 solver = "bicgstab"
             elif j == 0 and self.k > 0:
                 _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicg")
@@ -86,7 +89,8 @@ class GpuSequence:
                 out.setup_matvecs += ma + mat
                 solver = "rbicg"
             else:
-                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicgstab")
+                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicgstab",
+                                  precision=precision)
                 solver = "rbicgstab"
             if self.keep_x:
                 out.x.append(x)

@@ -322,3 +322,48 @@ def test_generated_space_full_size_3d(rb, torch_mod):
     # within the rounding-level spread between runs: require no loss
     assert st_g.iters <= st_0.iters + 5
     ctx.close()
+
+
+def test_fp32_ir_matches_fp64(rb, torch_mod, c0):
+    """FP32 storage + FP64 refinement: true FP64 residual <= rtol and the
+    solution within kappa * rtol of the oracle's FP64 solution, with and
+    without a recycle space; the error against FP64 is reported."""
+    seq, A, At = c0
+    As = A.to_scipy()
+    lam, vl, vr = sla.eig(As.toarray(), left=True, right=True)
+    order = np.argsort(np.abs(lam))
+    _say("fp32 ir 2d")
+    ctx = _ctx(rb, A, At, k_max=8, s_max=0)
+    b, sh = seq.rhs[1], seq.shadows[1]
+    xo, io = o.bicgstab(As, b, shadow=sh, rtol=1e-12)
+    for mode in ("bicgstab", "rbicgstab"):
+        if mode == "rbicgstab":
+            ctx.recycle("set", torch_mod.as_tensor(np.ascontiguousarray(vr[:, order[:8]].real.T), device="cuda"),
+                        torch_mod.as_tensor(np.ascontiguousarray(vl[:, order[:8]].real.T), device="cuda"))
+        bt = torch_mod.as_tensor(b, device="cuda")
+        x = torch_mod.zeros_like(bt)
+        _, st = ctx.solve(bt, x, shadow=torch_mod.as_tensor(sh, device="cuda"), rtol=1e-10,
+                          max_it=5000, mode=mode, precision="fp32_ir")
+        err = _rel(x.cpu().numpy(), xo)
+        print(f"fp32_ir {mode}: status {st.status} inner iters {st.iters} outer steps {st.ir_steps} "
+              f"true rel res {st.rel_res_true:.2e} error vs fp64 {err:.2e}", flush=True)
+        assert st.status == 0 and st.rel_res_true <= 1e-10
+        assert st.ir_steps >= 2 and st.k_used == (8 if mode == "rbicgstab" else 0)
+        assert err <= 1e-6
+    ctx.close()
+
+
+def test_fp32_ir_sequence_3d(rb, torch_mod):
+    """The recycled sequence pipeline with FP32-IR solves on a ragged grid."""
+    from paper_1406_2831_amd.sequence import GpuSequence
+    seq = w.seq_3d(N=23, nshift=2, nrhs=3, k=12)
+    _say("fp32 ir sequence 3d N=23")
+    gs = GpuSequence(seq, s_max=512)
+    res = gs.run(mode="rbicgstab", rtol=1e-10, precision="fp32_ir")
+    print(f"iters {res.iters} k {res.k_used} status {res.status}", flush=True)
+    assert all(s == 0 for s in res.status) and max(res.rel_res_true) <= 1e-10
+    for idx, x in enumerate(res.x):
+        A, _ = seq.matrix(seq.system(idx)[0])
+        xr, ir = o.bicgstab(A.to_scipy(), seq.rhs[idx], shadow=seq.shadows[idx], rtol=1e-12)
+        assert _rel(x.cpu().numpy(), xr) <= 1e-6, idx
+    gs.close()
