@@ -7,8 +7,12 @@ right-hand sides (20 systems), recycle dimension k = 20, true relative
 residual 1e-8.  One step = the whole sequence: per shift the matrix setup
 (sliced copy, C = A U, Ct = A^T Ut, bi-orthogonalisation), RBiCG on the first
 right-hand side with the recycle-space update from its Lanczos vectors, and
-RBiCGSTAB on the other three.  The same sequence is also timed with plain
-BiCGSTAB on the same kernels (the baseline the metric compares against).
+RBiCGSTAB on the other three, solved together (the same iterates as three
+separate solves, with the matrix and block reads shared).  The same sequence
+is also timed with plain BiCGSTAB on the same kernels (the baseline the
+metric compares against, its four right-hand sides per matrix solved
+together), and both again one system at a time and with FP32 storage under
+FP64 refinement.
 
 Prints one JSON line.  Inputs are generated and uploaded before timing.
 """
@@ -106,27 +110,26 @@ def main():
     gs = GpuSequence(seq, s_max=512, secant_max=args.secant_max)
     nsys = seq.num_systems
 
-    def run(mode, precision="fp64"):
-        return gs.run(mode=mode, rtol=args.rtol, precision=precision)
+    def run(mode, precision="fp64", multi=False):
+        return gs.run(mode=mode, rtol=args.rtol, precision=precision, multi_rhs=multi)
 
-    for _ in range(args.warmup):
-        run("rbicgstab")
-        run("bicgstab")
-    timed = {}
-    results = {}
-    passes = {}
-    x64 = None
-    modes = [("rbicgstab", "fp64"), ("bicgstab", "fp64")]
+    # variants of the same sequence: (key, solver mode, precision, multi-RHS)
+    variants = [("rbicgstab", "rbicgstab", "fp64", True), ("bicgstab", "bicgstab", "fp64", True),
+                ("rbicgstab_single", "rbicgstab", "fp64", False),
+                ("bicgstab_single", "bicgstab", "fp64", False)]
     if not args.no_fp32:
-        modes += [("rbicgstab", "fp32_ir"), ("bicgstab", "fp32_ir")]
-    for mode, prec in modes:
-        key = mode if prec == "fp64" else f"{mode}_fp32_ir"
-        if prec != "fp64" and args.warmup:
-            run(mode, prec)
+        variants += [("rbicgstab_fp32_ir", "rbicgstab", "fp32_ir", False),
+                     ("bicgstab_fp32_ir", "bicgstab", "fp32_ir", False)]
+    for _ in range(args.warmup):
+        for _key, mode, prec, multi in variants:
+            run(mode, prec, multi)
+    timed, results, passes = {}, {}, {}
+    x64 = None
+    for key, mode, prec, multi in variants:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            results[key] = run(mode, prec)
+            results[key] = run(mode, prec, multi)
         torch.cuda.synchronize()
         timed[key] = (time.perf_counter() - t0) / args.steps
         res = results[key]
@@ -137,28 +140,37 @@ def main():
             sys.exit(1)
         if key == "rbicgstab":
             x64 = [x.clone() for x in res.x]
-        elif prec == "fp32_ir":
-            # error of each FP32-storage result against the FP64 pipeline's
-            res.err_vs_fp64 = [float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
-                               for x, xr in zip(res.x, x64)]
-        if key == "rbicgstab":
-            # live per-kernel timing of the fused passes at the installed space's k
+            # live per-kernel timing of the fused passes at the installed space's k:
+            # the multi-RHS passes for the last matrix's right-hand sides, the
+            # single-system passes (FP64 and FP32 storage) and a plain product
             k_last = int(res.k_used[-1])
-            for name, which, kk in (("spmv1_project", 1, k_last), ("update", 0, k_last),
+            nr = seq.nrhs - 1
+            for name, which, kk in (("mspmv1_project", 8 + 4 * (nr - 1) + 1, k_last),
+                                    ("mupdate", 8 + 4 * (nr - 1), k_last),
+                                    ("mspmv2_project", 8 + 4 * (nr - 1) + 2, k_last),
+                                    ("spmv1_project", 1, k_last), ("update", 0, k_last),
                                     ("spmv2_project", 2, k_last), ("spmv", 3, 0),
                                     ("spmv1_project_fp32", 5, k_last), ("update_fp32", 4, k_last),
                                     ("spmv2_project_fp32", 6, k_last), ("spmv_fp32", 7, 0)):
                 passes[name] = gs.ctx.time_pass(which, kk, args.time_reps)
+        elif prec == "fp32_ir":
+            # error of each FP32-storage result against the FP64 pipeline's
+            res.err_vs_fp64 = [float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
+                               for x, xr in zip(res.x, x64)]
 
     rres = results["rbicgstab"]
-    ms_spmv1, bytes_spmv1 = passes["spmv1_project"]
-    ms_upd, bytes_upd = passes["update"]
-    ms_spmv2, bytes_spmv2 = passes["spmv2_project"]
-    ms_spmv, bytes_spmv = passes["spmv"]
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
-    achieved = gbs(bytes_spmv1, ms_spmv1)
-    dom_kernel = f"k_spmv1<{k_bucket(k_last)}>"
+    ms_dom, bytes_dom = passes["mspmv1_project"]
+    ms_spmv, bytes_spmv = passes["spmv"]
+    achieved = gbs(bytes_dom, ms_dom)
+    kb = k_bucket(k_last)
+    dom_kernel = f"k_mspmv1<{kb}>"
     traffic = counter_traffic(dom_kernel)
+
+    def summary(key):
+        r = results[key]
+        return {"systems_per_s": nsys / timed[key], "ms_per_step": timed[key] * 1e3, "iters": r.iters,
+                "matvecs": r.total_matvecs, "max_rel_res_true": max(r.rel_res_true)}
 
     out = {
         "metric": "systems solved/s + SpMV HBM GB/s at rel.res 1e-8, RBiCGSTAB vs BiCGSTAB",
@@ -174,23 +186,20 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3d 7-point convection-diffusion {args.grid}^3 (n={seq.n}), "
-                               f"5 shifts x 4 rhs = {nsys} systems, k={args.k}, rtol={args.rtol}",
+                               f"5 shifts x 4 rhs = {nsys} systems, k={args.k}, rtol={args.rtol}; "
+                               f"per shift RBiCG on rhs 1, RBiCGSTAB on rhs 2-4 solved together",
                    "n": seq.n, "nnz": int(seq.K.nnz), "systems": nsys, "k": args.k},
-        "bicgstab": {"systems_per_s": nsys / timed["bicgstab"],
-                     "ms_per_step": timed["bicgstab"] * 1e3,
-                     "iters": results["bicgstab"].iters,
-                     "matvecs": results["bicgstab"].total_matvecs},
-        "rbicgstab": {"iters": rres.iters, "solver": rres.solver, "k_used": rres.k_used,
-                      "matvecs": rres.total_matvecs,
-                      "max_rel_res_true": max(rres.rel_res_true)},
+        "rbicgstab": dict(summary("rbicgstab"), solver=rres.solver, k_used=rres.k_used),
+        "bicgstab": summary("bicgstab"),
         "rbicgstab_over_bicgstab_time": timed["rbicgstab"] / timed["bicgstab"],
+        "single_rhs": {"rbicgstab": summary("rbicgstab_single"), "bicgstab": summary("bicgstab_single")},
         "spmv_gbs": gbs(bytes_spmv, ms_spmv),
         "passes": dict({name: {"us": ms * 1e3, "gbs": gbs(by, ms)} for name, (ms, by) in passes.items()},
-                       k=k_last),
+                       k=k_last, multi_nrhs=seq.nrhs - 1),
         "roofline": {"bound": "hbm", "kernel": dom_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_spmv1, "us_per_launch": ms_spmv1 * 1e3},
+                     "bytes_per_launch": bytes_dom, "us_per_launch": ms_dom * 1e3},
     }
     # a plain device-to-device copy of known size (outside the timed region):
     # the reference the HBM counters of a profiled run are calibrated with

@@ -154,6 +154,28 @@ int rbicgstab_solve(rbs_ctx* ctx, const double* b, double* x, int32_t x_nonzero,
                     rbs_stats* stats);
 
 /*
+ * Solve nrhs systems A x_j = b_j with the bound matrix and the installed
+ * recycle space together (Section 6.2: the right-hand sides of one matrix
+ * after the first are independent given the space).  Each fused pass reads A,
+ * C and A^T Chat once for all systems, so the matrix and projection traffic
+ * is shared.  Initial guesses are zero (x_{-1} = 0).
+ *  nrhs     1..8
+ *  B, X     device, n x nrhs column-major with leading dimensions ldb, ldx >= n
+ *           (X is output only)
+ *  shadows  device, n x nrhs with leading dimension ldb, or NULL (rt_{-1} = r_{-1})
+ *  flags    RBS_RBICGSTAB or RBS_BICGSTAB (FP64)
+ *  stats    host array of nrhs (may be NULL); stats[j].ms is the whole call
+ * Systems stop updating as they converge; one whose true residual misses rtol
+ * is finished alone from its iterate (counted as a restart).  The fused
+ * passes carry 4 systems (one wavefront each per workgroup); more are solved
+ * in groups of 4.  Returns RBS_OK if every system converged, else the first
+ * numerical outcome (> 0) or an error (< 0).
+ */
+int rbicgstab_solve_multi(rbs_ctx* ctx, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                          int64_t ldx, const double* shadows, double rtol, int32_t max_it,
+                          int32_t flags, rbs_stats* stats);
+
+/*
  * Change the recycle space (Section 6.2: the space built while solving one
  * system is used for the next ones). SET copies U, Ut (device, n x k, ld = n,
  * 1 <= k <= k_max) into the context; FROM_LAST_SOLVE installs the space the
@@ -173,7 +195,9 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  * installed k): which = 0 the update pass, 1 the first SpMV + projection
  * pass, 2 the second SpMV + projection pass (their one-block finalize
  * kernels are not included), 3 a plain SpMV; which = 4..7 the same passes
- * with the FP32 storage of RBS_FP32_IR (4-byte values and vector entries).  The pass is launched `reps` times
+ * with the FP32 storage of RBS_FP32_IR (4-byte values and vector entries);
+ * which = 8 + 4 (nr - 1) + pass (pass 0..2) the multi-RHS pass of
+ * rbicgstab_solve_multi for nr systems (nr, k in its fused range).  The pass is launched `reps` times
  * back to back on the context's stream between two HIP events; *avg_ms
  * receives the mean duration per launch and *bytes the algorithmic bytes
  * one launch moves (CSR: 12 bytes per stored entry + 4 per row pointer;

@@ -35,6 +35,7 @@ struct PinnedStatus {
     SolveState solve;
     BicgState bicg;
     double sums[4];
+    SolveState multi[rbs::MULTI_MAX];
 };
 
 }  // namespace
@@ -63,6 +64,10 @@ struct rbs_ctx {
           *rt0f = nullptr, *rhf = nullptr, *bf = nullptr, *df = nullptr, *shf = nullptr;
     double* r64 = nullptr;   // FP64 residual of the refinement loop
     bool f32_valid = false;
+    // multi-RHS solves: n x MULTI_MAX vector blocks (ld) and one state per system
+    double *mx = nullptr, *mr = nullptr, *ms = nullptr, *mt = nullptr, *mp = nullptr, *mq = nullptr,
+           *mrt0 = nullptr, *mrh = nullptr;
+    SolveState* mst = nullptr;
     double* GhT = nullptr;   // A Ccheck: the Gh block of the transposed system
     bool ght_valid = false;
     double *x = nullptr, *r = nullptr, *s = nullptr, *t = nullptr, *p = nullptr, *q = nullptr,
@@ -153,6 +158,9 @@ size_t carve(rbs_ctx* c, char* base) {
                       &c->shf})
         *v = cv.take<float>(ld);
     c->r64 = cv.take<double>(ld);
+    for (double** v : {&c->mx, &c->mr, &c->ms, &c->mt, &c->mp, &c->mq, &c->mrt0, &c->mrh})
+        *v = cv.take<double>(ld * rbs::MULTI_MAX);
+    c->mst = cv.take<SolveState>(rbs::MULTI_MAX);
     double** blocks[] = {&c->U, &c->Ut, &c->C, &c->Ct, &c->Chat, &c->Ccheck, &c->Gh,
                          &c->T1, &c->T2, &c->T3, &c->GhT};
     for (double** b : blocks) *b = cv.take<double>(std::max<int64_t>(kb, 1));
@@ -171,7 +179,7 @@ size_t carve(rbs_ctx* c, char* base) {
     c->gpart_doubles = std::max(rbs::gemmt_partial_doubles(c->n, (int)mmax, (int)(2 * mmax)),
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
     c->gpart = cv.take<double>(c->gpart_doubles);
-    c->partials = cv.take<double>((size_t)1024 * (2 * rbs::KMAX + 8));
+    c->partials = cv.take<double>((size_t)1024 * rbs::PARTIAL_ROWS);
     c->partials2 = cv.take<double>((size_t)1024 * (2 * rbs::KMAX + 8));
     c->st = cv.take<SolveState>(1);
     c->bst = cv.take<BicgState>(1);
@@ -604,6 +612,125 @@ int solve_ir(rbs_ctx* c, int k, const double* b, double* x, int xnz, const doubl
     return status;
 }
 
+// ---------------------------------------------------------------- same-matrix multi-RHS
+
+// Single-system view of system j of the multi-RHS storage (for the prologue
+// and epilogue, which run per system).
+rbs::SolveBufs multi_sys_bufs(rbs_ctx* c, int k, int j, const double* b, double* xout,
+                              const double* shadow) {
+    rbs::SolveBufs B = solve_bufs(c, k, b, xout, shadow);
+    const int64_t o = (int64_t)j * c->ld;
+    B.x = c->mx + o;
+    B.r = c->mr + o;
+    B.s = c->ms + o;
+    B.t = c->mt + o;
+    B.p = c->mp + o;
+    B.q = c->mq + o;
+    B.rt0 = c->mrt0 + o;
+    B.rh = c->mrh + o;
+    B.state = c->mst + j;
+    return B;
+}
+
+rbs::MultiBufs multi_bufs(rbs_ctx* c, int k, int nr) {
+    rbs::MultiBufs M;
+    M.n = c->n;
+    M.ld = c->ld;
+    M.k = k;
+    M.nr = nr;
+    M.A = c->A;
+    M.C = c->C;
+    M.Gh = c->Gh;
+    M.x = c->mx;
+    M.r = c->mr;
+    M.s = c->ms;
+    M.t = c->mt;
+    M.p = c->mp;
+    M.q = c->mq;
+    M.rt0 = c->mrt0;
+    M.rh = c->mrh;
+    M.state = c->mst;
+    M.partials = c->partials;
+    return M;
+}
+
+// nr systems A x_j = b_j (same bound matrix, same recycle space, zero initial
+// guesses) advanced together: each pass reads A, C and Gh once for all of
+// them.  Systems that converge stop updating; a system whose true residual
+// misses rtol is finished by the single-system solver from its iterate.
+int solve_multi(rbs_ctx* c, int k, int nr, const double* B, int64_t ldb, double* X, int64_t ldx,
+                const double* shadows, double rtol, int max_it, rbs_stats* stats) {
+    hipStream_t s = c->stream;
+    for (int j = 0; j < nr; ++j) {
+        rbs::SolveBufs Bj = multi_sys_bufs(c, k, j, B + j * ldb, X + j * ldx,
+                                           shadows ? shadows + j * ldb : nullptr);
+        rbs::launch_solve_prologue(s, Bj, 0, rtol, max_it);
+    }
+    rbs::MultiBufs M = multi_bufs(c, k, nr);
+    auto all_done = [&]() {
+        for (int j = 0; j < nr; ++j)
+            if (!c->hp->multi[j].done) return false;
+        return true;
+    };
+    auto poll = [&]() -> int {
+        HIPCHK(c, hipMemcpy2DAsync(c->hp->multi, sizeof(SolveState), c->mst, sizeof(SolveState), 128, nr,
+                                   hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipEventRecord(c->ev[0], s));
+        return RBS_OK;
+    };
+    int rc;
+    rbs::launch_multi_iterations(s, M, CHUNK);
+    if ((rc = poll())) return rc;
+    int enq = CHUNK;
+    while (true) {
+        rbs::launch_multi_iterations(s, M, CHUNK);
+        enq += CHUNK;
+        HIPCHK(c, hipEventSynchronize(c->ev[0]));
+        if (all_done()) break;
+        if (enq > max_it + 4 * CHUNK) break;   // the device stops at max_it; safety net only
+        if ((rc = poll())) return rc;
+    }
+    HIPCHK(c, hipGetLastError());
+    int worst = RBS_OK;
+    for (int j = 0; j < nr; ++j) {
+        rbs::SolveBufs Bj = multi_sys_bufs(c, k, j, B + j * ldb, X + j * ldx, nullptr);
+        rbs::launch_solve_epilogue(s, Bj);
+        rbs::launch_true_residual(s, c->A, B + j * ldb, X + j * ldx, c->partials, c->dsums);
+        HIPCHK(c, hipGetLastError());
+        if ((rc = to_host(c, c->hp->sums, c->dsums, 2 * sizeof(double)))) return rc;
+        HIPCHK(c, hipMemcpy(&c->hp->solve, c->mst + j, 128, hipMemcpyDeviceToHost));
+        const SolveState h = c->hp->solve;
+        const double b2 = c->hp->sums[1];
+        double rel_true = b2 > 0 ? std::sqrt(c->hp->sums[0] / b2) : std::sqrt(c->hp->sums[0]);
+        int status = h.done ? h.status : RBS_MAXIT;
+        rbs_stats st{};
+        st.iters = h.iters_done;
+        st.total_iters = h.iters_done;
+        st.matvecs_A = 2 * h.iters_done + 1;
+        st.matvecs_At = 1;
+        st.k_used = k;
+        st.rel_res_recur = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+        st.rel_res_true = rel_true;
+        if (status == RBS_OK && !(rel_true <= rtol)) {
+            // finish this system alone from its iterate (true-residual restart)
+            rbs_stats s2{};
+            status = solve_rbicgstab(c, k, B + j * ldb, X + j * ldx, 1,
+                                     shadows ? shadows + j * ldb : nullptr, rtol, max_it, &s2);
+            if (status < 0) return status;
+            st.total_iters += s2.total_iters;
+            st.restarts = 1 + s2.restarts;
+            st.matvecs_A += s2.matvecs_A;
+            st.matvecs_At += s2.matvecs_At;
+            st.rel_res_true = s2.rel_res_true;
+            st.rel_res_recur = s2.rel_res_recur;
+        }
+        st.status = status;
+        if (stats) stats[j] = st;
+        if (status != RBS_OK && (worst == RBS_OK || status < 0)) worst = status;
+    }
+    return worst;
+}
+
 rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     rbs::BicgBufs B;
     B.n = c->n;
@@ -993,6 +1120,36 @@ int rbicgstab_solve(rbs_ctx* c, const double* b, double* x, int32_t x_nonzero, c
     return rc;
 }
 
+int rbicgstab_solve_multi(rbs_ctx* c, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                          int64_t ldx, const double* shadows, double rtol, int32_t max_it,
+                          int32_t flags, rbs_stats* stats) {
+    if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
+    if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound: call rbicgstab_setup first");
+    if (!B || !X || nrhs < 1 || nrhs > rbs::MULTI_MAX || ldb < c->n || ldx < c->n)
+        return fail(c, RBS_ERR_ARG, "need 1 <= nrhs <= 8 and device B, X with ld >= n");
+    if (!(rtol > 0) || max_it < 1) return fail(c, RBS_ERR_ARG, "rtol must be > 0 and max_it >= 1");
+    if (flags != RBS_RBICGSTAB && flags != RBS_BICGSTAB)
+        return fail(c, RBS_ERR_ARG, "multi-RHS solves take RBS_RBICGSTAB or RBS_BICGSTAB");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int k = flags == RBS_BICGSTAB ? 0 : c->k;
+    // groups of as many systems as one fused launch carries
+    const int w = rbs::multi_width(1, k);
+    int rc = RBS_OK;
+    for (int j0 = 0; j0 < nrhs; j0 += w) {
+        const int nr = std::min(w, nrhs - j0);
+        const int r = solve_multi(c, k, nr, B + j0 * ldb, ldb, X + j0 * ldx, ldx,
+                                  shadows ? shadows + j0 * ldb : nullptr, rtol, max_it,
+                                  stats ? stats + j0 : nullptr);
+        if (r < 0) return r;
+        if (r != RBS_OK && rc == RBS_OK) rc = r;
+    }
+    if (stats) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int j = 0; j < nrhs; ++j) stats[j].ms = ms;
+    }
+    return rc;
+}
+
 int recycle_update(rbs_ctx* c, int32_t mode, const double* U, const double* Ut, int32_t k) {
     if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
     if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound");
@@ -1040,26 +1197,34 @@ int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, doub
                         double* bytes) {
     if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
     if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound");
-    if (which < 0 || which > 7 || reps < 1 || k < 0 || k > c->k)
-        return fail(c, RBS_ERR_ARG, "which must be 0..7, reps >= 1 and 0 <= k <= k_used");
-    const bool f32 = which >= 4;
-    const int pass = which & 3;
+    const bool multi = which >= 8;
+    const int nr = multi ? (which - 8) / 4 + 1 : 1;
+    if (which < 0 || which >= 8 + 4 * rbs::MULTI_MAX || (multi && (which - 8) % 4 == 3) || reps < 1 ||
+        k < 0 || k > c->k || (multi && rbs::multi_width(nr, k) == 0))
+        return fail(c, RBS_ERR_ARG,
+                    "which must be 0..7 or 8 + 4 (nr - 1) + pass (pass 0..2, supported nr, k), reps >= 1 "
+                    "and 0 <= k <= k_used");
+    const bool f32 = !multi && which >= 4;
+    const int pass = multi ? (which - 8) % 4 : which & 3;
     if (f32) {
         int rc = ensure_f32(c);
         if (rc) return rc;
     }
     rbs::SolveBufs B = solve_bufs(c, k, c->s, c->x, nullptr);
     rbs::SolveBufsF Bf = solve_bufs_f32(c, k, false);
+    rbs::MultiBufs MB = multi_bufs(c, k, nr);
+    SolveState* prep = multi ? c->mst : c->st;
     auto launch = [&]() {
-        if (f32) rbs::launch_pass(c->stream, Bf, pass);
+        if (multi) rbs::launch_multi_pass(c->stream, MB, pass);
+        else if (f32) rbs::launch_pass(c->stream, Bf, pass);
         else rbs::launch_pass(c->stream, B, pass);
     };
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    rbs::launch_time_prep(c->stream, c->st);
+    rbs::launch_time_prep(c->stream, prep, nr);
     launch();   // warm-up launch
-    rbs::launch_time_prep(c->stream, c->st);
+    rbs::launch_time_prep(c->stream, prep, nr);
     hipEventRecord(e0, c->stream);
     for (int i = 0; i < reps; ++i) launch();
     hipEventRecord(e1, c->stream);
@@ -1069,19 +1234,22 @@ int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, doub
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (e != hipSuccess) return fail(c, RBS_ERR_HIP, std::string("timing: ") + hipGetErrorString(e));
-    HIPCHK(c, hipMemcpy(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost));
-    if (c->hp->solve.done) return fail(c, RBS_ERR_NONFINITE, "timing state terminated early");
+    for (int j = 0; j < nr; ++j) {
+        HIPCHK(c, hipMemcpy(&c->hp->solve, prep + j, 128, hipMemcpyDeviceToHost));
+        if (c->hp->solve.done) return fail(c, RBS_ERR_NONFINITE, "timing state terminated early");
+    }
     if (avg_ms) *avg_ms = ms / reps;
     if (bytes) {
         // algorithmic bytes per launch: CSR (int32 index + value per stored
         // entry, int32 row pointer) and every vector / block entry touched once
-        const double n = (double)c->n, nnz = (double)c->nnz, kk = (double)k;
+        // (multi-RHS: the vector terms scale with nr, the matrix and blocks do not)
+        const double n = (double)c->n, nnz = (double)c->nnz, kk = (double)k, m = (double)nr;
         const double w = f32 ? 4.0 : 8.0;   // bytes per value
         const double csr = (4.0 + w) * nnz + 4.0 * (n + 1);
         double v = 0.0;
-        if (pass == 0) v = 10.0 * w * n + w * n * kk;
-        else if (pass == 1) v = csr + 4.0 * w * n + 2.0 * w * n * kk;
-        else if (pass == 2) v = csr + 3.0 * w * n + w * n * kk;
+        if (pass == 0) v = 10.0 * w * n * m + w * n * kk;
+        else if (pass == 1) v = csr + 4.0 * w * n * m + 2.0 * w * n * kk;
+        else if (pass == 2) v = csr + 3.0 * w * n * m + w * n * kk;
         else v = csr + 2.0 * w * n;
         *bytes = v;
     }

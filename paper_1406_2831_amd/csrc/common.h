@@ -8,6 +8,9 @@ constexpr int WAVE = 64;          // CDNA wavefront width
 constexpr int BLOCK = 256;        // threads per block of the streaming kernels
 constexpr int KMAX = 64;          // largest recycle dimension
 constexpr int MAX_SUMS = KMAX + 8;
+// rows of the per-block partial-sum buffers: the largest fused reduction is
+// the multi-RHS update pass (4 systems x (KMAX + 3) sums)
+constexpr int PARTIAL_ROWS = 4 * (KMAX + 3);
 
 // Sliced ELLPACK with slice height = one wavefront (64 rows).  Slice s holds
 // rows [64 s, 64 s + 64) stored column-major inside the slice: entry j of

@@ -66,9 +66,30 @@ void launch_solve_epilogue(hipStream_t st, const SolveBufsT<T>& B);
 // (done = 0, tolerance below zero, fixed bounded scalars) and launch the
 // main kernel of one of the fused passes (0 update, 1 spmv1, 2 spmv2; their
 // one-block finalize kernels are not launched) or 3, a plain SpMV y = A x.
-void launch_time_prep(hipStream_t st, SolveState* state);
+void launch_time_prep(hipStream_t st, SolveState* state, int count = 1);
 template <typename T>
 void launch_pass(hipStream_t st, const SolveBufsT<T>& B, int which);
+// ---- same-matrix multi-RHS iteration -----------------------------------------
+// Algorithm 2 for nr <= 4 right-hand sides of one matrix, sharing the reads
+// of A, C and Gh: system j's vectors are column j of n x MULTI_MAX blocks
+// with leading dimension ld, its scalars state[j].  Systems whose state is
+// done (or j >= nr) are skipped.
+constexpr int MULTI_MAX = 8;
+struct MultiBufs {
+    int64_t n, ld;
+    int k, nr;
+    Sell A;
+    const double *C, *Gh;
+    double *x, *r, *s, *t, *p, *q, *rt0, *rh;
+    SolveState* state;
+    double* partials;
+};
+// systems one fused launch carries for nr systems with recycle dimension k (0: unsupported)
+int multi_width(int nr, int k);
+void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count);
+// timing support: the main kernel of one multi-RHS pass (0 update, 1 spmv1, 2 spmv2)
+void launch_multi_pass(hipStream_t st, const MultiBufs& B, int which);
+
 // y (float) = x (double) rounded, scaled by `scale`
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y);
 // x += scale * d  (x double, d float)

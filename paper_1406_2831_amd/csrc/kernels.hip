@@ -664,54 +664,58 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B) {
     block_partial<M>(acc, M, B.partials);
 }
 
+// Scalar part of the update finalize for one system: convergence / breakdown
+// tests on ||r||^2 and (rt0, r), then alpha from (rh, p) - w^T zeta.
+// tot = [||r||^2, (rt0, r), (rh, p), Gh^T p (k values)].
+__device__ void update_fin_scalars(SolveState* st, const double* tot, int k) {
+    const int i = st->iter;
+    const double rr = tot[0], rho = tot[1];
+    st->rr = rr;
+    if (!finite(rr) || !finite(rho)) {
+        st->done = 1;
+        st->status = S_NONFINITE;
+        st->iters_done = i - 1;
+    } else if (rr <= st->tol2) {
+        st->done = 1;
+        st->status = S_OK;
+        st->iters_done = i - 1;
+    } else if (st->omega_zero) {
+        st->done = 1;
+        st->status = S_BD_OMEGA;
+        st->iters_done = i - 1;
+    } else if (i > st->max_it) {
+        st->done = 1;
+        st->status = S_MAXIT;
+        st->iters_done = i - 1;
+    } else if (rho == 0.0) {
+        st->done = 1;
+        st->status = S_BD_RHO;
+        st->iters_done = i - 1;
+    } else {
+        double den = tot[2];
+        for (int j = 0; j < k; ++j) {
+            st->zeta[j] = tot[3 + j];
+            den -= st->w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
+        }
+        if (den == 0.0 || !finite(den)) {
+            st->done = 1;
+            st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
+            st->iters_done = i - 1;
+        } else {
+            st->rho = rho;
+            st->alpha = rho / den;
+        }
+    }
+}
+
 template <typename T, int K>
 __global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufsT<T> B, int nb) {
     constexpr int M = K + 3;
     __shared__ double tot[M];
     SolveState* st = B.state;
     if (st->done) return;
-    const int k = B.k;
     reduce_partials<M>(B.partials, nb, M, tot);
-    if (threadIdx.x == 0) {
-        const int i = st->iter;
-        const double rr = tot[0], rho = tot[1];
-        st->rr = rr;
-        if (!finite(rr) || !finite(rho)) {
-            st->done = 1;
-            st->status = S_NONFINITE;
-            st->iters_done = i - 1;
-        } else if (rr <= st->tol2) {
-            st->done = 1;
-            st->status = S_OK;
-            st->iters_done = i - 1;
-        } else if (st->omega_zero) {
-            st->done = 1;
-            st->status = S_BD_OMEGA;
-            st->iters_done = i - 1;
-        } else if (i > st->max_it) {
-            st->done = 1;
-            st->status = S_MAXIT;
-            st->iters_done = i - 1;
-        } else if (rho == 0.0) {
-            st->done = 1;
-            st->status = S_BD_RHO;
-            st->iters_done = i - 1;
-        } else {
-            double den = tot[2];
-            for (int j = 0; j < k; ++j) {
-                st->zeta[j] = tot[3 + j];
-                den -= st->w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
-            }
-            if (den == 0.0 || !finite(den)) {
-                st->done = 1;
-                st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
-                st->iters_done = i - 1;
-            } else {
-                st->rho = rho;
-                st->alpha = rho / den;
-            }
-        }
-    }
+    if (threadIdx.x == 0) update_fin_scalars(st, tot, B.k);
 }
 
 // spmv1: q = A p - C zeta ; s = r - alpha q ; gamma partials Gh^T s
@@ -782,33 +786,36 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B) {
     block_partial<M>(acc, M, B.partials);
 }
 
+// Scalar part of the second finalize for one system: omega, x_c, beta.
+// tot = [(s,t), (t,t), (rt0,s), (rt0,t), (s,s)].
+__device__ void spmv2_fin_scalars(SolveState* st, const double* tot, int k) {
+    const double st_ = tot[0], tt = tot[1], rts = tot[2], rtt = tot[3];
+    const double alpha = st->alpha;
+    double omega;
+    if (tt == 0.0) {
+        // (t, t) = 0: accept the half step x + alpha p if ||s|| <= tol
+        // (the next update pass sees r = s and tests it), else breakdown
+        omega = 0.0;
+        st->omega_zero = tot[4] <= st->tol2 ? 0 : 1;
+    } else {
+        omega = st_ / tt;
+        st->omega_zero = omega == 0.0 ? 1 : 0;
+    }
+    st->omega = omega;
+    for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + omega * st->gamma[j];
+    const double rho_new = rts - omega * rtt;   // (rt0, r_i) = (rt0, s) - omega (rt0, t)
+    st->beta = omega != 0.0 ? (rho_new / st->rho) * (alpha / omega) : 0.0;
+    st->iter += 1;
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_spmv2_fin(SolveBufsT<T> B, int nb) {
     constexpr int M = 5;
     __shared__ double tot[M];
     SolveState* st = B.state;
     if (st->done) return;
-    const int k = B.k;
     reduce_partials<M>(B.partials, nb, M, tot);
-    if (threadIdx.x == 0) {
-        const double st_ = tot[0], tt = tot[1], rts = tot[2], rtt = tot[3];
-        const double alpha = st->alpha;
-        double omega;
-        if (tt == 0.0) {
-            // (t, t) = 0: accept the half step x + alpha p if ||s|| <= tol
-            // (the next update pass sees r = s and tests it), else breakdown
-            omega = 0.0;
-            st->omega_zero = tot[4] <= st->tol2 ? 0 : 1;
-        } else {
-            omega = st_ / tt;
-            st->omega_zero = omega == 0.0 ? 1 : 0;
-        }
-        st->omega = omega;
-        for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + omega * st->gamma[j];
-        const double rho_new = rts - omega * rtt;   // (rt0, r_i) = (rt0, s) - omega (rt0, t)
-        st->beta = omega != 0.0 ? (rho_new / st->rho) * (alpha / omega) : 0.0;
-        st->iter += 1;
-    }
+    if (threadIdx.x == 0) spmv2_fin_scalars(st, tot, B.k);
 }
 
 // epilogue: x_out = x - U x_c (Algorithm 2 step 8)
@@ -851,6 +858,171 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
         out[0] = tot[0];
         out[1] = tot[1];
     }
+}
+
+// ---------------------------------------------------------------- multi-RHS passes
+// The three fused passes for up to MULTI_W systems of one matrix: wave j of a
+// block runs system j over the block's rows, so the waves of a block read the
+// same matrix entries and block values (C, Gh) at the same time (one HBM
+// fetch, the other waves hit the CU's cache) while each keeps the register
+// footprint of the single-system kernel.  Sums are laid out system-major
+// (system j's M values at j * M) and reduced by one-block finalizers as in
+// the single-system passes; the arithmetic per system, and its order, is the
+// single-system kernels'.
+constexpr int MULTI_W = BLOCK / WAVE;   // systems per launch (one wave each)
+
+__device__ __forceinline__ bool multi_active_any(const MultiBufs& B) {
+    bool any = false;
+    for (int j = 0; j < MULTI_W; ++j) any = any || (j < B.nr && !B.state[j].done);
+    return any;
+}
+
+// Rows of this block handled by one wave: [r0 + lane, r1) in steps of WAVE.
+// Wave sums of M values go to slot (system j) of the block partial.
+template <int M>
+__device__ __forceinline__ void multi_block_partial(double (&v)[M], int j, double* partials) {
+    __shared__ double tot[MULTI_W * M];
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) v[q] += __shfl_xor(v[q], off, WAVE);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) tot[j * M + q] = v[q];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < MULTI_W * M; t += BLOCK)
+        partials[(int64_t)t * MAX_GRID + blockIdx.x] = tot[t];
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B) {
+    constexpr int M = K + 3;
+    if (!multi_active_any(B)) return;
+    const int j = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const bool act = j < B.nr && !B.state[j].done;
+    const int k = B.k;
+    const int64_t ld = B.ld, so = (int64_t)j * ld;
+    double acc[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) acc[q] = 0.0;
+    if (act) {
+        const double alpha = B.state[j].alpha, omega = B.state[j].omega, beta = B.state[j].beta;
+        int64_t r0, r1;
+        block_rows(B.n, r0, r1);
+        for (int64_t row = r0 + lane; row < r1; row += WAVE) {
+            const int64_t o = row + so;
+            const double sv = B.s[o], tv = B.t[o], pv = B.p[o], qv = B.q[o];
+            const double rv = sv - omega * tv;
+            B.x[o] += alpha * pv + omega * sv;
+            const double pn = rv + beta * (pv - omega * qv);
+            B.r[o] = rv;
+            B.p[o] = pn;
+            acc[0] += rv * rv;
+            acc[1] += B.rt0[o] * rv;
+            acc[2] += B.rh[o] * pn;
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) acc[3 + jj] += B.Gh[row + col_off(jj, k, ld)] * pn;
+        }
+    }
+    multi_block_partial<M>(acc, j, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_mupdate_fin(MultiBufs B, int nb) {
+    constexpr int M = K + 3;
+    __shared__ double tot[MULTI_W * M];
+    if (!multi_active_any(B)) return;
+    reduce_partials<MULTI_W * M>(B.partials, nb, MULTI_W * M, tot);
+    const int j = threadIdx.x;
+    if (j < B.nr && !B.state[j].done) update_fin_scalars(&B.state[j], tot + j * M, B.k);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B) {
+    constexpr int M = K > 0 ? K : 1;
+    if (!multi_active_any(B)) return;
+    const int j = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const bool act = j < B.nr && !B.state[j].done;
+    const int k = B.k;
+    const int64_t ld = B.ld, so = (int64_t)j * ld;
+    double acc[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) acc[q] = 0.0;
+    if (act) {
+        const double alpha = B.state[j].alpha;
+        double zeta[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) zeta[q] = q < k ? B.state[j].zeta[q] : 0.0;
+        int64_t r0, r1;
+        block_rows(B.n, r0, r1);
+        for (int64_t row = r0 + lane; row < r1; row += WAVE) {
+            const int64_t o = row + so;
+            double qv = sell_row(B.A, row, B.p + so);
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) qv -= B.C[row + col_off(jj, k, ld)] * zeta[jj];
+            const double sv = B.r[o] - alpha * qv;
+            B.q[o] = qv;
+            B.s[o] = sv;
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) acc[jj] += B.Gh[row + col_off(jj, k, ld)] * sv;
+        }
+    }
+    if (K > 0) multi_block_partial<M>(acc, j, B.partials);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_mspmv1_fin(MultiBufs B, int nb) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[MULTI_W * M];
+    if (!multi_active_any(B)) return;
+    reduce_partials<MULTI_W * M>(B.partials, nb, MULTI_W * M, tot);
+    for (int idx = threadIdx.x; idx < MULTI_W * M; idx += BLOCK) {
+        const int j = idx / M, q = idx % M;
+        if (j < B.nr && !B.state[j].done && q < B.k) B.state[j].gamma[q] = tot[idx];
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B) {
+    constexpr int KM = K > 0 ? K : 1;
+    if (!multi_active_any(B)) return;
+    const int j = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const bool act = j < B.nr && !B.state[j].done;
+    const int k = B.k;
+    const int64_t ld = B.ld, so = (int64_t)j * ld;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act) {
+        double gam[KM];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) gam[q] = q < k ? B.state[j].gamma[q] : 0.0;
+        int64_t r0, r1;
+        block_rows(B.n, r0, r1);
+        for (int64_t row = r0 + lane; row < r1; row += WAVE) {
+            const int64_t o = row + so;
+            double tv = sell_row(B.A, row, B.s + so);
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) tv -= B.C[row + col_off(jj, k, ld)] * gam[jj];
+            B.t[o] = tv;
+            const double sv = B.s[o], rt = B.rt0[o];
+            acc[0] += sv * tv;
+            acc[1] += tv * tv;
+            acc[2] += rt * sv;
+            acc[3] += rt * tv;
+            acc[4] += sv * sv;
+        }
+    }
+    multi_block_partial<5>(acc, j, B.partials);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_mspmv2_fin(MultiBufs B, int nb) {
+    __shared__ double tot[MULTI_W * 5];
+    if (!multi_active_any(B)) return;
+    reduce_partials<MULTI_W * 5>(B.partials, nb, MULTI_W * 5, tot);
+    const int j = threadIdx.x;
+    if (j < B.nr && !B.state[j].done) spmv2_fin_scalars(&B.state[j], tot + j * 5, B.k);
 }
 
 // ---------------------------------------------------------------- iterative refinement support
@@ -1491,8 +1663,8 @@ void launch_solve_iterations(hipStream_t st, const SolveBufsT<T>& B, int count) 
     }
 }
 
-void launch_time_prep(hipStream_t st, SolveState* state) {
-    hipLaunchKernelGGL(k_time_prep, dim3(1), dim3(1), 0, st, state);
+void launch_time_prep(hipStream_t st, SolveState* state, int count) {
+    for (int j = 0; j < count; ++j) hipLaunchKernelGGL(k_time_prep, dim3(1), dim3(1), 0, st, state + j);
 }
 
 template <typename T>
@@ -1514,6 +1686,35 @@ void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const 
     const int g = stream_grid(A.n);
     hipLaunchKernelGGL(k_true_res, dim3(g), dim3(BLOCK), 0, st, A, b, x, partials);
     hipLaunchKernelGGL(k_true_res_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sums);
+}
+
+int multi_width(int nr, int k) {
+    return (nr >= 1 && nr <= MULTI_W && k >= 0 && k <= KMAX) ? MULTI_W : 0;
+}
+
+RBS_LAUNCHER(L_mupdate, k_mupdate, MultiBufs, false)
+RBS_LAUNCHER(L_mupdate_fin, k_mupdate_fin, MultiBufs, true)
+RBS_LAUNCHER(L_mspmv1, k_mspmv1, MultiBufs, false)
+RBS_LAUNCHER(L_mspmv1_fin, k_mspmv1_fin, MultiBufs, true)
+RBS_LAUNCHER(L_mspmv2, k_mspmv2, MultiBufs, false)
+
+void launch_multi_pass(hipStream_t st, const MultiBufs& B, int which) {
+    const int g = stream_grid(B.n);
+    if (which == 0) dispatch_k<L_mupdate>(B.k, st, g, B);
+    else if (which == 1) dispatch_k<L_mspmv1>(B.k, st, g, B);
+    else dispatch_k<L_mspmv2>(B.k, st, g, B);
+}
+
+void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count) {
+    const int g = stream_grid(B.n);
+    for (int it = 0; it < count; ++it) {
+        dispatch_k<L_mupdate>(B.k, st, g, B);
+        dispatch_k<L_mupdate_fin>(B.k, st, g, B, g);
+        dispatch_k<L_mspmv1>(B.k, st, g, B);
+        if (B.k > 0) dispatch_k<L_mspmv1_fin>(B.k, st, g, B, g);
+        dispatch_k<L_mspmv2>(B.k, st, g, B);
+        hipLaunchKernelGGL(k_mspmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
+    }
 }
 
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y) {

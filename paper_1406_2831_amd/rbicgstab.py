@@ -42,8 +42,8 @@ RBS_RECYCLE_CLEAR = 2
 
 EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "recycle_update",
            "rbicgstab_get_blocks", "rbicgstab_time_pass", "rbicgstab_setup_matvecs",
-           "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_destroy",
-           "rbicgstab_last_error")
+           "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_solve_multi",
+           "rbicgstab_destroy", "rbicgstab_last_error")
 
 
 class Stats(ctypes.Structure):
@@ -78,6 +78,9 @@ def load_library(path: str = LIB_PATH):
     lib.rbicgstab_setup.restype = ctypes.c_int
     lib.rbicgstab_solve.argtypes = [vp, vp, vp, i32, vp, f64, i32, i32, ctypes.POINTER(Stats)]
     lib.rbicgstab_solve.restype = ctypes.c_int
+    lib.rbicgstab_solve_multi.argtypes = [vp, i32, vp, i64, vp, i64, vp, f64, i32, i32,
+                                          ctypes.POINTER(Stats)]
+    lib.rbicgstab_solve_multi.restype = ctypes.c_int
     lib.recycle_update.argtypes = [vp, i32, vp, vp, i32]
     lib.recycle_update.restype = ctypes.c_int
     lib.rbicgstab_get_blocks.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
@@ -149,6 +152,18 @@ def rbicgstab_solve(handle, b: torch.Tensor, x: torch.Tensor, x_nonzero: bool = 
                              max_it, flags, ctypes.byref(st))
     _check(lib, handle, rc)
     return st
+
+
+def rbicgstab_solve_multi(handle, B: torch.Tensor, X: torch.Tensor, shadows: Optional[torch.Tensor] = None,
+                          rtol: float = 1e-8, max_it: int = 10000, flags: int = RBS_RBICGSTAB):
+    """B, X, shadows: (nrhs, n) row-major tensors == column-major n x nrhs blocks (ld = n)."""
+    lib = load_library()
+    nrhs, n = B.shape
+    stats = (Stats * nrhs)()
+    rc = lib.rbicgstab_solve_multi(handle, nrhs, _ptr(B), n, _ptr(X), X.shape[1], _ptr(shadows), rtol,
+                                   max_it, flags, stats)
+    _check(lib, handle, rc)
+    return list(stats)
 
 
 def recycle_update(handle, mode: int, U: Optional[torch.Tensor] = None,
@@ -260,6 +275,16 @@ class Context:
             x = torch.zeros_like(b)
         st = rbicgstab_solve(self.handle, b, x, x_nonzero, shadow, rtol, max_it, flags)
         return x, st
+
+    def solve_multi(self, B, X=None, shadows=None, rtol=1e-8, max_it=10000, mode: str = "rbicgstab"):
+        """B: (nrhs, n) device tensor (row j = right-hand side j); returns (X, [Stats])."""
+        flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB}[mode]
+        B = B.contiguous()
+        if X is None:
+            X = torch.zeros_like(B)
+        st = rbicgstab_solve_multi(self.handle, B, X, None if shadows is None else shadows.contiguous(),
+                                   rtol, max_it, flags)
+        return X, st
 
     def recycle(self, mode: str = "from_last_solve", U=None, Ut=None):
         m = {"set": RBS_RECYCLE_SET, "from_last_solve": RBS_RECYCLE_FROM_LAST_SOLVE,

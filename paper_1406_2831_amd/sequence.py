@@ -55,34 +55,55 @@ class GpuSequence:
         self.rhs = [torch.as_tensor(b, device=device) for b in seq.rhs]
         self.shadows = [torch.as_tensor(s, device=device) for s in seq.shadows]
         self.ctx = Context(seq.n, self.mrow, max(self.k, 1), s_max, device, secant_max)
-        self.xbuf = [torch.zeros(seq.n, dtype=torch.float64, device=device)
-                     for _ in range(seq.num_systems)]
+        # per-system solutions; rows of one (systems, n) block so that the
+        # right-hand sides of one matrix can also be solved together
+        self.xblock = torch.zeros((seq.num_systems, seq.n), dtype=torch.float64, device=device)
+        self.xbuf = [self.xblock[i] for i in range(seq.num_systems)]
+        self.rhs_block = torch.stack(self.rhs).contiguous()
+        self.shadow_block = torch.stack(self.shadows).contiguous()
 
     def run(self, mode: str = "rbicgstab", rtol: float = 1e-8, max_it: int = 20000,
-            systems: Optional[int] = None, precision: str = "fp64") -> GpuSequenceResult:
+            systems: Optional[int] = None, precision: str = "fp64",
+            multi_rhs: bool = False) -> GpuSequenceResult:
         """precision applies to the RBiCGSTAB / BiCGSTAB solves ("fp64" or
-        "fp32_ir"); RBiCG and the recycle-space update always run in FP64."""
+        "fp32_ir"); RBiCG and the recycle-space update always run in FP64.
+        multi_rhs: the RBiCGSTAB right-hand sides of each matrix (all of them
+        for BiCGSTAB) are solved together by rbicgstab_solve_multi (FP64)."""
         seq, ctx = self.seq, self.ctx
         out = GpuSequenceResult()
         last = seq.num_systems if systems is None else min(systems, seq.num_systems)
-        cur = -1
+        if multi_rhs and precision != "fp64":
+            raise ValueError("multi-RHS solves are FP64")
         if ctx.handle is not None:
             ctx.recycle("clear")
-        for idx in range(last):
+        results = {}
+        idx = 0
+        while idx < last:
             si, j = seq.system(idx)
-            if si != cur:
+            if j == 0:
                 A, At = self.mats[si]
                 ctx.setup(A, At)
-                cur = si
                 ma, mat = ctx.setup_matvecs()
                 out.setup_matvecs += ma + mat
+            gen = mode != "bicgstab" and j == 0 and self.k > 0
+            end = min((si + 1) * seq.nrhs, last)   # systems of this matrix
+            if multi_rhs and not gen and end - idx > 1:
+                grp = list(range(idx, end))
+                X = self.xblock[idx:end]
+                X.zero_()
+                _, sts = ctx.solve_multi(self.rhs_block[idx:end], X, self.shadow_block[idx:end],
+                                         rtol=rtol, max_it=max_it, mode=mode)
+                for g, st in zip(grp, sts):
+                    results[g] = (st, mode)
+                idx = end
+                continue
             b, sh, x = self.rhs[idx], self.shadows[idx], self.xbuf[idx]
             x.zero_()
             if mode == "bicgstab":
                 _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="bicgstab",
                                   precision=precision)
                 solver = "bicgstab"
-            elif j == 0 and self.k > 0:
+            elif gen:
                 _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicg")
                 ctx.recycle("from_last_solve")
                 ma, mat = ctx.setup_matvecs()
@@ -92,8 +113,12 @@ class GpuSequence:
                 _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicgstab",
                                   precision=precision)
                 solver = "rbicgstab"
+            results[idx] = (st, solver)
+            idx += 1
+        for i in range(last):
+            st, solver = results[i]
             if self.keep_x:
-                out.x.append(x)
+                out.x.append(self.xbuf[i])
             out.status.append(st.status)
             out.iters.append(st.total_iters)
             out.matvecs.append(st.matvecs_A + st.matvecs_At)

@@ -367,3 +367,56 @@ def test_fp32_ir_sequence_3d(rb, torch_mod):
         xr, ir = o.bicgstab(A.to_scipy(), seq.rhs[idx], shadow=seq.shadows[idx], rtol=1e-12)
         assert _rel(x.cpu().numpy(), xr) <= 1e-6, idx
     gs.close()
+
+
+def test_multi_rhs_matches_single_solves(rb, torch_mod, c0):
+    """rbicgstab_solve_multi: each system follows the single-system iteration
+    (its sums are taken over rows in another order, so the histories agree to
+    rounding): iteration counts within a few, solutions within kappa * rtol of
+    the one-at-a-time solves and of a direct solve; a converged system stops
+    while the others go on."""
+    seq, A, At = c0
+    As = A.to_scipy()
+    lam, vl, vr = sla.eig(As.toarray(), left=True, right=True)
+    order = np.argsort(np.abs(lam))
+    rng = np.random.default_rng(77)
+    nr = 3
+    Bm = rng.standard_normal((nr, A.n))
+    Bm[2] *= 1e-3                                   # a differently scaled right-hand side
+    Sm = rng.standard_normal((nr, A.n))
+    _say("multi-rhs 2d")
+    ctx = _ctx(rb, A, At, k_max=8, s_max=0)
+    for mode, ks in (("bicgstab", 0), ("rbicgstab", 8)):
+        if ks:
+            ctx.recycle("set", torch_mod.as_tensor(np.ascontiguousarray(vr[:, order[:ks]].real.T), device="cuda"),
+                        torch_mod.as_tensor(np.ascontiguousarray(vl[:, order[:ks]].real.T), device="cuda"))
+        X, sts = ctx.solve_multi(torch_mod.as_tensor(Bm, device="cuda"),
+                                 shadows=torch_mod.as_tensor(Sm, device="cuda"), rtol=1e-10, mode=mode)
+        Xn = X.cpu().numpy()
+        for j in range(nr):
+            xs, st1 = _solve(ctx, torch_mod, Bm[j], shadow=Sm[j], mode=mode, rtol=1e-10)
+            print(f"{mode} rhs {j}: multi iters {sts[j].iters} single {st1.iters}", flush=True)
+            assert sts[j].status == 0 and sts[j].rel_res_true <= 1e-10 and sts[j].k_used == ks
+            assert abs(sts[j].iters - st1.iters) <= max(3, 0.05 * st1.iters)
+            assert _rel(Xn[j], xs) <= 1e-6
+            xd = np.linalg.solve(As.toarray(), Bm[j])
+            assert _rel(Xn[j], xd) <= 1e-6
+    ctx.close()
+
+
+def test_multi_rhs_sequence_3d(rb, torch_mod):
+    """The recycled sequence with the RBiCGSTAB right-hand sides of each matrix
+    solved together, on a ragged grid, against path-independent references."""
+    from paper_1406_2831_amd.sequence import GpuSequence
+    seq = w.seq_3d(N=23, nshift=2, nrhs=4, k=12)
+    _say("multi-rhs sequence 3d N=23")
+    gs = GpuSequence(seq, s_max=512)
+    for mode in ("rbicgstab", "bicgstab"):
+        res = gs.run(mode=mode, rtol=1e-10, multi_rhs=True)
+        print(f"{mode}: iters {res.iters} k {res.k_used} solver {res.solver}", flush=True)
+        assert all(s == 0 for s in res.status) and max(res.rel_res_true) <= 1e-10
+        for idx, x in enumerate(res.x):
+            A, _ = seq.matrix(seq.system(idx)[0])
+            xr, ir = o.bicgstab(A.to_scipy(), seq.rhs[idx], shadow=seq.shadows[idx], rtol=1e-12)
+            assert _rel(x.cpu().numpy(), xr) <= 1e-6, (mode, idx)
+    gs.close()
