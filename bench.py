@@ -79,6 +79,89 @@ def cpu_baseline(seq, rtol, systems):
             "seconds": dt}
 
 
+def adjoint_workload(args):
+    """Gradients of L = c^T x, x = A(sigma)^-1 b, A = K + sigma M on a 3D 7-point
+    grid (default 128^3, n = 2,097,152): one step = forward RBiCGSTAB solve with the
+    recycle space + transposed RBiCGSTAB solve reusing it (swapped) + the gradient
+    kernel (dL/db, dL/dsigma, dL/dK values).  The space comes from one RBiCG
+    forward solve before timing.  After timing, directional derivatives are
+    checked against central differences (step 1e-6, solves at rtol 1e-12)."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_1406_2831_amd.adjoint import ShiftedSystem, recycled_solve
+
+    N = args.grid if args.grid != 64 else 128
+    seq, c, bdirs = w.adjoint_problem(N=N, ndirs=args.fd_dirs)
+    K, mdiag, sigma, b = seq.K, seq.mdiag, float(seq.sigmas[0]), seq.rhs[0]
+    sysm = ShiftedSystem(K, mdiag, k_max=args.k, s_max=512, secant_max=args.secant_max)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    bt = dev(b).requires_grad_(True)
+    sg = torch.tensor(sigma, dtype=torch.float64, device="cuda", requires_grad=True)
+    kv = dev(K.val).requires_grad_(True)
+    ct = dev(c)
+    rtol = args.rtol
+
+    def step(mode="rbicgstab"):
+        for t in (bt, sg, kv):
+            t.grad = None
+        x = recycled_solve(sysm, bt, sg, kv, rtol, 20000, mode)
+        (x * ct).sum().backward()
+        return x
+
+    x = step("rbicg")                       # builds and installs the recycle space
+    k_used = sysm.ctx.blocks()[1]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fwd = sysm.ctx.solve(bt.detach(), rtol=rtol, mode="rbicgstab")[1]
+    adj = sysm.ctx.solve(ct, rtol=rtol, mode="rbicgstab", transpose=True)[1]
+    # the same with plain BiCGSTAB forward and adjoint (the non-recycling baseline)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step("bicgstab")
+    torch.cuda.synchronize()
+    dt0 = (time.perf_counter() - t0) / args.steps
+    # finite-difference check of the gradient on random directions
+    gb, gs, gk = bt.grad.cpu().numpy(), sg.grad.item(), kv.grad.cpu().numpy()
+    step()
+    gb, gs, gk = bt.grad.cpu().numpy(), sg.grad.item(), kv.grad.cpu().numpy()
+    dirs = w.generator(3, 1, "dirs")
+    h, fds, ans = 1e-6, [], []
+    for i in range(args.fd_dirs):
+        db, ds = bdirs[i], dirs.standard_normal()
+        dk = dirs.standard_normal(K.nnz) * np.abs(K.val)
+        vals = []
+        for sgn in (1.0, -1.0):
+            with torch.no_grad():
+                xp, _ = sysm.solve(dev(b + sgn * h * db), sigma + sgn * h * ds, dev(K.val + sgn * h * dk),
+                                   rtol=1e-12, max_it=50000)
+                vals.append(float((xp * ct).sum().item()))
+        fds.append((vals[0] - vals[1]) / (2 * h))
+        ans.append(gb @ db + gs * ds + gk @ dk)
+    fds, ans = np.array(fds), np.array(ans)
+    fd_err = float(np.max(np.abs(fds - ans)) / np.sqrt(np.mean(ans ** 2)))
+    out = {
+        "metric": "gradient evaluations/s (forward + transposed recycled solve + gradients)",
+        "value": 1.0 / dt, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"adjoint of c^T x on 3d 7-point convection-diffusion {N}^3 "
+                               f"(n={seq.n}), sigma={sigma}, k={args.k}, rtol={rtol}",
+                   "n": seq.n, "nnz": int(K.nnz), "k_used": k_used},
+        "forward_iters": fwd.iters, "adjoint_iters": adj.iters,
+        "bicgstab_ms_per_step": dt0 * 1e3,
+        "fd_check": {"directions": args.fd_dirs, "step": h, "max_err_over_rms": fd_err},
+    }
+    sysm.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,11 +179,19 @@ def main():
                     help="skip the FP32-storage / FP64-refinement runs (reported beside the FP64 line)")
     ap.add_argument("--secant-max", type=float, default=0.0,
                     help="oblique-projector cap of the recycle setup (0: library default)")
+    ap.add_argument("--workload", choices=("sequence", "adjoint"), default="sequence",
+                    help="sequence: the shifted 64^3 sequence (default); adjoint: gradients of "
+                         "c^T x on the 128^3 problem through the transposed recycled solve")
+    ap.add_argument("--fd-dirs", type=int, default=16,
+                    help="adjoint workload: finite-difference directions checked after timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no "
-              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "adjoint":
+        return adjoint_workload(args)
 
     import torch
     import workloads as w
