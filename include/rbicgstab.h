@@ -236,6 +236,44 @@ int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const i
                              const double* mdiag, double sigma, const int64_t* perm_t, double* val,
                              double* valT, hipStream_t stream);
 
+/*
+ * Batches of independent systems (each with its own matrix of any size, its
+ * own recycle space and context) advanced together: every pass of an
+ * iteration is one persistent launch whose workgroups walk a list of row
+ * tiles of all unfinished systems, every finalize one launch with a workgroup
+ * per system.  Iterations can be replayed from a captured HIP graph.
+ *
+ * rbicgstab_batch_workspace_bytes: device workspace for nsys systems of sizes
+ *   n[0..nsys) (host array); 0 for invalid arguments.
+ * rbicgstab_batch_create: *batch on `workspace` (caller-owned, 256-byte
+ *   aligned) for the bound contexts ctxs[0..nsys) (which stay owned by the
+ *   caller and must outlive the batch).  RBS_BATCH_TUNE picks the tile height
+ *   (256..2048 rows) and the persistent grid (256..2048 workgroups) by timing
+ *   the batched passes on these systems; otherwise 512 rows and 1024
+ *   workgroups.  RBS_BATCH_GRAPH replays each chunk of iterations from a
+ *   captured graph (re-captured when the launch shape changes).  The batch
+ *   uses its own stream; it waits for the contexts' streams first.
+ * rbicgstab_batch_solve: system j solves A_j x_j = b_j with its installed space
+ *   (RBS_RBICGSTAB) or none (RBS_BICGSTAB), zero initial guess; bvec, x and
+ *   shadows (may be NULL) are host arrays of nsys device pointers; stats is a
+ *   host array of nsys (may be NULL).  Per-system restarts as in
+ *   rbicgstab_solve.  Returns RBS_OK if every system converged.
+ * rbicgstab_batch_config: the tile height, grid and (when tuned) the measured
+ *   ms per batched iteration of the chosen configuration.
+ */
+typedef struct rbs_batch rbs_batch;
+enum { RBS_BATCH_TUNE = 1, RBS_BATCH_GRAPH = 2 };
+size_t rbicgstab_batch_workspace_bytes(int32_t nsys, const int64_t* n);
+int rbicgstab_batch_create(rbs_batch** batch, int32_t nsys, rbs_ctx* const* ctxs, void* workspace,
+                           size_t ws_bytes, int32_t flags);
+int rbicgstab_batch_solve(rbs_batch* batch, const double* const* b, double* const* x,
+                          const double* const* shadows, double rtol, int32_t max_it, int32_t flags,
+                          rbs_stats* stats);
+int rbicgstab_batch_config(const rbs_batch* batch, int32_t* tile_rows, int32_t* grid,
+                           double* ms_per_iter);
+int rbicgstab_batch_destroy(rbs_batch* batch);
+const char* rbicgstab_batch_last_error(const rbs_batch* batch);
+
 /* Matrix-vector products issued by the last setup / recycle_update (host out). */
 int rbicgstab_setup_matvecs(const rbs_ctx* ctx, int32_t* matvecs_A, int32_t* matvecs_At);
 

@@ -1010,6 +1010,171 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
 
 // ============================================================================ C ABI
 
+// ---------------------------------------------------------------- batches of systems
+
+struct rbs_batch {
+    int nsys = 0;
+    std::vector<rbs_ctx*> ctx;
+    hipStream_t stream = nullptr;        // the batch's own stream (captured into a graph)
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    rbs::SolveBufs* d_sys = nullptr;
+    rbs::BatchTile* d_tiles = nullptr;
+    int32_t* d_tile_begin = nullptr;
+    double* d_partials = nullptr;
+    SolveState* d_states = nullptr;      // gathered state headers (polling)
+    SolveState* h_states = nullptr;      // pinned host copy
+    int max_tiles = 0, ntiles = 0, tile_rows = 0, grid = 0, kmax = 0;
+    double tuned_ms = 0.0;               // measured ms per batched iteration of the chosen config
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_kmax = -1, graph_grid = -1, graph_ntiles = -1;   // launch shape the graph holds
+    hipEvent_t ev = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int bfail(rbs_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return bfail(b, RBS_ERR_HIP, std::string(#call) + ": " +   \
+                                                           hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr int BATCH_TILE_MIN = 64;   // rows of the smallest tile (one slice)
+
+size_t batch_carve(rbs_batch* b, char* base, int nsys, int max_tiles) {
+    Carver cv{base};
+    b->d_sys = cv.take<rbs::SolveBufs>(nsys);
+    b->d_tiles = cv.take<rbs::BatchTile>(max_tiles);
+    b->d_tile_begin = cv.take<int32_t>(nsys + 1);
+    b->d_partials = cv.take<double>((size_t)(rbs::KMAX + 3) * max_tiles);
+    b->d_states = cv.take<SolveState>(nsys);
+    return round_up(cv.off, ALIGN);
+}
+
+int batch_max_tiles(int nsys, const int64_t* n) {
+    int64_t t = 0;
+    for (int j = 0; j < nsys; ++j) t += (n[j] + BATCH_TILE_MIN - 1) / BATCH_TILE_MIN;
+    return (int)t;
+}
+
+// tile list for tiles of `rows` rows (a multiple of 64) over every system
+int batch_tiles(rbs_batch* b, int rows) {
+    std::vector<rbs::BatchTile> tiles;
+    std::vector<int32_t> begin(b->nsys + 1, 0);
+    for (int j = 0; j < b->nsys; ++j) {
+        begin[j] = (int32_t)tiles.size();
+        const int64_t n = b->ctx[j]->n;
+        for (int64_t r0 = 0; r0 < n; r0 += rows) {
+            rbs::BatchTile t;
+            t.sys = j;
+            t.pad = 0;
+            t.r0 = r0;
+            t.r1 = std::min<int64_t>(n, r0 + rows);
+            tiles.push_back(t);
+        }
+    }
+    begin[b->nsys] = (int32_t)tiles.size();
+    if ((int)tiles.size() > b->max_tiles) return bfail(b, RBS_ERR_WORKSPACE, "tile list exceeds the workspace");
+    BHIPCHK(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(rbs::BatchTile),
+                              hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_tile_begin, begin.data(), begin.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->ntiles = (int)tiles.size();
+    b->tile_rows = rows;
+    return RBS_OK;
+}
+
+rbs::BatchBufs batch_bufs(const rbs_batch* b) {
+    rbs::BatchBufs B;
+    B.sys = b->d_sys;
+    B.tiles = b->d_tiles;
+    B.tile_begin = b->d_tile_begin;
+    B.nsys = b->nsys;
+    B.ntiles = b->ntiles;
+    B.kmax = b->kmax;
+    B.partials = b->d_partials;
+    return B;
+}
+
+// descriptors of every system (its installed k, its own vectors and state)
+int batch_upload(rbs_batch* b, const double* const* bvec, double* const* x, const double* const* sh) {
+    std::vector<rbs::SolveBufs> d(b->nsys);
+    b->kmax = 0;
+    for (int j = 0; j < b->nsys; ++j) {
+        rbs_ctx* c = b->ctx[j];
+        d[j] = solve_bufs(c, c->k, bvec ? bvec[j] : c->s, x ? x[j] : c->x, sh ? sh[j] : nullptr);
+        b->kmax = std::max(b->kmax, c->k);
+    }
+    BHIPCHK(b, hipMemcpyAsync(b->d_sys, d.data(), d.size() * sizeof(rbs::SolveBufs), hipMemcpyHostToDevice,
+                              b->stream));
+    return RBS_OK;
+}
+
+void batch_destroy_graph(rbs_batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Autotuner: time the three batched passes (main kernels, non-terminating
+// scalar states) for each (tile rows, grid) candidate and keep the fastest.
+int batch_tune(rbs_batch* b) {
+    static const int tile_cand[] = {256, 512, 1024, 2048};
+    static const int grid_cand[] = {256, 512, 1024, 2048};
+    int rc = batch_upload(b, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    double best = 1e300;
+    int best_rows = tile_cand[1], best_grid = grid_cand[2];
+    for (int rows : tile_cand) {
+        if ((rc = batch_tiles(b, rows))) break;
+        for (int grid : grid_cand) {
+            const rbs::BatchBufs B = batch_bufs(b);
+            for (int j = 0; j < b->nsys; ++j) rbs::launch_time_prep(b->stream, b->ctx[j]->st, 1);
+            for (int w = 0; w < 3; ++w) rbs::launch_batch_pass(b->stream, B, grid, w);   // warm-up
+            hipEventRecord(e0, b->stream);
+            for (int rep = 0; rep < 3; ++rep)
+                for (int w = 0; w < 3; ++w) rbs::launch_batch_pass(b->stream, B, grid, w);
+            hipEventRecord(e1, b->stream);
+            hipError_t e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = bfail(b, RBS_ERR_HIP, std::string("tuning: ") + hipGetErrorString(e));
+                break;
+            }
+            if (ms / 3.0 < best) {
+                best = ms / 3.0;
+                best_rows = rows;
+                best_grid = grid;
+            }
+        }
+        if (rc) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    b->tuned_ms = best;
+    b->grid = best_grid;
+    return batch_tiles(b, best_rows);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t rbicgstab_workspace_bytes(int64_t n, int32_t max_row_nnz, int32_t k_max, int32_t s_max) {
@@ -1306,6 +1471,230 @@ int rbicgstab_destroy(rbs_ctx* c) {
 
 const char* rbicgstab_last_error(const rbs_ctx* c) {
     return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+size_t rbicgstab_batch_workspace_bytes(int32_t nsys, const int64_t* n) {
+    if (nsys < 1 || !n) return 0;
+    for (int j = 0; j < nsys; ++j)
+        if (n[j] < 1) return 0;
+    rbs_batch tmp;
+    return batch_carve(&tmp, nullptr, nsys, batch_max_tiles(nsys, n));
+}
+
+int rbicgstab_batch_create(rbs_batch** pb, int32_t nsys, rbs_ctx* const* ctxs, void* workspace,
+                           size_t ws_bytes, int32_t flags) {
+    if (!pb || nsys < 1 || !ctxs) return bfail(nullptr, RBS_ERR_ARG, "need nsys >= 1 contexts");
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0)
+        return bfail(nullptr, RBS_ERR_WORKSPACE, "workspace must be 256-byte aligned device memory");
+    if (flags & ~(RBS_BATCH_TUNE | RBS_BATCH_GRAPH)) return bfail(nullptr, RBS_ERR_ARG, "unknown batch flags");
+    std::vector<int64_t> n(nsys);
+    for (int j = 0; j < nsys; ++j) {
+        if (!ctxs[j] || !ctxs[j]->bound) return bfail(nullptr, RBS_ERR_ARG, "every context must be bound");
+        n[j] = ctxs[j]->n;
+    }
+    auto* b = new rbs_batch();
+    b->nsys = nsys;
+    b->ctx.assign(ctxs, ctxs + nsys);
+    b->max_tiles = batch_max_tiles(nsys, n.data());
+    const size_t need = batch_carve(b, nullptr, nsys, b->max_tiles);
+    if (ws_bytes < need) {
+        delete b;
+        return bfail(nullptr, RBS_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(need));
+    }
+    b->ws = static_cast<char*>(workspace);
+    b->ws_bytes = ws_bytes;
+    batch_carve(b, b->ws, nsys, b->max_tiles);
+    void* hp = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc(&hp, sizeof(SolveState) * nsys, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        rbicgstab_batch_destroy(b);
+        return bfail(nullptr, RBS_ERR_HIP, std::string("batch create: ") + hipGetErrorString(e));
+    }
+    b->h_states = static_cast<SolveState*>(hp);
+    b->use_graph = (flags & RBS_BATCH_GRAPH) != 0;
+    // the contexts' pending work (setup, space generation) precedes the batch's
+    for (int j = 0; j < nsys; ++j) {
+        e = hipStreamSynchronize(ctxs[j]->stream);
+        if (e != hipSuccess) break;
+    }
+    int rc = e == hipSuccess ? RBS_OK : bfail(nullptr, RBS_ERR_HIP, hipGetErrorString(e));
+    if (!rc) {
+        if (flags & RBS_BATCH_TUNE) {
+            rc = batch_tune(b);
+        } else {
+            b->grid = 1024;
+            rc = batch_upload(b, nullptr, nullptr, nullptr);
+            if (!rc) rc = batch_tiles(b, 512);
+        }
+    }
+    if (rc) {
+        g_create_error = b->err;
+        rbicgstab_batch_destroy(b);
+        return rc;
+    }
+    *pb = b;
+    return RBS_OK;
+}
+
+int rbicgstab_batch_config(const rbs_batch* b, int32_t* tile_rows, int32_t* grid, double* ms_per_iter) {
+    if (!b) return bfail(nullptr, RBS_ERR_ARG, "batch is NULL");
+    if (tile_rows) *tile_rows = b->tile_rows;
+    if (grid) *grid = b->grid;
+    if (ms_per_iter) *ms_per_iter = b->tuned_ms;
+    return RBS_OK;
+}
+
+int rbicgstab_batch_solve(rbs_batch* b, const double* const* bvec, double* const* x,
+                          const double* const* shadows, double rtol, int32_t max_it, int32_t flags,
+                          rbs_stats* stats) {
+    if (!b) return bfail(nullptr, RBS_ERR_ARG, "batch is NULL");
+    if (!bvec || !x) return bfail(b, RBS_ERR_ARG, "b and x must be host arrays of device pointers");
+    if (!(rtol > 0) || max_it < 1) return bfail(b, RBS_ERR_ARG, "rtol must be > 0 and max_it >= 1");
+    if (flags != RBS_RBICGSTAB && flags != RBS_BICGSTAB)
+        return bfail(b, RBS_ERR_ARG, "batched solves take RBS_RBICGSTAB or RBS_BICGSTAB");
+    for (int j = 0; j < b->nsys; ++j)
+        if (!bvec[j] || !x[j] || !b->ctx[j]->bound) return bfail(b, RBS_ERR_ARG, "missing vector or unbound context");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = b->stream;
+    // every system's installed space (or none, for BiCGSTAB), its own vectors
+    std::vector<int> ksave(b->nsys);
+    for (int j = 0; j < b->nsys; ++j) {
+        ksave[j] = b->ctx[j]->k;
+        if (flags == RBS_BICGSTAB) b->ctx[j]->k = 0;
+        BHIPCHK(b, hipStreamSynchronize(b->ctx[j]->stream));
+    }
+    int rc = batch_upload(b, bvec, x, shadows);
+    // prologues on the batch stream (single-system kernels: once per solve)
+    for (int j = 0; j < b->nsys && !rc; ++j) {
+        rbs_ctx* c = b->ctx[j];
+        rbs::SolveBufs Bj = solve_bufs(c, c->k, bvec[j], x[j], shadows ? shadows[j] : nullptr);
+        rbs::launch_solve_prologue(s, Bj, 0, rtol, max_it);
+    }
+    const rbs::BatchBufs B = batch_bufs(b);
+    auto restore = [&]() {
+        for (int j = 0; j < b->nsys; ++j) b->ctx[j]->k = ksave[j];
+    };
+    if (rc) {
+        restore();
+        return rc;
+    }
+    auto enqueue = [&]() -> int {
+        if (b->use_graph) {
+            if (b->exec && (b->graph_kmax != b->kmax || b->graph_grid != b->grid ||
+                            b->graph_ntiles != b->ntiles))
+                batch_destroy_graph(b);
+            if (!b->exec) {   // capture one chunk of iterations; replays reuse it while the shape holds
+                b->graph_kmax = b->kmax;
+                b->graph_grid = b->grid;
+                b->graph_ntiles = b->ntiles;
+                BHIPCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                rbs::launch_batch_iterations(s, B, b->grid, CHUNK);
+                BHIPCHK(b, hipStreamEndCapture(s, &b->graph));
+                BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            }
+            BHIPCHK(b, hipGraphLaunch(b->exec, s));
+        } else {
+            rbs::launch_batch_iterations(s, B, b->grid, CHUNK);
+        }
+        return RBS_OK;
+    };
+    auto poll = [&]() -> int {
+        rbs::launch_gather_states(s, B, b->d_states);
+        BHIPCHK(b, hipMemcpy2DAsync(b->h_states, sizeof(SolveState), b->d_states, sizeof(SolveState), 128,
+                                    b->nsys, hipMemcpyDeviceToHost, s));
+        BHIPCHK(b, hipEventRecord(b->ev, s));
+        return RBS_OK;
+    };
+    auto all_done = [&]() {
+        for (int j = 0; j < b->nsys; ++j)
+            if (!b->h_states[j].done) return false;
+        return true;
+    };
+    if (!rc) rc = enqueue();
+    if (!rc) rc = poll();
+    int enq = CHUNK;
+    while (!rc) {
+        if ((rc = enqueue())) break;
+        enq += CHUNK;
+        hipError_t e = hipEventSynchronize(b->ev);
+        if (e != hipSuccess) {
+            rc = bfail(b, RBS_ERR_HIP, hipGetErrorString(e));
+            break;
+        }
+        if (all_done() || enq > max_it + 4 * CHUNK) break;
+        rc = poll();
+    }
+    if (rc) {
+        restore();
+        return rc;
+    }
+    // epilogues, true residuals, per-system restarts
+    int worst = RBS_OK;
+    BHIPCHK(b, hipStreamSynchronize(s));
+    for (int j = 0; j < b->nsys; ++j) {
+        rbs_ctx* c = b->ctx[j];
+        rbs::SolveBufs Bj = solve_bufs(c, c->k, bvec[j], x[j], nullptr);
+        rbs::launch_solve_epilogue(c->stream, Bj);
+        rbs::launch_true_residual(c->stream, c->A, bvec[j], x[j], c->partials, c->dsums);
+        int r = to_host(c, c->hp->sums, c->dsums, 2 * sizeof(double));
+        if (!r) {
+            hipError_t e = hipMemcpy(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) r = fail(c, RBS_ERR_HIP, hipGetErrorString(e));
+        }
+        if (r) {
+            restore();
+            return r;
+        }
+        const SolveState h = c->hp->solve;
+        const double b2 = c->hp->sums[1];
+        rbs_stats st{};
+        st.iters = st.total_iters = h.iters_done;
+        st.matvecs_A = 2 * h.iters_done + 1;
+        st.matvecs_At = 1;
+        st.k_used = c->k;
+        st.rel_res_recur = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+        st.rel_res_true = b2 > 0 ? std::sqrt(c->hp->sums[0] / b2) : std::sqrt(c->hp->sums[0]);
+        int status = h.done ? h.status : RBS_MAXIT;
+        if (status == RBS_OK && !(st.rel_res_true <= rtol)) {
+            rbs_stats s2{};
+            status = solve_rbicgstab(c, c->k, bvec[j], x[j], 1, shadows ? shadows[j] : nullptr, rtol, max_it, &s2);
+            if (status < 0) {
+                restore();
+                return status;
+            }
+            st.total_iters += s2.total_iters;
+            st.restarts = 1 + s2.restarts;
+            st.matvecs_A += s2.matvecs_A;
+            st.matvecs_At += s2.matvecs_At;
+            st.rel_res_true = s2.rel_res_true;
+        }
+        st.status = status;
+        if (stats) stats[j] = st;
+        if (status != RBS_OK && (worst == RBS_OK || status < 0)) worst = status;
+    }
+    restore();
+    if (stats) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int j = 0; j < b->nsys; ++j) stats[j].ms = ms;
+    }
+    return worst;
+}
+
+int rbicgstab_batch_destroy(rbs_batch* b) {
+    if (!b) return RBS_OK;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    batch_destroy_graph(b);
+    if (b->ev) hipEventDestroy(b->ev);
+    if (b->h_states) hipHostFree(b->h_states);
+    if (b->stream) hipStreamDestroy(b->stream);
+    delete b;
+    return RBS_OK;
+}
+
+const char* rbicgstab_batch_last_error(const rbs_batch* b) {
+    return b ? b->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

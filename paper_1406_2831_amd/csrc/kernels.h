@@ -90,6 +90,31 @@ void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count);
 // timing support: the main kernel of one multi-RHS pass (0 update, 1 spmv1, 2 spmv2)
 void launch_multi_pass(hipStream_t st, const MultiBufs& B, int which);
 
+// ---- batched independent systems --------------------------------------------
+// Algorithm 2 for a batch of systems, each with its own matrix (any n), recycle
+// space and state, advanced together: each pass is one persistent launch whose
+// workgroups walk a list of row tiles of all systems (tile t = rows [r0, r1) of
+// system sys), each finalize one workgroup per system.  Partial sums are
+// value-major with row stride ntiles (partials[v * ntiles + t]).
+struct BatchTile {
+    int32_t sys;
+    int32_t pad;
+    int64_t r0, r1;
+};
+struct BatchBufs {
+    const SolveBufs* sys;       // device array: system j's buffers (its k may be 0)
+    const BatchTile* tiles;     // device array
+    const int32_t* tile_begin;  // device array (nsys + 1): system j owns tiles [tb[j], tb[j+1])
+    int nsys, ntiles, kmax;
+    double* partials;
+};
+// count iterations of every unfinished system; grid = workgroups of each pass
+void launch_batch_iterations(hipStream_t st, const BatchBufs& B, int grid, int count);
+// timing support: the main kernel of one batched pass (0 update, 1 spmv1, 2 spmv2)
+void launch_batch_pass(hipStream_t st, const BatchBufs& B, int grid, int which);
+// out[j] = first 128 bytes (the scalar header) of system j's state
+void launch_gather_states(hipStream_t st, const BatchBufs& B, SolveState* out);
+
 // y (float) = x (double) rounded, scaled by `scale`
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y);
 // x += scale * d  (x double, d float)

@@ -635,20 +635,16 @@ __global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufsT<T> B, int nb) {
     }
 }
 
-// update pass (end of iteration i-1 and start of iteration i)
+// update pass (end of iteration i-1 and start of iteration i) over the rows
+// r0, r0 + step, ... < r1 of one system; the K + 3 sums accumulate into acc.
+// k > 0 is required when K > 0 (the batched passes check it per system).
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B) {
-    constexpr int M = K + 3;
-    SolveState* st = B.state;
-    if (st->done) return;
+__device__ __forceinline__ void update_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
+                                            double (&acc)[K + 3]) {
+    const SolveState* st = B.state;
     const int k = B.k;
     const double alpha = st->alpha, omega = st->omega, beta = st->beta;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+    for (int64_t row = r0; row < r1; row += step) {
         const double sv = B.s[row], tv = B.t[row], pv = B.p[row], qv = B.q[row];
         const double rv = sv - omega * tv;
         B.x[row] += alpha * pv + omega * sv;
@@ -661,6 +657,18 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B) {
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[3 + j] += B.Gh[row + col_off(j, k, B.ld)] * pn;
     }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B) {
+    constexpr int M = K + 3;
+    if (B.state->done) return;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    update_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
     block_partial<M>(acc, M, B.partials);
 }
 
@@ -718,23 +726,18 @@ __global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufsT<T> B, int nb) {
     if (threadIdx.x == 0) update_fin_scalars(st, tot, B.k);
 }
 
-// spmv1: q = A p - C zeta ; s = r - alpha q ; gamma partials Gh^T s
+// spmv1: q = A p - C zeta ; s = r - alpha q ; partials Gh^T s (rows as update_rows)
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B) {
+__device__ __forceinline__ void spmv1_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
+                                           double (&acc)[K > 0 ? K : 1]) {
     constexpr int M = K > 0 ? K : 1;
-    SolveState* st = B.state;
-    if (st->done) return;
+    const SolveState* st = B.state;
     const int k = B.k;
     const double alpha = st->alpha;
     double zeta[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) zeta[j] = (j < k) ? st->zeta[j] : 0.0;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+    for (int64_t row = r0; row < r1; row += step) {
         double qv = sell_row(B.A, row, B.p);
 #pragma unroll
         for (int j = 0; j < K; ++j) qv -= B.C[row + col_off(j, k, B.ld)] * zeta[j];
@@ -744,6 +747,18 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B) {
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] += B.Gh[row + col_off(j, k, B.ld)] * sv;
     }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B) {
+    constexpr int M = K > 0 ? K : 1;
+    if (B.state->done) return;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    spmv1_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
     if (K > 0) block_partial<M>(acc, M, B.partials);
 }
 
@@ -760,18 +775,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1_fin(SolveBufsT<T> B, int nb) {
 
 // spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B) {
-    constexpr int M = 5;
-    SolveState* st = B.state;
-    if (st->done) return;
+__device__ __forceinline__ void spmv2_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
+                                           double (&acc)[5]) {
+    const SolveState* st = B.state;
     const int k = B.k;
     double gam[K > 0 ? K : 1];
 #pragma unroll
     for (int j = 0; j < K; ++j) gam[j] = (j < k) ? st->gamma[j] : 0.0;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
+    for (int64_t row = r0; row < r1; row += step) {
         double tv = sell_row(B.A, row, B.s);
 #pragma unroll
         for (int j = 0; j < K; ++j) tv -= B.C[row + col_off(j, k, B.ld)] * gam[j];
@@ -783,7 +794,16 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B) {
         acc[3] += rt * tv;
         acc[4] += sv * sv;
     }
-    block_partial<M>(acc, M, B.partials);
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B) {
+    if (B.state->done) return;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    spmv2_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
+    block_partial<5>(acc, 5, B.partials);
 }
 
 // Scalar part of the second finalize for one system: omega, x_c, beta.
@@ -858,6 +878,128 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
         out[0] = tot[0];
         out[1] = tot[1];
     }
+}
+
+// ---------------------------------------------------------------- batched passes
+// Persistent kernels over the tiles of a batch of independent systems: the
+// per-row work is the single-system pass's (update_rows / spmv1_rows /
+// spmv2_rows); a system without recycle space (k = 0) runs the K = 0 body.
+
+template <int M>
+__device__ __forceinline__ void tile_partial(double (&v)[M], double* partials, int stride, int t) {
+    __shared__ double red[(BLOCK / WAVE) * M];
+    __shared__ double tot[M];
+    block_sum<M>(v, M, red, tot);
+    if (threadIdx.x < M) partials[(int64_t)threadIdx.x * stride + t] = tot[threadIdx.x];
+    __syncthreads();   // tot is rewritten by the next tile
+}
+
+// One workgroup sums a system's tile partials [b0, b1) in tile order.
+template <int M>
+__device__ __forceinline__ void reduce_tile_partials(const double* __restrict__ partials, int stride,
+                                                     int b0, int b1, double* tot) {
+    __shared__ double red[(BLOCK / WAVE) * M];
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        acc[j] = 0.0;
+        for (int b = b0 + threadIdx.x; b < b1; b += BLOCK) acc[j] += partials[(int64_t)j * stride + b];
+    }
+    block_sum<M>(acc, M, red, tot);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufs B) {
+    constexpr int M = K + 3;
+    for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
+        const BatchTile tl = B.tiles[t];
+        const SolveBufs S = B.sys[tl.sys];
+        if (S.state->done) continue;
+        double acc[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc[j] = 0.0;
+        if (S.k > 0) {
+            update_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+        } else {
+            double a0[3] = {0.0, 0.0, 0.0};
+            update_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
+            acc[0] = a0[0];
+            acc[1] = a0[1];
+            acc[2] = a0[2];
+        }
+        tile_partial<M>(acc, B.partials, B.ntiles, t);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_update_fin(BatchBufs B) {
+    constexpr int M = K + 3;
+    __shared__ double tot[M];
+    const int j = blockIdx.x;
+    SolveState* st = B.sys[j].state;
+    if (st->done) return;
+    reduce_tile_partials<M>(B.partials, B.ntiles, B.tile_begin[j], B.tile_begin[j + 1], tot);
+    if (threadIdx.x == 0) update_fin_scalars(st, tot, B.sys[j].k);
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufs B) {
+    constexpr int M = K > 0 ? K : 1;
+    for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
+        const BatchTile tl = B.tiles[t];
+        const SolveBufs S = B.sys[tl.sys];
+        if (S.state->done) continue;
+        double acc[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc[j] = 0.0;
+        if (S.k > 0) {
+            spmv1_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+        } else {
+            double a0[1] = {0.0};
+            spmv1_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
+        }
+        if (K > 0) tile_partial<M>(acc, B.partials, B.ntiles, t);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv1_fin(BatchBufs B) {
+    constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
+    const int j = blockIdx.x;
+    SolveState* st = B.sys[j].state;
+    const int k = B.sys[j].k;
+    if (st->done || k == 0) return;
+    reduce_tile_partials<M>(B.partials, B.ntiles, B.tile_begin[j], B.tile_begin[j + 1], tot);
+    if (threadIdx.x < k) st->gamma[threadIdx.x] = tot[threadIdx.x];
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufs B) {
+    for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
+        const BatchTile tl = B.tiles[t];
+        const SolveBufs S = B.sys[tl.sys];
+        if (S.state->done) continue;
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (S.k > 0) spmv2_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+        else spmv2_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+        tile_partial<5>(acc, B.partials, B.ntiles, t);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv2_fin(BatchBufs B) {
+    __shared__ double tot[5];
+    const int j = blockIdx.x;
+    SolveState* st = B.sys[j].state;
+    if (st->done) return;
+    reduce_tile_partials<5>(B.partials, B.ntiles, B.tile_begin[j], B.tile_begin[j + 1], tot);
+    if (threadIdx.x == 0) spmv2_fin_scalars(st, tot, B.sys[j].k);
+}
+
+__global__ void k_gather_states(BatchBufs B, SolveState* out) {
+    // 128-byte scalar header of each state, 16 doubles per system
+    const int j = blockIdx.x, i = threadIdx.x;
+    if (i < 16) reinterpret_cast<double*>(out + j)[i] = reinterpret_cast<const double*>(B.sys[j].state)[i];
 }
 
 // ---------------------------------------------------------------- multi-RHS passes
@@ -1715,6 +1857,49 @@ void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count) {
         dispatch_k<L_mspmv2>(B.k, st, g, B);
         hipLaunchKernelGGL(k_mspmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
     }
+}
+
+template <int K>
+struct BatchLaunch {
+    static void iter(hipStream_t st, const BatchBufs& B, int grid, int count) {
+        for (int it = 0; it < count; ++it) {
+            hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+            hipLaunchKernelGGL(k_batch_update_fin<K>, dim3(B.nsys), dim3(BLOCK), 0, st, B);
+            hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+            if (K > 0) hipLaunchKernelGGL(k_batch_spmv1_fin<K>, dim3(B.nsys), dim3(BLOCK), 0, st, B);
+            hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+            hipLaunchKernelGGL(k_batch_spmv2_fin, dim3(B.nsys), dim3(BLOCK), 0, st, B);
+        }
+    }
+    static void pass(hipStream_t st, const BatchBufs& B, int grid, int which) {
+        if (which == 0) hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+        else if (which == 1) hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+        else hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+    }
+};
+
+void launch_batch_iterations(hipStream_t st, const BatchBufs& B, int grid, int count) {
+    const int k = B.kmax;
+    if (k == 0) BatchLaunch<0>::iter(st, B, grid, count);
+    else if (k <= 4) BatchLaunch<4>::iter(st, B, grid, count);
+    else if (k <= 8) BatchLaunch<8>::iter(st, B, grid, count);
+    else if (k <= 16) BatchLaunch<16>::iter(st, B, grid, count);
+    else if (k <= 32) BatchLaunch<32>::iter(st, B, grid, count);
+    else BatchLaunch<64>::iter(st, B, grid, count);
+}
+
+void launch_batch_pass(hipStream_t st, const BatchBufs& B, int grid, int which) {
+    const int k = B.kmax;
+    if (k == 0) BatchLaunch<0>::pass(st, B, grid, which);
+    else if (k <= 4) BatchLaunch<4>::pass(st, B, grid, which);
+    else if (k <= 8) BatchLaunch<8>::pass(st, B, grid, which);
+    else if (k <= 16) BatchLaunch<16>::pass(st, B, grid, which);
+    else if (k <= 32) BatchLaunch<32>::pass(st, B, grid, which);
+    else BatchLaunch<64>::pass(st, B, grid, which);
+}
+
+void launch_gather_states(hipStream_t st, const BatchBufs& B, SolveState* out) {
+    hipLaunchKernelGGL(k_gather_states, dim3(B.nsys), dim3(64), 0, st, B, out);
 }
 
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y) {

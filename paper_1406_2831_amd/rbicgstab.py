@@ -43,7 +43,11 @@ RBS_RECYCLE_CLEAR = 2
 EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "recycle_update",
            "rbicgstab_get_blocks", "rbicgstab_time_pass", "rbicgstab_setup_matvecs",
            "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_solve_multi",
-           "rbicgstab_destroy", "rbicgstab_last_error")
+           "rbicgstab_destroy", "rbicgstab_last_error", "rbicgstab_batch_workspace_bytes",
+           "rbicgstab_batch_create", "rbicgstab_batch_solve", "rbicgstab_batch_config",
+           "rbicgstab_batch_destroy", "rbicgstab_batch_last_error")
+RBS_BATCH_TUNE = 1
+RBS_BATCH_GRAPH = 2
 
 
 class Stats(ctypes.Structure):
@@ -81,6 +85,19 @@ def load_library(path: str = LIB_PATH):
     lib.rbicgstab_solve_multi.argtypes = [vp, i32, vp, i64, vp, i64, vp, f64, i32, i32,
                                           ctypes.POINTER(Stats)]
     lib.rbicgstab_solve_multi.restype = ctypes.c_int
+    lib.rbicgstab_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(i64)]
+    lib.rbicgstab_batch_workspace_bytes.restype = sz
+    lib.rbicgstab_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), vp, sz, i32]
+    lib.rbicgstab_batch_create.restype = ctypes.c_int
+    lib.rbicgstab_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), f64,
+                                          i32, i32, ctypes.POINTER(Stats)]
+    lib.rbicgstab_batch_solve.restype = ctypes.c_int
+    lib.rbicgstab_batch_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(f64)]
+    lib.rbicgstab_batch_config.restype = ctypes.c_int
+    lib.rbicgstab_batch_destroy.argtypes = [vp]
+    lib.rbicgstab_batch_destroy.restype = ctypes.c_int
+    lib.rbicgstab_batch_last_error.argtypes = [vp]
+    lib.rbicgstab_batch_last_error.restype = ctypes.c_char_p
     lib.recycle_update.argtypes = [vp, i32, vp, vp, i32]
     lib.recycle_update.restype = ctypes.c_int
     lib.rbicgstab_get_blocks.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
@@ -309,6 +326,66 @@ class Context:
 
     def close(self):
         rbicgstab_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batch of bound contexts solved together (rbicgstab_batch_*)."""
+
+    def __init__(self, contexts, tune: bool = True, graph: bool = True, device: str = "cuda"):
+        lib = load_library()
+        self.contexts = list(contexts)
+        nsys = len(self.contexts)
+        n = (ctypes.c_int64 * nsys)(*[c.n for c in self.contexts])
+        ws = int(lib.rbicgstab_batch_workspace_bytes(nsys, n))
+        if ws == 0:
+            raise RbsError(RBS_ERR_ARG, "invalid batch sizes")
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
+        handles = (ctypes.c_void_p * nsys)(*[c.handle.value for c in self.contexts])
+        h = ctypes.c_void_p(None)
+        flags = (RBS_BATCH_TUNE if tune else 0) | (RBS_BATCH_GRAPH if graph else 0)
+        rc = lib.rbicgstab_batch_create(ctypes.byref(h), nsys, handles, _ptr(self.workspace), ws, flags)
+        if rc < 0:
+            msg = lib.rbicgstab_batch_last_error(None)
+            raise RbsError(rc, msg.decode() if msg else "")
+        self.handle = h
+
+    def _check(self, rc):
+        if rc < 0:
+            msg = load_library().rbicgstab_batch_last_error(self.handle)
+            raise RbsError(rc, msg.decode() if msg else "")
+        return rc
+
+    def config(self):
+        rows, grid, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        self._check(load_library().rbicgstab_batch_config(self.handle, ctypes.byref(rows), ctypes.byref(grid),
+                                                          ctypes.byref(ms)))
+        return {"tile_rows": rows.value, "grid": grid.value, "tuned_ms_per_iter": ms.value}
+
+    def solve(self, bs, xs, shadows=None, rtol=1e-8, max_it=10000, mode: str = "rbicgstab"):
+        """bs, xs (, shadows): lists of device tensors, one per system."""
+        lib = load_library()
+        nsys = len(self.contexts)
+        P = ctypes.c_void_p * nsys
+        pb = P(*[t.data_ptr() for t in bs])
+        px = P(*[t.data_ptr() for t in xs])
+        ps = P(*[t.data_ptr() for t in shadows]) if shadows is not None else None
+        stats = (Stats * nsys)()
+        flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB}[mode]
+        torch.cuda.current_stream().synchronize()
+        rc = lib.rbicgstab_batch_solve(self.handle, pb, px, ps, rtol, max_it, flags, stats)
+        self._check(rc)
+        return list(stats)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().rbicgstab_batch_destroy(self.handle)
         self.handle = None
 
     def __del__(self):

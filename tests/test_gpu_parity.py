@@ -420,3 +420,46 @@ def test_multi_rhs_sequence_3d(rb, torch_mod):
             xr, ir = o.bicgstab(A.to_scipy(), seq.rhs[idx], shadow=seq.shadows[idx], rtol=1e-12)
             assert _rel(x.cpu().numpy(), xr) <= 1e-6, (mode, idx)
     gs.close()
+
+
+def test_batched_uneven_systems(rb, torch_mod):
+    """Batches of independent systems of uneven size (own matrix, own recycle
+    space built by RBiCG): the persistent batched passes, tuned and replayed
+    from a captured graph, against per-system solves and path-independent
+    references; two solves in a row (graph replays) and an eager batch agree."""
+    from paper_1406_2831_amd.sequence import max_row_nnz
+    systems = w.batched_systems(count=5, scale=0.3)
+    ctxs, refs, bs, shs = [], [], [], []
+    _say("batched 5 uneven systems: spaces by RBiCG")
+    for (A, At, b, sh) in systems:
+        ctx = rb.Context(A.n, max_row_nnz(A, At), 16, 512)
+        ctx.setup(A, At)
+        bt = torch_mod.as_tensor(b, device="cuda")
+        st = ctx.solve(bt, torch_mod.zeros_like(bt), rtol=1e-10, mode="rbicg")[1]
+        assert st.status == 0
+        ctx.recycle("from_last_solve")
+        xr, ir = o.bicgstab(A.to_scipy(), b, shadow=sh, rtol=1e-12)
+        assert ir.status == o.OK
+        ctxs.append(ctx)
+        refs.append(xr)
+        bs.append(bt)
+        shs.append(torch_mod.as_tensor(sh, device="cuda"))
+    print("n:", [c.n for c in ctxs], "k:", [c.blocks()[1] for c in ctxs], flush=True)
+    for graph in (True, False):
+        batch = rb.Batch(ctxs, tune=graph, graph=graph)
+        print("config", batch.config(), flush=True)
+        for mode in ("rbicgstab", "bicgstab"):
+            for rep in range(2 if graph else 1):
+                xs = [torch_mod.zeros_like(b) for b in bs]
+                sts = batch.solve(bs, xs, shs, rtol=1e-10, mode=mode)
+                print(f"graph={graph} {mode} rep {rep}: iters {[s.iters for s in sts]}", flush=True)
+                for j, (x, st) in enumerate(zip(xs, sts)):
+                    assert st.status == 0 and st.rel_res_true <= 1e-10, (mode, j, st.as_dict())
+                    assert _rel(x.cpu().numpy(), refs[j]) <= 1e-6, (mode, j)
+                    # the same system alone
+                    x1, st1 = _solve(ctxs[j], torch_mod, systems[j][2], shadow=systems[j][3], mode=mode,
+                                     rtol=1e-10)
+                    assert abs(st1.iters - st.iters) <= max(3, 0.05 * st1.iters), (mode, j)
+        batch.close()
+    for c in ctxs:
+        c.close()
