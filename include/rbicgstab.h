@@ -83,7 +83,9 @@ enum {
                            * vectors, matrix values and recycle blocks (FP64 sums and scalars)  *
                            * to a relative residual 1e-5 (or what is still missing); x += ||r|| d *
                            * in FP64; at most 10 outer steps.  The recycle space itself (D_c    *
-                           * solve, Ritz step) stays FP64.  stats.iters = inner iterations,     *
+                           * solve, Ritz step) stays FP64.  A correction whose FP32 solve     *
+                           * produces non-finite values is redone without the space, then in  *
+                           * FP64 (counted in stats.restarts).  stats.iters = inner iterations, *
                            * stats.ir_steps = outer steps, stats.rel_res_true = FP64 residual.  */
     RBS_TRANSPOSE = 8     /* solve A^T x = b reusing the space with the roles of U and Ut      *
                            * swapped (OR-ed with RBS_RBICGSTAB or RBS_BICGSTAB): for A^T the   *

@@ -547,7 +547,7 @@ int solve_ir(rbs_ctx* c, int k, const double* b, double* x, int xnz, const doubl
     if (!xnz) rbs::launch_fill(s, x, c->n, 0.0);
     if (shadow) rbs::launch_to_float(s, c->n, shadow, 1.0, c->shf);
     rbs::SolveBufsF B = solve_bufs_f32(c, k, shadow != nullptr);
-    int status = RBS_MAXIT, total_iters = 0, steps = 0, mvA = 0, mvAt = 0;
+    int status = RBS_MAXIT, total_iters = 0, steps = 0, mvA = 0, mvAt = 0, fallbacks = 0;
     double rel = NAN, rel_inner = NAN;
     for (int outer = 0;; ++outer) {
         rbs::launch_residual(s, c->A, b, x, c->r64, c->partials, c->dsums);
@@ -572,35 +572,64 @@ int solve_ir(rbs_ctx* c, int k, const double* b, double* x, int xnz, const doubl
         rbs::launch_to_float(s, c->n, c->r64, 1.0 / rn, c->bf);
         // ask for what is still missing, but no less than FP32 storage can give
         const double want = std::max(INNER_RTOL, 0.5 * rtol / rel);
-        rbs::launch_solve_prologue(s, B, 0, want, max_it - total_iters);
-        mvAt += 1;
-        rc = iterate_until_done(
-            c, [&](int cnt) { rbs::launch_solve_iterations(s, B, cnt); },
-            [&]() { return c->hp->solve.done != 0; }, &c->hp->solve, c->st, 128, max_it);
-        if (rc) return rc;
-        rbs::launch_solve_epilogue(s, B);
-        rbs::launch_add_float(s, c->n, x, c->df, rn);
-        HIPCHK(c, hipGetLastError());
-        if ((rc = to_host(c, &c->hp->solve, c->st, 128))) return rc;
-        const SolveState& h = c->hp->solve;
-        total_iters += h.iters_done;
-        mvA += 2 * h.iters_done;
+        // one FP32 inner solve; returns its status (the state is in c->hp->solve)
+        auto inner = [&](const rbs::SolveBufsF& Bu) -> int {
+            rbs::launch_solve_prologue(s, Bu, 0, want, max_it - total_iters);
+            mvAt += 1;
+            int r2 = iterate_until_done(
+                c, [&](int cnt) { rbs::launch_solve_iterations(s, Bu, cnt); },
+                [&]() { return c->hp->solve.done != 0; }, &c->hp->solve, c->st, 128, max_it);
+            if (r2) return r2;
+            rbs::launch_solve_epilogue(s, Bu);
+            HIPCHK(c, hipGetLastError());
+            if ((r2 = to_host(c, &c->hp->solve, c->st, 128))) return r2;
+            const SolveState& h = c->hp->solve;
+            total_iters += h.iters_done;
+            mvA += 2 * h.iters_done;
+            rel_inner = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+            return h.status;
+        };
+        // a correction is usable unless the inner solve produced non-finite values
+        // or broke down before any progress
+        auto usable = [&](int st_in) {
+            if (st_in < 0) return false;
+            return st_in == RBS_OK || st_in == RBS_MAXIT || (c->hp->solve.iters_done > 0 && std::isfinite(rel_inner));
+        };
+        int st_in = inner(B);
+        if (st_in < 0 && st_in != RBS_ERR_NONFINITE) return st_in;
+        if (!usable(st_in) && k > 0) {
+            // FP32 rounding can make the oblique projection of a poorly conditioned
+            // space blow up: retry this correction without the space
+            ++fallbacks;
+            st_in = inner(solve_bufs_f32(c, 0, shadow != nullptr));
+            if (st_in < 0 && st_in != RBS_ERR_NONFINITE) return st_in;
+        }
         ++steps;
-        rel_inner = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
-        if (h.status == RBS_ERR_NONFINITE) {
-            status = RBS_ERR_NONFINITE;
-            break;
+        if (usable(st_in)) {
+            rbs::launch_add_float(s, c->n, x, c->df, rn);
+        } else {
+            // last resort: this correction in FP64 (the library's FP64 solver on r)
+            ++fallbacks;
+            rbs_stats s64{};
+            const int st64 = solve_rbicgstab(c, k, c->r64, c->rt, 0, shadow, std::max(want, rtol / rel * 0.5),
+                                             max_it, &s64);
+            if (st64 < 0) return st64;
+            total_iters += s64.total_iters;
+            mvA += s64.matvecs_A;
+            mvAt += s64.matvecs_At;
+            if (st64 != RBS_OK && st64 != RBS_MAXIT) {
+                status = st64;
+                break;
+            }
+            rbs::launch_axpy(s, c->n, x, c->rt, 1.0);
         }
-        if (h.status != RBS_OK && h.status != RBS_MAXIT && h.iters_done == 0) {
-            status = h.status;   // breakdown before any progress: refinement cannot continue
-            break;
-        }
+        HIPCHK(c, hipGetLastError());
     }
     if (stats) {
         stats->status = status;
         stats->iters = total_iters;
         stats->total_iters = total_iters;
-        stats->restarts = 0;
+        stats->restarts = fallbacks;   // corrections redone without the space or in FP64
         stats->matvecs_A = mvA;
         stats->matvecs_At = mvAt;
         stats->k_used = k;

@@ -585,34 +585,45 @@ int orth_factor_chol(int m, const double* Gram, double shift, std::vector<double
         if (g > 0) idx.push_back(i);
     }
     const int r = (int)idx.size();
-    std::vector<double> R((size_t)r * r, 0.0);   // upper triangular, R^T R = D G D + shift I
+    // L (lower, column-major): L L^T = D G D + shift I; column-oriented so that
+    // every inner loop runs down a contiguous column
+    std::vector<double> L((size_t)r * r, 0.0);
     for (int j = 0; j < r; ++j)
-        for (int i = 0; i <= j; ++i)
-            R[i + (size_t)j * r] = d[idx[i]] * Gram[idx[i] + (size_t)idx[j] * m] * d[idx[j]] +
+        for (int i = j; i < r; ++i)
+            L[i + (size_t)j * r] = d[idx[i]] * Gram[idx[i] + (size_t)idx[j] * m] * d[idx[j]] +
                                    (i == j ? shift : 0.0);
-    for (int j = 0; j < r; ++j) {   // right-looking Cholesky on the upper triangle
-        const double pv = R[j + (size_t)j * r];
+    for (int j = 0; j < r; ++j) {
+        double* lj = L.data() + (size_t)j * r;
+        const double pv = lj[j];
         if (!(pv > 0.0) || !std::isfinite(pv)) return -1;
-        const double rj = std::sqrt(pv);
-        R[j + (size_t)j * r] = rj;
-        for (int c = j + 1; c < r; ++c) R[j + (size_t)c * r] /= rj;
-        for (int c = j + 1; c < r; ++c) {
-            const double a = R[j + (size_t)c * r];
-            for (int i = j + 1; i <= c; ++i) R[i + (size_t)c * r] -= R[j + (size_t)i * r] * a;
+        const double ljj = std::sqrt(pv);
+        lj[j] = ljj;
+        const double inv = 1.0 / ljj;
+        for (int i = j + 1; i < r; ++i) lj[i] *= inv;
+        for (int c = j + 1; c < r; ++c) {   // trailing update of column c
+            const double a = lj[c];
+            if (a == 0.0) continue;
+            double* lc = L.data() + (size_t)c * r;
+            for (int i = c; i < r; ++i) lc[i] -= lj[i] * a;
         }
     }
+    // X = L^-1 (lower), column by column with column-oriented forward substitution
+    std::vector<double> X((size_t)r * r, 0.0);
+    for (int b = 0; b < r; ++b) {
+        double* xb = X.data() + (size_t)b * r;
+        xb[b] = 1.0;
+        for (int c = b; c < r; ++c) {
+            const double* lc = L.data() + (size_t)c * r;
+            const double v = xb[c] / lc[c];
+            xb[c] = v;
+            if (v == 0.0) continue;
+            for (int i = c + 1; i < r; ++i) xb[i] -= lc[i] * v;
+        }
+    }
+    // S = D R^-1 with R = L^T: R^-1 = X^T
     S.assign((size_t)m * r, 0.0);
-    std::vector<double> e(r);
-    for (int b = 0; b < r; ++b) {   // column b of R^-1
-        std::fill(e.begin(), e.end(), 0.0);
-        e[b] = 1.0;
-        for (int a = b; a >= 0; --a) {
-            double s = e[a];
-            for (int c = a + 1; c <= b; ++c) s -= R[a + (size_t)c * r] * e[c];
-            e[a] = s / R[a + (size_t)a * r];
-        }
-        for (int a = 0; a <= b; ++a) S[idx[a] + (size_t)b * m] = d[idx[a]] * e[a];
-    }
+    for (int b = 0; b < r; ++b)
+        for (int a = 0; a <= b; ++a) S[idx[a] + (size_t)b * m] = d[idx[a]] * X[b + (size_t)a * r];
     return r;
 }
 

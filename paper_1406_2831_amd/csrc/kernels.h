@@ -117,6 +117,8 @@ void launch_gather_states(hipStream_t st, const BatchBufs& B, SolveState* out);
 
 // y (float) = x (double) rounded, scaled by `scale`
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y);
+// x += scale * d  (both double)
+void launch_axpy(hipStream_t st, int64_t n, double* x, const double* d, double scale);
 // x += scale * d  (x double, d float)
 void launch_add_float(hipStream_t st, int64_t n, double* x, const float* d, double scale);
 // r = b - A x (FP64); out_sums[0] = ||r||^2, out_sums[1] = ||b||^2

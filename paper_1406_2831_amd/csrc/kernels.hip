@@ -1175,6 +1175,12 @@ __global__ __launch_bounds__(BLOCK) void k_to_float(int64_t n, const double* __r
         y[i] = (float)(x[i] * scale);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_axpy(int64_t n, double* __restrict__ x,
+                                                const double* __restrict__ d, double scale) {
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        x[i] += scale * d[i];
+}
+
 __global__ __launch_bounds__(BLOCK) void k_add_float(int64_t n, double* __restrict__ x,
                                                      const float* __restrict__ d, double scale) {
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
@@ -1904,6 +1910,10 @@ void launch_gather_states(hipStream_t st, const BatchBufs& B, SolveState* out) {
 
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y) {
     hipLaunchKernelGGL(k_to_float, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, x, scale, y);
+}
+
+void launch_axpy(hipStream_t st, int64_t n, double* x, const double* d, double scale) {
+    hipLaunchKernelGGL(k_axpy, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, x, d, scale);
 }
 
 void launch_add_float(hipStream_t st, int64_t n, double* x, const float* d, double scale) {
