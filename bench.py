@@ -253,6 +253,70 @@ def batched_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def large_workload(args):
+    """The 27-point nonsymmetric stencil on 160^3 (n = 4,096,000, nnz = 109,215,352),
+    k = 30, first --large-shifts shifts x 5 right-hand sides of the 10-shift sequence:
+    RBiCG (FP64) on the first right-hand side of each shift, then RBiCGSTAB with FP32
+    storage under FP64 refinement on the others; BiCGSTAB (FP32-IR) on all as the
+    baseline.  One step, no warm-up (each run takes seconds).  Also times the fused
+    passes in FP32 and FP64 at this HBM-resident size."""
+    import torch
+    import workloads as w
+    from paper_1406_2831_amd.sequence import GpuSequence
+
+    N = args.grid if args.grid != 64 else 160
+    seq = w.seq_3d27(N=N, nshift=10, nrhs=5, k=30)
+    nsys = args.large_shifts * seq.nrhs
+    # keep the first shifts only (the sequence's systems are shift-major)
+    seq.sigmas = seq.sigmas[: args.large_shifts]
+    seq.rhs, seq.shadows = seq.rhs[:nsys], seq.shadows[:nsys]
+    gs = GpuSequence(seq, s_max=512, secant_max=args.secant_max)
+    res, timed = {}, {}
+    for key, mode, prec in (("rbicgstab_fp32_ir", "rbicgstab", "fp32_ir"),
+                            ("bicgstab_fp32_ir", "bicgstab", "fp32_ir"),
+                            ("rbicgstab_fp64", "rbicgstab", "fp64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gs.run(mode=mode, rtol=args.rtol, max_it=40000, precision=prec)
+        torch.cuda.synchronize()
+        timed[key] = time.perf_counter() - t0
+        res[key] = r
+        if any(s_ != 0 for s_ in r.status) or max(r.rel_res_true) > args.rtol:
+            print(f"{key}: not every system converged: {r.status} {r.rel_res_true}", file=sys.stderr)
+            sys.exit(1)
+    k_last = int(res["rbicgstab_fp32_ir"].k_used[-1])
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
+    passes = {}
+    for name, which, kk in (("spmv1_project_fp32", 5, k_last), ("update_fp32", 4, k_last),
+                            ("spmv2_project_fp32", 6, k_last), ("spmv_fp32", 7, 0),
+                            ("spmv1_project", 1, k_last), ("update", 0, k_last),
+                            ("spmv2_project", 2, k_last), ("spmv", 3, 0)):
+        ms, by = gs.ctx.time_pass(which, kk, 20)
+        passes[name] = {"us": ms * 1e3, "gbs": gbs(by, ms), "bytes": by}
+    dom = passes["spmv1_project_fp32"]
+    out = {
+        "metric": "systems solved/s at rel.res 1e-8 (FP64 true residual), RBiCGSTAB FP32-IR",
+        "value": nsys / timed["rbicgstab_fp32_ir"], "unit": "systems/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": timed["rbicgstab_fp32_ir"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage / f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"3d 27-point convection-diffusion {N}^3 (n={seq.n}, nnz={seq.K.nnz}), "
+                               f"first {args.large_shifts} of 10 shifts x 5 rhs = {nsys} systems, k=30, "
+                               f"rtol={args.rtol}", "n": seq.n, "nnz": int(seq.K.nnz)},
+        "systems_per_s": {k_: nsys / v for k_, v in timed.items()},
+        "iters": {k_: r.iters for k_, r in res.items()},
+        "k_used": res["rbicgstab_fp32_ir"].k_used,
+        "matvecs": {k_: r.total_matvecs for k_, r in res.items()},
+        "passes": dict(passes, k=k_last),
+        "roofline": {"bound": "hbm", "kernel": f"k_spmv1<float, {k_bucket(k_last)}>",
+                     "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dom["bytes"], "us_per_launch": dom["us"]},
+    }
+    gs.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,10 +334,13 @@ def main():
                     help="skip the FP32-storage / FP64-refinement runs (reported beside the FP64 line)")
     ap.add_argument("--secant-max", type=float, default=0.0,
                     help="oblique-projector cap of the recycle setup (0: library default)")
-    ap.add_argument("--workload", choices=("sequence", "adjoint", "batched"), default="sequence",
+    ap.add_argument("--workload", choices=("sequence", "adjoint", "batched", "large"), default="sequence",
                     help="sequence: the shifted 64^3 sequence (default); adjoint: gradients of "
                          "c^T x on the 128^3 problem through the transposed recycled solve; "
-                         "batched: 32 shifted systems of uneven size solved together")
+                         "batched: 32 shifted systems of uneven size solved together; large: the "
+                         "27-point 160^3 sequence with FP32 storage under FP64 refinement")
+    ap.add_argument("--large-shifts", type=int, default=2,
+                    help="large workload: shifts of the 10-shift sequence run (a stated subset)")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--fd-dirs", type=int, default=16,
                     help="adjoint workload: finite-difference directions checked after timing")
@@ -287,6 +354,8 @@ def main():
         return adjoint_workload(args)
     if args.workload == "batched":
         return batched_workload(args)
+    if args.workload == "large":
+        return large_workload(args)
 
     import torch
     import workloads as w
