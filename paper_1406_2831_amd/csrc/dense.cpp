@@ -11,6 +11,27 @@ namespace dense {
 
 using cd = std::complex<double>;
 
+// sum a[i] b[i] with 16 independent partial sums, so that the compiler can
+// keep several vector accumulators in flight (a single running sum is one
+// serial chain of dependent additions).
+static inline double dot(const double* a, const double* b, int n) {
+    double acc[16] = {0.0};
+    int i = 0;
+    for (; i + 16 <= n; i += 16)
+        for (int t = 0; t < 16; ++t) acc[t] += a[i + t] * b[i + t];
+    for (; i < n; ++i) acc[0] += a[i] * b[i];
+    for (int w = 8; w >= 1; w >>= 1)
+        for (int t = 0; t < w; ++t) acc[t] += acc[t + w];
+    return acc[0];
+}
+
+// acc - a * b in plain real arithmetic (the library operator* carries an
+// Inf/NaN recovery branch that keeps the inner loops from vectorising).
+static inline cd cfms(cd acc, cd a, cd b) {
+    return cd(acc.real() - (a.real() * b.real() - a.imag() * b.imag()),
+              acc.imag() - (a.real() * b.imag() + a.imag() * b.real()));
+}
+
 int lu_factor(int n, double* A, int lda, int* piv) {
     auto a = [&](int i, int j) -> double& { return A[i + (size_t)j * lda]; };
     int info = 0;
@@ -43,31 +64,60 @@ int lu_factor(int n, double* A, int lda, int* piv) {
 void lu_solve(int n, const double* LU, int lda, const int* piv, double* B, int ldb, int nrhs,
               bool trans) {
     auto a = [&](int i, int j) { return LU[i + (size_t)j * lda]; };
+    if (!trans) {
+        // four right-hand sides per sweep over the factors: each column of L
+        // and U is read once per group
+        std::vector<double> pad;   // zero columns completing a short last group
+        for (int c0 = 0; c0 < nrhs; c0 += 4) {
+            const int nc = std::min(4, nrhs - c0);
+            if (nc < 4) pad.assign((size_t)(4 - nc) * n, 0.0);
+            double* b[4];
+            for (int t = 0; t < 4; ++t)
+                b[t] = t < nc ? B + (size_t)(c0 + t) * ldb : pad.data() + (size_t)(t - nc) * n;
+            for (int t = 0; t < nc; ++t)
+                for (int j = 0; j < n; ++j)
+                    if (piv[j] != j) std::swap(b[t][j], b[t][piv[j]]);
+            for (int j = 0; j < n; ++j) {        // L y = b (unit lower)
+                const double* lj = LU + (size_t)j * lda;
+                const double y0 = b[0][j], y1 = b[1][j], y2 = b[2][j], y3 = b[3][j];
+                for (int i = j + 1; i < n; ++i) {
+                    const double l = lj[i];
+                    b[0][i] -= l * y0;
+                    b[1][i] -= l * y1;
+                    b[2][i] -= l * y2;
+                    b[3][i] -= l * y3;
+                }
+            }
+            for (int j = n - 1; j >= 0; --j) {   // U x = y
+                const double* uj = LU + (size_t)j * lda;
+                const double inv = 1.0 / uj[j];
+                for (int t = 0; t < 4; ++t) b[t][j] *= inv;
+                const double y0 = b[0][j], y1 = b[1][j], y2 = b[2][j], y3 = b[3][j];
+                for (int i = 0; i < j; ++i) {
+                    const double u = uj[i];
+                    b[0][i] -= u * y0;
+                    b[1][i] -= u * y1;
+                    b[2][i] -= u * y2;
+                    b[3][i] -= u * y3;
+                }
+            }
+        }
+        return;
+    }
     for (int c = 0; c < nrhs; ++c) {
         double* b = B + (size_t)c * ldb;
-        if (!trans) {
-            for (int j = 0; j < n; ++j)
-                if (piv[j] != j) std::swap(b[j], b[piv[j]]);
-            for (int j = 0; j < n; ++j)          // L y = b (unit lower)
-                for (int i = j + 1; i < n; ++i) b[i] -= a(i, j) * b[j];
-            for (int j = n - 1; j >= 0; --j) {   // U x = y
-                b[j] /= a(j, j);
-                for (int i = 0; i < j; ++i) b[i] -= a(i, j) * b[j];
-            }
-        } else {
-            for (int j = 0; j < n; ++j) {        // U^T y = b (lower)
-                double s = b[j];
-                for (int i = 0; i < j; ++i) s -= a(i, j) * b[i];
-                b[j] = s / a(j, j);
-            }
-            for (int j = n - 1; j >= 0; --j) {   // L^T z = y (unit upper)
-                double s = b[j];
-                for (int i = j + 1; i < n; ++i) s -= a(i, j) * b[i];
-                b[j] = s;
-            }
-            for (int j = n - 1; j >= 0; --j)
-                if (piv[j] != j) std::swap(b[j], b[piv[j]]);
+        for (int j = 0; j < n; ++j) {        // U^T y = b (lower)
+            double s = b[j];
+            for (int i = 0; i < j; ++i) s -= a(i, j) * b[i];
+            b[j] = s / a(j, j);
         }
+        for (int j = n - 1; j >= 0; --j) {   // L^T z = y (unit upper)
+            double s = b[j];
+            for (int i = j + 1; i < n; ++i) s -= a(i, j) * b[i];
+            b[j] = s;
+        }
+        for (int j = n - 1; j >= 0; --j)
+            if (piv[j] != j) std::swap(b[j], b[piv[j]]);
     }
 }
 
@@ -294,14 +344,12 @@ static bool hessenberg_qr(int n, std::vector<double> a, std::vector<cd>& lam) {
     return true;
 }
 
-bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<double>& Qh,
+bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<double>& V,
                  std::vector<cd>& lambda) {
     Hh.assign(H, H + (size_t)n * n);
-    Qh.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) Qh[i + (size_t)i * n] = 1.0;
+    V.assign((size_t)n * n, 0.0);
     double* hp = Hh.data();
-    double* qp = Qh.data();
-    std::vector<double> v(n), w(n), wq(n);
+    std::vector<double> v(n), w(n);
     for (int k = 0; k + 2 < n; ++k) {
         // Householder vector v (zero above k+1) annihilating H(k+2.., k)
         double* hk = hp + (size_t)k * n;
@@ -316,86 +364,104 @@ bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<do
         for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
         if (vn == 0.0) continue;
         const double tau = 2.0 / vn;
-        // H <- (I - tau v v^T) H: one dot and one update per column (contiguous)
-        for (int j = 0; j < n; ++j) {
+        // H <- (I - tau v v^T) H on columns k.. (rows k+1.. of columns < k are
+        // already zero): one dot and one update per column (contiguous)
+        for (int j = k; j < n; ++j) {
             double* hj = hp + (size_t)j * n;
-            double s = 0.0;
-            for (int i = k + 1; i < n; ++i) s += v[i] * hj[i];
-            s *= tau;
+            const double s = tau * dot(v.data() + k + 1, hj + k + 1, n - k - 1);
             for (int i = k + 1; i < n; ++i) hj[i] -= s * v[i];
         }
-        // H <- H (I - tau v v^T), Q <- Q (I - tau v v^T): w = H v, wq = Q v
-        // accumulated column by column, then rank-one updates of columns k+1..
-        for (int i = 0; i < n; ++i) w[i] = wq[i] = 0.0;
+        // H <- H (I - tau v v^T): w = H v column by column, then rank-one updates
+        for (int i = 0; i < n; ++i) w[i] = 0.0;
         for (int j = k + 1; j < n; ++j) {
             const double vj = v[j];
             const double* hj = hp + (size_t)j * n;
-            const double* qj = qp + (size_t)j * n;
-            for (int i = 0; i < n; ++i) {
-                w[i] += hj[i] * vj;
-                wq[i] += qj[i] * vj;
-            }
+            for (int i = 0; i < n; ++i) w[i] += hj[i] * vj;
         }
         for (int j = k + 1; j < n; ++j) {
             const double tv = tau * v[j];
             double* hj = hp + (size_t)j * n;
-            double* qj = qp + (size_t)j * n;
-            for (int i = 0; i < n; ++i) {
-                hj[i] -= w[i] * tv;
-                qj[i] -= wq[i] * tv;
-            }
+            for (int i = 0; i < n; ++i) hj[i] -= w[i] * tv;
         }
         for (int i = k + 2; i < n; ++i) hk[i] = 0.0;
+        // reflector k kept as I - u u^T with u = sqrt(tau) v
+        const double st = std::sqrt(tau);
+        double* uk = V.data() + (size_t)k * n;
+        for (int i = k + 1; i < n; ++i) uk[i] = st * v[i];
     }
     return hessenberg_qr(n, Hh, lambda);
 }
 
+void hess_back(int n, const std::vector<double>& V, std::vector<cd>& y) {
+    // Q = P_0 P_1 ... P_{n-3}: apply the last reflector first
+    for (int k = n - 3; k >= 0; --k) {
+        const double* u = V.data() + (size_t)k * n;
+        double sr = 0.0, si = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            sr += u[i] * y[i].real();
+            si += u[i] * y[i].imag();
+        }
+        if (sr == 0.0 && si == 0.0) continue;
+        for (int i = k + 1; i < n; ++i) y[i] -= cd(u[i] * sr, u[i] * si);
+    }
+}
+
 void hess_eigvec(int n, const std::vector<double>& Hh, cd lam, bool left, std::vector<cd>& y) {
     // LU with adjacent-row partial pivoting of the Hessenberg Hh - lam I (O(n^2)),
-    // then two steps of inverse iteration.
-    std::vector<cd> M((size_t)n * n);
+    // then three steps of inverse iteration.  M is stored row-major so that the
+    // row operations of the elimination and both triangular solves run along
+    // contiguous rows.
+    std::vector<cd> M((size_t)n * n, cd(0.0));
     double hn = 0.0;
-    for (int j = 0; j < n; ++j)
-        for (int i = 0; i < n; ++i) {
-            M[i + (size_t)j * n] = Hh[i + (size_t)j * n] - (i == j ? lam : cd(0.0));
-            hn = std::max(hn, std::abs(M[i + (size_t)j * n]));
+    for (int j = 0; j < n; ++j) {
+        const int i1 = std::min(n - 1, j + 1);
+        for (int i = 0; i <= i1; ++i) {
+            const cd v = Hh[i + (size_t)j * n] - (i == j ? lam : cd(0.0));
+            M[(size_t)i * n + j] = v;
+            hn = std::max(hn, std::abs(v));
         }
-    auto m = [&](int i, int j) -> cd& { return M[i + (size_t)j * n]; };
+    }
+    auto row = [&](int i) { return M.data() + (size_t)i * n; };
     std::vector<cd> mult(n, 0.0);
     std::vector<char> swp(n, 0);
     const double tiny = 1e-14 * (hn > 0 ? hn : 1.0);
     for (int j = 0; j + 1 < n; ++j) {
-        if (std::abs(m(j + 1, j)) > std::abs(m(j, j))) {
+        cd* rj = row(j);
+        cd* rn = row(j + 1);
+        if (std::abs(rn[j]) > std::abs(rj[j])) {
             swp[j] = 1;
-            for (int c = j; c < n; ++c) std::swap(m(j, c), m(j + 1, c));
+            for (int c = j; c < n; ++c) std::swap(rj[c], rn[c]);
         }
-        if (std::abs(m(j, j)) < tiny) m(j, j) = tiny;
-        mult[j] = m(j + 1, j) / m(j, j);
-        m(j + 1, j) = 0.0;
-        for (int c = j + 1; c < n; ++c) m(j + 1, c) -= mult[j] * m(j, c);
+        if (std::abs(rj[j]) < tiny) rj[j] = tiny;
+        mult[j] = rn[j] / rj[j];
+        rn[j] = 0.0;
+        const cd f = mult[j];
+        for (int c = j + 1; c < n; ++c) rn[c] = cfms(rn[c], f, rj[c]);
     }
-    if (std::abs(m(n - 1, n - 1)) < tiny) m(n - 1, n - 1) = tiny;
+    if (std::abs(row(n - 1)[n - 1]) < tiny) row(n - 1)[n - 1] = tiny;
     y.assign(n, cd(1.0));
     for (int i = 0; i < n; ++i) y[i] = cd(1.0 + 0.1 * std::sin(1.0 + i), 0.0);   // fixed start
     for (int it = 0; it < 3; ++it) {
         if (!left) {
             for (int j = 0; j + 1 < n; ++j) {
                 if (swp[j]) std::swap(y[j], y[j + 1]);
-                y[j + 1] -= mult[j] * y[j];
+                y[j + 1] = cfms(y[j + 1], mult[j], y[j]);
             }
-            for (int j = n - 1; j >= 0; --j) {
+            for (int j = n - 1; j >= 0; --j) {   // U x = y, row j contiguous
+                const cd* rj = row(j);
                 cd s = y[j];
-                for (int c = j + 1; c < n; ++c) s -= m(j, c) * y[c];
-                y[j] = s / m(j, j);
+                for (int c = j + 1; c < n; ++c) s = cfms(s, rj[c], y[c]);
+                y[j] = s / rj[j];
             }
         } else {
-            for (int j = 0; j < n; ++j) {   // U^T w = y
-                cd s = y[j];
-                for (int i = 0; i < j; ++i) s -= m(i, j) * y[i];
-                y[j] = s / m(j, j);
+            for (int j = 0; j < n; ++j) {        // U^T w = y, eliminating with row j
+                const cd* rj = row(j);
+                const cd wj = y[j] / rj[j];
+                y[j] = wj;
+                for (int c = j + 1; c < n; ++c) y[c] = cfms(y[c], rj[c], wj);
             }
             for (int j = n - 2; j >= 0; --j) {
-                y[j] -= mult[j] * y[j + 1];
+                y[j] = cfms(y[j], mult[j], y[j + 1]);
                 if (swp[j]) std::swap(y[j], y[j + 1]);
             }
         }
@@ -465,18 +531,19 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
     if (lu_factor(me, Flu.data(), me, piv.data()) != 0) return false;
     std::vector<double> H = Gp;
     lu_solve(me, Flu.data(), me, piv.data(), H.data(), me, me, false);
-    std::vector<double> Hh, Qh;
+    std::vector<double> Hh, V;
     std::vector<cd> lam;
-    if (!eig_general(me, H.data(), Hh, Qh, lam)) return false;
+    if (!eig_general(me, H.data(), Hh, V, lam)) return false;
     std::vector<int> idx, pair;
     ritz_select(lam, k, idx, pair);
-    std::vector<cd> vh;
-    for (size_t t = 0; t < idx.size(); ++t) {
-        const cd th = lam[idx[t]];
-        hess_eigvec(me, Hh, th, want_left, vh);
-        std::vector<cd> v(me, 0.0);
-        for (int i = 0; i < me; ++i)
-            for (int j = 0; j < me; ++j) v[i] += Qh[i + (size_t)j * me] * vh[j];
+    // eigenvectors of the selected values: independent, computed on up to
+    // four threads, each into its own slot
+    const int nsel = (int)idx.size();
+    std::vector<std::vector<cd>> vecs(nsel);
+    auto one = [&](int t) {
+        std::vector<cd>& v = vecs[t];
+        hess_eigvec(me, Hh, lam[idx[t]], want_left, v);
+        hess_back(me, V, v);   // vector of H (H^T) from that of Hh (Hh^T)
         if (want_left) {   // pencil left vector = Fp^-T (left vector of H)
             std::vector<double> vr(me), vi(me);
             for (int i = 0; i < me; ++i) {
@@ -487,6 +554,20 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
             lu_solve(me, Flu.data(), me, piv.data(), vi.data(), me, 1, true);
             for (int i = 0; i < me; ++i) v[i] = cd(vr[i], vi[i]);
         }
+    };
+    const int nth = std::min(4, nsel);
+    {
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nth; ++w)
+            pool.emplace_back([&, w]() {
+                for (int t = w; t < nsel; t += nth) one(t);
+            });
+        for (int t = 0; t < nsel; t += std::max(nth, 1)) one(t);
+        for (auto& th : pool) th.join();
+    }
+    for (int t = 0; t < nsel; ++t) {
+        const cd th = lam[idx[t]];
+        const std::vector<cd>& v = vecs[t];
         if (!pair[t]) {   // real eigenvalue: remove the common phase
             cd ph = 0.0;
             for (int i = 0; i < me; ++i)

@@ -25,10 +25,14 @@ int pivoted_cholesky(int m, const double* G, double tol, std::vector<int>& perm,
 
 // Eigenvalues of a general real matrix H (n x n): Householder reduction to
 // Hessenberg form followed by the Francis double-shift QR iteration.
-// On return Hh holds the Hessenberg form and Qh the orthogonal Q with
-// H = Qh Hh Qh^T.  Returns false if the QR iteration did not converge.
-bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<double>& Qh,
+// On return Hh holds the Hessenberg form, H = Q Hh Q^T with
+// Q = P_0 P_1 ... P_{n-3}, P_k = I - u_k u_k^T and u_k column k of V (n x n,
+// zero in rows 0..k).  Returns false if the QR iteration did not converge.
+bool eig_general(int n, const double* H, std::vector<double>& Hh, std::vector<double>& V,
                  std::vector<std::complex<double>>& lambda);
+
+// y <- Q y with Q given by eig_general's reflectors V.
+void hess_back(int n, const std::vector<double>& V, std::vector<std::complex<double>>& y);
 
 // Eigenvector of the Hessenberg matrix Hh for eigenvalue lam by inverse
 // iteration (left = true: eigenvector of Hh^T).

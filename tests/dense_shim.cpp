@@ -20,9 +20,9 @@ int shim_lu_solve(int n, const double* A, double* b, int trans) {
 void shim_svd(int m, const double* M, double* P, double* sig, double* Q) { svd(m, M, P, sig, Q); }
 
 int shim_eig(int n, const double* H, double* wr, double* wi) {
-    std::vector<double> Hh, Qh;
+    std::vector<double> Hh, V;
     std::vector<std::complex<double>> lam;
-    if (!eig_general(n, H, Hh, Qh, lam)) return 1;
+    if (!eig_general(n, H, Hh, V, lam)) return 1;
     for (int i = 0; i < n; ++i) {
         wr[i] = lam[i].real();
         wi[i] = lam[i].imag();
