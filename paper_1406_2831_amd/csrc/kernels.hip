@@ -501,6 +501,87 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
             }
 }
 
+// Y[:, 0:ko] = X[:, 0:m] S on the matrix cores, computed as Y^T = S^T X^T so
+// that the X operand of each v_mfma_f64_16x16x4 (B: lane j + 16 kk holds
+// X[row j, k kk]) and the result (D: lane j + 16 (i % 4), register i / 4) both
+// cover 16 consecutive rows of one column.  A wave owns 64 rows x 64 columns
+// of Y (4 x 4 tiles), a block of four waves 256 rows; S is staged through LDS
+// in chunks of 16 values of k shared by the four waves, and the X operands of
+// the next chunk are loaded before the current chunk's products.  Work items
+// (row tile, column tile) are dealt to the XCDs in contiguous ranges so that
+// the column tiles of one row tile share that XCD's L2.
+constexpr int TS_ROWS = 256, TS_COLS = 64, TS_KC = 16, TS_STRIDE = TS_COLS + 16;
+
+__global__ __launch_bounds__(BLOCK) void k_gemm_ts_mfma(int64_t n, const double* __restrict__ X,
+                                                        int64_t ldx, int m, const double* __restrict__ S,
+                                                        int ko, double* __restrict__ Y, int64_t ldy,
+                                                        int row_tiles, int col_tiles) {
+    __shared__ double sS[TS_KC * TS_STRIDE];
+    const int total = row_tiles * col_tiles;
+    int item = blockIdx.x;
+    if ((gridDim.x & 7) == 0) item = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (item >= total) return;   // the grid is padded to a multiple of 8
+    const int rtile = item / col_tiles, ctile = item % col_tiles;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)rtile * TS_ROWS + w * 64;
+    const int c0 = ctile * TS_COLS;
+    const int sk = threadIdx.x & 15, sc = threadIdx.x >> 4;   // S loader: k row sk, columns sc + 16 q
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    double xn[4][4];   // X operands of the next chunk: [k step][row tile]
+    auto load_x = [&](int k0) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int kk = k0 + ks * 4 + lk;
+                const int64_t row = row0 + rb * 16 + lr;
+                xn[ks][rb] = (kk < m && row < n) ? X[row + (int64_t)kk * ldx] : 0.0;
+            }
+    };
+    load_x(0);
+    for (int k0 = 0; k0 < m; k0 += TS_KC) {
+        __syncthreads();   // the previous chunk's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < TS_COLS / 16; ++q) {
+            const int c = sc + 16 * q, kk = k0 + sk;
+            sS[sk * TS_STRIDE + c] = (kk < m && c0 + c < ko) ? S[kk + (int64_t)(c0 + c) * m] : 0.0;
+        }
+        double xb[4][4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) xb[ks][rb] = xn[ks][rb];
+        if (k0 + TS_KC < m) load_x(k0 + TS_KC);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            double a[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) a[cb] = sS[(ks * 4 + lk) * TS_STRIDE + cb * 16 + lr];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cb], xb[ks][rb], acc[cb][rb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = c0 + cb * 16 + 4 * r + lk;
+                const int64_t row = row0 + rb * 16 + lr;
+                if (col < ko && row < n) Y[row + (int64_t)col * ldy] = acc[cb][rb][r];
+            }
+}
+
 // ---------------------------------------------------------------- Algorithm 2 passes
 //
 // Every reducing pass writes one partial row per block; the matching *_fin
@@ -1722,7 +1803,16 @@ void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, do
 
 void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m, const double* S,
                     int ko, double* Y, int64_t ldy) {
-    if (ko <= 0) return;
+    if (ko <= 0 || n <= 0) return;
+    if (ko > GC && m >= TS_KC) {   // wide products on the matrix cores
+        const int64_t rt = (n + TS_ROWS - 1) / TS_ROWS;
+        const int ct = (ko + TS_COLS - 1) / TS_COLS;
+        int64_t g = rt * ct;
+        if (g >= 64) g = (g + 7) / 8 * 8;
+        hipLaunchKernelGGL(k_gemm_ts_mfma, dim3((unsigned)g), dim3(BLOCK), 0, st, n, X, ldx, m, S, ko, Y,
+                           ldy, (int)rt, ct);
+        return;
+    }
     hipLaunchKernelGGL(k_gemm_ts, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, X, ldx, m, S, ko, Y, ldy);
 }
 

@@ -285,10 +285,12 @@ def test_generated_space_full_size_3d(rb, torch_mod):
     the spaces are compared by what they do: installed on the GPU, the space
     the GPU built and the one the oracle builds from its own Lanczos vectors
     keep about the same number of directions and cut RBiCGSTAB iterations on
-    the next right-hand side about equally.  (The Ritz algebra itself is
-    pinned on identical inputs by tests/test_host_dense.py.)"""
+    the next right-hand sides about equally.  On this operator one solve's
+    iteration count moves by +-10% under rounding-level changes of the space,
+    so the counts are summed over three right-hand sides.  (The Ritz algebra
+    itself is pinned on identical inputs by tests/test_host_dense.py.)"""
     from paper_1406_2831_amd.sequence import max_row_nnz
-    seq = w.seq_3d(N=64, nshift=1, nrhs=2, k=20)
+    seq = w.seq_3d(N=64, nshift=1, nrhs=4, k=20)
     A, At = seq.matrix(0)
     As, Ats = A.to_scipy(), At.to_scipy()
     _say("generated space vs oracle (64^3)")
@@ -298,8 +300,15 @@ def test_generated_space_full_size_3d(rb, torch_mod):
     assert st.status == 0 and st.ritz_updates == 1
     ctx.recycle("from_last_solve")
     _, k_g = ctx.blocks()
-    _, st_g = _solve(ctx, torch_mod, seq.rhs[1], shadow=seq.shadows[1], rtol=1e-8)
-    _, st_0 = _solve(ctx, torch_mod, seq.rhs[1], shadow=seq.shadows[1], rtol=1e-8, mode="bicgstab")
+
+    def later(mode="rbicgstab"):
+        sts = [_solve(ctx, torch_mod, seq.rhs[j], shadow=seq.shadows[j], rtol=1e-8, mode=mode)[1]
+               for j in range(1, 4)]
+        assert all(t.status == 0 for t in sts)
+        return [t.iters for t in sts]
+
+    it_g = later()
+    it_0 = later("bicgstab")
     st_ = {}
 
     def cyc(V, Vt):
@@ -310,17 +319,15 @@ def test_generated_space_full_size_3d(rb, torch_mod):
     ctx.recycle("set", torch_mod.as_tensor(np.ascontiguousarray(Uo.T), device="cuda"),
                 torch_mod.as_tensor(np.ascontiguousarray(Uto.T), device="cuda"))
     _, k_o = ctx.blocks()
-    _, st_o = _solve(ctx, torch_mod, seq.rhs[1], shadow=seq.shadows[1], rtol=1e-8)
+    it_o = later()
     print(f"rbicg iters gpu {st.iters} oracle {io.iters}; k kept gpu-space {k_g} oracle-space {k_o}; "
-          f"next rhs iters: gpu-space {st_g.iters} oracle-space {st_o.iters} bicgstab {st_0.iters}",
-          flush=True)
+          f"next rhs iters: gpu-space {it_g} oracle-space {it_o} bicgstab {it_0}", flush=True)
     assert abs(st.iters - io.iters) <= 3
     assert abs(k_g - k_o) <= 2 and k_g >= 8
-    assert st_g.status == 0 and st_o.status == 0
-    assert st_g.iters <= 1.1 * st_o.iters + 5
-    # on this operator the space saves only a few percent of the iterations,
-    # within the rounding-level spread between runs: require no loss
-    assert st_g.iters <= st_0.iters + 5
+    assert sum(it_g) <= 1.1 * sum(it_o) + 5
+    # on this operator the space saves only a few percent of the iterations:
+    # require no loss beyond the rounding-level spread
+    assert sum(it_g) <= 1.05 * sum(it_0) + 5
     ctx.close()
 
 
