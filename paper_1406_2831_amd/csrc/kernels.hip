@@ -413,6 +413,33 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tile
     *dst = s;
 }
 
+// The same sum with one wavefront per output entry: the lanes take every
+// 64th chunk, then a butterfly adds the lanes.  Used when there are many
+// chunks and few entries (the k x k products of the recycle blocks).
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_wave(int mx, int my, int tiles_y, int stride,
+                                                             int nchunks, int symmetric,
+                                                             const double* __restrict__ partial,
+                                                             double* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (idx >= (int64_t)mx * my) return;   // uniform per wave
+    int i = (int)(idx % mx), j = (int)(idx / mx);
+    double* dst = out + i + (int64_t)j * mx;
+    if (symmetric && i / T > j / T) {
+        const int t = i;
+        i = j;
+        j = t;
+    }
+    const int slot = (i / T) * tiles_y + (j / T);
+    const int off = (i % T) * T + (j % T);
+    double s = 0.0;
+    for (int c = lane; c < nchunks; c += WAVE) s += partial[((int64_t)c * stride + slot) * (T * T) + off];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+    if (lane == 0) *dst = s;
+}
+
 // Tall-skinny X^T Y on the matrix cores: a 128 x 128 output tile per block,
 // each of the 4 waves owns a 64 x 64 quarter as 4 x 4 tiles of
 // v_mfma_f64_16x16x4 (operand lanes: A(i, kk) and B(kk, j) from lane
@@ -1089,9 +1116,9 @@ __global__ void k_gather_states(BatchBufs B, SolveState* out) {
 // same matrix entries and block values (C, Gh) at the same time (one HBM
 // fetch, the other waves hit the CU's cache) while each keeps the register
 // footprint of the single-system kernel.  Sums are laid out system-major
-// (system j's M values at j * M) and reduced by one-block finalizers as in
-// the single-system passes; the arithmetic per system, and its order, is the
-// single-system kernels'.
+// (system j's M values at j * M) and reduced by finalizers with one block per
+// system; the arithmetic per system, and its order, is the single-system
+// kernels'.
 constexpr int MULTI_W = BLOCK / WAVE;   // systems per launch (one wave each)
 
 __device__ __forceinline__ bool multi_active_any(const MultiBufs& B) {
@@ -1153,14 +1180,17 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B) {
     multi_block_partial<M>(acc, j, B.partials);
 }
 
+// The multi-RHS finalizers run one block per system (grid MULTI_W): block j
+// reduces system j's M rows of the partials, as the single-system finalizer
+// does, so the systems' reductions proceed side by side.
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mupdate_fin(MultiBufs B, int nb) {
     constexpr int M = K + 3;
-    __shared__ double tot[MULTI_W * M];
-    if (!multi_active_any(B)) return;
-    reduce_partials<MULTI_W * M>(B.partials, nb, MULTI_W * M, tot);
-    const int j = threadIdx.x;
-    if (j < B.nr && !B.state[j].done) update_fin_scalars(&B.state[j], tot + j * M, B.k);
+    __shared__ double tot[M];
+    const int j = blockIdx.x;
+    if (j >= B.nr || B.state[j].done) return;
+    reduce_partials<M>(B.partials + (int64_t)j * M * MAX_GRID, nb, M, tot);
+    if (threadIdx.x == 0) update_fin_scalars(&B.state[j], tot, B.k);
 }
 
 template <int K>
@@ -1199,13 +1229,11 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B) {
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mspmv1_fin(MultiBufs B, int nb) {
     constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[MULTI_W * M];
-    if (!multi_active_any(B)) return;
-    reduce_partials<MULTI_W * M>(B.partials, nb, MULTI_W * M, tot);
-    for (int idx = threadIdx.x; idx < MULTI_W * M; idx += BLOCK) {
-        const int j = idx / M, q = idx % M;
-        if (j < B.nr && !B.state[j].done && q < B.k) B.state[j].gamma[q] = tot[idx];
-    }
+    __shared__ double tot[M];
+    const int j = blockIdx.x;
+    if (j >= B.nr || B.state[j].done) return;
+    reduce_partials<M>(B.partials + (int64_t)j * M * MAX_GRID, nb, M, tot);
+    if (threadIdx.x < B.k) B.state[j].gamma[threadIdx.x] = tot[threadIdx.x];
 }
 
 template <int K>
@@ -1241,11 +1269,11 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B) {
 }
 
 __global__ __launch_bounds__(BLOCK) void k_mspmv2_fin(MultiBufs B, int nb) {
-    __shared__ double tot[MULTI_W * 5];
-    if (!multi_active_any(B)) return;
-    reduce_partials<MULTI_W * 5>(B.partials, nb, MULTI_W * 5, tot);
-    const int j = threadIdx.x;
-    if (j < B.nr && !B.state[j].done) spmv2_fin_scalars(&B.state[j], tot + j * 5, B.k);
+    __shared__ double tot[5];
+    const int j = blockIdx.x;
+    if (j >= B.nr || B.state[j].done) return;
+    reduce_partials<5>(B.partials + (int64_t)j * 5 * MAX_GRID, nb, 5, tot);
+    if (threadIdx.x == 0) spmv2_fin_scalars(&B.state[j], tot, B.k);
 }
 
 // ---------------------------------------------------------------- iterative refinement support
@@ -1872,8 +1900,14 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
         gemmt_shape(n, mx, my, GT, GS, MAX_GRID, false, tiles_y, ntiles, launched, nchunks, rpc);
         hipLaunchKernelGGL(k_gemmt_tile, dim3(ntiles, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1,
                            ldy1, my1, Y2, ldy2, my2, tiles_y, rpc, sym ? 1 : 0, partial);
-        hipLaunchKernelGGL(k_gemmt_reduce<GT>, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, tiles_y, ntiles,
-                           nchunks, sym ? 1 : 0, 0, partial, out);
+        if (nchunks >= WAVE && total <= 65536) {
+            const unsigned wgrid = (unsigned)((total + BLOCK / WAVE - 1) / (BLOCK / WAVE));
+            hipLaunchKernelGGL(k_gemmt_reduce_wave<GT>, dim3(wgrid), dim3(BLOCK), 0, st, mx, my, tiles_y,
+                               ntiles, nchunks, sym ? 1 : 0, partial, out);
+        } else {
+            hipLaunchKernelGGL(k_gemmt_reduce<GT>, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, tiles_y, ntiles,
+                               nchunks, sym ? 1 : 0, 0, partial, out);
+        }
     }
 }
 
@@ -1931,9 +1965,9 @@ int multi_width(int nr, int k) {
 }
 
 RBS_LAUNCHER(L_mupdate, k_mupdate, MultiBufs, false)
-RBS_LAUNCHER(L_mupdate_fin, k_mupdate_fin, MultiBufs, true)
+RBS_LAUNCHER(L_mupdate_fin, k_mupdate_fin, MultiBufs, false)
 RBS_LAUNCHER(L_mspmv1, k_mspmv1, MultiBufs, false)
-RBS_LAUNCHER(L_mspmv1_fin, k_mspmv1_fin, MultiBufs, true)
+RBS_LAUNCHER(L_mspmv1_fin, k_mspmv1_fin, MultiBufs, false)
 RBS_LAUNCHER(L_mspmv2, k_mspmv2, MultiBufs, false)
 
 void launch_multi_pass(hipStream_t st, const MultiBufs& B, int which) {
@@ -1947,11 +1981,11 @@ void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
         dispatch_k<L_mupdate>(B.k, st, g, B);
-        dispatch_k<L_mupdate_fin>(B.k, st, g, B, g);
+        dispatch_k<L_mupdate_fin>(B.k, st, MULTI_W, B, g);
         dispatch_k<L_mspmv1>(B.k, st, g, B);
-        if (B.k > 0) dispatch_k<L_mspmv1_fin>(B.k, st, g, B, g);
+        if (B.k > 0) dispatch_k<L_mspmv1_fin>(B.k, st, MULTI_W, B, g);
         dispatch_k<L_mspmv2>(B.k, st, g, B);
-        hipLaunchKernelGGL(k_mspmv2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
+        hipLaunchKernelGGL(k_mspmv2_fin, dim3(MULTI_W), dim3(BLOCK), 0, st, B, g);
     }
 }
 
