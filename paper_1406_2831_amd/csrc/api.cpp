@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -92,6 +93,11 @@ struct rbs_ctx {
     int64_t nnz = 0;
     PinnedStatus* hp = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // Ritz step: pinned host copies of the Gram matrices, factors and pencil
+    // inputs (allocated at the first Ritz step), and its events
+    double* hritz = nullptr;
+    size_t hritz_doubles = 0;
+    hipEvent_t rev[3] = {nullptr, nullptr, nullptr};
     std::string err;
 };
 
@@ -174,7 +180,7 @@ size_t carve(rbs_ctx* c, char* base) {
     c->AW = cv.take<double>(std::max<int64_t>(ld * wcols, 1));
     c->Wtmp = cv.take<double>(std::max<int64_t>(ld * wcols, 1));
     const int64_t mmax = c->k_max + std::max(c->s_max, 0);
-    c->dsmall_doubles = (size_t)(6 * mmax * mmax + 4 * mmax * c->k_max + 64);
+    c->dsmall_doubles = (size_t)(11 * mmax * mmax + 4 * mmax * c->k_max + 64);
     c->dsmall = cv.take<double>(c->dsmall_doubles);
     c->gpart_doubles = std::max(rbs::gemmt_partial_doubles(c->n, (int)mmax, (int)(2 * mmax)),
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
@@ -804,49 +810,80 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
 // lose bi-orthogonality and are far from orthogonal), and a second, unshifted
 // pass makes it orthonormal.  No direction is dropped except zero columns, so
 // the basis spans the whole stored Krylov space.  Pivoted, truncated Cholesky
-// is the fallback if a pass breaks down.  Returns the rank kept.
-int orth_inplace(rbs_ctx* c, double* X, double* AX, int m) {
+// is the fallback if a pass breaks down.
+//
+// The Ritz step orthonormalises W and Wt; the two jobs advance alternately so
+// that the host factorisation of one overlaps the device products of the
+// other (Gram matrices come back through pinned buffers and events).
+struct OrthJob {
+    double* X = nullptr;
+    double* AX = nullptr;
+    int m0 = 0, m = 0, pass = 0;
+    int mpass[2] = {0, 0}, rpass[2] = {0, 0};
+    double *dG = nullptr, *dS[2] = {nullptr, nullptr}, *dStot = nullptr;   // device scratch
+    double *hG = nullptr, *hS = nullptr;                                   // pinned host
+    hipEvent_t ev = nullptr;
+    bool done = false;
+    int rank = 0;
+};
+
+// Gram matrix X^T X of the job's current columns to the host (asynchronous).
+int orth_gram(rbs_ctx* c, OrthJob& j) {
+    hipStream_t s = c->stream;
+    rbs::launch_gemmt(s, c->n, j.X, c->ldw, j.m, j.X, c->ldw, j.m, nullptr, 0, 0, c->gpart, j.dG);
+    HIPCHK(c, hipMemcpyAsync(j.hG, j.dG, (size_t)j.m * j.m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(j.ev, s));
+    return RBS_OK;
+}
+
+// Waits for the job's Gram matrix, factors it on the host and enqueues the
+// transform (and the next Gram product, or the AX transform after the last pass).
+int orth_advance(rbs_ctx* c, OrthJob& j) {
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
-    const int m0 = m;
-    // device scratch: Gram | S0 | S1 | S0 S1 (each at most mmax^2 doubles)
-    const size_t mm = (size_t)(c->k_max + std::max(c->s_max, 0)) * (c->k_max + std::max(c->s_max, 0));
-    double* dG = c->dsmall;
-    double* dS[2] = {c->dsmall + mm, c->dsmall + 2 * mm};
-    double* dStot = c->dsmall + 3 * mm;
-    int mpass[2] = {0, 0}, rpass[2] = {0, 0};
-    int npass = 0;
-    for (int pass = 0; pass < 2 && m > 0; ++pass) {
-        rbs::launch_gemmt(s, c->n, X, ld, m, X, ld, m, nullptr, 0, 0, c->gpart, dG);
-        std::vector<double> G((size_t)m * m);
-        int rc = to_host(c, G.data(), dG, G.size() * sizeof(double));
-        if (rc) return rc;
-        std::vector<double> S;
-        const double eps = std::numeric_limits<double>::epsilon();
-        const double shift =
-            pass == 0 ? 11.0 * ((double)c->n * m + (double)m * (m + 1)) * eps * m : 0.0;
-        int r = rbs::dense::orth_factor_chol(m, G.data(), shift, S);
-        if (r < 0) r = rbs::dense::orth_factor(m, G.data(), pass == 0 ? 1e-12 : 1e-14, S);
-        if (r == 0) return 0;
-        if ((rc = to_device(c, dS[pass], S.data(), S.size() * sizeof(double)))) return rc;
-        rbs::launch_gemm_ts(s, c->n, X, ld, m, dS[pass], r, c->Wtmp, ld);
-        if ((rc = copy_cols(c, X, ld, c->Wtmp, ld, r))) return rc;
-        mpass[pass] = m;
-        rpass[pass] = r;
-        npass = pass + 1;
-        m = r;
+    HIPCHK(c, hipEventSynchronize(j.ev));
+    const int m = j.m;
+    std::vector<double> S;
+    const double eps = std::numeric_limits<double>::epsilon();
+    const double shift = j.pass == 0 ? 11.0 * ((double)c->n * m + (double)m * (m + 1)) * eps * m : 0.0;
+    int r = rbs::dense::orth_factor_chol(m, j.hG, shift, S);
+    if (r < 0) r = rbs::dense::orth_factor(m, j.hG, j.pass == 0 ? 1e-12 : 1e-14, S);
+    if (r <= 0) {
+        j.done = true;
+        j.rank = 0;
+        return RBS_OK;
     }
-    if (AX && m > 0) {   // AX needs only the product of the transforms: one pass over it
-        const double* T = dS[0];
-        if (npass == 2) {
-            rbs::launch_gemm_ts(s, m0, dS[0], m0, mpass[1], dS[1], rpass[1], dStot, m0);
-            T = dStot;
-        }
-        rbs::launch_gemm_ts(s, c->n, AX, ld, m0, T, m, c->Wtmp, ld);
-        int rc = copy_cols(c, AX, ld, c->Wtmp, ld, m);
-        if (rc) return rc;
+    std::memcpy(j.hS, S.data(), S.size() * sizeof(double));
+    HIPCHK(c, hipMemcpyAsync(j.dS[j.pass], j.hS, S.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    rbs::launch_gemm_ts(s, c->n, j.X, ld, m, j.dS[j.pass], r, c->Wtmp, ld);
+    int rc = copy_cols(c, j.X, ld, c->Wtmp, ld, r);
+    if (rc) return rc;
+    j.mpass[j.pass] = m;
+    j.rpass[j.pass] = r;
+    j.m = r;
+    ++j.pass;
+    if (j.pass < 2) return orth_gram(c, j);
+    if (j.AX) {   // AX needs only the product of the two transforms: one pass over it
+        rbs::launch_gemm_ts(s, j.m0, j.dS[0], j.m0, j.mpass[1], j.dS[1], j.rpass[1], j.dStot, j.m0);
+        rbs::launch_gemm_ts(s, c->n, j.AX, ld, j.m0, j.dStot, j.m, c->Wtmp, ld);
+        if ((rc = copy_cols(c, j.AX, ld, c->Wtmp, ld, j.m))) return rc;
     }
-    return m;
+    j.done = true;
+    j.rank = j.m;
+    return RBS_OK;
+}
+
+// Pinned host buffers and events of the Ritz step (first use only).
+int ritz_host_buffers(rbs_ctx* c) {
+    if (c->hritz) return RBS_OK;
+    const size_t mmax = (size_t)(c->k_max + std::max(c->s_max, 0));
+    const size_t want = 8 * mmax * mmax + 64;
+    void* h = nullptr;
+    HIPCHK(c, hipHostMalloc(&h, want * sizeof(double), hipHostMallocDefault));
+    c->hritz = static_cast<double*>(h);
+    c->hritz_doubles = want;
+    for (auto& ev : c->rev) HIPCHK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    return RBS_OK;
 }
 
 // Cycle-end recycle-space update from the gen_k current columns and ns new
@@ -861,58 +898,107 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
+    int rc = ritz_host_buffers(c);
+    if (rc) return rc;
     // A W by explicit products (the Lanczos recurrences give it only up to a
     // cancellation that grows with ||p|| / ||r||, which perturbs the Ritz
     // vectors of clustered values)
     rbs::launch_spmm(s, c->A, c->W, ld, c->AW, ld, m);
     c->ritz_mv += m;
-    const int r = orth_inplace(c, c->W, c->AW, m);
-    if (r < 0) return r;
-    if (r == 0) {
-        c->gen_k = 0;
-        return RBS_OK;
-    }
-    // right (harmonic) pencil inputs first; its host eigenproblem then runs on
-    // a worker thread while the device orthonormalises Wt and forms Qt^T [Q AQ]
-    double* dF2 = c->dsmall;                    // r x r : Q^T AQ
-    double* dG2 = dF2 + (size_t)r * r;          // r x r : (AQ)^T AQ
-    rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
-    rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dG2);
-    std::vector<double> h2((size_t)2 * r * r);
-    int rc = to_host(c, h2.data(), dF2, h2.size() * sizeof(double));
-    if (rc) return rc;
-    const double* F2 = h2.data();
-    const double* G2 = F2 + (size_t)r * r;
-    const auto t_host = std::chrono::steady_clock::now();
+    // device scratch: W job Gram | S0 | S1 | S0 S1, Wt job Gram | S0 | S1,
+    // then Q^T AQ | (AQ)^T AQ and Qt^T [Q AQ]; pinned host: the two jobs' Gram
+    // and factor, the right pencil's inputs, the left pencil's inputs
+    const size_t mm = (size_t)(c->k_max + std::max(c->s_max, 0)) * (c->k_max + std::max(c->s_max, 0));
+    double* d = c->dsmall;
+    double* h = c->hritz;
+    OrthJob jw, jt;
+    jw.X = c->W;
+    jw.AX = c->AW;
+    jt.X = c->Wt;
+    jw.m0 = jw.m = jt.m0 = jt.m = m;
+    jw.dG = d;
+    jw.dS[0] = d + mm;
+    jw.dS[1] = d + 2 * mm;
+    jw.dStot = d + 3 * mm;
+    jt.dG = d + 4 * mm;
+    jt.dS[0] = d + 5 * mm;
+    jt.dS[1] = d + 6 * mm;
+    jw.hG = h;
+    jw.hS = h + mm;
+    jt.hG = h + 2 * mm;
+    jt.hS = h + 3 * mm;
+    double* hF2 = h + 4 * mm;   // 2 r^2 <= 2 mm
+    double* hFG = h + 6 * mm;   // 2 rt r <= 2 mm
+    double* dF2 = d + 7 * mm;   // r x r : Q^T AQ, then r x r : (AQ)^T AQ
+    double* dFG = d + 9 * mm;   // rt x 2r : Qt^T [Q AQ]
+    jw.ev = c->rev[0];
+    jt.ev = c->rev[1];
+    hipEvent_t ev_right = c->rev[2];
+    if ((rc = orth_gram(c, jw)) || (rc = orth_gram(c, jt))) return rc;
     rbs::dense::PencilResult right, left;
-    std::thread worker([&]() { right = rbs::dense::ritz_right_harmonic(r, G2, F2, c->k_max); });
+    std::thread worker;
     struct Joiner {
         std::thread& t;
         ~Joiner() {
             if (t.joinable()) t.join();
         }
     } joiner{worker};
-    const int rt = orth_inplace(c, c->Wt, nullptr, m);
-    if (rt < 0) return rt;
-    if (rt == 0) {
+    bool right_started = false;
+    int r = 0;
+    std::atomic<int> worker_rc{RBS_OK};
+    double t_right_ms = 0.0;
+    while (!jw.done || !jt.done) {
+        if (!jw.done) {
+            if ((rc = orth_advance(c, jw))) return rc;
+            if (jw.done) {
+                r = jw.rank;
+                if (r == 0) break;
+                // right (harmonic) pencil inputs; its host eigenproblem runs on a
+                // worker thread as soon as they arrive
+                rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
+                rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart,
+                                  dF2 + (size_t)r * r);
+                HIPCHK(c, hipMemcpyAsync(hF2, dF2, (size_t)2 * r * r * sizeof(double),
+                                         hipMemcpyDeviceToHost, s));
+                HIPCHK(c, hipEventRecord(ev_right, s));
+                t_right_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                       t_start).count();
+                const int kmax = c->k_max;
+                worker = std::thread([&, r, kmax]() {
+                    if (hipEventSynchronize(ev_right) != hipSuccess) {
+                        worker_rc = RBS_ERR_HIP;
+                        return;
+                    }
+                    right = rbs::dense::ritz_right_harmonic(r, hF2 + (size_t)r * r, hF2, kmax);
+                });
+                right_started = true;
+            }
+        }
+        if (!jt.done && (rc = orth_advance(c, jt))) return rc;
+    }
+    (void)right_started;
+    if (r == 0 || jt.rank == 0) {
+        if (worker.joinable()) worker.join();
+        HIPCHK(c, hipStreamSynchronize(s));
         c->gen_k = 0;
         return RBS_OK;
     }
-    double* dFG = c->dsmall;                    // rt x 2r : Qt^T [Q AQ]
+    const int rt = jt.rank;
     rbs::launch_gemmt(s, c->n, c->Wt, ld, rt, c->W, ld, r, c->AW, ld, r, c->gpart, dFG);
-    std::vector<double> hFG((size_t)2 * rt * r);
-    if ((rc = to_host(c, hFG.data(), dFG, hFG.size() * sizeof(double)))) return rc;
+    HIPCHK(c, hipMemcpyAsync(hFG, dFG, (size_t)2 * rt * r * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     const auto t_left = std::chrono::steady_clock::now();
-    left = rbs::dense::ritz_left_two_sided(r, rt, hFG.data(), hFG.data() + (size_t)rt * r, c->k_max);
+    left = rbs::dense::ritz_left_two_sided(r, rt, hFG, hFG + (size_t)rt * r, c->k_max);
     worker.join();
+    if (worker_rc != RBS_OK) return fail(c, worker_rc, "Ritz step: waiting for the Gram products failed");
     rbs::dense::RitzResult res = rbs::dense::ritz_combine(r, rt, right, left);
     if (trace_enabled()) {
         const auto t_end = std::chrono::steady_clock::now();
         auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
         std::fprintf(stderr,
-                     "[rbs] ritz m=%d r=%d rt=%d k=%d: to right pencil %.2f ms, Wt side (overlapped) "
-                     "%.2f ms, left pencil + join %.2f ms, total %.2f ms\n",
-                     m, r, rt, res.kout, ms(t_start, t_host), ms(t_host, t_left), ms(t_left, t_end),
+                     "[rbs] ritz m=%d r=%d rt=%d k=%d: right pencil inputs queued at %.2f ms, both bases "
+                     "and left inputs %.2f ms, left pencil + join %.2f ms, total %.2f ms\n",
+                     m, r, rt, res.kout, t_right_ms, ms(t_start, t_left), ms(t_left, t_end),
                      ms(t_start, t_end));
     }
     if (!res.ok || res.kout == 0) {
@@ -1493,7 +1579,10 @@ int rbicgstab_destroy(rbs_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     for (auto& ev : c->ev)
         if (ev) hipEventDestroy(ev);
+    for (auto& ev : c->rev)
+        if (ev) hipEventDestroy(ev);
     if (c->hp) hipHostFree(c->hp);
+    if (c->hritz) hipHostFree(c->hritz);
     delete c;
     return RBS_OK;
 }

@@ -688,18 +688,29 @@ int orth_factor_chol(int m, const double* Gram, double shift, std::vector<double
             for (int i = c; i < r; ++i) lc[i] -= lj[i] * a;
         }
     }
-    // X = L^-1 (lower), column by column with column-oriented forward substitution
+    // X = L^-1 (lower), column by column with column-oriented forward
+    // substitution; the columns are independent and are shared round-robin
+    // among up to four threads (column b costs ~ (r - b)^2)
     std::vector<double> X((size_t)r * r, 0.0);
-    for (int b = 0; b < r; ++b) {
-        double* xb = X.data() + (size_t)b * r;
-        xb[b] = 1.0;
-        for (int c = b; c < r; ++c) {
-            const double* lc = L.data() + (size_t)c * r;
-            const double v = xb[c] / lc[c];
-            xb[c] = v;
-            if (v == 0.0) continue;
-            for (int i = c + 1; i < r; ++i) xb[i] -= lc[i] * v;
+    auto columns = [&](int b0, int step) {
+        for (int b = b0; b < r; b += step) {
+            double* xb = X.data() + (size_t)b * r;
+            xb[b] = 1.0;
+            for (int c = b; c < r; ++c) {
+                const double* lc = L.data() + (size_t)c * r;
+                const double v = xb[c] / lc[c];
+                xb[c] = v;
+                if (v == 0.0) continue;
+                for (int i = c + 1; i < r; ++i) xb[i] -= lc[i] * v;
+            }
         }
+    };
+    const int nth = r >= 128 ? 4 : 1;
+    {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t) pool.emplace_back(columns, t, nth);
+        columns(0, nth);
+        for (auto& th : pool) th.join();
     }
     // S = D R^-1 with R = L^T: R^-1 = X^T
     S.assign((size_t)m * r, 0.0);
