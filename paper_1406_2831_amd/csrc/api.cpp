@@ -77,7 +77,6 @@ struct rbs_ctx {
     double *W = nullptr, *Wt = nullptr, *AW = nullptr, *Wtmp = nullptr;
     int64_t ldw = 0;
     double* partials = nullptr;
-    double* partials2 = nullptr;
     SolveState* st = nullptr;
     BicgState* bst = nullptr;
     double* dsums = nullptr;
@@ -186,7 +185,6 @@ size_t carve(rbs_ctx* c, char* base) {
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
     c->gpart = cv.take<double>(c->gpart_doubles);
     c->partials = cv.take<double>((size_t)1024 * rbs::PARTIAL_ROWS);
-    c->partials2 = cv.take<double>((size_t)1024 * (2 * rbs::KMAX + 8));
     c->st = cv.take<SolveState>(1);
     c->bst = cv.take<BicgState>(1);
     c->dsums = cv.take<double>(8);
@@ -417,16 +415,29 @@ int iterate_until_done(rbs_ctx* c, Enqueue enqueue, Done done, void* hdst, const
     return RBS_OK;
 }
 
+// A Ccheck (the Gh block of the transposed system, and the dual-side block of
+// the two-pass RBiCG iteration), formed once per matrix; returns the products
+// with A it cost (0 when already formed).
+int ensure_ght(rbs_ctx* c, int k, int* products) {
+    *products = 0;
+    if (k <= 0 || c->ght_valid) return RBS_OK;
+    rbs::launch_spmm(c->stream, c->A, c->Ccheck, c->ld, c->GhT, c->ld, k);
+    HIPCHK(c, hipGetLastError());
+    c->ght_valid = true;
+    *products = k;
+    return RBS_OK;
+}
+
 int solve_rbicgstab(rbs_ctx* c, int k, const double* b, double* x, int xnz, const double* shadow,
                     double rtol, int max_it, rbs_stats* stats, bool transpose = false) {
     int status = RBS_MAXIT;
     int total_iters = 0, iters = 0, restarts = 0, mvA = 0, mvAt = 0;
-    if (transpose && k > 0 && !c->ght_valid) {
+    if (transpose) {
         // Gh of the transposed system: (A^T)^T Chat' = A Ccheck, once per matrix
-        rbs::launch_spmm(c->stream, c->A, c->Ccheck, c->ld, c->GhT, c->ld, k);
-        HIPCHK(c, hipGetLastError());
-        c->ght_valid = true;
-        mvAt += k;   // counted in the operator's own column, swapped back below
+        int prod = 0;
+        const int rc0 = ensure_ght(c, k, &prod);
+        if (rc0) return rc0;
+        mvAt += prod;   // counted in the operator's own column, swapped back below
     }
     rbs::SolveBufs B = solve_bufs(c, k, b, x, shadow, transpose);
     double rel_true = NAN, rel_recur = NAN;
@@ -779,6 +790,8 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     B.Ut = c->Ut;
     B.Ct = c->Ct;
     B.Ccheck = c->Ccheck;
+    B.Gh = c->Gh;
+    B.GhT = c->GhT;
     B.b = b;
     B.xout = xout;
     B.x = c->x;
@@ -796,7 +809,6 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     B.col0 = c->gen_k;
     B.state = c->bst;
     B.partials = c->partials;
-    B.partials2 = c->partials2;
     return B;
 }
 
@@ -1028,6 +1040,8 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
     int rc;
     c->gen_valid = false;
     c->ritz_mv = 0;
+    int ght_mv = 0;
+    if ((rc = ensure_ght(c, c->k, &ght_mv))) return rc;
     // the space being built starts from the installed one: W = [U], Wt = [Ut]
     c->gen_k = c->k;
     if ((rc = copy_cols(c, c->W, c->ldw, c->U, c->ld, c->k))) return rc;
@@ -1084,7 +1098,7 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
     const double rel_true = b2 > 0 ? std::sqrt(c->hp->sums[0] / b2) : std::sqrt(c->hp->sums[0]);
     int status = h.status;
     int iters = h.iters_done;
-    int mvA = iters + 1 + (xnz ? 1 : 0), mvAt = iters;
+    int mvA = iters + 1 + (xnz ? 1 : 0) + ght_mv, mvAt = iters;
     double rel_recur = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
     int total_iters = iters, restarts = 0;
     if (status == RBS_OK && rel_true <= rtol) {

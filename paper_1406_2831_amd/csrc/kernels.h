@@ -131,6 +131,7 @@ struct BicgBufs {
     int k;
     Sell A, At;
     const double *U, *C, *Chat, *Ut, *Ct, *Ccheck;
+    const double *Gh, *GhT;   // A^T Chat and A Ccheck (k columns each)
     const double* b;
     double* xout;
     double *x, *r, *rt, *p, *pt, *z, *zt, *q, *qt;
@@ -139,7 +140,6 @@ struct BicgBufs {
     int col0;              // first Lanczos column (= recycle dimension of the store)
     BicgState* state;
     double* partials;      // per-block partial sums
-    double* partials2;     // second buffer (the A^T product's sums)
 };
 void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap);
 void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count);

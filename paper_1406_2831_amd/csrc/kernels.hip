@@ -1491,45 +1491,68 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
     }
 }
 
+// The RBiCG iteration in two fused passes.  With Gh = A^T Chat and
+// GhT = A Ccheck (both formed once per matrix), zeta = Chat^T A p = Gh^T p and
+// zetat = Ccheck^T A^T pt = GhT^T pt are sums over the new p, pt, so they are
+// reduced in the pass that forms p and pt, and the projected products
+// q = A p - C zeta, qt = A^T pt - Ct zetat come out of the SpMV pass directly.
+//
 // BQ1: r -= alpha q; rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt;
-//      store r, rt into the cycle store; sums ||r||^2, (rt, r)
+//      store r, rt into the cycle store; sums ||r||^2, (rt, r), Gh^T p, GhT^T pt
+template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
-    constexpr int M = 2;
+    constexpr int M = 2 + 2 * K;
     BicgState* st = B.state;
     if (st->done) return;
     const double alpha = st->alpha, beta = st->beta;
+    const int k = B.k;
     const int slot = st->stored;
     const bool store = slot < st->store_cap;
     double* wcol = B.W + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
     double* wtcol = B.Wt + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
-    double acc[M] = {0.0, 0.0};
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         const double rv = B.r[row] - alpha * B.q[row];
         const double rtv = B.rt[row] - alpha * B.qt[row];
         const double pv = B.p[row], ptv = B.pt[row];
+        const double pn = rv + beta * pv, ptn = rtv + beta * ptv;
         B.x[row] += alpha * pv;
         B.r[row] = rv;
         B.rt[row] = rtv;
-        B.p[row] = rv + beta * pv;
-        B.pt[row] = rtv + beta * ptv;
+        B.p[row] = pn;
+        B.pt[row] = ptn;
         if (store) {
             wcol[row] = rv;
             wtcol[row] = rtv;
         }
         acc[0] += rv * rv;
         acc[1] += rtv * rv;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t o = row + col_off(j, k, B.ld);
+            acc[2 + j] += B.Gh[o] * pn;
+            acc[2 + K + j] += B.GhT[o] * ptn;
+        }
     }
     block_partial<M>(acc, M, B.partials);
 }
 
+template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bupdate_fin(BicgBufs B, int nb) {
-    constexpr int M = 2;
+    constexpr int M = 2 + 2 * K;
     __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
+    const int k = B.k;
     reduce_partials<M>(B.partials, nb, M, tot);
+    if (threadIdx.x < k) {
+        st->zeta[threadIdx.x] = tot[2 + threadIdx.x];
+        st->zetat[threadIdx.x] = tot[2 + K + threadIdx.x];
+    }
     if (threadIdx.x == 0) {
         const int i = st->iter;
         const int slot = st->stored;
@@ -1560,72 +1583,10 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate_fin(BicgBufs B, int nb) {
     }
 }
 
-// BQ2: z = A p (cycle store gets A r_{i-1} = z_i - beta_{i-1} z_{i-1}); zeta = Chat^T z
+// BQ2: q = A p - C zeta ; qt = A^T pt - Ct zetat ; sums (pt, q), (rt, q), (qt, r),
+//      (qt, q) for alpha = rho / (pt, q) and beta from (rt - a qt, r - a q) expanded
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bspmv(BicgBufs B) {
-    constexpr int M = K > 0 ? K : 1;
-    BicgState* st = B.state;
-    if (st->done) return;
-    const int k = B.k;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
-        const double zv = sell_row(B.A, row, B.p);
-        B.z[row] = zv;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] += B.Chat[row + col_off(j, k, B.ld)] * zv;
-    }
-    if (K > 0) block_partial<M>(acc, M, B.partials);
-}
-
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bspmv_fin(BicgBufs B, int nb) {
-    constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
-    BicgState* st = B.state;
-    if (st->done) return;
-    reduce_partials<M>(B.partials, nb, M, tot);
-    if (threadIdx.x < B.k) st->zeta[threadIdx.x] = tot[threadIdx.x];
-}
-
-// BQ2t: zt = A^T pt ; zetat = Ccheck^T zt  (partials go to the second half of the buffer)
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bspmvt(BicgBufs B) {
-    constexpr int M = K > 0 ? K : 1;
-    BicgState* st = B.state;
-    if (st->done) return;
-    const int k = B.k;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
-        const double zv = sell_row(B.At, row, B.pt);
-        B.zt[row] = zv;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] += B.Ccheck[row + col_off(j, k, B.ld)] * zv;
-    }
-    if (K > 0) block_partial<M>(acc, M, B.partials2);
-}
-
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bspmvt_fin(BicgBufs B, int nb) {
-    constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
-    BicgState* st = B.state;
-    if (st->done) return;
-    reduce_partials<M>(B.partials2, nb, M, tot);
-    if (threadIdx.x < B.k) st->zetat[threadIdx.x] = tot[threadIdx.x];
-}
-
-// BQ3: q = z - C zeta ; qt = zt - Ct zetat ; alpha = rho / (pt, q);
-//      beta from (rt - a qt, r - a q) expanded
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bproj(BicgBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_bspmvq(BicgBufs B) {
     constexpr int M = 4;
     BicgState* st = B.state;
     if (st->done) return;
@@ -1640,7 +1601,8 @@ __global__ __launch_bounds__(BLOCK) void k_bproj(BicgBufs B) {
     block_rows(B.n, r0, r1);
     double acc[M] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
-        double qv = B.z[row], qtv = B.zt[row];
+        double qv = sell_row(B.A, row, B.p);
+        double qtv = sell_row(B.At, row, B.pt);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t o = row + col_off(j, k, B.ld);
@@ -1768,11 +1730,9 @@ RBS_LAUNCHER_T(L_epi, k_epi, false)
 RBS_LAUNCHER(L_bpro1, k_bpro1, BicgBufs, false)
 RBS_LAUNCHER(L_bpro1_fin, k_bpro1_fin, BicgBufs, true)
 RBS_LAUNCHER(L_bpro2, k_bpro2, BicgBufs, false)
-RBS_LAUNCHER(L_bspmv, k_bspmv, BicgBufs, false)
-RBS_LAUNCHER(L_bspmv_fin, k_bspmv_fin, BicgBufs, true)
-RBS_LAUNCHER(L_bspmvt, k_bspmvt, BicgBufs, false)
-RBS_LAUNCHER(L_bspmvt_fin, k_bspmvt_fin, BicgBufs, true)
-RBS_LAUNCHER(L_bproj, k_bproj, BicgBufs, false)
+RBS_LAUNCHER(L_bupdate, k_bupdate, BicgBufs, false)
+RBS_LAUNCHER(L_bupdate_fin, k_bupdate_fin, BicgBufs, true)
+RBS_LAUNCHER(L_bspmvq, k_bspmvq, BicgBufs, false)
 RBS_LAUNCHER(L_bepi, k_bepi, BicgBufs, false)
 
 }  // namespace
@@ -2083,15 +2043,9 @@ void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int ma
 void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
-        hipLaunchKernelGGL(k_bupdate, dim3(g), dim3(BLOCK), 0, st, B);
-        hipLaunchKernelGGL(k_bupdate_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
-        dispatch_k<L_bspmv>(B.k, st, g, B);
-        dispatch_k<L_bspmvt>(B.k, st, g, B);
-        if (B.k > 0) {
-            dispatch_k<L_bspmv_fin>(B.k, st, g, B, g);
-            dispatch_k<L_bspmvt_fin>(B.k, st, g, B, g);
-        }
-        dispatch_k<L_bproj>(B.k, st, g, B);
+        dispatch_k<L_bupdate>(B.k, st, g, B);
+        dispatch_k<L_bupdate_fin>(B.k, st, g, B, g);
+        dispatch_k<L_bspmvq>(B.k, st, g, B);
         hipLaunchKernelGGL(k_bproj_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
     }
 }
