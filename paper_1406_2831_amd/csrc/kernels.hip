@@ -1151,7 +1151,10 @@ template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B) {
     constexpr int M = K + 3;
     if (!multi_active_any(B)) return;
-    const int j = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    // the system index is uniform over a wave: keep it (and the scalars read
+    // with it) in scalar registers, which leaves the vector registers to the
+    // loads in flight
+    const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
     const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
     const int64_t ld = B.ld, so = (int64_t)j * ld;
@@ -1197,7 +1200,10 @@ template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B) {
     constexpr int M = K > 0 ? K : 1;
     if (!multi_active_any(B)) return;
-    const int j = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    // the system index is uniform over a wave: keep it (and the scalars read
+    // with it) in scalar registers, which leaves the vector registers to the
+    // loads in flight
+    const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
     const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
     const int64_t ld = B.ld, so = (int64_t)j * ld;
@@ -1240,7 +1246,10 @@ template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B) {
     constexpr int KM = K > 0 ? K : 1;
     if (!multi_active_any(B)) return;
-    const int j = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    // the system index is uniform over a wave: keep it (and the scalars read
+    // with it) in scalar registers, which leaves the vector registers to the
+    // loads in flight
+    const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
     const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
     const int64_t ld = B.ld, so = (int64_t)j * ld;
