@@ -53,23 +53,63 @@ __device__ __forceinline__ void block_rows(int64_t n, int64_t& r0, int64_t& r1) 
 }
 
 
+constexpr int pow2_at_least(int m) {
+    int p = 1;
+    while (p < m) p <<= 1;
+    return p;
+}
+
+// Sums of M per-lane values over the 64 lanes of a wave, stored to dst[0..M)
+// (LDS), each by one lane.  Reduce-scatter: with P = M rounded up to a power
+// of two (values taken 64 at a time when M > 64), each of the first log2(P)
+// exchange steps halves the values a lane carries: the lane keeps one half,
+// sends the other to its partner and adds the partner's copy of the half it
+// kept.  That is about P exchanges instead of the 6 M of a butterfly on every
+// value; the steps left over (P < 64) are butterflies on the one value each
+// lane still holds.
+template <int P, int S>   // exchange step S (partner lane ^ (32 >> S)) on P values
+__device__ __forceinline__ void wave_sums_step(double (&v)[P], int lane, int& base) {
+    constexpr int OFF = (WAVE / 2) >> S, CNT = P >> (S + 1);
+    if constexpr (CNT >= 1) {
+        const bool upper = (lane & OFF) != 0;
+#pragma unroll
+        for (int i = 0; i < CNT; ++i) {
+            const double send = upper ? v[i] : v[i + CNT];
+            const double keep = upper ? v[i + CNT] : v[i];
+            v[i] = keep + __shfl_xor(send, OFF, WAVE);
+        }
+        if (upper) base += CNT;
+    } else {
+        v[0] += __shfl_xor(v[0], OFF, WAVE);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void wave_sums(const double (&w)[M], double* dst) {
+    constexpr int P = pow2_at_least(M) < WAVE ? pow2_at_least(M) : WAVE;
+    constexpr int DUP = WAVE / P;   // lanes left holding the same sum
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int c0 = 0; c0 < M; c0 += P) {
+        double v[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = c0 + i < M ? w[c0 + i] : 0.0;
+        int base = 0;   // index (within the chunk) of the value this lane ends with
+        wave_sums_step<P, 0>(v, lane, base);
+        wave_sums_step<P, 1>(v, lane, base);
+        wave_sums_step<P, 2>(v, lane, base);
+        wave_sums_step<P, 3>(v, lane, base);
+        wave_sums_step<P, 4>(v, lane, base);
+        wave_sums_step<P, 5>(v, lane, base);
+        if ((lane & (DUP - 1)) == 0 && c0 + base < M) dst[c0 + base] = v[0];
+    }
+}
+
 // Sum m (<= M) per-thread values over the block; totals land in tot[0..m).
-// The butterfly steps run over all m values at once, so each step issues m
-// independent cross-lane exchanges and waits once (not once per value).
-// w is consumed (overwritten with the wave sums).
 template <int M>
 __device__ __forceinline__ void block_sum(double (&w)[M], int m, double* red, double* tot) {
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) w[j] += __shfl_xor(w[j], off, WAVE);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-            if (j < m) red[wid * M + j] = w[j];
-    }
+    const int wid = threadIdx.x / WAVE;
+    wave_sums<M>(w, red + wid * M);
     __syncthreads();
     if (threadIdx.x < m) {
         double s = 0.0;
@@ -1132,16 +1172,7 @@ __device__ __forceinline__ bool multi_active_any(const MultiBufs& B) {
 template <int M>
 __device__ __forceinline__ void multi_block_partial(double (&v)[M], int j, double* partials) {
     __shared__ double tot[MULTI_W * M];
-    const int lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-#pragma unroll
-        for (int q = 0; q < M; ++q) v[q] += __shfl_xor(v[q], off, WAVE);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < M; ++q) tot[j * M + q] = v[q];
-    }
+    wave_sums<M>(v, tot + j * M);
     __syncthreads();
     for (int t = threadIdx.x; t < MULTI_W * M; t += BLOCK)
         partials[(int64_t)t * MAX_GRID + blockIdx.x] = tot[t];
@@ -2033,7 +2064,7 @@ void launch_shifted_values(hipStream_t st, int64_t n, int64_t nnz, const double*
                            const int64_t* diag_pos, const double* mdiag, double sigma,
                            const int64_t* perm_t, double* val, double* valT) {
     if (nnz <= 0) return;
-    hipMemcpyAsync(val, kval, nnz * sizeof(double), hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(val, kval, nnz * sizeof(double), hipMemcpyDeviceToDevice, st);   // errors surface at the caller's next checked call
     hipLaunchKernelGGL(k_shift_diag, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, n,
                        diag_pos, kval, mdiag, sigma, val);
     if (perm_t && valT)
