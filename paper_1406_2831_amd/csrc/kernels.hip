@@ -534,8 +534,10 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
             if (rok && gi < mx) vx = X[row + (int64_t)gi * ldx];
             if (rok && gj < my)
                 vy = gj < my1 ? Y1[row + (int64_t)gj * ldy1] : Y2[row + (int64_t)(gj - my1) * ldy2];
-            sx[lr * MSTRIDE + c] = vx;
-            sy[lr * MSTRIDE + c] = vy;
+            // column index XOR-swizzled by the row within its 16-column group:
+            // the 16 rows a lane group stores then fall in distinct banks
+            sx[lr * MSTRIDE + (c ^ lr)] = vx;
+            sy[lr * MSTRIDE + (c ^ lr)] = vy;
         }
         __syncthreads();
 #pragma unroll
@@ -544,8 +546,8 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
             double a[4], b[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                a[t] = sx[r * MSTRIDE + wi * 64 + t * 16 + (lane & 15)];
-                b[t] = sy[r * MSTRIDE + wj * 64 + t * 16 + (lane & 15)];
+                a[t] = sx[r * MSTRIDE + ((wi * 64 + t * 16 + (lane & 15)) ^ r)];
+                b[t] = sy[r * MSTRIDE + ((wj * 64 + t * 16 + (lane & 15)) ^ r)];
             }
 #pragma unroll
             for (int it = 0; it < 4; ++it)
