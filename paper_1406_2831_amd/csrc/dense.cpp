@@ -66,9 +66,13 @@ void lu_solve(int n, const double* LU, int lda, const int* piv, double* B, int l
     auto a = [&](int i, int j) { return LU[i + (size_t)j * lda]; };
     if (!trans) {
         // four right-hand sides per sweep over the factors: each column of L
-        // and U is read once per group
+        // and U is read once per group; with many right-hand sides the groups
+        // are shared round-robin among up to four threads
+        const int ngroups = (nrhs + 3) / 4;
+        const int nth = (ngroups >= 16 && (size_t)n * nrhs >= 16384) ? 4 : 1;
+        auto groups = [&](int g0, int gstep) {
         std::vector<double> pad;   // zero columns completing a short last group
-        for (int c0 = 0; c0 < nrhs; c0 += 4) {
+        for (int c0 = 4 * g0; c0 < nrhs; c0 += 4 * gstep) {
             const int nc = std::min(4, nrhs - c0);
             if (nc < 4) pad.assign((size_t)(4 - nc) * n, 0.0);
             double* b[4];
@@ -102,6 +106,11 @@ void lu_solve(int n, const double* LU, int lda, const int* piv, double* B, int l
                 }
             }
         }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t) pool.emplace_back(groups, t, nth);
+        groups(0, nth);
+        for (auto& th : pool) th.join();
         return;
     }
     for (int c = 0; c < nrhs; ++c) {
