@@ -828,8 +828,10 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
 // that the host factorisation of one overlaps the device products of the
 // other (Gram matrices come back through pinned buffers and events).
 struct OrthJob {
-    double* X = nullptr;
-    double* AX = nullptr;
+    // the context's buffer pointers: a transform writes the spare buffer
+    // (c->Wtmp), which then takes the basis' place (no copy back)
+    double** X = nullptr;
+    double** AX = nullptr;
     int m0 = 0, m = 0, pass = 0;
     int mpass[2] = {0, 0}, rpass[2] = {0, 0};
     double *dG = nullptr, *dS[2] = {nullptr, nullptr}, *dStot = nullptr;   // device scratch
@@ -842,7 +844,7 @@ struct OrthJob {
 // Gram matrix X^T X of the job's current columns to the host (asynchronous).
 int orth_gram(rbs_ctx* c, OrthJob& j) {
     hipStream_t s = c->stream;
-    rbs::launch_gemmt(s, c->n, j.X, c->ldw, j.m, j.X, c->ldw, j.m, nullptr, 0, 0, c->gpart, j.dG);
+    rbs::launch_gemmt(s, c->n, *j.X, c->ldw, j.m, *j.X, c->ldw, j.m, nullptr, 0, 0, c->gpart, j.dG);
     HIPCHK(c, hipMemcpyAsync(j.hG, j.dG, (size_t)j.m * j.m * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipEventRecord(j.ev, s));
     return RBS_OK;
@@ -867,9 +869,8 @@ int orth_advance(rbs_ctx* c, OrthJob& j) {
     }
     std::memcpy(j.hS, S.data(), S.size() * sizeof(double));
     HIPCHK(c, hipMemcpyAsync(j.dS[j.pass], j.hS, S.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    rbs::launch_gemm_ts(s, c->n, j.X, ld, m, j.dS[j.pass], r, c->Wtmp, ld);
-    int rc = copy_cols(c, j.X, ld, c->Wtmp, ld, r);
-    if (rc) return rc;
+    rbs::launch_gemm_ts(s, c->n, *j.X, ld, m, j.dS[j.pass], r, c->Wtmp, ld);
+    std::swap(*j.X, c->Wtmp);   // stream order: later writes to the old buffer follow this read
     j.mpass[j.pass] = m;
     j.rpass[j.pass] = r;
     j.m = r;
@@ -877,8 +878,8 @@ int orth_advance(rbs_ctx* c, OrthJob& j) {
     if (j.pass < 2) return orth_gram(c, j);
     if (j.AX) {   // AX needs only the product of the two transforms: one pass over it
         rbs::launch_gemm_ts(s, j.m0, j.dS[0], j.m0, j.mpass[1], j.dS[1], j.rpass[1], j.dStot, j.m0);
-        rbs::launch_gemm_ts(s, c->n, j.AX, ld, j.m0, j.dStot, j.m, c->Wtmp, ld);
-        if ((rc = copy_cols(c, j.AX, ld, c->Wtmp, ld, j.m))) return rc;
+        rbs::launch_gemm_ts(s, c->n, *j.AX, ld, j.m0, j.dStot, j.m, c->Wtmp, ld);
+        std::swap(*j.AX, c->Wtmp);
     }
     j.done = true;
     j.rank = j.m;
@@ -924,9 +925,9 @@ int ritz_cycle(rbs_ctx* c, int ns) {
     double* d = c->dsmall;
     double* h = c->hritz;
     OrthJob jw, jt;
-    jw.X = c->W;
-    jw.AX = c->AW;
-    jt.X = c->Wt;
+    jw.X = &c->W;
+    jw.AX = &c->AW;
+    jt.X = &c->Wt;
     jw.m0 = jw.m = jt.m0 = jt.m = m;
     jw.dG = d;
     jw.dS[0] = d + mm;
@@ -1082,6 +1083,8 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
         if (r == 1) break;
         if ((rc = ritz_cycle(c, c->s_max))) return rc;
         ++ritz_updates;
+        B.W = c->W;     // the Ritz step rotates the store's buffers
+        B.Wt = c->Wt;
         B.col0 = c->gen_k;
         rbs::launch_bicg_reset_cycle(c->stream, c->bst);
         since_flush = 0;

@@ -278,6 +278,30 @@ def test_generated_space_matches_oracle(rb, torch_mod):
     ctx.close()
 
 
+def test_rbicg_store_cycles(rb, torch_mod, c0):
+    """RBiCG whose Lanczos store fills several times (s_max = 24): the Ritz
+    step runs mid-solve and the iteration continues into the rotated store;
+    the solve converges to the direct solution and the space it leaves makes
+    a working RBiCGSTAB solve."""
+    seq, A, At = c0
+    Ad = A.to_scipy().toarray()
+    b = seq.rhs[0]
+    _say("rbicg with a 24-vector store (mid-solve Ritz steps)")
+    ctx = _ctx(rb, A, At, k_max=8, s_max=24)
+    x, st = _solve(ctx, torch_mod, b, mode="rbicg", rtol=1e-10)
+    print(f"rbicg iters {st.iters} ritz updates {st.ritz_updates}", flush=True)
+    assert st.status == 0 and st.rel_res_true <= 1e-10
+    assert st.ritz_updates >= 3
+    assert _rel(x, np.linalg.solve(Ad, b)) <= 1e-6
+    ctx.recycle("from_last_solve")
+    assert ctx.blocks()[1] > 0
+    b2, sh2 = seq.rhs[1], seq.shadows[1]
+    x2, st2 = _solve(ctx, torch_mod, b2, sh2)
+    assert st2.status == 0 and st2.rel_res_true <= 1e-10
+    assert _rel(x2, np.linalg.solve(Ad, b2)) <= 1e-6
+    ctx.close()
+
+
 def test_generated_space_full_size_3d(rb, torch_mod):
     """The generated space at the benchmark's size (64^3, k = 20, 512-vector
     store).  After ~300 BiCG steps the computed Lanczos bases of two
