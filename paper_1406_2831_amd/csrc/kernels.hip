@@ -492,9 +492,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 128, MR = 16, MSTRIDE = MT + 16;
 
 __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* __restrict__ X,
-                                                      int64_t ldx, int mx, const double* __restrict__ Y1,
-                                                      int64_t ldy1, int my1, const double* __restrict__ Y2,
-                                                      int64_t ldy2, int my2, int tiles_y,
+                                                      int64_t ldx, int mx, const double* __restrict__ Y,
+                                                      int64_t ldy, int my, int tiles_y,
                                                       int64_t rows_per_chunk, int symmetric,
                                                       double* __restrict__ partial) {
     __shared__ double sx[MR * MSTRIDE];
@@ -512,7 +511,6 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
         tx = blockIdx.x / tiles_y;
         ty = blockIdx.x % tiles_y;
     }
-    const int my = my1 + my2;
     const int64_t c0 = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t c1 = (c0 + rows_per_chunk < n) ? c0 + rows_per_chunk : n;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
@@ -526,18 +524,21 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
     for (int64_t base = c0; base < c1; base += MR) {
         const int64_t row = base + lr;
         const bool rok = row < c1;
+        double px[MT / 16], py[MT / 16];   // this slab's operands: all loads first
 #pragma unroll
         for (int q = 0; q < MT / 16; ++q) {
             const int c = lc + 16 * q;
             const int gi = tx * MT + c, gj = ty * MT + c;
-            double vx = 0.0, vy = 0.0;
-            if (rok && gi < mx) vx = X[row + (int64_t)gi * ldx];
-            if (rok && gj < my)
-                vy = gj < my1 ? Y1[row + (int64_t)gj * ldy1] : Y2[row + (int64_t)(gj - my1) * ldy2];
+            px[q] = (rok && gi < mx) ? X[row + (int64_t)gi * ldx] : 0.0;
+            py[q] = (rok && gj < my) ? Y[row + (int64_t)gj * ldy] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < MT / 16; ++q) {
+            const int c = lc + 16 * q;
             // column index XOR-swizzled by the row within its 16-column group:
             // the 16 rows a lane group stores then fall in distinct banks
-            sx[lr * MSTRIDE + (c ^ lr)] = vx;
-            sy[lr * MSTRIDE + (c ^ lr)] = vy;
+            sx[lr * MSTRIDE + (c ^ lr)] = px[q];
+            sy[lr * MSTRIDE + (c ^ lr)] = py[q];
         }
         __syncthreads();
 #pragma unroll
@@ -636,7 +637,8 @@ __global__ __launch_bounds__(BLOCK) void k_gemm_ts_mfma(int64_t n, const double*
             for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb)
-                    acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cb], xb[ks][rb], acc[cb][rb], 0, 0, 0);
+                    if (c0 + cb * 16 < ko && row0 + rb * 16 < n)   // skip 16-blocks past the edge
+                        acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cb], xb[ks][rb], acc[cb][rb], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -1887,6 +1889,14 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
                   double* out) {
     const int my = my1 + my2;
     if (mx <= 0 || my <= 0) return;
+    if (my2 > 0 && my1 > 0 && (mx >= MFMA_MIN_DIM || my >= MFMA_MIN_DIM)) {
+        // X^T [Y1 Y2] as two products into the two column ranges of out (the
+        // matrix-core kernel reads one Y block; the second launch reuses the
+        // partial buffer after the first reduction, in stream order)
+        launch_gemmt(st, n, X, ldx, mx, Y1, ldy1, my1, nullptr, 0, 0, partial, out);
+        launch_gemmt(st, n, X, ldx, mx, Y2, ldy2, my2, nullptr, 0, 0, partial, out + (int64_t)mx * my1);
+        return;
+    }
     int tiles_y, ntiles, launched, nchunks;
     int64_t rpc;
     const bool sym = X == Y1 && my2 == 0 && mx == my1 && ldx == ldy1;
@@ -1895,7 +1905,7 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
     if (mx >= MFMA_MIN_DIM || my >= MFMA_MIN_DIM) {
         gemmt_shape(n, mx, my, MT, MR, MFMA_GRID, sym, tiles_y, ntiles, launched, nchunks, rpc);
         hipLaunchKernelGGL(k_gemmt_mfma, dim3(launched, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1,
-                           ldy1, my1, Y2, ldy2, my2, tiles_y, rpc, sym ? 1 : 0, partial);
+                           ldy1, my1, tiles_y, rpc, sym ? 1 : 0, partial);
         hipLaunchKernelGGL(k_gemmt_reduce<MT>, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, tiles_y, launched,
                            nchunks, sym ? 1 : 0, sym ? 1 : 0, partial, out);
     } else {
