@@ -1564,7 +1564,18 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
         const double rtv = B.rt[row] - alpha * B.qt[row];
         const double pv = B.p[row], ptv = B.pt[row];
         const double pn = rv + beta * pv, ptn = rtv + beta * ptv;
-        B.x[row] += alpha * pv;
+        const double xv = B.x[row] + alpha * pv;
+        acc[0] += rv * rv;
+        acc[1] += rtv * rv;
+        // the block-column loads come before this row's stores, so that the
+        // compiler can issue them together (no store they might alias in between)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t o = row + col_off(j, k, B.ld);
+            acc[2 + j] += B.Gh[o] * pn;
+            acc[2 + K + j] += B.GhT[o] * ptn;
+        }
+        B.x[row] = xv;
         B.r[row] = rv;
         B.rt[row] = rtv;
         B.p[row] = pn;
@@ -1572,14 +1583,6 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
         if (store) {
             wcol[row] = rv;
             wtcol[row] = rtv;
-        }
-        acc[0] += rv * rv;
-        acc[1] += rtv * rv;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t o = row + col_off(j, k, B.ld);
-            acc[2 + j] += B.Gh[o] * pn;
-            acc[2 + K + j] += B.GhT[o] * ptn;
         }
     }
     block_partial<M>(acc, M, B.partials);
