@@ -546,7 +546,7 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
     std::vector<int> idx, pair;
     ritz_select(lam, k, idx, pair);
     // eigenvectors of the selected values: independent, computed on up to
-    // four threads, each into its own slot
+    // eight threads, each into its own slot
     const int nsel = (int)idx.size();
     std::vector<std::vector<cd>> vecs(nsel);
     auto one = [&](int t) {
@@ -564,7 +564,7 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
             for (int i = 0; i < me; ++i) v[i] = cd(vr[i], vi[i]);
         }
     };
-    const int nth = std::min(4, nsel);
+    const int nth = std::min(8, nsel);
     {
         std::vector<std::thread> pool;
         for (int w = 1; w < nth; ++w)
