@@ -9,16 +9,16 @@ code with it: the only thing both sides consume is the seeded input module
 Contents (each function cites the passage of the paper it follows):
 
 * ``krylov.bicgstab``   -- van der Vorst's BiCGSTAB (the non-recycling baseline).
-* ``krylov.rbicgstab``  -- Algorithm 2 (RBiCGSTAB), Section 4.
-* ``krylov.rbicg``      -- Algorithm 1 (RBiCG), Section 3, with the cycle store
+* ``krylov.rbicgstab``  -- RBiCGSTAB, Section 4 (BiCGSTAB on the projected operator).
+* ``krylov.rbicg``      -- RBiCG, Section 3 (BiCG on the projected pair), with the cycle store
                            of Lanczos vectors described in Section 6.2.
-* ``recycle.make_blocks``     -- Algorithm 2 step 1 / eq. (CcheckChat).
+* ``recycle.make_blocks``     -- the recycle blocks of Section 3, eq. (CcheckChat).
 * ``recycle.recycle_space``   -- recycle-space selection (our reading; the
                                  paper defers it to its reference on RBiCG):
                                  harmonic right / two-sided left Ritz vectors.
 * ``sequence.run_sequence``   -- the Section 6.2 driver (RBiCG on a matrix
                                  change, RBiCGSTAB for the other right-hand sides).
-* ``adjoint.adjoint_solve``   -- A^T lambda = c by Algorithm 2 with the swapped
+* ``adjoint.adjoint_solve``   -- A^T lambda = c by RBiCGSTAB with the swapped
                                  recycle space; ``adjoint.gradients`` -- dL/db,
                                  dL/dsigma, dL/dK for A(sigma) = K + sigma M.
 

@@ -9,7 +9,7 @@ lambda of A^T lambda = c,
     dL/dA = -lambda x^T        (restricted to A's stored entries, which are K's),
     dL/dsigma = <dL/dA, M> = -sum_i lambda_i m_i x_i.
 
-The adjoint system is solved by Algorithm 2 on A^T with the recycle space
+The adjoint system is solved by RBiCGSTAB (Section 4) on A^T with the recycle space
 of A with the roles of U and Ut exchanged: for A^T the right space is Ut and
 the left space U, so its blocks are built by ``make_blocks(A^T, A, Ut, U)``
 (the same construction as for A, applied to the transposed operator).
@@ -23,13 +23,13 @@ from .recycle import Blocks, make_blocks
 
 
 def transposed_blocks(A, At, U: np.ndarray, Ut: np.ndarray, **kw) -> Blocks:
-    """Algorithm 2 step 1 for the operator A^T with right space Ut, left space U."""
+    """The recycle blocks (eq. CcheckChat) of the operator A^T with right space Ut, left space U."""
     return make_blocks(At, A, Ut, U, **kw)
 
 
 def adjoint_solve(A, At, U: np.ndarray, Ut: np.ndarray, c: np.ndarray, rtol: float = 1e-10,
                   shadow=None, max_it: int = 20000):
-    """lambda with A^T lambda = c by Algorithm 2 on A^T (swapped recycle space)."""
+    """lambda with A^T lambda = c by RBiCGSTAB on A^T (swapped recycle space)."""
     blocks = transposed_blocks(A, At, U, Ut)
     return rbicgstab(At, blocks, c, shadow_m1=shadow, rtol=rtol, max_it=max_it)
 

@@ -1,4 +1,4 @@
-"""BiCGSTAB, RBiCGSTAB (Algorithm 2) and RBiCG (Algorithm 1) in plain FP64 -- TEST INFRASTRUCTURE ONLY.
+"""BiCGSTAB, RBiCGSTAB (Section 4) and RBiCG (Section 3) in plain FP64 -- TEST INFRASTRUCTURE ONLY.
 
 Real arithmetic throughout, so the paper's ``*`` is a transpose and complex
 conjugates of scalars are the scalars themselves (Section 1 notation).
@@ -14,7 +14,8 @@ Readings of points the paper leaves open (listed again in the design notes):
   ``omega``, and any non-finite scalar, is reported; if
   ``(t, t) = 0`` while ``||s|| <= tol`` the half step ``x + alpha p`` is
   accepted;
-* RBiCG stops on the primary residual only (the dual system is auxiliary).
+* RBiCG stops when the primary and the dual residual both meet the
+  relative tolerance (each against its own right-hand side).
 """
 from __future__ import annotations
 
@@ -34,7 +35,7 @@ NONFINITE = -5
 
 
 def _zero(val: float, a: np.ndarray, b: np.ndarray) -> bool:
-    """Breakdown test of Algorithm 2 step 3 and of the recurrences: an exact zero."""
+    """Breakdown test of the start (r_0, rt_0) = 0 and of the recurrences: an exact zero."""
     return val == 0.0
 
 
@@ -48,6 +49,7 @@ class SolveInfo:
     restarts: int = 0
     rel_res_recur: float = np.nan
     rel_res_true: float = np.nan
+    rel_res_dual: float = np.nan   # RBiCG: true relative residual of the dual system
     res_hist: List[float] = field(default_factory=list)
     trace: dict = field(default_factory=dict)   # optional per-iteration vectors (tests)
 
@@ -59,7 +61,7 @@ def _bad(*vals) -> bool:
 def bicgstab(A, b: np.ndarray, x0: Optional[np.ndarray] = None,
              shadow: Optional[np.ndarray] = None, rtol: float = 1e-8,
              max_it: int = 10000, max_restarts: int = 3, record: bool = False):
-    """van der Vorst's BiCGSTAB (the baseline named in Section 1; k = 0 case of Algorithm 2).
+    """van der Vorst's BiCGSTAB (the baseline named in Section 1; the k = 0 case of Section 4).
 
     ``shadow`` is the fixed vector ``r^`` of the inner products (defaults to
     the initial residual).  Returns ``(x, SolveInfo)``.
@@ -149,19 +151,63 @@ def bicgstab(A, b: np.ndarray, x0: Optional[np.ndarray] = None,
     return x, info
 
 
+class _Projected:
+    """The projected operators of Sections 3 and 4 built from recycle blocks.
+
+    ``B v = (I - C Chat^T) A v`` (primary side) and
+    ``Bt v = (I - Ct Ccheck^T) A^T v`` (dual side).  Each application also
+    returns the coefficient vector that the projection removed
+    (``Chat^T A v`` or ``Ccheck^T A^T v``): because ``C = A U`` (and
+    ``Ct = A^T Ut``), the removed part is ``A U`` times that vector, so a
+    running sum of the coefficients is the ``U`` component that the final
+    correction ``x - U x_c`` takes back out.
+    """
+
+    def __init__(self, A, At, blocks: Blocks):
+        self.A, self.At, self.bl = A, At, blocks
+        self.k = blocks.k
+
+    def primary(self, v):
+        Av = self.A @ v
+        coef = self.bl.Chat.T @ Av
+        return Av - self.bl.C @ coef, coef
+
+    def dual(self, v):
+        Atv = self.At @ v
+        coef = self.bl.Ccheck.T @ Atv
+        return Atv - self.bl.Ct @ coef, coef
+
+
+def _initial_projection(blocks: Blocks, r_m1: np.ndarray, x: np.ndarray):
+    """eq. (minusXR), primary side: x_0 = x_{-1} + U Chat^T r_{-1}, r_0 = r_{-1} - C Chat^T r_{-1}."""
+    coef = blocks.Chat.T @ r_m1
+    return x + blocks.U @ coef, r_m1 - blocks.C @ coef
+
+
+def _initial_projection_dual(blocks: Blocks, rt_m1: np.ndarray, xt: np.ndarray):
+    """eq. (minusXR), dual side: xt_0 = xt_{-1} + Ut Ccheck^T rt_{-1}, rt_0 = rt_{-1} - Ct Ccheck^T rt_{-1}."""
+    coef = blocks.Ccheck.T @ rt_m1
+    return xt + blocks.Ut @ coef, rt_m1 - blocks.Ct @ coef
+
+
 def rbicgstab(A, blocks: Blocks, b: np.ndarray, x_m1: Optional[np.ndarray] = None,
               shadow_m1: Optional[np.ndarray] = None, rtol: float = 1e-8,
               max_it: int = 10000, max_restarts: int = 3, record: bool = False):
-    """Algorithm 2 (RBiCGSTAB), Section 4, in the paper's order and notation.
+    """RBiCGSTAB (Section 4): BiCGSTAB applied to the projected operator.
 
-    ``blocks`` carries ``U``, ``C = A U``, ``Chat = Ct D_c^{-1}`` (step 1) and
-    ``Ct``, ``Ccheck`` for the shadow projection of eq. (minusXR).
-    ``shadow_m1`` is the random ``rt_{-1}`` of step 2 (defaults to ``r_{-1}``).
-    Returns ``(x, SolveInfo)``; ``x`` already includes step 8's ``- U x_c``.
+    Section 4 derives the method as van der Vorst's BiCGSTAB run on
+    ``B = (I - C Chat^T) A`` from the projected start of eq. (minusXR), with
+    the shadow vector projected by ``I - Ct Ccheck^T``.  Every product with
+    ``B`` leaves behind the coefficients ``Chat^T A v``; weighted by the step
+    lengths they accumulate into the k-vector ``x_c``, and the solution is
+    ``x - U x_c`` (``C = A U``).  ``blocks`` carries ``U``, ``C``,
+    ``Chat = Ct D_c^{-1}`` and, for the shadow, ``Ct`` and ``Ccheck``.
+    ``shadow_m1`` is the random shadow before projection (defaults to the
+    initial residual).  Returns ``(x, SolveInfo)``, ``x`` corrected.
     """
     n = b.shape[0]
-    U, C, Chat, Ct, Ccheck = blocks.U, blocks.C, blocks.Chat, blocks.Ct, blocks.Ccheck
-    k = U.shape[1]
+    Bop = _Projected(A, None, blocks)
+    k = blocks.k
     info = SolveInfo()
     bnorm = np.linalg.norm(b)
     if _bad(bnorm):
@@ -172,20 +218,16 @@ def rbicgstab(A, blocks: Blocks, b: np.ndarray, x_m1: Optional[np.ndarray] = Non
     started_nonzero = x_m1 is not None and np.any(x != 0)
     trace = {"r": [], "x": [], "xc": [], "s": [], "q": [], "t": []} if record else {}
     for attempt in range(max_restarts + 1):
-        # step 2: x_{-1}, r_{-1} = b - A x_{-1}, then eq. (minusXR)
         if started_nonzero or attempt > 0:
             r_m1 = b - A @ x
             info.matvecs_A += 1
         else:
             r_m1 = b.copy()
-        rt_m1 = r_m1.copy() if shadow_m1 is None else np.array(shadow_m1, dtype=np.float64)
-        zeta0 = Chat.T @ r_m1
-        x = x + U @ zeta0                       # x_0 = x_{-1} + U Chat^* r_{-1}
-        r = r_m1 - C @ zeta0                    # r_0 = (I - C Chat^*) r_{-1}
-        rt0 = rt_m1 - Ct @ (Ccheck.T @ rt_m1)   # rt_0 = (I - Ct Ccheck^*) rt_{-1}
+        shadow = r_m1.copy() if shadow_m1 is None else np.array(shadow_m1, dtype=np.float64)
+        x, r = _initial_projection(blocks, r_m1, x)
+        _, rt0 = _initial_projection_dual(blocks, shadow, np.zeros(n))
         if record:
             trace["r0"], trace["x0"], trace["rt0"] = r.copy(), x.copy(), rt0.copy()
-        # step 3
         rho = rt0 @ r
         status = MAXIT
         info.iters = 0
@@ -195,25 +237,19 @@ def rbicgstab(A, blocks: Blocks, b: np.ndarray, x_m1: Optional[np.ndarray] = Non
         elif _bad(rho) or _zero(rho, rt0, r):
             status = NONFINITE if _bad(rho) else BREAKDOWN_RHO
         else:
-            # step 4
             beta = omega = 0.0
             p = np.zeros(n)
-            q = np.zeros(n)
-            # step 6
+            q = np.zeros(n)          # the previous B p
             for i in range(1, max_it + 1):
-                p = r + beta * p - beta * omega * q
-                q = A @ p
-                zeta = Chat.T @ q
-                q = q - C @ zeta
+                p = r + beta * (p - omega * q)
+                q, zeta = Bop.primary(p)
                 den = rt0 @ q
                 if _bad(den) or _zero(den, rt0, q):
                     status = NONFINITE if _bad(den) else BREAKDOWN_ALPHA
                     break
                 alpha = rho / den
                 s = r - alpha * q
-                t = A @ s
-                gamma = Chat.T @ t
-                t = t - C @ gamma
+                t, gamma = Bop.primary(s)
                 info.matvecs_A += 2
                 info.iters = i
                 tt = t @ t
@@ -229,35 +265,30 @@ def rbicgstab(A, blocks: Blocks, b: np.ndarray, x_m1: Optional[np.ndarray] = Non
                 omega = (s @ t) / tt
                 x = x + alpha * p + omega * s
                 xc = xc + alpha * zeta + omega * gamma
-                r_new = r - alpha * q - omega * t
+                r_new = s - omega * t
                 rn = np.linalg.norm(r_new)
                 info.res_hist.append(rn / bnorm)
                 if record:
                     for key, val in (("r", r_new), ("x", x), ("xc", xc), ("s", s),
                                      ("q", q), ("t", t)):
                         trace[key].append(val.copy())
+                r = r_new
                 if _bad(rn):
                     status = NONFINITE
-                    r = r_new
                     break
                 if rn <= tol:
-                    r = r_new
                     status = OK
                     break
                 if omega == 0.0:
-                    r = r_new
                     status = BREAKDOWN_OMEGA
                     break
-                rho_new = rt0 @ r_new
-                if _zero(rho_new, rt0, r_new):
-                    r = r_new
+                rho_new = rt0 @ r
+                if _zero(rho_new, rt0, r):
                     status = BREAKDOWN_RHO
                     break
                 beta = (rho_new / rho) * (alpha / omega)
                 rho = rho_new
-                r = r_new
-        # step 8
-        x = x - U @ xc
+        x = x - blocks.U @ xc
         info.total_iters += info.iters
         info.rel_res_recur = np.linalg.norm(r) / bnorm
         rt = np.linalg.norm(b - A @ x) / bnorm
@@ -277,27 +308,38 @@ def rbicg(A, At, blocks: Blocks, b: np.ndarray, bt: Optional[np.ndarray] = None,
           x_m1: Optional[np.ndarray] = None, xt_m1: Optional[np.ndarray] = None,
           rtol: float = 1e-8, max_it: int = 10000, s: int = 0,
           on_cycle: Optional[Callable[[np.ndarray, np.ndarray], None]] = None,
-          record: bool = False):
-    """Algorithm 1 (RBiCG), Section 3, with the Section 6.2 cycle store.
+          stop: str = "both", record: bool = False):
+    """RBiCG (Section 3): BiCG on the primary and dual systems with the
+    projected operators ``B = (I - C Chat^T) A`` and ``Bt = (I - Ct Ccheck^T) A^T``
+    (augmented bi-Lanczos, Theorem 1), started by eq. (minusXR) on both sides.
 
-    The dual right-hand side ``bt`` defaults to the vector of all ones (the
-    choice made in Section 6.2).  The Lanczos vectors are the normalised
-    residuals ``r_{i-1}/||r_{i-1}||`` and ``rt_{i-1}/||rt_{i-1}||``; every ``s``
-    iterations (and once more at the end for a partial cycle) they are handed
-    to ``on_cycle(V, Vt)`` and discarded.  Returns ``(x, xt, SolveInfo)``.
+    Both solutions are corrected at the end by the accumulated ``U`` and
+    ``Ut`` components.  The solve stops when both residuals meet their
+    tolerance (``||r|| <= rtol ||b||`` and ``||rt|| <= rtol ||bt||``), the
+    rule of the RBiCG algorithm in Section 3; ``stop="primary"`` stops on the
+    primary residual alone (an option, not the paper's rule).  The dual
+    right-hand side ``bt`` defaults to the vector of all ones (the choice of
+    Section 6.2).  The Lanczos vectors are the normalised residuals
+    ``r_{i-1}/||r_{i-1}||`` and ``rt_{i-1}/||rt_{i-1}||``; every ``s``
+    iterations (and once more at the end for a partial cycle) they are
+    handed to ``on_cycle(V, Vt)`` and discarded.  ``info.rel_res_dual`` is the
+    dual system's true relative residual.  Returns ``(x, xt, SolveInfo)``.
     """
+    if stop not in ("both", "primary"):
+        raise ValueError("stop must be 'both' or 'primary'")
     n = b.shape[0]
-    U, C, Chat = blocks.U, blocks.C, blocks.Chat
-    Ut, Ct, Ccheck = blocks.Ut, blocks.Ct, blocks.Ccheck
-    k = U.shape[1]
+    ops = _Projected(A, At, blocks)
+    k = blocks.k
     info = SolveInfo()
     if bt is None:
         bt = np.ones(n)
     bnorm = np.linalg.norm(b)
-    if _bad(bnorm):
+    btnorm = np.linalg.norm(bt)
+    if _bad(bnorm) or _bad(btnorm):
         info.status = NONFINITE
         return np.zeros(n), np.zeros(n), info
     tol = rtol * bnorm
+    tol_dual = rtol * btnorm if stop == "both" else np.inf
     x = np.zeros(n) if x_m1 is None else np.array(x_m1, dtype=np.float64)
     xt = np.zeros(n) if xt_m1 is None else np.array(xt_m1, dtype=np.float64)
     if np.any(x != 0):
@@ -310,19 +352,13 @@ def rbicg(A, At, blocks: Blocks, b: np.ndarray, bt: Optional[np.ndarray] = None,
         info.matvecs_At += 1
     else:
         rt_m1 = np.array(bt, dtype=np.float64)
-    # step 2: eq. (minusXR)
-    zeta0 = Chat.T @ r_m1
-    x = x + U @ zeta0
-    r = r_m1 - C @ zeta0
-    zt0 = Ccheck.T @ rt_m1
-    xt = xt + Ut @ zt0
-    rt = rt_m1 - Ct @ zt0
+    x, r = _initial_projection(blocks, r_m1, x)
+    xt, rt = _initial_projection_dual(blocks, rt_m1, xt)
     trace = {"r": [r.copy()], "rt": [rt.copy()]} if record else {}
-    # step 4
     p = np.zeros(n)
     pt = np.zeros(n)
-    zc = np.zeros(k)
-    ztc = np.zeros(k)
+    zc = np.zeros(k)      # accumulated U coefficients of x
+    ztc = np.zeros(k)     # accumulated Ut coefficients of xt
     beta = 0.0
     rho = rt @ r
     status = MAXIT
@@ -334,9 +370,12 @@ def rbicg(A, At, blocks: Blocks, b: np.ndarray, bt: Optional[np.ndarray] = None,
         V.clear()
         Vt.clear()
 
-    if np.linalg.norm(r) <= tol:
+    def converged(rn, rtn):
+        return rn <= tol and rtn <= tol_dual
+
+    if converged(np.linalg.norm(r), np.linalg.norm(rt)):
         status = OK
-    elif _bad(rho) or _zero(rho, rt, r):   # step 3 reports; the caller re-chooses the dual start
+    elif _bad(rho) or _zero(rho, rt, r):   # the caller re-chooses the dual start
         status = NONFINITE if _bad(rho) else BREAKDOWN_RHO
     else:
         for i in range(1, max_it + 1):
@@ -345,35 +384,31 @@ def rbicg(A, At, blocks: Blocks, b: np.ndarray, bt: Optional[np.ndarray] = None,
                 Vt.append(rt / np.linalg.norm(rt))
             p = r + beta * p
             pt = rt + beta * pt
-            z = A @ p
-            zt = At @ pt
+            q, zeta = ops.primary(p)
+            qt, zetat = ops.dual(pt)
             info.matvecs_A += 1
             info.matvecs_At += 1
-            zeta = Chat.T @ z
-            zetat = Ccheck.T @ zt
-            q = z - C @ zeta
-            qt = zt - Ct @ zetat
             den = pt @ q
             info.iters = i
             if _bad(den) or _zero(den, pt, q):
                 status = NONFINITE if _bad(den) else BREAKDOWN_ALPHA
                 break
-            alpha = rho / den
+            alpha = rho / den        # real arithmetic: the dual step is the same alpha
             zc = zc + alpha * zeta
             ztc = ztc + alpha * zetat
             x = x + alpha * p
             xt = xt + alpha * pt
             r = r - alpha * q
             rt = rt - alpha * qt
-            rn = np.linalg.norm(r)
+            rn, rtn = np.linalg.norm(r), np.linalg.norm(rt)
             info.res_hist.append(rn / bnorm)
             if record:
                 trace["r"].append(r.copy())
                 trace["rt"].append(rt.copy())
-            if _bad(rn):
+            if _bad(rn) or _bad(rtn):
                 status = NONFINITE
                 break
-            if rn <= tol:
+            if converged(rn, rtn):
                 status = OK
                 break
             rho_new = rt @ r
@@ -386,13 +421,14 @@ def rbicg(A, At, blocks: Blocks, b: np.ndarray, bt: Optional[np.ndarray] = None,
                 flush()
     if s > 0:
         flush()
-    # step 7
-    x = x - U @ zc
-    xt = xt - Ut @ ztc
+    x = x - blocks.U @ zc
+    xt = xt - blocks.Ut @ ztc
     info.total_iters = info.iters
     info.rel_res_recur = np.linalg.norm(r) / bnorm
     info.rel_res_true = np.linalg.norm(b - A @ x) / bnorm
+    info.rel_res_dual = np.linalg.norm(bt - At @ xt) / btnorm
     info.matvecs_A += 1
+    info.matvecs_At += 1
     if status == OK and info.rel_res_true > rtol:
         status = MAXIT
     info.status = status

@@ -1,7 +1,7 @@
 """Recycle blocks and recycle-space selection (oracle, FP64) -- TEST INFRASTRUCTURE ONLY.
 
-``make_blocks`` establishes the precondition of Algorithm 2 step 1 (and of
-Algorithm 1 step 1): given ``U`` and ``Ut``, form ``C = A U``, ``Ct = A^T Ut``,
+``make_blocks`` establishes what RBiCG and RBiCGSTAB assume of their recycle
+space (Sections 3 and 4): given ``U`` and ``Ut``, form ``C = A U``, ``Ct = A^T Ut``,
 make ``C`` and ``Ct`` bi-orthogonal with a positive diagonal ``D_c = Ct^T C``
 (Section 3, the paragraph introducing ``U``, ``Ut``, ``C``, ``Ct``), and form
 ``Chat = Ct D_c^{-1}`` and ``Ccheck = C D_c^{-1}`` (eq. CcheckChat).
@@ -52,14 +52,14 @@ class Blocks:
 
 
 def empty_blocks(n: int) -> Blocks:
-    """Empty recycle space: Algorithm 1 step 1, 'initialize ... to empty matrices'."""
+    """No recycle space (k = 0): the first system of a sequence has none (Section 3)."""
     z = np.zeros((n, 0))
     return Blocks(z, z.copy(), z.copy(), z.copy(), z.copy(), z.copy())
 
 
 def make_blocks(A, At, U: np.ndarray, Ut: np.ndarray, drop: float = 1e-12,
                 secant_max: float = 1e2) -> Blocks:
-    """Algorithm 2 step 1 with the bi-orthogonalisation reading described above."""
+    """C, Ct, Chat, Ccheck for (U, Ut) with the bi-orthogonalisation reading described above."""
     n = A.shape[0]
     if U.shape[1] == 0:
         return empty_blocks(n)

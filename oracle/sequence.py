@@ -1,10 +1,10 @@
 """Sequence driver of Section 6.2 (oracle, FP64) -- TEST INFRASTRUCTURE ONLY.
 
 For each matrix ``A(i)`` (shift-major order of Section 6.1): the first
-right-hand side is solved with RBiCG (Algorithm 1; dual right-hand side of
+right-hand side is solved with RBiCG (Section 3; dual right-hand side of
 all ones), whose Lanczos vectors build or improve the recycle space in
 cycles of ``s`` iterations; every other right-hand side of the same matrix
-is solved with RBiCGSTAB (Algorithm 2) using that space.  The first system
+is solved with RBiCGSTAB (Section 4) using that space.  The first system
 starts with an empty space.  ``mode="bicgstab"`` runs the non-recycling
 baseline on every system.
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 #include <thread>
 
@@ -220,136 +221,158 @@ int pivoted_cholesky(int m, const double* G, double tol, std::vector<int>& perm,
     return r;
 }
 
-// Francis double-shift QR on an upper Hessenberg matrix (eigenvalues only),
-// following the Wilkinson-Reinsch formulation: deflate at negligible
-// subdiagonals, exceptional shifts after 10 and 20 stalled sweeps.
-static bool hessenberg_qr(int n, std::vector<double> a, std::vector<cd>& lam) {
-    auto A = [&](int i, int j) -> double& { return a[i + (size_t)j * n]; };
-    std::vector<double> wr(n), wi(n);
-    double anorm = 0.0;
-    for (int i = 0; i < n; ++i)
-        for (int j = std::max(i - 1, 0); j < n; ++j) anorm += std::fabs(A(i, j));
-    int nn = n - 1;
-    double t = 0.0;
-    while (nn >= 0) {
-        int its = 0, l = 0;
-        do {
-            for (l = nn; l >= 1; --l) {
-                double s = std::fabs(A(l - 1, l - 1)) + std::fabs(A(l, l));
-                if (s == 0.0) s = anorm;
-                if (std::fabs(A(l, l - 1)) + s == s) {
-                    A(l, l - 1) = 0.0;
-                    break;
-                }
-            }
-            double x = A(nn, nn);
-            if (l == nn) {   // one real root
-                wr[nn] = x + t;
-                wi[nn] = 0.0;
-                --nn;
-            } else {
-                double y = A(nn - 1, nn - 1), w = A(nn, nn - 1) * A(nn - 1, nn);
-                if (l == nn - 1) {   // a 2x2 block
-                    const double p = 0.5 * (y - x), q = p * p + w;
-                    double z = std::sqrt(std::fabs(q));
-                    x += t;
-                    if (q >= 0.0) {
-                        z = p + std::copysign(z, p);
-                        wr[nn - 1] = wr[nn] = x + z;
-                        if (z != 0.0) wr[nn] = x - w / z;
-                        wi[nn - 1] = wi[nn] = 0.0;
-                    } else {
-                        wr[nn - 1] = wr[nn] = x + p;
-                        wi[nn - 1] = -z;
-                        wi[nn] = z;
-                    }
-                    nn -= 2;
-                } else {
-                    if (its == 60) return false;
-                    if (its == 10 || its == 20) {
-                        t += x;
-                        for (int i = 0; i <= nn; ++i) A(i, i) -= x;
-                        const double s = std::fabs(A(nn, nn - 1)) + std::fabs(A(nn - 1, nn - 2));
-                        y = x = 0.75 * s;
-                        w = -0.4375 * s * s;
-                    }
-                    ++its;
-                    int m = nn - 2;
-                    double p = 0, q = 0, r = 0, z = 0;
-                    for (m = nn - 2; m >= l; --m) {
-                        z = A(m, m);
-                        r = x - z;
-                        double s = y - z;
-                        p = (r * s - w) / A(m + 1, m) + A(m, m + 1);
-                        q = A(m + 1, m + 1) - z - r - s;
-                        r = A(m + 2, m + 1);
-                        s = std::fabs(p) + std::fabs(q) + std::fabs(r);
-                        p /= s;
-                        q /= s;
-                        r /= s;
-                        if (m == l) break;
-                        const double u = std::fabs(A(m, m - 1)) * (std::fabs(q) + std::fabs(r));
-                        const double v = std::fabs(p) * (std::fabs(A(m - 1, m - 1)) + std::fabs(z) +
-                                                         std::fabs(A(m + 1, m + 1)));
-                        if (u + v == v) break;
-                    }
-                    for (int i = m + 2; i <= nn; ++i) {
-                        A(i, i - 2) = 0.0;
-                        if (i != m + 2) A(i, i - 3) = 0.0;
-                    }
-                    for (int k = m; k <= nn - 1; ++k) {
-                        if (k != m) {
-                            p = A(k, k - 1);
-                            q = A(k + 1, k - 1);
-                            r = 0.0;
-                            if (k != nn - 1) r = A(k + 2, k - 1);
-                            x = std::fabs(p) + std::fabs(q) + std::fabs(r);
-                            if (x != 0.0) {
-                                p /= x;
-                                q /= x;
-                                r /= x;
-                            }
-                        }
-                        const double s = std::copysign(std::sqrt(p * p + q * q + r * r), p);
-                        if (s != 0.0) {
-                            if (k == m) {
-                                if (l != m) A(k, k - 1) = -A(k, k - 1);
-                            } else {
-                                A(k, k - 1) = -s * x;
-                            }
-                            p += s;
-                            x = p / s;
-                            y = q / s;
-                            z = r / s;
-                            q /= p;
-                            r /= p;
-                            for (int j = k; j <= nn; ++j) {
-                                p = A(k, j) + q * A(k + 1, j);
-                                if (k != nn - 1) {
-                                    p += r * A(k + 2, j);
-                                    A(k + 2, j) -= p * z;
-                                }
-                                A(k + 1, j) -= p * y;
-                                A(k, j) -= p * x;
-                            }
-                            const int mmin = nn < k + 3 ? nn : k + 3;
-                            for (int i = l; i <= mmin; ++i) {
-                                p = x * A(i, k) + y * A(i, k + 1);
-                                if (k != nn - 1) {
-                                    p += z * A(i, k + 2);
-                                    A(i, k + 2) -= p * r;
-                                }
-                                A(i, k + 1) -= p * q;
-                                A(i, k) -= p;
-                            }
-                        }
-                    }
-                }
-            }
-        } while (l < nn - 1);
+// Eigenvalues of an upper Hessenberg matrix by the implicitly double-shifted
+// (Francis) QR iteration, after Golub and Van Loan, Matrix Computations,
+// Section 7.5 (the Francis step and the deflating driver around it).
+//
+// The matrix is worked on in an active window [lo, hi] whose subdiagonal has
+// no negligible entry.  A window of size 1 or 2 yields its eigenvalues
+// directly; a larger one receives one double-shift step with the two
+// eigenvalues of its trailing 2 x 2 block as shifts, applied implicitly by
+// chasing a 3-row bulge down the window with Householder reflectors.  Only
+// the window is updated (eigenvalues only).  When a window has resisted
+// deflation for a multiple of eleven steps, one step uses made-up shifts
+// built from the last subdiagonal's size, which breaks the cycles the
+// standard shifts can fall into.
+
+namespace {
+
+// Householder reflector P = I - tau u u^T with u = [1, u1, u2] such that
+// P [v0 v1 v2]^T = [-sigma 0 0]^T.  Returns false for a zero vector.
+struct Reflector3 {
+    double u1 = 0.0, u2 = 0.0, tau = 0.0;
+};
+
+bool make_reflector(double v0, double v1, double v2, Reflector3& r) {
+    const double scale = std::fabs(v0) + std::fabs(v1) + std::fabs(v2);
+    if (scale == 0.0) return false;
+    v0 /= scale;
+    v1 /= scale;
+    v2 /= scale;
+    const double sigma = std::copysign(std::sqrt(v0 * v0 + v1 * v1 + v2 * v2), v0);
+    const double head = v0 + sigma;   // |head| >= |v0|: no cancellation
+    r.u1 = v1 / head;
+    r.u2 = v2 / head;
+    r.tau = head / sigma;
+    return true;
+}
+
+// Eigenvalues of [[a, b], [c, d]] (the real pair, or the conjugate pair).
+void eig2x2(double a, double b, double c, double d, cd& l1, cd& l2) {
+    const double half = 0.5 * (a - d);
+    const double disc = half * half + b * c;
+    const double mid = 0.5 * (a + d);
+    if (disc >= 0.0) {
+        // larger-magnitude root first, the other from the determinant
+        const double big = mid + std::copysign(std::sqrt(disc), mid == 0.0 ? 1.0 : mid);
+        const double det = a * d - b * c;
+        l1 = cd(big, 0.0);
+        l2 = cd(big != 0.0 ? det / big : mid - (big - mid), 0.0);
+    } else {
+        const double im = std::sqrt(-disc);
+        l1 = cd(mid, im);
+        l2 = cd(mid, -im);
     }
-    lam.resize(n);
-    for (int i = 0; i < n; ++i) lam[i] = cd(wr[i], wi[i]);
+}
+
+}  // namespace
+
+static bool hessenberg_qr(int n, std::vector<double> a, std::vector<cd>& lam) {
+    auto H = [&](int i, int j) -> double& { return a[i + (size_t)j * n]; };
+    lam.assign(n, cd(0.0));
+    if (n == 0) return true;
+    const double eps = std::numeric_limits<double>::epsilon();
+    double hnorm = 0.0;   // max-abs entry: the scale of "negligible" for zero diagonals
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i <= std::min(j + 1, n - 1); ++i) hnorm = std::max(hnorm, std::fabs(H(i, j)));
+    const int step_cap = 40 * n + 40;
+    int steps = 0;
+    int hi = n - 1;
+    int stalled = 0;   // steps spent on the current trailing window without deflation
+    while (hi >= 0) {
+        // find the top of the unreduced window ending at hi
+        int lo = hi;
+        while (lo > 0) {
+            const double diag = std::fabs(H(lo, lo)) + std::fabs(H(lo - 1, lo - 1));
+            const double ref = diag > 0.0 ? diag : hnorm;
+            if (std::fabs(H(lo, lo - 1)) <= eps * ref) {
+                H(lo, lo - 1) = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (lo == hi) {              // 1 x 1: a real eigenvalue
+            lam[hi] = cd(H(hi, hi), 0.0);
+            --hi;
+            stalled = 0;
+            continue;
+        }
+        if (lo == hi - 1) {          // 2 x 2: a real pair or a conjugate pair
+            eig2x2(H(hi - 1, hi - 1), H(hi - 1, hi), H(hi, hi - 1), H(hi, hi), lam[hi - 1], lam[hi]);
+            hi -= 2;
+            stalled = 0;
+            continue;
+        }
+        if (++steps > step_cap) return false;
+        ++stalled;
+        // shifts: sum s and product t of the trailing 2 x 2 block's eigenvalues
+        double s, t;
+        if (stalled % 11 == 0) {
+            const double e = std::fabs(H(hi, hi - 1)) + std::fabs(H(hi - 1, hi - 2));
+            const double c = H(hi, hi) + 1.5 * e;
+            s = 2.0 * c;
+            t = c * c + 0.25 * e * e;
+        } else {
+            s = H(hi - 1, hi - 1) + H(hi, hi);
+            t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
+        }
+        // first column of (H - r1 I)(H - r2 I) = H^2 - s H + t I restricted to the window
+        const double h00 = H(lo, lo), h10 = H(lo + 1, lo), h01 = H(lo, lo + 1);
+        const double h11 = H(lo + 1, lo + 1), h21 = H(lo + 2, lo + 1);
+        double x = h00 * h00 + h01 * h10 - s * h00 + t;
+        double y = h10 * (h00 + h11 - s);
+        double z = h10 * h21;
+        // chase the bulge: reflector k acts on rows / columns k, k+1, k+2
+        for (int k = lo; k <= hi - 1; ++k) {
+            const int nr = k + 2 <= hi ? 3 : 2;   // the last reflector spans two rows
+            Reflector3 r;
+            if (!make_reflector(x, y, nr == 3 ? z : 0.0, r)) {
+                if (k + 1 <= hi - 1) {
+                    x = H(k + 1, k);
+                    y = H(k + 2, k);
+                    z = k + 3 <= hi ? H(k + 3, k) : 0.0;
+                }
+                continue;
+            }
+            const int c0 = k > lo ? k - 1 : lo;
+            for (int j = c0; j <= hi; ++j) {      // rows k.. from the left
+                double d = H(k, j) + r.u1 * H(k + 1, j);
+                if (nr == 3) d += r.u2 * H(k + 2, j);
+                d *= r.tau;
+                H(k, j) -= d;
+                H(k + 1, j) -= d * r.u1;
+                if (nr == 3) H(k + 2, j) -= d * r.u2;
+            }
+            const int r1 = std::min(k + 3, hi);
+            for (int i = lo; i <= r1; ++i) {      // columns k.. from the right
+                double d = H(i, k) + r.u1 * H(i, k + 1);
+                if (nr == 3) d += r.u2 * H(i, k + 2);
+                d *= r.tau;
+                H(i, k) -= d;
+                H(i, k + 1) -= d * r.u1;
+                if (nr == 3) H(i, k + 2) -= d * r.u2;
+            }
+            if (k > lo) {   // the bulge below the subdiagonal is gone exactly
+                H(k + 1, k - 1) = 0.0;
+                if (nr == 3) H(k + 2, k - 1) = 0.0;
+            }
+            if (k + 1 <= hi - 1) {
+                x = H(k + 1, k);
+                y = H(k + 2, k);
+                z = k + 3 <= hi ? H(k + 3, k) : 0.0;
+            }
+        }
+    }
     return true;
 }
 
@@ -530,19 +553,30 @@ void ritz_select(const std::vector<cd>& theta, int k, std::vector<int>& idx, std
 
 namespace {
 
-// Pencil (Gp, Fp) in reduced coordinates: eigenvalues of H = Fp^-1 Gp, the k
-// selected ones, and their right eigenvectors (want_left: left vectors of the
-// pencil, yt^T Gp = theta yt^T Fp) as real columns ([Re, Im] for a pair).
+// Pencil Gp y = theta Fp y in reduced coordinates: the k selected values
+// (smallest |theta|) and their right eigenvectors (want_left: left vectors
+// of the pencil, yt^T Gp = theta yt^T Fp) as real columns ([Re, Im] for a
+// pair).  The pencil is solved in the reciprocal form Fp y = mu Gp y,
+// mu = 1 / theta, as the standard problem H = Gp^-1 Fp: the small theta
+// wanted here are the large mu, whose accuracy depends on the conditioning
+// of Gp only.  Fp (the projected identity Qt^T Q of a two-sided projection,
+// or (AQ)^T Q) can be close to singular on strongly non-normal operators;
+// its near-null directions become mu ~ 0 (theta ~ infinity), which the
+// selection never takes.  A left vector z of H (z^T H = mu z^T) gives the
+// pencil's left vector yt = Gp^-T z.
 bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<double>& Fp, int k,
                     bool want_left, std::vector<double>& cols, std::vector<cd>& theta) {
     std::vector<int> piv(me);
-    std::vector<double> Flu = Fp;
-    if (lu_factor(me, Flu.data(), me, piv.data()) != 0) return false;
-    std::vector<double> H = Gp;
-    lu_solve(me, Flu.data(), me, piv.data(), H.data(), me, me, false);
+    std::vector<double> Glu = Gp;
+    if (lu_factor(me, Glu.data(), me, piv.data()) != 0) return false;
+    std::vector<double> H = Fp;
+    lu_solve(me, Glu.data(), me, piv.data(), H.data(), me, me, false);
     std::vector<double> Hh, V;
-    std::vector<cd> lam;
-    if (!eig_general(me, H.data(), Hh, V, lam)) return false;
+    std::vector<cd> mu;
+    if (!eig_general(me, H.data(), Hh, V, mu)) return false;
+    std::vector<cd> lam(me);
+    for (int i = 0; i < me; ++i)
+        lam[i] = mu[i] == cd(0.0) ? cd(std::numeric_limits<double>::infinity(), 0.0) : 1.0 / mu[i];
     std::vector<int> idx, pair;
     ritz_select(lam, k, idx, pair);
     // eigenvectors of the selected values: independent, computed on up to
@@ -551,16 +585,16 @@ bool pencil_vectors(int me, const std::vector<double>& Gp, const std::vector<dou
     std::vector<std::vector<cd>> vecs(nsel);
     auto one = [&](int t) {
         std::vector<cd>& v = vecs[t];
-        hess_eigvec(me, Hh, lam[idx[t]], want_left, v);
+        hess_eigvec(me, Hh, mu[idx[t]], want_left, v);
         hess_back(me, V, v);   // vector of H (H^T) from that of Hh (Hh^T)
-        if (want_left) {   // pencil left vector = Fp^-T (left vector of H)
+        if (want_left) {   // pencil left vector = Gp^-T (left vector of H)
             std::vector<double> vr(me), vi(me);
             for (int i = 0; i < me; ++i) {
                 vr[i] = v[i].real();
                 vi[i] = v[i].imag();
             }
-            lu_solve(me, Flu.data(), me, piv.data(), vr.data(), me, 1, true);
-            lu_solve(me, Flu.data(), me, piv.data(), vi.data(), me, 1, true);
+            lu_solve(me, Glu.data(), me, piv.data(), vr.data(), me, 1, true);
+            lu_solve(me, Glu.data(), me, piv.data(), vi.data(), me, 1, true);
             for (int i = 0; i < me; ++i) v[i] = cd(vr[i], vi[i]);
         }
     };

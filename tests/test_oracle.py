@@ -246,6 +246,55 @@ def test_rbicg_projected_orthogonality(c0, eig_c0):
     assert _rel(x, xd) < np.linalg.cond(A.toarray()) * 1e-12 * 10
 
 
+def test_rbicg_dual_solution_with_recycle_space(c0, eig_c0):
+    """RBiCG solves the dual system A^T xt = bt too (Section 3): with a recycle
+    space the dual iterate is corrected by the accumulated Ut component, and the
+    solve stops only when both residuals meet the tolerance."""
+    seq, A, At = c0
+    # an inexact space: with exact eigenvectors the dual coefficients vanish
+    # identically (A Ccheck is a multiple of C, and C^T pt = 0), so the
+    # correction would go untested
+    lam, vl, vr = eig_c0
+    rng = np.random.default_rng(21)
+    U = vr[:, :6] + 1e-3 * rng.standard_normal((A.shape[0], 6))
+    Ut = vl[:, :6] + 1e-3 * rng.standard_normal((A.shape[0], 6))
+    bl = o.make_blocks(A, At, U, Ut, secant_max=np.inf)
+    assert bl.k == 6
+    n = A.shape[0]
+    b = seq.rhs[1]
+    bt = np.ones(n)
+    rtol = 1e-8
+    x, xt, info = o.rbicg(A, At, bl, b, rtol=rtol)
+    assert info.status == o.OK
+    Ad = A.toarray()
+    kappa = np.linalg.cond(Ad)
+    xd = np.linalg.solve(Ad, b)
+    xtd = np.linalg.solve(Ad.T, bt)
+    assert _rel(x, xd) < kappa * rtol * 10
+    assert _rel(xt, xtd) < kappa * rtol * 10
+    assert np.linalg.norm(bt - At @ xt) <= 10 * rtol * np.linalg.norm(bt)
+    assert info.rel_res_dual <= 10 * rtol
+
+
+def test_rbicg_stops_on_both_residuals(c0):
+    """The stopping rule of RBiCG in Section 3 asks for both residuals; stopping on the
+    primary one alone (an option) leaves the dual residual above the tolerance."""
+    seq, A, At = c0
+    n = A.shape[0]
+    b = seq.rhs[1]
+    rng = np.random.default_rng(3)
+    bt = rng.standard_normal(n) * np.exp(np.linspace(-3.0, 3.0, n))   # a harder dual system
+    _, xt_b, ib = o.rbicg(A, At, o.empty_blocks(n), b, bt=bt, rtol=1e-8, stop="both")
+    _, xt_p, ip = o.rbicg(A, At, o.empty_blocks(n), b, bt=bt, rtol=1e-8, stop="primary")
+    assert ib.status == o.OK and ip.status == o.OK
+    assert ib.rel_res_dual <= 1e-8 * 1.5
+    assert ib.rel_res_true <= 1e-8 and ip.rel_res_true <= 1e-8
+    assert ip.iters <= ib.iters
+    dual_recur = lambda xt: np.linalg.norm(bt - At @ xt) / np.linalg.norm(bt)
+    if ip.iters < ib.iters:
+        assert dual_recur(xt_p) > 1e-8
+
+
 def test_rbicg_cycles_cover_all_lanczos_vectors(c0):
     seq, A, At = c0
     got = []
@@ -286,9 +335,19 @@ def test_two_sided_ritz_recovers_planted_pairs(c0, eig_c0):
     Wt = np.hstack([vl[:, :k], padt])
     U, Ut, vals, m = o.two_sided_ritz(A, W, Wt, k)
     assert np.allclose(np.sort(vals.real), np.sort(lam[:k].real), rtol=1e-9)
-    # the returned space is the planted one
+    # the returned spaces are the planted ones, on both sides
     cosines = sla.svdvals(sla.orth(U).T @ sla.orth(vr[:, :k]))
     assert cosines.min() > 1 - 1e-9
+    cosines_left = sla.svdvals(sla.orth(Ut).T @ sla.orth(vl[:, :k]))
+    assert cosines_left.min() > 1 - 1e-9
+    # and vector by vector: the j-th left vector belongs to the j-th value
+    for j in range(k):
+        i = int(np.argmin(np.abs(lam[:k] - vals[j])))
+        c = abs(Ut[:, j] @ vl[:, i]) / (np.linalg.norm(Ut[:, j]) * np.linalg.norm(vl[:, i]))
+        assert c > 1 - 1e-9, j
+    # a left eigenvector satisfies u^T A = theta u^T
+    res = np.linalg.norm(At @ Ut - Ut * vals.real, axis=0) / np.abs(vals)
+    assert res.max() < 1e-8
 
 
 def test_ritz_select_pairs():
