@@ -61,7 +61,7 @@ typedef struct {
 enum {
     RBS_OK = 0,
     RBS_MAXIT = 1,             /* max_it reached (or true residual above tol after restarts) */
-    RBS_BREAKDOWN_RHO = 2,     /* (rt0, r) = 0: Algorithm 2 step 3 / Algorithm 1 step 3      */
+    RBS_BREAKDOWN_RHO = 2,     /* (rt0, r) = 0 at the start (eq. minusXR) or in the recurrence */
     RBS_BREAKDOWN_ALPHA = 3,   /* (rt0, q) = 0 (RBiCGSTAB) or (pt, q) = 0 (RBiCG)            */
     RBS_BREAKDOWN_OMEGA = 4,   /* omega = 0 or (t, t) = 0 with ||s|| > tol                   */
     RBS_ERR_ARG = -1,
@@ -87,6 +87,10 @@ enum {
                            * produces non-finite values is redone without the space, then in  *
                            * FP64 (counted in stats.restarts).  stats.iters = inner iterations, *
                            * stats.ir_steps = outer steps, stats.rel_res_true = FP64 residual.  */
+    RBS_STOP_PRIMARY = 32, /* with RBS_RBICG_GEN: stop on the primary residual alone.  By    *
+                           * default RBiCG stops only when ||r|| <= rtol ||b|| and the dual   *
+                           * residual ||rt|| <= rtol ||ones|| (the RBiCG algorithm of          *
+                           * Section 3); this option is not the paper's rule                  */
     RBS_TRANSPOSE = 8     /* solve A^T x = b reusing the space with the roles of U and Ut      *
                            * swapped (OR-ed with RBS_RBICGSTAB or RBS_BICGSTAB): for A^T the   *
                            * right space is Ut, C' = A^T Ut = Ct, Chat' = Ccheck and          *
@@ -120,7 +124,7 @@ size_t rbicgstab_workspace_bytes(int64_t n, int32_t max_row_nnz, int32_t k_max, 
  * existing context is rebound to the new matrix and keeps its recycle space
  * (U, Ut): C = A U and Ct = A^T Ut are recomputed for the new matrix, C and Ct
  * are made bi-orthogonal with D_c = I, and Chat = Ct D_c^-1, Ccheck = C D_c^-1
- * are formed (Algorithm 2 step 1, Section 3 eq. CcheckChat). Pairs whose
+ * are formed (Section 3, eq. CcheckChat). Pairs whose
  * D_c entry is negligible or whose oblique projector norm exceeds
  * secant_max are dropped (k shrinks; see rbs_stats.k_used).
  *
@@ -139,8 +143,8 @@ int rbicgstab_setup(rbs_ctx** ctx, int64_t n, int64_t nnz,
  * Solve A x = b (or A^T x = b with RBS_TRANSPOSE) with the bound matrix.
  *  b       device, n
  *  x       device, n: in = initial guess x_{-1} (used only if x_nonzero),
- *          out = solution including the final  x <- x - U x_c  (Algorithm 2 step 8)
- *  shadow  device, n, or NULL: the random rt_{-1} of Algorithm 2 step 2; NULL
+ *          out = solution including the final  x <- x - U x_c  (Section 4)
+ *  shadow  device, n, or NULL: the random shadow rt_{-1} of RBiCGSTAB (Section 4); NULL
  *          uses r_{-1}. Ignored by RBS_RBICG_GEN, whose dual right-hand side is
  *          the vector of all ones (Section 6.2).
  *  rtol    relative tolerance: stop when ||r_i|| <= rtol ||b||; success is
@@ -192,11 +196,11 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
                          double* Chat, double* Ccheck, int32_t* k_used /* host */);
 
 /*
- * Time the main kernel of one of the fused per-iteration passes of
- * Algorithm 2 on the bound matrix with recycle dimension k (0 <= k <=
- * installed k): which = 0 the update pass, 1 the first SpMV + projection
- * pass, 2 the second SpMV + projection pass (their one-block finalize
- * kernels are not included), 3 a plain SpMV; which = 4..7 the same passes
+ * Time one of the fused per-iteration passes of Algorithm 2 on the bound
+ * matrix with recycle dimension k (0 <= k <= installed k): which = 0 the
+ * update pass, 1 the first SpMV + projection pass, 2 the second SpMV +
+ * projection pass (each including its in-kernel reduction by the last
+ * workgroup, with the scalar update skipped), 3 a plain SpMV; which = 4..7 the same passes
  * with the FP32 storage of RBS_FP32_IR (4-byte values and vector entries);
  * which = 8 + 4 (nr - 1) + pass (pass 0..2) the multi-RHS pass of
  * rbicgstab_solve_multi for nr systems (nr, k in its fused range).  The pass is launched `reps` times

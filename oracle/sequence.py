@@ -39,7 +39,11 @@ class SequenceResult:
     solver: List[str] = field(default_factory=list)
     rel_res_true: List[float] = field(default_factory=list)
     seconds: List[float] = field(default_factory=list)
-    k_used: List[int] = field(default_factory=list)
+    k_used: List[int] = field(default_factory=list)   # recycle dimension each solve projects with
+    # largest condition number of the column-scaled Lanczos stores whose Ritz
+    # steps built the space each solve projects with, and the spaces upstream
+    # of it (nan: no space, or not tracked)
+    store_cond: List[float] = field(default_factory=list)
 
     @property
     def total_matvecs(self) -> int:
@@ -50,10 +54,17 @@ S_DEFAULT = 512   # Lanczos vectors kept per cycle (a whole solve at these sizes
 
 
 def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
-                 rtol: float = 1e-8, max_it: int = 20000, systems=None) -> SequenceResult:
+                 rtol: float = 1e-8, max_it: int = 20000, systems=None,
+                 rbicg_stop: str = "both", secant_max: float = 1e2,
+                 track_store_cond: bool = False) -> SequenceResult:
     """Solve the systems of ``seq`` (a ``workloads.ShiftedSequence``) in order.
 
     ``systems`` limits the run to the first ``systems`` systems (a bounded sample).
+    ``rbicg_stop`` is RBiCG's stopping rule (``krylov.rbicg``'s ``stop``);
+    ``secant_max`` the oblique-projector cap of ``recycle.make_blocks``.
+    ``track_store_cond`` records, per solve, the condition number of the
+    (column-scaled) stored Lanczos basis its recycle space was computed from:
+    the Ritz step is only as well determined as that basis.
     """
     k = seq.k if k is None else k
     if s is None:
@@ -66,6 +77,7 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
     cur_shift = -1
     A = At = None
     blocks = empty_blocks(n)
+    space_cond = np.nan
     for idx in range(last):
         si, j = seq.system(idx)
         t0 = time.perf_counter()
@@ -75,9 +87,11 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
             A, At = Acsr.to_scipy(), Atcsr.to_scipy()
             cur_shift = si
             if mode != "bicgstab":
-                blocks = make_blocks(A, At, U, Ut)
+                blocks = make_blocks(A, At, U, Ut, secant_max=secant_max)
                 mv += blocks.matvecs_A + blocks.matvecs_At
         b = seq.rhs[idx]
+        k_solve = blocks.k if mode != "bicgstab" else 0   # the projection this solve uses
+        cond_solve = space_cond if k_solve > 0 else np.nan
         if mode == "bicgstab":
             x, info = bicgstab(A, b, shadow=seq.shadows[idx], rtol=rtol, max_it=max_it)
             mv += info.matvecs_A
@@ -88,12 +102,15 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
             def on_cycle(V, Vt):
                 W = np.hstack([state["U"], V])
                 Wt = np.hstack([state["Ut"], Vt])
+                if track_store_cond:
+                    state["cond"] = max(np.linalg.cond(W / np.linalg.norm(W, axis=0)),
+                                        np.linalg.cond(Wt / np.linalg.norm(Wt, axis=0)))
                 Un, Utn, m = recycle_space(A, W, Wt, k)
                 state["U"], state["Ut"] = Un, Utn
                 state["mv"] += m
 
             x, _, info = rbicg(A, At, blocks, b, rtol=rtol, max_it=max_it, s=s,
-                               on_cycle=on_cycle)
+                               on_cycle=on_cycle, stop=rbicg_stop)
             mv += info.matvecs_A + info.matvecs_At + state["mv"]
             solver = "rbicg"
             converged = info.status == OK
@@ -107,7 +124,9 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
                 info.rel_res_true = info2.rel_res_true
             if converged:
                 U, Ut = state["U"], state["Ut"]
-                blocks = make_blocks(A, At, U, Ut)
+                # a space is as well determined as its store and every space upstream
+                space_cond = np.nanmax([state.get("cond", np.nan), cond_solve])
+                blocks = make_blocks(A, At, U, Ut, secant_max=secant_max)
                 U, Ut = blocks.U, blocks.Ut
                 mv += blocks.matvecs_A + blocks.matvecs_At
         else:
@@ -122,5 +141,6 @@ def run_sequence(seq, mode: str = "rbicgstab", k: int = None, s: int = None,
         out.matvecs.append(mv)
         out.solver.append(solver)
         out.rel_res_true.append(info.rel_res_true)
-        out.k_used.append(blocks.k)
+        out.k_used.append(k_solve)
+        out.store_cond.append(cond_solve)
     return out

@@ -77,6 +77,8 @@ struct rbs_ctx {
     double *W = nullptr, *Wt = nullptr, *AW = nullptr, *Wtmp = nullptr;
     int64_t ldw = 0;
     double* partials = nullptr;
+    unsigned* tickets = nullptr;   // completion counters of the fused passes (zero between launches)
+    double* gpart_cmp = nullptr;   // group sums of the fused passes' reductions
     SolveState* st = nullptr;
     BicgState* bst = nullptr;
     double* dsums = nullptr;
@@ -185,6 +187,8 @@ size_t carve(rbs_ctx* c, char* base) {
                                 rbs::gemmt_partial_doubles(c->n, c->k_max, c->k_max));
     c->gpart = cv.take<double>(c->gpart_doubles);
     c->partials = cv.take<double>((size_t)1024 * rbs::PARTIAL_ROWS);
+    c->tickets = cv.take<unsigned>(rbs::TICKET_WORDS);
+    c->gpart_cmp = cv.take<double>((size_t)rbs::PARTIAL_ROWS * rbs::TICKET_GROUPS);
     c->st = cv.take<SolveState>(1);
     c->bst = cv.take<BicgState>(1);
     c->dsums = cv.take<double>(8);
@@ -244,7 +248,7 @@ int to_device(rbs_ctx* c, void* d, const void* h, size_t bytes) {
     return RBS_OK;
 }
 
-// Algorithm 2 step 1 for the installed (U, Ut): C = A U, Ct = A^T Ut, then
+// Recycle blocks (Section 3, eq. CcheckChat) for the installed (U, Ut): C = A U, Ct = A^T Ut, then
 // SVD bi-orthogonalisation to D_c = I with the drop / secant rule, then
 // Chat = Ct D^-T, Ccheck = C D^-1, and Gh = A^T Chat for the fused iteration.
 int setup_blocks(rbs_ctx* c) {
@@ -356,6 +360,16 @@ int setup_blocks(rbs_ctx* c) {
     return RBS_OK;
 }
 
+// The context's in-pass reduction area (per-block partials, group sums, counters).
+rbs::Completion completion(rbs_ctx* c) {
+    rbs::Completion cp;
+    cp.part = c->partials;
+    cp.pstride = 1024;
+    cp.gpart = c->gpart_cmp;
+    cp.ctr = c->tickets;
+    return cp;
+}
+
 // Buffers of one solve.  transpose = true solves A^T x = b with the blocks
 // of A's recycle space swapped (the transposed system's right space is Ut,
 // C' = A^T Ut = Ct, Chat' = Ccheck, Ccheck' = Chat, and Gh' = A Ccheck).
@@ -386,6 +400,7 @@ rbs::SolveBufs solve_bufs(rbs_ctx* c, int k, const double* b, double* xout, cons
     B.rh = c->rh;
     B.state = c->st;
     B.partials = c->partials;
+    B.cp = completion(c);
     return B;
 }
 
@@ -548,6 +563,7 @@ rbs::SolveBufsF solve_bufs_f32(rbs_ctx* c, int k, bool with_shadow) {
     B.rh = c->rhf;
     B.state = c->st;
     B.partials = c->partials;
+    B.cp = completion(c);
     return B;
 }
 
@@ -697,6 +713,7 @@ rbs::MultiBufs multi_bufs(rbs_ctx* c, int k, int nr) {
     M.rh = c->mrh;
     M.state = c->mst;
     M.partials = c->partials;
+    M.cp = completion(c);
     return M;
 }
 
@@ -809,6 +826,7 @@ rbs::BicgBufs bicg_bufs(rbs_ctx* c, const double* b, double* xout) {
     B.col0 = c->gen_k;
     B.state = c->bst;
     B.partials = c->partials;
+    B.cp = completion(c);
     return B;
 }
 
@@ -1036,7 +1054,7 @@ int ritz_cycle(rbs_ctx* c, int ns) {
 }
 
 int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* shadow, double rtol,
-                int max_it, rbs_stats* stats) {
+                int max_it, bool stop_both, rbs_stats* stats) {
     if (c->s_max <= 0) return fail(c, RBS_ERR_ARG, "RBS_RBICG_GEN needs s_max > 0");
     int rc;
     c->gen_valid = false;
@@ -1048,7 +1066,7 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
     if ((rc = copy_cols(c, c->W, c->ldw, c->U, c->ld, c->k))) return rc;
     if ((rc = copy_cols(c, c->Wt, c->ldw, c->Ut, c->ld, c->k))) return rc;
     rbs::BicgBufs B = bicg_bufs(c, b, x);
-    rbs::launch_bicg_prologue(c->stream, B, rtol, max_it, c->s_max);
+    rbs::launch_bicg_prologue(c->stream, B, rtol, max_it, c->s_max, stop_both ? 1 : 0);
     int ritz_updates = 0;
     int since_flush = 0;
     auto poll = [&]() -> int {
@@ -1154,6 +1172,8 @@ struct rbs_batch {
     rbs::BatchTile* d_tiles = nullptr;
     int32_t* d_tile_begin = nullptr;
     double* d_partials = nullptr;
+    unsigned* d_tickets = nullptr;       // per-system completion counters of the fused passes
+    double* d_gpart = nullptr;           // per-system group sums of the fused passes
     SolveState* d_states = nullptr;      // gathered state headers (polling)
     SolveState* h_states = nullptr;      // pinned host copy
     int max_tiles = 0, ntiles = 0, tile_rows = 0, grid = 0, kmax = 0;
@@ -1189,6 +1209,8 @@ size_t batch_carve(rbs_batch* b, char* base, int nsys, int max_tiles) {
     b->d_tiles = cv.take<rbs::BatchTile>(max_tiles);
     b->d_tile_begin = cv.take<int32_t>(nsys + 1);
     b->d_partials = cv.take<double>((size_t)(rbs::KMAX + 3) * max_tiles);
+    b->d_gpart = cv.take<double>((size_t)nsys * (rbs::KMAX + 3) * rbs::TICKET_GROUPS);
+    b->d_tickets = cv.take<unsigned>((size_t)nsys * rbs::TICKET_WORDS);
     b->d_states = cv.take<SolveState>(nsys);
     return round_up(cv.off, ALIGN);
 }
@@ -1236,6 +1258,8 @@ rbs::BatchBufs batch_bufs(const rbs_batch* b) {
     B.ntiles = b->ntiles;
     B.kmax = b->kmax;
     B.partials = b->d_partials;
+    B.tickets = b->d_tickets;
+    B.gpart = b->d_gpart;
     return B;
 }
 
@@ -1397,7 +1421,11 @@ int rbicgstab_solve(rbs_ctx* c, const double* b, double* x, int32_t x_nonzero, c
     const int mode = flags & 3;
     const bool tr = (flags & RBS_TRANSPOSE) != 0;
     const bool ir = (flags & RBS_FP32_IR) != 0;
-    if (flags & ~(3 | RBS_TRANSPOSE | RBS_FP32_IR)) return fail(c, RBS_ERR_ARG, "unknown solve flags");
+    const bool primary_stop = (flags & RBS_STOP_PRIMARY) != 0;
+    if (flags & ~(3 | RBS_TRANSPOSE | RBS_FP32_IR | RBS_STOP_PRIMARY))
+        return fail(c, RBS_ERR_ARG, "unknown solve flags");
+    if (primary_stop && mode != RBS_RBICG_GEN)
+        return fail(c, RBS_ERR_ARG, "RBS_STOP_PRIMARY applies to RBS_RBICG_GEN only");
     if (tr && mode == RBS_RBICG_GEN)
         return fail(c, RBS_ERR_ARG, "RBS_TRANSPOSE applies to RBS_RBICGSTAB and RBS_BICGSTAB only");
     if (ir && (tr || mode == RBS_RBICG_GEN || mode == 3))
@@ -1405,7 +1433,7 @@ int rbicgstab_solve(rbs_ctx* c, const double* b, double* x, int32_t x_nonzero, c
     if (ir)
         rc = solve_ir(c, mode == RBS_BICGSTAB ? 0 : c->k, b, x, x_nonzero, shadow, rtol, max_it, stats);
     else if (mode == RBS_RBICG_GEN)
-        rc = solve_rbicg(c, b, x, x_nonzero, shadow, rtol, max_it, stats);
+        rc = solve_rbicg(c, b, x, x_nonzero, shadow, rtol, max_it, !primary_stop, stats);
     else if (mode == RBS_BICGSTAB)
         rc = solve_rbicgstab(c, 0, b, x, x_nonzero, shadow, rtol, max_it, stats, tr);
     else if (mode == RBS_RBICGSTAB)
@@ -1649,6 +1677,13 @@ int rbicgstab_batch_create(rbs_batch** pb, int32_t nsys, rbs_ctx* const* ctxs, v
     }
     b->h_states = static_cast<SolveState*>(hp);
     b->use_graph = (flags & RBS_BATCH_GRAPH) != 0;
+    // the fused passes' completion counters start (and end every launch) at zero
+    if (e == hipSuccess)
+        e = hipMemsetAsync(b->d_tickets, 0, sizeof(unsigned) * nsys * rbs::TICKET_WORDS, b->stream);
+    if (e != hipSuccess) {
+        rbicgstab_batch_destroy(b);
+        return bfail(nullptr, RBS_ERR_HIP, std::string("batch create: ") + hipGetErrorString(e));
+    }
     // the contexts' pending work (setup, space generation) precedes the batch's
     for (int j = 0; j < nsys; ++j) {
         e = hipStreamSynchronize(ctxs[j]->stream);

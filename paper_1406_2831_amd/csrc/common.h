@@ -11,6 +11,12 @@ constexpr int MAX_SUMS = KMAX + 8;
 // rows of the per-block partial-sum buffers: the largest fused reduction is
 // the multi-RHS update pass (4 systems x (KMAX + 3) sums)
 constexpr int PARTIAL_ROWS = 4 * (KMAX + 3);
+// in-pass completion of the fused reductions: participants count themselves
+// in TICKET_GROUPS group counters and one top counter, each on its own
+// 128-byte line (TICKET_STRIDE unsigned apart)
+constexpr int TICKET_GROUPS = 32;
+constexpr int TICKET_STRIDE = 32;
+constexpr int TICKET_WORDS = (TICKET_GROUPS + 1) * TICKET_STRIDE;   // counters of one reduction
 
 // Sliced ELLPACK with slice height = one wavefront (64 rows).  Slice s holds
 // rows [64 s, 64 s + 64) stored column-major inside the slice: entry j of
@@ -60,6 +66,8 @@ struct SolveState {
 // RBiCG (Algorithm 1) per-iteration scalars.
 struct BicgState {
     double alpha, beta, rho, tol2, bnorm2, rr;
+    double tol2_dual;                 // (rtol ||bt||)^2, or +inf when only the primary residual stops
+    double rtrt;                      // ||rt_{i-1}||^2 of the last update pass
     int32_t iter, done, status, iters_done, max_it, k;
     int32_t store_base, store_cap;    // cycle-store column of r_{i-1}; capacity
     int32_t stored;                   // Lanczos vectors stored in the current cycle

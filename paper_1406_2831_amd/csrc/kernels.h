@@ -36,6 +36,19 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
                   const double* Y1, int64_t ldy1, int my1, const double* Y2, int64_t ldy2,
                   int my2, double* partial, double* out);
 
+// Where one in-pass reduction keeps its partials and counters: participant
+// i's m values go to part[v * pstride + i]; group g's sums to
+// gpart[v * TICKET_GROUPS + g] (gpart holds PARTIAL_ROWS x TICKET_GROUPS
+// doubles); the counters (TICKET_WORDS unsigned, zero between launches) are
+// ctr[g * TICKET_STRIDE] for the groups and ctr[TICKET_GROUPS * TICKET_STRIDE]
+// for the top.
+struct Completion {
+    double* part;
+    int64_t pstride;
+    double* gpart;
+    unsigned* ctr;
+};
+
 // ---- solve kernels (Algorithm 2 / BiCGSTAB) -------------------------------
 // T is the storage type of the vectors, blocks and matrix values of one solve:
 // double, or float for the FP32-storage inner solves of iterative refinement
@@ -52,6 +65,7 @@ struct SolveBufsT {
     T *x, *r, *s, *t, *p, *q, *rt0, *rh;
     SolveState* state;
     double* partials;      // per-block partial sums, value-major ((2 KMAX + 8) x 1024)
+    Completion cp;         // in-pass reductions of the iteration (part = partials, stride 1024)
 };
 using SolveBufs = SolveBufsT<double>;
 using SolveBufsF = SolveBufsT<float>;
@@ -63,9 +77,9 @@ void launch_solve_iterations(hipStream_t st, const SolveBufsT<T>& B, int count);
 template <typename T>
 void launch_solve_epilogue(hipStream_t st, const SolveBufsT<T>& B);
 // Timing support: put the solve state in a non-terminating configuration
-// (done = 0, tolerance below zero, fixed bounded scalars) and launch the
-// main kernel of one of the fused passes (0 update, 1 spmv1, 2 spmv2; their
-// one-block finalize kernels are not launched) or 3, a plain SpMV y = A x.
+// (done = 0, tolerance below zero, fixed bounded scalars) and launch one of
+// the fused passes (0 update, 1 spmv1, 2 spmv2) with its in-kernel reduction
+// but without the scalar update, or 3, a plain SpMV y = A x.
 void launch_time_prep(hipStream_t st, SolveState* state, int count = 1);
 template <typename T>
 void launch_pass(hipStream_t st, const SolveBufsT<T>& B, int which);
@@ -83,6 +97,7 @@ struct MultiBufs {
     double *x, *r, *s, *t, *p, *q, *rt0, *rh;
     SolveState* state;
     double* partials;
+    Completion cp;
 };
 // systems one fused launch carries for nr systems with recycle dimension k (0: unsupported)
 int multi_width(int nr, int k);
@@ -107,6 +122,8 @@ struct BatchBufs {
     const int32_t* tile_begin;  // device array (nsys + 1): system j owns tiles [tb[j], tb[j+1])
     int nsys, ntiles, kmax;
     double* partials;
+    double* gpart;              // device array: (KMAX + 3) x TICKET_GROUPS group sums per system
+    unsigned* tickets;          // device array: TICKET_WORDS completion counters per system
 };
 // count iterations of every unfinished system; grid = workgroups of each pass
 void launch_batch_iterations(hipStream_t st, const BatchBufs& B, int grid, int count);
@@ -140,8 +157,12 @@ struct BicgBufs {
     int col0;              // first Lanczos column (= recycle dimension of the store)
     BicgState* state;
     double* partials;      // per-block partial sums
+    Completion cp;         // in-pass reductions of the iteration
 };
-void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap);
+// stop_both = 1: stop when ||r|| <= rtol ||b|| and ||rt|| <= rtol ||ones|| (Section 3);
+// 0: on the primary residual alone
+void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap,
+                          int stop_both);
 void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count);
 void launch_bicg_epilogue(hipStream_t st, const BicgBufs& B);
 void launch_bicg_reset_cycle(hipStream_t st, BicgState* state);

@@ -169,6 +169,113 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
     }
 }
 
+// ---------------------------------------------------------------- in-pass completion
+//
+// A reducing pass finishes its own reduction.  Every participant (a
+// workgroup, or a tile of a batched pass) stores its partial sums with
+// device-coherent stores (relaxed agent-scope atomics, which write through
+// the XCD's L2), waits until they are performed, and counts itself in one of
+// TICKET_GROUPS counters (participant i in group i mod G).  The last member
+// of a group sums the group's partials in participant order, stores the group
+// sum the same way and counts the group in a top counter; the last group's
+// member sums the group sums in group order and runs the scalar update.  The
+// order of every sum is fixed by the launch shape, so results are the same on
+// every run.  Counters sit on separate 128-byte lines and are reset by the
+// participant that read them last, so they are zero between launches.  Two
+// levels keep the same-address atomics per counter near the square root of
+// the participant count: 1024 workgroups on one counter serialise for
+// microseconds.  Only the partials cross workgroups inside a kernel; the
+// vectors and the scalar state a pass writes reach the next pass through the
+// kernel boundary.
+
+__device__ __forceinline__ void store_coherent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// s_waitcnt vmcnt(0): this wave's stores have been performed
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// After this workgroup's coherent stores: count it on *ctr and return (to
+// every thread) whether it was the last of `expected`; the last resets *ctr.
+__device__ __forceinline__ bool count_in(unsigned* ctr, unsigned expected) {
+    __shared__ int last;
+    wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = t == expected - 1 ? 1 : 0;
+        if (last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return last != 0;
+}
+
+// Sums of m (<= M) per-thread values over a workgroup of any multiple of 64
+// threads up to BLOCK; totals land in tot[0..m).
+template <int M>
+__device__ __forceinline__ void block_sum_any(double (&w)[M], int m, double* red, double* tot) {
+    const int wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    wave_sums<M>(w, red + wid * M);
+    __syncthreads();
+    if (threadIdx.x < m) {
+        double s = 0.0;
+        for (int q = 0; q < nw; ++q) s += red[q * M + threadIdx.x];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// m sums over the participants held in sums[0..m) (LDS, this participant's
+// totals); returns true (to every thread) for the one participant that
+// finishes the reduction, with the totals in tot[0..m) (LDS).
+__device__ __forceinline__ bool complete(const Completion& cp, const double* sums, int m, int i, int count,
+                                         double* tot) {
+    for (int v = threadIdx.x; v < m; v += blockDim.x) store_coherent(cp.part + (int64_t)v * cp.pstride + i, sums[v]);
+    const int G = count < TICKET_GROUPS ? count : TICKET_GROUPS;
+    const int g = i % G;
+    const int gsize = (count - g + G - 1) / G;   // participants g, g + G, ...
+    if (!count_in(cp.ctr + g * TICKET_STRIDE, (unsigned)gsize)) return false;
+    for (int v = threadIdx.x; v < m; v += blockDim.x) {
+        const double* row = cp.part + (int64_t)v * cp.pstride;
+        double acc = 0.0;
+        for (int j0 = 0; j0 < gsize; j0 += 8) {   // loads of eight members in flight
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = j0 + u < gsize ? load_coherent(row + g + (j0 + u) * G) : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t[u];
+        }
+        store_coherent(cp.gpart + v * TICKET_GROUPS + g, acc);
+    }
+    if (!count_in(cp.ctr + TICKET_GROUPS * TICKET_STRIDE, (unsigned)G)) return false;
+    for (int v = threadIdx.x; v < m; v += blockDim.x) {
+        const double* row = cp.gpart + v * TICKET_GROUPS;
+        double t[TICKET_GROUPS];
+#pragma unroll
+        for (int u = 0; u < TICKET_GROUPS; ++u) t[u] = u < G ? load_coherent(row + u) : 0.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < TICKET_GROUPS; ++u) acc += t[u];
+        tot[v] = acc;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Workgroup sums of m (<= M) values, then complete(): participant i of count.
+template <int M>
+__device__ __forceinline__ bool block_complete(double (&v)[M], int m, const Completion& cp, int i, int count,
+                                               double* tot) {
+    __shared__ double red[(BLOCK / WAVE) * M];
+    __shared__ double sums[M];
+    block_sum_any<M>(v, m, red, sums);
+    return complete(cp, sums, m, i, count, tot);
+}
+
 // Row product of the sliced matrix.  Entries are fetched eight at a time
 // with clamped (always valid) indices and zero weights past the slice
 // width, so a wave has eight index/value loads and then eight gathers in
@@ -811,17 +918,24 @@ __device__ __forceinline__ void update_rows(const SolveBufsT<T>& B, int64_t r0, 
     }
 }
 
+__device__ void update_fin_scalars(SolveState* st, const double* tot, int k);
+__device__ void spmv2_fin_scalars(SolveState* st, const double* tot, int k);
+
+// fin = 0 (timing only): the last workgroup reduces but leaves the state alone
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B) {
+__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B, int fin) {
     constexpr int M = K + 3;
-    if (B.state->done) return;
+    SolveState* st = B.state;
+    if (st->done) return;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     double acc[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
     update_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
-    block_partial<M>(acc, M, B.partials);
+    __shared__ double tot[M];
+    if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
+    if (fin && threadIdx.x == 0) update_fin_scalars(st, tot, B.k);
 }
 
 // Scalar part of the update finalize for one system: convergence / breakdown
@@ -868,16 +982,6 @@ __device__ void update_fin_scalars(SolveState* st, const double* tot, int k) {
     }
 }
 
-template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_update_fin(SolveBufsT<T> B, int nb) {
-    constexpr int M = K + 3;
-    __shared__ double tot[M];
-    SolveState* st = B.state;
-    if (st->done) return;
-    reduce_partials<M>(B.partials, nb, M, tot);
-    if (threadIdx.x == 0) update_fin_scalars(st, tot, B.k);
-}
-
 // spmv1: q = A p - C zeta ; s = r - alpha q ; partials Gh^T s (rows as update_rows)
 template <typename T, int K>
 __device__ __forceinline__ void spmv1_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
@@ -902,27 +1006,21 @@ __device__ __forceinline__ void spmv1_rows(const SolveBufsT<T>& B, int64_t r0, i
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B) {
+__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B, int fin) {
     constexpr int M = K > 0 ? K : 1;
-    if (B.state->done) return;
+    SolveState* st = B.state;
+    if (st->done) return;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     double acc[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
     spmv1_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
-    if (K > 0) block_partial<M>(acc, M, B.partials);
-}
-
-template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv1_fin(SolveBufsT<T> B, int nb) {
-    constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
-    SolveState* st = B.state;
-    if (st->done) return;
-    const int k = B.k;
-    reduce_partials<M>(B.partials, nb, M, tot);
-    if (threadIdx.x < k) st->gamma[threadIdx.x] = tot[threadIdx.x];
+    if constexpr (K > 0) {
+        __shared__ double tot[M];
+        if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
+        if (fin && threadIdx.x < B.k) st->gamma[threadIdx.x] = tot[threadIdx.x];
+    }
 }
 
 // spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
@@ -949,13 +1047,16 @@ __device__ __forceinline__ void spmv2_rows(const SolveBufsT<T>& B, int64_t r0, i
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B) {
-    if (B.state->done) return;
+__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B, int fin) {
+    SolveState* st = B.state;
+    if (st->done) return;
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     spmv2_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
-    block_partial<5>(acc, 5, B.partials);
+    __shared__ double tot[5];
+    if (!block_complete<5>(acc, 5, B.cp, blockIdx.x, gridDim.x, tot)) return;
+    if (fin && threadIdx.x == 0) spmv2_fin_scalars(st, tot, B.k);
 }
 
 // Scalar part of the second finalize for one system: omega, x_c, beta.
@@ -980,17 +1081,7 @@ __device__ void spmv2_fin_scalars(SolveState* st, const double* tot, int k) {
     st->iter += 1;
 }
 
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_spmv2_fin(SolveBufsT<T> B, int nb) {
-    constexpr int M = 5;
-    __shared__ double tot[M];
-    SolveState* st = B.state;
-    if (st->done) return;
-    reduce_partials<M>(B.partials, nb, M, tot);
-    if (threadIdx.x == 0) spmv2_fin_scalars(st, tot, B.k);
-}
-
-// epilogue: x_out = x - U x_c (Algorithm 2 step 8)
+// epilogue: x_out = x - U x_c (the final correction of RBiCGSTAB, Section 4)
 template <typename T, int K>
 __global__ __launch_bounds__(BLOCK) void k_epi(SolveBufsT<T> B) {
     const SolveState* st = B.state;
@@ -1036,33 +1127,30 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
 // Persistent kernels over the tiles of a batch of independent systems: the
 // per-row work is the single-system pass's (update_rows / spmv1_rows /
 // spmv2_rows); a system without recycle space (k = 0) runs the K = 0 body.
+// Each tile's partial goes to column t of the value-major tile partials; the
+// workgroup that completes a system's last tile (a ticket per system) sums
+// that system's tile partials in tile order and updates its scalars, so a
+// system's reduction is done as soon as its own tiles are, while the other
+// workgroups go on with other systems' tiles.
 
+// tile t of system sys: its partial, then the system's completion (tiles
+// b0..b1 of the system are its participants; per-system group sums and counters)
 template <int M>
-__device__ __forceinline__ void tile_partial(double (&v)[M], double* partials, int stride, int t) {
-    __shared__ double red[(BLOCK / WAVE) * M];
-    __shared__ double tot[M];
-    block_sum<M>(v, M, red, tot);
-    if (threadIdx.x < M) partials[(int64_t)threadIdx.x * stride + t] = tot[threadIdx.x];
-    __syncthreads();   // tot is rewritten by the next tile
-}
-
-// One workgroup sums a system's tile partials [b0, b1) in tile order.
-template <int M>
-__device__ __forceinline__ void reduce_tile_partials(const double* __restrict__ partials, int stride,
-                                                     int b0, int b1, double* tot) {
-    __shared__ double red[(BLOCK / WAVE) * M];
-    double acc[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        acc[j] = 0.0;
-        for (int b = b0 + threadIdx.x; b < b1; b += BLOCK) acc[j] += partials[(int64_t)j * stride + b];
-    }
-    block_sum<M>(acc, M, red, tot);
+__device__ __forceinline__ bool tile_done(double (&v)[M], const BatchBufs& B, int t, int sys,
+                                          double* tot) {
+    const int b0 = B.tile_begin[sys], b1 = B.tile_begin[sys + 1];
+    Completion cp;
+    cp.part = B.partials + b0;
+    cp.pstride = B.ntiles;
+    cp.gpart = B.gpart + (int64_t)sys * (KMAX + 3) * TICKET_GROUPS;
+    cp.ctr = B.tickets + (int64_t)sys * (TICKET_GROUPS + 1) * TICKET_STRIDE;
+    return block_complete<M>(v, M, cp, t - b0, b1 - b0, tot);
 }
 
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufs B, int fin) {
     constexpr int M = K + 3;
+    __shared__ double tot[M];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
         const SolveBufs S = B.sys[tl.sys];
@@ -1079,24 +1167,17 @@ __global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufs B) {
             acc[1] = a0[1];
             acc[2] = a0[2];
         }
-        tile_partial<M>(acc, B.partials, B.ntiles, t);
+        if (tile_done<M>(acc, B, t, tl.sys, tot)) {
+            if (fin && threadIdx.x == 0) update_fin_scalars(S.state, tot, S.k);
+        }
+        __syncthreads();   // tot and the ticket flag are reused by the next tile
     }
 }
 
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_update_fin(BatchBufs B) {
-    constexpr int M = K + 3;
-    __shared__ double tot[M];
-    const int j = blockIdx.x;
-    SolveState* st = B.sys[j].state;
-    if (st->done) return;
-    reduce_tile_partials<M>(B.partials, B.ntiles, B.tile_begin[j], B.tile_begin[j + 1], tot);
-    if (threadIdx.x == 0) update_fin_scalars(st, tot, B.sys[j].k);
-}
-
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufs B, int fin) {
     constexpr int M = K > 0 ? K : 1;
+    __shared__ double tot[M];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
         const SolveBufs S = B.sys[tl.sys];
@@ -1110,24 +1191,18 @@ __global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufs B) {
             double a0[1] = {0.0};
             spmv1_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
         }
-        if (K > 0) tile_partial<M>(acc, B.partials, B.ntiles, t);
+        if constexpr (K > 0) {
+            if (tile_done<M>(acc, B, t, tl.sys, tot)) {
+                if (fin && threadIdx.x < S.k) S.state->gamma[threadIdx.x] = tot[threadIdx.x];
+            }
+            __syncthreads();
+        }
     }
 }
 
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_spmv1_fin(BatchBufs B) {
-    constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
-    const int j = blockIdx.x;
-    SolveState* st = B.sys[j].state;
-    const int k = B.sys[j].k;
-    if (st->done || k == 0) return;
-    reduce_tile_partials<M>(B.partials, B.ntiles, B.tile_begin[j], B.tile_begin[j + 1], tot);
-    if (threadIdx.x < k) st->gamma[threadIdx.x] = tot[threadIdx.x];
-}
-
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufs B, int fin) {
+    __shared__ double tot[5];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
         const SolveBufs S = B.sys[tl.sys];
@@ -1135,17 +1210,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufs B) {
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (S.k > 0) spmv2_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
         else spmv2_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
-        tile_partial<5>(acc, B.partials, B.ntiles, t);
+        if (tile_done<5>(acc, B, t, tl.sys, tot)) {
+            if (fin && threadIdx.x == 0) spmv2_fin_scalars(S.state, tot, S.k);
+        }
+        __syncthreads();
     }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_batch_spmv2_fin(BatchBufs B) {
-    __shared__ double tot[5];
-    const int j = blockIdx.x;
-    SolveState* st = B.sys[j].state;
-    if (st->done) return;
-    reduce_tile_partials<5>(B.partials, B.ntiles, B.tile_begin[j], B.tile_begin[j + 1], tot);
-    if (threadIdx.x == 0) spmv2_fin_scalars(st, tot, B.sys[j].k);
 }
 
 __global__ void k_gather_states(BatchBufs B, SolveState* out) {
@@ -1155,14 +1224,15 @@ __global__ void k_gather_states(BatchBufs B, SolveState* out) {
 }
 
 // ---------------------------------------------------------------- multi-RHS passes
-// The three fused passes for up to MULTI_W systems of one matrix: wave j of a
-// block runs system j over the block's rows, so the waves of a block read the
-// same matrix entries and block values (C, Gh) at the same time (one HBM
-// fetch, the other waves hit the CU's cache) while each keeps the register
-// footprint of the single-system kernel.  Sums are laid out system-major
-// (system j's M values at j * M) and reduced by finalizers with one block per
-// system; the arithmetic per system, and its order, is the single-system
-// kernels'.
+// The three fused passes for up to MULTI_W systems of one matrix: a workgroup
+// has one wave per system (nr waves), and wave j runs system j over the
+// workgroup's rows, so the waves read the same matrix entries and block values
+// (C, Gh) at about the same time (one HBM fetch, the other waves hit the CU's
+// cache) while each keeps the register footprint of the single-system kernel.
+// Wave sums go to the value-major partials system-major (system j's M values
+// at rows j M ..); the last workgroup to finish reduces every active system's
+// values in block order and updates its scalars, with the arithmetic, and its
+// order, of the single-system passes.
 constexpr int MULTI_W = BLOCK / WAVE;   // systems per launch (one wave each)
 
 __device__ __forceinline__ bool multi_active_any(const MultiBufs& B) {
@@ -1171,19 +1241,18 @@ __device__ __forceinline__ bool multi_active_any(const MultiBufs& B) {
     return any;
 }
 
-// Rows of this block handled by one wave: [r0 + lane, r1) in steps of WAVE.
-// Wave sums of M values go to slot (system j) of the block partial.
+// Wave j's M sums are values j M .. of the workgroup's partial; then the
+// completion over the workgroups (totals of all systems in tot).
 template <int M>
-__device__ __forceinline__ void multi_block_partial(double (&v)[M], int j, double* partials) {
-    __shared__ double tot[MULTI_W * M];
-    wave_sums<M>(v, tot + j * M);
+__device__ __forceinline__ bool multi_complete(double (&v)[M], int j, const MultiBufs& B, double* tot) {
+    __shared__ double sums[MULTI_W * M];
+    wave_sums<M>(v, sums + j * M);
     __syncthreads();
-    for (int t = threadIdx.x; t < MULTI_W * M; t += BLOCK)
-        partials[(int64_t)t * MAX_GRID + blockIdx.x] = tot[t];
+    return complete(B.cp, sums, B.nr * M, blockIdx.x, gridDim.x, tot);
 }
 
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
     constexpr int M = K + 3;
     if (!multi_active_any(B)) return;
     // the system index is uniform over a wave: keep it (and the scalars read
@@ -1215,29 +1284,16 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B) {
             for (int jj = 0; jj < K; ++jj) acc[3 + jj] += B.Gh[row + col_off(jj, k, ld)] * pn;
         }
     }
-    multi_block_partial<M>(acc, j, B.partials);
-}
-
-// The multi-RHS finalizers run one block per system (grid MULTI_W): block j
-// reduces system j's M rows of the partials, as the single-system finalizer
-// does, so the systems' reductions proceed side by side.
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_mupdate_fin(MultiBufs B, int nb) {
-    constexpr int M = K + 3;
-    __shared__ double tot[M];
-    const int j = blockIdx.x;
-    if (j >= B.nr || B.state[j].done) return;
-    reduce_partials<M>(B.partials + (int64_t)j * M * MAX_GRID, nb, M, tot);
-    if (threadIdx.x == 0) update_fin_scalars(&B.state[j], tot, B.k);
+    __shared__ double tot[MULTI_W * M];
+    if (!multi_complete<M>(acc, j, B, tot)) return;
+    if (fin && threadIdx.x < B.nr && !B.state[threadIdx.x].done)
+        update_fin_scalars(&B.state[threadIdx.x], tot + threadIdx.x * M, B.k);
 }
 
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
     constexpr int M = K > 0 ? K : 1;
     if (!multi_active_any(B)) return;
-    // the system index is uniform over a wave: keep it (and the scalars read
-    // with it) in scalar registers, which leaves the vector registers to the
-    // loads in flight
     const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
     const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
@@ -1264,26 +1320,21 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B) {
             for (int jj = 0; jj < K; ++jj) acc[jj] += B.Gh[row + col_off(jj, k, ld)] * sv;
         }
     }
-    if (K > 0) multi_block_partial<M>(acc, j, B.partials);
+    if constexpr (K > 0) {
+        __shared__ double tot[MULTI_W * M];
+        if (!multi_complete<M>(acc, j, B, tot)) return;
+        if (fin)
+            for (int t = threadIdx.x; t < B.nr * k; t += blockDim.x) {
+                const int sy = t / k, q = t % k;
+                if (!B.state[sy].done) B.state[sy].gamma[q] = tot[sy * M + q];
+            }
+    }
 }
 
 template <int K>
-__global__ __launch_bounds__(BLOCK) void k_mspmv1_fin(MultiBufs B, int nb) {
-    constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
-    const int j = blockIdx.x;
-    if (j >= B.nr || B.state[j].done) return;
-    reduce_partials<M>(B.partials + (int64_t)j * M * MAX_GRID, nb, M, tot);
-    if (threadIdx.x < B.k) B.state[j].gamma[threadIdx.x] = tot[threadIdx.x];
-}
-
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B) {
+__global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B, int fin) {
     constexpr int KM = K > 0 ? K : 1;
     if (!multi_active_any(B)) return;
-    // the system index is uniform over a wave: keep it (and the scalars read
-    // with it) in scalar registers, which leaves the vector registers to the
-    // loads in flight
     const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
     const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
@@ -1309,15 +1360,10 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B) {
             acc[4] += sv * sv;
         }
     }
-    multi_block_partial<5>(acc, j, B.partials);
-}
-
-__global__ __launch_bounds__(BLOCK) void k_mspmv2_fin(MultiBufs B, int nb) {
-    __shared__ double tot[5];
-    const int j = blockIdx.x;
-    if (j >= B.nr || B.state[j].done) return;
-    reduce_partials<5>(B.partials + (int64_t)j * 5 * MAX_GRID, nb, 5, tot);
-    if (threadIdx.x == 0) spmv2_fin_scalars(&B.state[j], tot, B.k);
+    __shared__ double tot[MULTI_W * 5];
+    if (!multi_complete<5>(acc, j, B, tot)) return;
+    if (fin && threadIdx.x < B.nr && !B.state[threadIdx.x].done)
+        spmv2_fin_scalars(&B.state[threadIdx.x], tot + threadIdx.x * 5, B.k);
 }
 
 // ---------------------------------------------------------------- iterative refinement support
@@ -1438,7 +1484,7 @@ __global__ __launch_bounds__(BLOCK) void k_bpro1(BicgBufs B, int xnz) {
 
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bpro1_fin(BicgBufs B, int nb, double rtol, int max_it,
-                                                     int store_cap) {
+                                                     int store_cap, int stop_both) {
     constexpr int M = 2 * K + 1;
     __shared__ double tot[M];
     const int k = B.k;
@@ -1448,6 +1494,8 @@ __global__ __launch_bounds__(BLOCK) void k_bpro1_fin(BicgBufs B, int nb, double 
         const double b2 = tot[0];
         st->bnorm2 = b2;
         st->tol2 = rtol * rtol * b2;
+        // dual right-hand side = ones: ||bt||^2 = n
+        st->tol2_dual = stop_both ? rtol * rtol * (double)B.n : __builtin_huge_val();
         st->done = 0;
         st->status = S_MAXIT;
         st->iters_done = 0;
@@ -1470,7 +1518,7 @@ __global__ __launch_bounds__(BLOCK) void k_bpro1_fin(BicgBufs B, int nb, double 
 // BP2: eq. (minusXR) for the primary and the dual system
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
-    constexpr int M = 2;
+    constexpr int M = 3;
     BicgState* st = B.state;
     if (st->done) return;
     const int k = B.k;
@@ -1482,7 +1530,7 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
     }
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
-    double acc[M] = {0.0, 0.0};
+    double acc[M] = {0.0, 0.0, 0.0};
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         double xv = xnz ? B.xout[row] : 0.0;
         double rv = B.r[row];
@@ -1504,12 +1552,13 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2(BicgBufs B, int xnz) {
         B.z[row] = 0.0;
         acc[0] += rv * rv;
         acc[1] += rtv * rv;
+        acc[2] += rtv * rtv;
     }
     block_partial<M>(acc, M, B.partials);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
-    constexpr int M = 2;
+    constexpr int M = 3;
     __shared__ double tot[M];
     BicgState* st = B.state;
     if (st->done) return;
@@ -1522,10 +1571,11 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
         st->stored = 0;
         st->rr = tot[0];
         st->rho = tot[1];
-        if (!finite(tot[0]) || !finite(tot[1])) {
+        st->rtrt = tot[2];
+        if (!finite(tot[0]) || !finite(tot[1]) || !finite(tot[2])) {
             st->done = 1;
             st->status = S_NONFINITE;
-        } else if (tot[0] <= st->tol2) {
+        } else if (tot[0] <= st->tol2 && tot[2] <= st->tol2_dual) {
             st->done = 1;
             st->status = S_OK;
         } else if (tot[1] == 0.0) {
@@ -1542,10 +1592,10 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
 // q = A p - C zeta, qt = A^T pt - Ct zetat come out of the SpMV pass directly.
 //
 // BQ1: r -= alpha q; rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt;
-//      store r, rt into the cycle store; sums ||r||^2, (rt, r), Gh^T p, GhT^T pt
+//      store r, rt into the cycle store; sums ||r||^2, (rt, r), ||rt||^2, Gh^T p, GhT^T pt
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
-    constexpr int M = 2 + 2 * K;
+    constexpr int M = 3 + 2 * K;
     BicgState* st = B.state;
     if (st->done) return;
     const double alpha = st->alpha, beta = st->beta;
@@ -1567,13 +1617,14 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
         const double xv = B.x[row] + alpha * pv;
         acc[0] += rv * rv;
         acc[1] += rtv * rv;
+        acc[2] += rtv * rtv;
         // the block-column loads come before this row's stores, so that the
         // compiler can issue them together (no store they might alias in between)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t o = row + col_off(j, k, B.ld);
-            acc[2 + j] += B.Gh[o] * pn;
-            acc[2 + K + j] += B.GhT[o] * ptn;
+            acc[3 + j] += B.Gh[o] * pn;
+            acc[3 + K + j] += B.GhT[o] * ptn;
         }
         B.x[row] = xv;
         B.r[row] = rv;
@@ -1585,32 +1636,26 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
             wtcol[row] = rtv;
         }
     }
-    block_partial<M>(acc, M, B.partials);
-}
-
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_bupdate_fin(BicgBufs B, int nb) {
-    constexpr int M = 2 + 2 * K;
     __shared__ double tot[M];
-    BicgState* st = B.state;
-    if (st->done) return;
-    const int k = B.k;
-    reduce_partials<M>(B.partials, nb, M, tot);
+    if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
     if (threadIdx.x < k) {
-        st->zeta[threadIdx.x] = tot[2 + threadIdx.x];
-        st->zetat[threadIdx.x] = tot[2 + K + threadIdx.x];
+        st->zeta[threadIdx.x] = tot[3 + threadIdx.x];
+        st->zetat[threadIdx.x] = tot[3 + K + threadIdx.x];
     }
     if (threadIdx.x == 0) {
         const int i = st->iter;
         const int slot = st->stored;
         const bool store = slot < st->store_cap;
-        const double rr = tot[0], rho = tot[1];
+        const double rr = tot[0], rho = tot[1], rtrt = tot[2];
         st->rr = rr;
-        if (!finite(rr) || !finite(rho)) {
+        st->rtrt = rtrt;
+        // Section 3: RBiCG stops when both the primary and the dual residual meet
+        // the tolerance (tol2_dual is +inf when only the primary one is asked for)
+        if (!finite(rr) || !finite(rho) || !finite(rtrt)) {
             st->done = 1;
             st->status = S_NONFINITE;
             st->iters_done = i - 1;
-        } else if (rr <= st->tol2) {
+        } else if (rr <= st->tol2 && rtrt <= st->tol2_dual) {
             st->done = 1;
             st->status = S_OK;
             st->iters_done = i - 1;
@@ -1664,16 +1709,8 @@ __global__ __launch_bounds__(BLOCK) void k_bspmvq(BicgBufs B) {
         acc[2] += qtv * rv;
         acc[3] += qtv * qv;
     }
-    block_partial<M>(acc, M, B.partials);
-}
-
-__global__ __launch_bounds__(BLOCK) void k_bproj_fin(BicgBufs B, int nb) {
-    constexpr int M = 4;
     __shared__ double tot[M];
-    BicgState* st = B.state;
-    if (st->done) return;
-    const int k = B.k;
-    reduce_partials<M>(B.partials, nb, M, tot);
+    if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
     if (threadIdx.x == 0) {
         const double den = tot[0];
         if (den == 0.0 || !finite(den)) {
@@ -1769,16 +1806,13 @@ RBS_LAUNCHER_T(L_pro1_fin, k_pro1_fin, true)
 RBS_LAUNCHER_T(L_pro2, k_pro2, false)
 RBS_LAUNCHER_T(L_pro2_fin, k_pro2_fin, true)
 RBS_LAUNCHER_T(L_update, k_update, false)
-RBS_LAUNCHER_T(L_update_fin, k_update_fin, true)
 RBS_LAUNCHER_T(L_spmv1, k_spmv1, false)
-RBS_LAUNCHER_T(L_spmv1_fin, k_spmv1_fin, true)
 RBS_LAUNCHER_T(L_spmv2, k_spmv2, false)
 RBS_LAUNCHER_T(L_epi, k_epi, false)
 RBS_LAUNCHER(L_bpro1, k_bpro1, BicgBufs, false)
 RBS_LAUNCHER(L_bpro1_fin, k_bpro1_fin, BicgBufs, true)
 RBS_LAUNCHER(L_bpro2, k_bpro2, BicgBufs, false)
 RBS_LAUNCHER(L_bupdate, k_bupdate, BicgBufs, false)
-RBS_LAUNCHER(L_bupdate_fin, k_bupdate_fin, BicgBufs, true)
 RBS_LAUNCHER(L_bspmvq, k_bspmvq, BicgBufs, false)
 RBS_LAUNCHER(L_bepi, k_bepi, BicgBufs, false)
 
@@ -1941,12 +1975,9 @@ template <typename T>
 void launch_solve_iterations(hipStream_t st, const SolveBufsT<T>& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
-        dispatch_k<L_update>(B.k, st, g, B);
-        dispatch_k<L_update_fin>(B.k, st, g, B, g);
-        dispatch_k<L_spmv1>(B.k, st, g, B);
-        if (B.k > 0) dispatch_k<L_spmv1_fin>(B.k, st, g, B, g);
-        dispatch_k<L_spmv2>(B.k, st, g, B);
-        hipLaunchKernelGGL(k_spmv2_fin<T>, dim3(1), dim3(BLOCK), 0, st, B, g);
+        dispatch_k<L_update>(B.k, st, g, B, 1);
+        dispatch_k<L_spmv1>(B.k, st, g, B, 1);
+        dispatch_k<L_spmv2>(B.k, st, g, B, 1);
     }
 }
 
@@ -1957,9 +1988,9 @@ void launch_time_prep(hipStream_t st, SolveState* state, int count) {
 template <typename T>
 void launch_pass(hipStream_t st, const SolveBufsT<T>& B, int which) {
     const int g = stream_grid(B.n);
-    if (which == 0) dispatch_k<L_update>(B.k, st, g, B);
-    else if (which == 1) dispatch_k<L_spmv1>(B.k, st, g, B);
-    else if (which == 2) dispatch_k<L_spmv2>(B.k, st, g, B);
+    if (which == 0) dispatch_k<L_update>(B.k, st, g, B, 0);
+    else if (which == 1) dispatch_k<L_spmv1>(B.k, st, g, B, 0);
+    else if (which == 2) dispatch_k<L_spmv2>(B.k, st, g, B, 0);
     else launch_spmv(st, B.A, B.p, B.q);
 }
 
@@ -1979,28 +2010,31 @@ int multi_width(int nr, int k) {
     return (nr >= 1 && nr <= MULTI_W && k >= 0 && k <= KMAX) ? MULTI_W : 0;
 }
 
-RBS_LAUNCHER(L_mupdate, k_mupdate, MultiBufs, false)
-RBS_LAUNCHER(L_mupdate_fin, k_mupdate_fin, MultiBufs, false)
-RBS_LAUNCHER(L_mspmv1, k_mspmv1, MultiBufs, false)
-RBS_LAUNCHER(L_mspmv1_fin, k_mspmv1_fin, MultiBufs, false)
-RBS_LAUNCHER(L_mspmv2, k_mspmv2, MultiBufs, false)
+// multi-RHS launches: one wave per system
+#define RBS_LAUNCHER_M(NAME, KERNEL)                                                        \
+    template <int K>                                                                         \
+    struct NAME {                                                                            \
+        static void run(hipStream_t st, int grid, const MultiBufs& B, int fin) {              \
+            hipLaunchKernelGGL(KERNEL<K>, dim3(grid), dim3(WAVE * B.nr), 0, st, B, fin);      \
+        }                                                                                    \
+    };
+RBS_LAUNCHER_M(L_mupdate, k_mupdate)
+RBS_LAUNCHER_M(L_mspmv1, k_mspmv1)
+RBS_LAUNCHER_M(L_mspmv2, k_mspmv2)
 
 void launch_multi_pass(hipStream_t st, const MultiBufs& B, int which) {
     const int g = stream_grid(B.n);
-    if (which == 0) dispatch_k<L_mupdate>(B.k, st, g, B);
-    else if (which == 1) dispatch_k<L_mspmv1>(B.k, st, g, B);
-    else dispatch_k<L_mspmv2>(B.k, st, g, B);
+    if (which == 0) dispatch_k<L_mupdate>(B.k, st, g, B, 0);
+    else if (which == 1) dispatch_k<L_mspmv1>(B.k, st, g, B, 0);
+    else dispatch_k<L_mspmv2>(B.k, st, g, B, 0);
 }
 
 void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
-        dispatch_k<L_mupdate>(B.k, st, g, B);
-        dispatch_k<L_mupdate_fin>(B.k, st, MULTI_W, B, g);
-        dispatch_k<L_mspmv1>(B.k, st, g, B);
-        if (B.k > 0) dispatch_k<L_mspmv1_fin>(B.k, st, MULTI_W, B, g);
-        dispatch_k<L_mspmv2>(B.k, st, g, B);
-        hipLaunchKernelGGL(k_mspmv2_fin, dim3(MULTI_W), dim3(BLOCK), 0, st, B, g);
+        dispatch_k<L_mupdate>(B.k, st, g, B, 1);
+        dispatch_k<L_mspmv1>(B.k, st, g, B, 1);
+        dispatch_k<L_mspmv2>(B.k, st, g, B, 1);
     }
 }
 
@@ -2008,18 +2042,15 @@ template <int K>
 struct BatchLaunch {
     static void iter(hipStream_t st, const BatchBufs& B, int grid, int count) {
         for (int it = 0; it < count; ++it) {
-            hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B);
-            hipLaunchKernelGGL(k_batch_update_fin<K>, dim3(B.nsys), dim3(BLOCK), 0, st, B);
-            hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B);
-            if (K > 0) hipLaunchKernelGGL(k_batch_spmv1_fin<K>, dim3(B.nsys), dim3(BLOCK), 0, st, B);
-            hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B);
-            hipLaunchKernelGGL(k_batch_spmv2_fin, dim3(B.nsys), dim3(BLOCK), 0, st, B);
+            hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B, 1);
+            hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B, 1);
+            hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B, 1);
         }
     }
     static void pass(hipStream_t st, const BatchBufs& B, int grid, int which) {
-        if (which == 0) hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B);
-        else if (which == 1) hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B);
-        else hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B);
+        if (which == 0) hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B, 0);
+        else if (which == 1) hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B, 0);
+        else hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B, 0);
     }
 };
 
@@ -2087,10 +2118,11 @@ void launch_shifted_values(hipStream_t st, int64_t n, int64_t nnz, const double*
                            perm_t, val, valT);
 }
 
-void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap) {
+void launch_bicg_prologue(hipStream_t st, const BicgBufs& B, double rtol, int max_it, int store_cap,
+                          int stop_both) {
     const int g = stream_grid(B.n);
     dispatch_k<L_bpro1>(B.k, st, g, B, 0);
-    dispatch_k<L_bpro1_fin>(B.k, st, g, B, g, rtol, max_it, store_cap);
+    dispatch_k<L_bpro1_fin>(B.k, st, g, B, g, rtol, max_it, store_cap, stop_both);
     dispatch_k<L_bpro2>(B.k, st, g, B, 0);
     hipLaunchKernelGGL(k_bpro2_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
 }
@@ -2099,9 +2131,7 @@ void launch_bicg_iterations(hipStream_t st, const BicgBufs& B, int count) {
     const int g = stream_grid(B.n);
     for (int it = 0; it < count; ++it) {
         dispatch_k<L_bupdate>(B.k, st, g, B);
-        dispatch_k<L_bupdate_fin>(B.k, st, g, B, g);
         dispatch_k<L_bspmvq>(B.k, st, g, B);
-        hipLaunchKernelGGL(k_bproj_fin, dim3(1), dim3(BLOCK), 0, st, B, g);
     }
 }
 

@@ -35,6 +35,7 @@ RBS_BICGSTAB = 1
 RBS_RBICG_GEN = 2
 RBS_TRANSPOSE = 8
 RBS_FP32_IR = 16
+RBS_STOP_PRIMARY = 32
 
 RBS_RECYCLE_SET = 0
 RBS_RECYCLE_FROM_LAST_SOLVE = 1
@@ -283,11 +284,14 @@ class Context:
         return self
 
     def solve(self, b, x=None, x_nonzero=False, shadow=None, rtol=1e-8, max_it=10000,
-              mode: str = "rbicgstab", transpose: bool = False, precision: str = "fp64"):
-        """precision: "fp64", or "fp32_ir" (FP32 storage under FP64 iterative refinement)."""
+              mode: str = "rbicgstab", transpose: bool = False, precision: str = "fp64",
+              stop: str = "both"):
+        """precision: "fp64", or "fp32_ir" (FP32 storage under FP64 iterative refinement).
+        stop (mode "rbicg"): "both" residuals (the default), or "primary" alone."""
         flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB,
                  "rbicg": RBS_RBICG_GEN}[mode] | (RBS_TRANSPOSE if transpose else 0)
         flags |= {"fp64": 0, "fp32_ir": RBS_FP32_IR}[precision]
+        flags |= {"both": 0, "primary": RBS_STOP_PRIMARY}[stop] if mode == "rbicg" else 0
         if x is None:
             x = torch.zeros_like(b)
         st = rbicgstab_solve(self.handle, b, x, x_nonzero, shadow, rtol, max_it, flags)

@@ -64,11 +64,12 @@ class GpuSequence:
 
     def run(self, mode: str = "rbicgstab", rtol: float = 1e-8, max_it: int = 20000,
             systems: Optional[int] = None, precision: str = "fp64",
-            multi_rhs: bool = False) -> GpuSequenceResult:
+            multi_rhs: bool = False, rbicg_stop: str = "both") -> GpuSequenceResult:
         """precision applies to the RBiCGSTAB / BiCGSTAB solves ("fp64" or
         "fp32_ir"); RBiCG and the recycle-space update always run in FP64.
         multi_rhs: the RBiCGSTAB right-hand sides of each matrix (all of them
-        for BiCGSTAB) are solved together by rbicgstab_solve_multi (FP64)."""
+        for BiCGSTAB) are solved together by rbicgstab_solve_multi (FP64).
+        rbicg_stop: RBiCG's stopping rule, "both" residuals or "primary" alone."""
         seq, ctx = self.seq, self.ctx
         out = GpuSequenceResult()
         last = seq.num_systems if systems is None else min(systems, seq.num_systems)
@@ -104,7 +105,8 @@ class GpuSequence:
                                   precision=precision)
                 solver = "bicgstab"
             elif gen:
-                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicg")
+                _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicg",
+                                  stop=rbicg_stop)
                 ctx.recycle("from_last_solve")
                 ma, mat = ctx.setup_matvecs()
                 out.setup_matvecs += ma + mat
