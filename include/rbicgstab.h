@@ -230,6 +230,28 @@ int rbicgstab_adjoint_grads(rbs_ctx* ctx, int64_t nnz, const int32_t* rowptr,
                             const double* mdiag, double* grad_val, double* grad_sigma);
 
 /*
+ * rbicgstab_adjoint_grads without allocation and without a context, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same gradients and
+ * arguments as rbicgstab_adjoint_grads (n rows, CSR pattern rowptr / colidx,
+ * lambda, x, mdiag, grad_val all device), except that grad_sigma is a DEVICE
+ * pointer to one double (written -sum_i lambda_i m_i x_i, or 0 if mdiag is
+ * NULL) and the work is enqueued on `stream` without waiting for it.
+ * The block partial sums live in a file-scope device array of 1024 doubles
+ * (8 KiB, one copy per GPU, held until the process ends) that serves every
+ * n, since the streaming grid never has more than 1024 workgroups; n must be
+ * below 2^31.  Calls that overlap on one GPU (other streams, other host
+ * threads) share that array and race; serialise them.  Nothing is allocated:
+ * the array's device address is looked up once per device on the first call.
+ * Errors: RBS_ERR_ARG for bad sizes or NULL pointers, RBS_ERR_HIP for a
+ * failed lookup or launch (rbicgstab_last_error(NULL) describes them).
+ */
+int rbicgstab_adjoint_grads_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr,
+                                    const int32_t* colidx, const double* lambda, const double* x,
+                                    const double* mdiag, double* grad_val, double* grad_sigma,
+                                    hipStream_t stream);
+
+/*
  * Values of A(sigma) = K + sigma M on a fixed pattern (Section 6.1's
  * parametrised family): val = kval, then val[diag_pos[i]] += sigma mdiag[i].
  * With perm_t non-NULL also valT[e] = val[perm_t[e]] (the values of A^T in

@@ -1598,6 +1598,20 @@ int rbicgstab_adjoint_grads(rbs_ctx* c, int64_t nnz, const int32_t* rowptr, cons
     return RBS_OK;
 }
 
+int rbicgstab_adjoint_grads_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                                    const double* lambda, const double* x, const double* mdiag,
+                                    double* grad_val, double* grad_sigma, hipStream_t stream) {
+    if (n < 1 || n >= (int64_t(1) << 31) || nnz < 0 || !rowptr || !colidx || !grad_val || !lambda || !x ||
+        !grad_sigma)
+        return fail(nullptr, RBS_ERR_ARG,
+                    "1 <= n < 2^31, nnz >= 0; rowptr, colidx, lambda, x, grad_val and grad_sigma are "
+                    "required (grad_sigma is a device pointer)");
+    const hipError_t e = rbs::launch_adjoint_grads_noalloc(stream, n, rowptr, colidx, lambda, x, mdiag,
+                                                           grad_val, grad_sigma);
+    if (e != hipSuccess) return fail(nullptr, RBS_ERR_HIP, hipGetErrorString(e));
+    return RBS_OK;
+}
+
 int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const int64_t* diag_pos,
                              const double* mdiag, double sigma, const int64_t* perm_t, double* val,
                              double* valT, hipStream_t stream) {

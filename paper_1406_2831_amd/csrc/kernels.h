@@ -175,6 +175,14 @@ void launch_true_residual(hipStream_t st, const Sell& A, const double* b, const 
 void launch_adjoint_grads(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colidx,
                           const double* lam, const double* x, const double* mdiag, double* grad,
                           double* partials, double* out_sigma);
+// The same gradients with the block partials in a file-scope device array
+// instead of a context's workspace (no allocation, no context): *out_sigma is
+// a device pointer.  Returns the first HIP error of the symbol lookup or launch.
+hipError_t launch_adjoint_grads_noalloc(hipStream_t st, int64_t n, const int32_t* rowptr,
+                                        const int32_t* colidx, const double* lam, const double* x,
+                                        const double* mdiag, double* grad, double* out_sigma);
+// doubles of that device array (the block partials of the largest streaming grid)
+size_t noalloc_scratch_doubles();
 // val = kval with sigma * mdiag added on the diagonal entries; valT[e] = val[perm_t[e]].
 void launch_shifted_values(hipStream_t st, int64_t n, int64_t nnz, const double* kval,
                            const int64_t* diag_pos, const double* mdiag, double sigma,

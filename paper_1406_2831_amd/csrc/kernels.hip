@@ -21,6 +21,9 @@
 // sliced-ELL matrix copy whose slices are exactly one wavefront tall.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -2095,6 +2098,56 @@ void launch_residual(hipStream_t st, const Sell& A, const double* b, const doubl
     const int g = stream_grid(A.n);
     hipLaunchKernelGGL(k_residual, dim3(g), dim3(BLOCK), 0, st, A, b, x, r, partials);
     hipLaunchKernelGGL(k_true_res_fin, dim3(1), dim3(BLOCK), 0, st, partials, g, out_sums);
+}
+
+// ---------------------------------------------------------------- no-allocation adjoint gradients
+// Scratch of the no-allocation gradient call: one partial per workgroup of
+// the streaming grid (at most MAX_GRID), whatever n is.  One copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; its device address comes from hipGetSymbolAddress, looked up
+// once per device with that device current.
+static __device__ __align__(256) double scratch[MAX_GRID];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::atomic<double*> g_scratch_ptr[MAX_DEVICES];
+std::mutex g_scratch_mutex;
+}  // namespace
+
+hipError_t noalloc_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    double* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            void* addr = nullptr;
+            e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            p = static_cast<double*>(addr);
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return hipSuccess;
+}
+
+size_t noalloc_scratch_doubles() { return (size_t)MAX_GRID; }
+
+hipError_t launch_adjoint_grads_noalloc(hipStream_t st, int64_t n, const int32_t* rowptr,
+                                        const int32_t* colidx, const double* lam, const double* x,
+                                        const double* mdiag, double* grad, double* out_sigma) {
+    double* part = nullptr;
+    hipError_t e = noalloc_scratch(&part);
+    if (e != hipSuccess) return e;
+    const int g = stream_grid(n);   // <= MAX_GRID partials: the scratch always holds them
+    hipLaunchKernelGGL(k_adjoint_grads, dim3(g), dim3(BLOCK), 0, st, n, rowptr, colidx, lam, x, mdiag,
+                       grad, part);
+    hipLaunchKernelGGL(k_adjoint_grads_fin, dim3(1), dim3(BLOCK), 0, st, part, g, out_sigma);
+    return hipGetLastError();
 }
 
 void launch_adjoint_grads(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colidx,

@@ -46,7 +46,7 @@ EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "r
            "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_solve_multi",
            "rbicgstab_destroy", "rbicgstab_last_error", "rbicgstab_batch_workspace_bytes",
            "rbicgstab_batch_create", "rbicgstab_batch_solve", "rbicgstab_batch_config",
-           "rbicgstab_batch_destroy", "rbicgstab_batch_last_error")
+           "rbicgstab_batch_destroy", "rbicgstab_batch_last_error", "rbicgstab_adjoint_grads_noalloc")
 RBS_BATCH_TUNE = 1
 RBS_BATCH_GRAPH = 2
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.rbicgstab_time_pass.restype = ctypes.c_int
     lib.rbicgstab_adjoint_grads.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(f64)]
     lib.rbicgstab_adjoint_grads.restype = ctypes.c_int
+    lib.rbicgstab_adjoint_grads_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rbicgstab_adjoint_grads_noalloc.restype = ctypes.c_int
     lib.rbicgstab_shifted_values.argtypes = [i64, i64, vp, vp, vp, f64, vp, vp, vp, vp]
     lib.rbicgstab_shifted_values.restype = ctypes.c_int
     lib.rbicgstab_setup_matvecs.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -222,6 +224,17 @@ def rbicgstab_adjoint_grads(handle, rowptr: torch.Tensor, colidx: torch.Tensor, 
                                                     _ptr(lam), _ptr(x), _ptr(mdiag), _ptr(grad_val),
                                                     ctypes.byref(gs)))
     return gs.value
+
+
+def rbicgstab_adjoint_grads_noalloc(rowptr: torch.Tensor, colidx: torch.Tensor, lam: torch.Tensor,
+                                    x: torch.Tensor, mdiag: Optional[torch.Tensor], grad_val: torch.Tensor,
+                                    grad_sigma: torch.Tensor, stream=None) -> None:
+    """The same gradients without a context or any allocation: grad_val (nnz) and
+    grad_sigma (one double) are device tensors; the work is enqueued on `stream`."""
+    lib = load_library()
+    _check(lib, None, lib.rbicgstab_adjoint_grads_noalloc(lam.numel(), colidx.numel(), _ptr(rowptr),
+                                                          _ptr(colidx), _ptr(lam), _ptr(x), _ptr(mdiag),
+                                                          _ptr(grad_val), _ptr(grad_sigma), _stream(stream)))
 
 
 def rbicgstab_shifted_values(kval: torch.Tensor, diag_pos: torch.Tensor, mdiag: torch.Tensor,
