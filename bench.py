@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 K_BUCKETS = (0, 4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64)
 
 
@@ -320,6 +321,49 @@ def large_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def study_workload(args):
+    """Choices of the recycle-space generation, measured on the sequence (GPU,
+    multi-RHS RBiCGSTAB pipeline, one warm-up and one timed run per setting):
+    the RBiCG cycle length s_max (the Ritz step runs every s_max stored vectors;
+    Section 6.2 uses 25), the oblique-projector cap secant_max, and RBiCG's
+    stopping rule (both residuals, as in Section 3, or the primary alone).
+    Reports iterations, recycle dimensions, products and time per setting."""
+    import torch
+    import workloads as w
+    from paper_1406_2831_amd.sequence import GpuSequence
+
+    seq = w.seq_3d(N=args.grid, k=args.k)
+    nsys = seq.num_systems
+    settings = [("bicgstab", 512, 0.0, "both", "bicgstab")]
+    settings += [(f"s_max={s_}", s_, 0.0, "both", "rbicgstab") for s_ in (25, 50, 128, 256, 512)]
+    settings += [(f"secant_max={c_:g}", 512, c_, "both", "rbicgstab") for c_ in (10.0, 1e3, 1e4, float("inf"))]
+    settings += [("stop=primary", 512, 0.0, "primary", "rbicgstab")]
+    rows = {}
+    for name, s_max, cap, stop, mode in settings:
+        gs = GpuSequence(seq, s_max=s_max, secant_max=cap, keep_x=False)
+        r = None
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = gs.run(mode=mode, rtol=args.rtol, multi_rhs=True, rbicg_stop=stop)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        gen = [sv == "rbicg" for sv in r.solver]
+        rows[name] = {"systems_per_s": nsys / dt, "ms": dt * 1e3, "iters": r.iters, "k_used": r.k_used,
+                      "matvecs": r.total_matvecs, "status": r.status,
+                      "rbicgstab_iters": sum(i for i, g in zip(r.iters, gen) if not g),
+                      "rbicg_iters": sum(i for i, g in zip(r.iters, gen) if g),
+                      "ritz_ms": sum(r.ritz_ms), "ritz_m": r.ritz_m,
+                      "converged": all(st == 0 for st in r.status) and max(r.rel_res_true) <= args.rtol}
+        gs.close()
+        del gs
+        torch.cuda.empty_cache()
+        print(f"[study] {name}: {rows[name]['systems_per_s']:.1f} systems/s, "
+              f"rbicgstab iters {rows[name]['rbicgstab_iters']}, k {r.k_used}", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": f"recycle-space choices, 3d 7-point {args.grid}^3, 5 shifts x 4 rhs, "
+                                  f"k={args.k}, rtol={args.rtol}", "settings": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,15 +377,21 @@ def main():
     ap.add_argument("--time-reps", type=int, default=100)
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of the known-size copy used to calibrate HBM counters (0: skip)")
+    ap.add_argument("--s-max", type=int, default=512,
+                    help="Lanczos vectors stored per RBiCG cycle (the Ritz step runs every s_max vectors)")
+    ap.add_argument("--no-hbm128", action="store_true",
+                    help="skip the fused-pass timing at 128^3 (HBM-resident working set)")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the FP32-storage / FP64-refinement runs (reported beside the FP64 line)")
     ap.add_argument("--secant-max", type=float, default=0.0,
                     help="oblique-projector cap of the recycle setup (0: library default)")
-    ap.add_argument("--workload", choices=("sequence", "adjoint", "batched", "large"), default="sequence",
+    ap.add_argument("--workload", choices=("sequence", "adjoint", "batched", "large", "study"),
+                    default="sequence",
                     help="sequence: the shifted 64^3 sequence (default); adjoint: gradients of "
                          "c^T x on the 128^3 problem through the transposed recycled solve; "
                          "batched: 32 shifted systems of uneven size solved together; large: the "
-                         "27-point 160^3 sequence with FP32 storage under FP64 refinement")
+                         "27-point 160^3 sequence with FP32 storage under FP64 refinement; study: "
+                         "cycle length, projector cap and RBiCG stopping rule on the sequence")
     ap.add_argument("--large-shifts", type=int, default=2,
                     help="large workload: shifts of the 10-shift sequence run (a stated subset)")
     ap.add_argument("--batch-count", type=int, default=32)
@@ -359,14 +409,18 @@ def main():
         return batched_workload(args)
     if args.workload == "large":
         return large_workload(args)
+    if args.workload == "study":
+        return study_workload(args)
 
+    import numpy as np
     import torch
     import workloads as w
     from paper_1406_2831_amd.sequence import GpuSequence
 
     seq = w.seq_3d(N=args.grid, k=args.k)
-    gs = GpuSequence(seq, s_max=512, secant_max=args.secant_max)
+    gs = GpuSequence(seq, s_max=args.s_max, secant_max=args.secant_max)
     nsys = seq.num_systems
+    n, nnz = seq.n, int(seq.K.nnz)
 
     def run(mode, precision="fp64", multi=False):
         return gs.run(mode=mode, rtol=args.rtol, precision=precision, multi_rhs=multi)
@@ -381,7 +435,7 @@ def main():
     for _ in range(args.warmup):
         for _key, mode, prec, multi in variants:
             run(mode, prec, multi)
-    timed, results, passes = {}, {}, {}
+    timed, results = {}, {}
     x64 = None
     for key, mode, prec, multi in variants:
         torch.cuda.synchronize()
@@ -399,9 +453,61 @@ def main():
         if key == "rbicgstab":
             x64 = [x.clone() for x in res.x]
         elif prec == "fp32_ir":
-            # error of each FP32-storage result against the FP64 pipeline's
+            # error of each FP32-storage result against the FP64 pipeline's; the
+            # RBiCG systems run in FP64 in both pipelines and are left out
             res.err_vs_fp64 = [float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
-                               for x, xr in zip(res.x, x64)]
+                               for x, xr, sv in zip(res.x, x64, res.solver) if sv != "rbicg"]
+    rres = results["rbicgstab"]
+
+    # parity at the benchmark's tolerance on a sampled system: the second system
+    # (first RBiCGSTAB solve) of each pipeline against the oracle's BiCGSTAB at
+    # rtol 1e-12 on the host; bound kappa * rtol with kappa ~ 4 / (pi h)^2
+    sample = 1
+    A0, _ = seq.matrix(seq.system(sample)[0])
+    kappa = 4.0 / (np.pi / (args.grid + 1)) ** 2
+    parity = {"system": sample, "bound": kappa * args.rtol, "kappa": kappa}
+    if not args.no_cpu_baseline:
+        import oracle as o
+        xo, io = o.bicgstab(A0.to_scipy(), seq.rhs[sample], shadow=seq.shadows[sample], rtol=1e-12)
+        for key in results:
+            xg = results[key].x[sample].cpu().numpy()
+            parity[key] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        parity["within_bound"] = all(v <= parity["bound"] for k_, v in parity.items() if k_ in results)
+
+    # where the headline pipeline's time and products go (last timed step)
+    is_gen = [sv == "rbicg" for sv in rres.solver]
+    ritz_ms = sum(rres.ritz_ms)
+    phases = {
+        "setup_and_install_ms": rres.setup_ms,
+        "rbicg_ms": sum(ms for ms, g in zip(rres.ms, is_gen) if g) - ritz_ms,
+        "ritz_ms": ritz_ms,
+        "rbicgstab_ms": sum(ms for ms, g in zip(rres.ms, is_gen) if not g),
+        "ritz_m": rres.ritz_m,
+        "matvecs_setup": rres.setup_matvecs,
+        "matvecs_rbicg_and_ritz": sum(mv for mv, g in zip(rres.matvecs, is_gen) if g),
+        "matvecs_rbicgstab": sum(mv for mv, g in zip(rres.matvecs, is_gen) if not g),
+        "note": "rbicg_ms excludes the Ritz steps, which run inside the RBiCG solve calls",
+    }
+
+    # end-to-end time per iteration against the byte model (one system at a time):
+    # B_0 = 2 (12 nnz + 4 (n+1) + 16 n) + 128 n per BiCGSTAB iteration,
+    # B_R(k) = B_0 + 16 n + 32 n k per RBiCGSTAB iteration (projections and x_c)
+    spmv_b = 12 * nnz + 4 * (n + 1) + 16 * n
+    B0 = 2 * spmv_b + 128 * n
+    BR = lambda kk: 2 * spmv_b + 144 * n + 32 * n * kk
+    r1, b1 = results["rbicgstab_single"], results["bicgstab_single"]
+    it_b = sum(b1.iters)
+    us_b = sum(b1.ms) * 1e3 / it_b
+    stab = [(ms, it, kk) for ms, it, kk, sv in zip(r1.ms, r1.iters, r1.k_used, r1.solver) if sv == "rbicgstab"]
+    it_r = sum(it for _, it, _ in stab)
+    us_r = sum(ms for ms, _, _ in stab) * 1e3 / it_r
+    br_avg = sum(BR(kk) * it for _, it, kk in stab) / it_r
+    per_iter = {
+        "bicgstab_us": us_b, "bicgstab_bytes": B0, "bicgstab_frac": B0 / (us_b * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "rbicgstab_us": us_r, "rbicgstab_bytes": br_avg,
+        "rbicgstab_frac": br_avg / (us_r * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "note": "host wall time of the solve calls / iterations (prologue, true residual and polling included)",
+    }
 
     # live per-kernel timing of the fused passes (outside the timed steps) with the
     # space the first matrix's RBiCG solve generates: the multi-RHS passes for that
@@ -411,6 +517,8 @@ def main():
     gs.run(mode="rbicgstab", rtol=args.rtol, systems=1)
     k_last = int(gs.ctx.blocks()[1])
     nr = seq.nrhs - 1
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
+    passes = {}
     for name, which, kk in (("mspmv1_project", 8 + 4 * (nr - 1) + 1, k_last),
                             ("mupdate", 8 + 4 * (nr - 1), k_last),
                             ("mspmv2_project", 8 + 4 * (nr - 1) + 2, k_last),
@@ -418,15 +526,26 @@ def main():
                             ("spmv2_project", 2, k_last), ("spmv", 3, 0),
                             ("spmv1_project_fp32", 5, k_last), ("update_fp32", 4, k_last),
                             ("spmv2_project_fp32", 6, k_last), ("spmv_fp32", 7, 0)):
-        passes[name] = gs.ctx.time_pass(which, kk, args.time_reps)
-    rres = results["rbicgstab"]
-    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
-    ms_dom, bytes_dom = passes["mspmv1_project"]
-    ms_spmv, bytes_spmv = passes["spmv"]
-    achieved = gbs(bytes_dom, ms_dom)
-    kb = k_bucket(k_last)
-    dom_kernel = f"k_mspmv1<{kb}>"
-    traffic = counter_traffic(dom_kernel)
+        ms, by = gs.ctx.time_pass(which, kk, args.time_reps)
+        passes[name] = {"us": ms * 1e3, "gbs": gbs(by, ms), "frac": gbs(by, ms) / HBM_PEAK_GBS}
+
+    # the kernel with the largest share of device time in the timed pipeline is the
+    # Ritz step's Gram product k_gemmt_mfma (rocprofv3 kernel statistics in
+    # profiles/): per Ritz step five symmetric X^T X (n m (m+1) useful flops each)
+    # and three X^T Y (2 n m^2); timed live at the median m of the timed run's Ritz
+    # steps on the context's stream (after everything that needs the RBiCG store)
+    m_ritz = int(np.median([m for m in rres.ritz_m if m > 0]))
+    reps = max(3, args.time_reps // 20)
+    t_sym, f_sym = gs.ctx.time_pass(40, m_ritz, reps)
+    t_gen, f_gen = gs.ctx.time_pass(41, m_ritz, reps)
+    t_ts, f_ts = gs.ctx.time_pass(42, m_ritz, reps)
+    gram_tflops = (5 * f_sym + 3 * f_gen) / ((5 * t_sym + 3 * t_gen) * 1e-3) / 1e12
+    ritz_kernels = {
+        "m": m_ritz, "n": n,
+        "gemmt_sym": {"us": t_sym * 1e3, "tflops": f_sym / (t_sym * 1e-3) / 1e12, "flops": f_sym},
+        "gemmt_gen": {"us": t_gen * 1e3, "tflops": f_gen / (t_gen * 1e-3) / 1e12, "flops": f_gen},
+        "gemm_ts": {"us": t_ts * 1e3, "tflops": f_ts / (t_ts * 1e-3) / 1e12, "flops": f_ts},
+    }
 
     def summary(key):
         r = results[key]
@@ -446,36 +565,49 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3d 7-point convection-diffusion {args.grid}^3 (n={seq.n}), "
+        "config": {"workload": f"3d 7-point convection-diffusion {args.grid}^3 (n={n}), "
                                f"5 shifts x 4 rhs = {nsys} systems, k={args.k}, rtol={args.rtol}; "
                                f"per shift RBiCG on rhs 1, RBiCGSTAB on rhs 2-4 solved together",
-                   "n": seq.n, "nnz": int(seq.K.nnz), "systems": nsys, "k": args.k},
+                   "n": n, "nnz": nnz, "systems": nsys, "k": args.k, "s_max": args.s_max},
         "rbicgstab": dict(summary("rbicgstab"), solver=rres.solver, k_used=rres.k_used),
         "bicgstab": summary("bicgstab"),
         "rbicgstab_over_bicgstab_time": timed["rbicgstab"] / timed["bicgstab"],
+        "phases": phases,
         "single_rhs": {"rbicgstab": summary("rbicgstab_single"), "bicgstab": summary("bicgstab_single")},
-        "spmv_gbs": gbs(bytes_spmv, ms_spmv),
-        "passes": dict({name: {"us": ms * 1e3, "gbs": gbs(by, ms)} for name, (ms, by) in passes.items()},
-                       k=k_last, multi_nrhs=seq.nrhs - 1),
-        "roofline": {"bound": "hbm", "kernel": dom_kernel,
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_dom, "us_per_launch": ms_dom * 1e3},
+        "per_iteration": per_iter,
+        "spmv_gbs": passes["spmv"]["gbs"],
+        "passes": dict(passes, k=k_last, multi_nrhs=nr),
+        "ritz_kernels": ritz_kernels,
+        "roofline": {"bound": "mfma", "kernel": "k_gemmt_mfma",
+                     "achieved": gram_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": gram_tflops / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": counter_traffic(f"k_gemmt_mfma m={m_ritz}"),
+                     "flops_per_launch": (5 * f_sym + 3 * f_gen) / 8,
+                     "us_per_launch": (5 * t_sym + 3 * t_gen) / 8 * 1e3,
+                     "mix": "5 X^T X + 3 X^T Y per Ritz step"},
+        "parity_sample": parity,
     }
-    # a plain device-to-device copy of known size (outside the timed region):
-    # the reference the HBM counters of a profiled run are calibrated with
     if not args.no_fp32:
         r32, b32 = results["rbicgstab_fp32_ir"], results["bicgstab_fp32_ir"]
+        errs = r32.err_vs_fp64 + b32.err_vs_fp64
         out["fp32_ir"] = {
             "rbicgstab_systems_per_s": nsys / timed["rbicgstab_fp32_ir"],
             "rbicgstab_ms_per_step": timed["rbicgstab_fp32_ir"] * 1e3,
             "bicgstab_systems_per_s": nsys / timed["bicgstab_fp32_ir"],
             "bicgstab_ms_per_step": timed["bicgstab_fp32_ir"] * 1e3,
+            "note": "the RBiCG system of each matrix runs in FP64 in both RBiCGSTAB pipelines; its time is "
+                    "part of the FP32-IR systems/s and it is left out of the error lists",
             "rbicgstab_inner_iters": r32.iters, "bicgstab_inner_iters": b32.iters,
             "rbicgstab_matvecs": r32.total_matvecs, "bicgstab_matvecs": b32.total_matvecs,
             "max_rel_res_true_fp64": max(max(r32.rel_res_true), max(b32.rel_res_true)),
-            "rbicgstab_err_vs_fp64": r32.err_vs_fp64, "bicgstab_err_vs_fp64": b32.err_vs_fp64}
+            "rbicgstab_err_vs_fp64": r32.err_vs_fp64, "bicgstab_err_vs_fp64": b32.err_vs_fp64,
+            "max_err_vs_fp64": max(errs), "err_bound": kappa * args.rtol,
+            "within_bound": max(errs) <= kappa * args.rtol}
+    if not args.no_hbm128:
+        out["hbm_resident_128"] = hbm_resident_passes(args)
     if args.calib_copy_mib > 0:
+        # a plain device-to-device copy of known size (outside the timed region):
+        # the reference the HBM counters of a profiled run are calibrated with
         nel = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -487,6 +619,60 @@ def main():
         out["cpu_baseline"] = cpu_baseline(seq, args.rtol, args.cpu_systems)
     gs.close()
     print(json.dumps(out), flush=True)
+
+
+def hbm_resident_passes(args, N=128, k=20):
+    """The fused passes and whole iterations where the working set is far past the
+    last-level cache: 3D 7-point operator at N^3 (n = 2,097,152 at 128), sigma = 1,
+    the k lowest eigenpairs of the sigma = 0 operator as recycle space.  Per-pass
+    rooflines (live HIP events) and the end-to-end time per iteration of BiCGSTAB
+    and RBiCGSTAB runs of a fixed 100 iterations (no convergence test)."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_1406_2831_amd.rbicgstab import Context
+    from paper_1406_2831_amd.sequence import max_row_nnz
+
+    K = w.convdiff((N, N, N), w.VEL3, w.PECLET)
+    mdiag = w.generator(3, 0, "M").uniform(0.5, 1.5, size=K.n)
+    A = w.shifted(K, mdiag, 1.0)
+    At = A.transpose()
+    n, nnz = A.n, A.nnz
+    ctx = Context(n, max_row_nnz(A, At), k, 0, "cuda", float("inf"))
+    ctx.setup(A, At)
+    # the exact eigenvectors of K (sigma = 0): a well-conditioned oblique projector for A
+    _, U, Ut = w.separable_eigenpairs((N, N, N), w.VEL3, w.PECLET, k)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a.T), dtype=torch.float64, device="cuda")
+    ctx.recycle("set", dev(U), dev(Ut))
+    del U, Ut
+    kk = ctx.blocks()[1]
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
+    passes = {}
+    for name, which in (("update", 0), ("spmv1_project", 1), ("spmv2_project", 2), ("spmv", 3),
+                        ("update_fp32", 4), ("spmv1_project_fp32", 5), ("spmv2_project_fp32", 6),
+                        ("mupdate_3rhs", 8 + 4 * 2), ("mspmv1_project_3rhs", 8 + 4 * 2 + 1),
+                        ("mspmv2_project_3rhs", 8 + 4 * 2 + 2)):
+        ms, by = ctx.time_pass(which, kk if which != 3 else 0, 20)
+        passes[name] = {"us": ms * 1e3, "gbs": gbs(by, ms), "frac": gbs(by, ms) / HBM_PEAK_GBS, "bytes": by}
+    b = torch.as_tensor(w.generator(3, 0, "b").standard_normal(n), device="cuda")
+    sh = torch.as_tensor(w.generator(3, 0, "shadow").standard_normal(n), device="cuda")
+    spmv_b = 12 * nnz + 4 * (n + 1) + 16 * n
+    iters = {}
+    for mode, byts in (("bicgstab", 2 * spmv_b + 128 * n), ("rbicgstab", 2 * spmv_b + 144 * n + 32 * n * kk)):
+        x = torch.zeros_like(b)
+        ctx.solve(b, x, shadow=sh, rtol=1e-30, max_it=20, mode=mode)   # warm-up
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.solve(b, x, shadow=sh, rtol=1e-30, max_it=100, mode=mode)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) * 1e6 / max(st.iters, 1)
+        iters[mode] = {"us_per_iter": us, "iters": st.iters, "bytes_per_iter": byts,
+                       "frac": byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    ctx.close()
+    return {"grid": N, "n": n, "nnz": nnz, "k": kk, "passes": passes, "iteration": iters,
+            "note": "recycle space: the k lowest closed-form eigenpairs of the sigma = 0 operator; "
+                    "iterations timed end to end on the host around one solve call"}
 
 
 if __name__ == "__main__":

@@ -55,7 +55,8 @@ typedef struct {
     double rel_res_true;   /* ||b - A x|| / ||b|| computed in FP64 at the end   */
     double ms;             /* host wall time of the call                        */
     int32_t ir_steps;      /* outer refinement steps (RBS_FP32_IR only)         */
-    int32_t reserved;
+    int32_t ritz_m;        /* stored vectors of the last Ritz step (RBICG_GEN)   */
+    double ritz_ms;        /* host wall time of the Ritz steps (RBICG_GEN; part of ms) */
 } rbs_stats;
 
 enum {
@@ -207,8 +208,15 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  * back to back on the context's stream between two HIP events; *avg_ms
  * receives the mean duration per launch and *bytes the algorithmic bytes
  * one launch moves (CSR: 12 bytes per stored entry + 4 per row pointer;
- * 8 bytes per vector / block entry read or written once; 8 and 4 for FP32).  The context's
- * solve vectors are used as operands and left in an unspecified state.
+ * 8 bytes per vector / block entry read or written once; 8 and 4 for FP32).
+ * which = 40, 41, 42 time the matrix-core kernels of the Ritz step on the
+ * first k columns of the RBiCG store (k <= k_max + s_max): 40 the Gram
+ * product X^T X (upper triangle), 41 the product X^T Y of two n x k blocks,
+ * 42 the basis transform X S with S k x k; *bytes then receives the useful
+ * FP64 flops of one launch (n k (k + 1), 2 n k^2, 2 n k^2).  The context's
+ * solve vectors (and for 40..42 the RBiCG store, so also the space a
+ * following FROM_LAST_SOLVE would install) are used as operands and left in
+ * an unspecified state.
  */
 int rbicgstab_time_pass(rbs_ctx* ctx, int32_t which, int32_t k, int32_t reps, double* avg_ms,
                         double* bytes);

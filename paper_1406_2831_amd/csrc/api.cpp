@@ -55,6 +55,8 @@ struct rbs_ctx {
     double *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr, *Chat = nullptr,
            *Ccheck = nullptr, *Gh = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;
     int ritz_mv = 0;         // products with A spent by Ritz steps of the current RBiCG solve
+    double ritz_ms = 0.0;    // host wall time of those Ritz steps
+    int ritz_m = 0;          // stored vectors of the last one
     // FP32 storage for the inner solves of iterative refinement (RBS_FP32_IR):
     // value copies of A, A^T (sharing their slices and columns), of the blocks,
     // and a float vector set; refreshed lazily after every setup
@@ -923,7 +925,18 @@ int ritz_host_buffers(rbs_ctx* c) {
 // small problems solved on the host are well conditioned: harmonic Ritz
 // vectors of A on range(W) (right) and the left vectors of the two-sided
 // projection on (Wt, W).  The new space replaces the first columns.
+int ritz_cycle_work(rbs_ctx* c, int ns);
+
+// One Ritz step, timed (host wall time, which is also the device time it waits for).
 int ritz_cycle(rbs_ctx* c, int ns) {
+    const auto t0 = std::chrono::steady_clock::now();
+    c->ritz_m = c->gen_k + ns;
+    const int rc = ritz_cycle_work(c, ns);
+    c->ritz_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int ritz_cycle_work(rbs_ctx* c, int ns) {
     const int m = c->gen_k + ns;
     if (m <= 0) return RBS_OK;
     const auto t_start = std::chrono::steady_clock::now();
@@ -1059,6 +1072,8 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
     int rc;
     c->gen_valid = false;
     c->ritz_mv = 0;
+    c->ritz_ms = 0.0;
+    c->ritz_m = 0;
     int ght_mv = 0;
     if ((rc = ensure_ght(c, c->k, &ght_mv))) return rc;
     // the space being built starts from the installed one: W = [U], Wt = [Ut]
@@ -1150,10 +1165,50 @@ int solve_rbicg(rbs_ctx* c, const double* b, double* x, int xnz, const double* s
         stats->matvecs_At = mvAt;
         stats->k_used = c->k;
         stats->ritz_updates = ritz_updates;
+        stats->ritz_m = c->ritz_m;
+        stats->ritz_ms = c->ritz_ms;
         stats->rel_res_recur = rel_recur;
         if (restarts == 0) stats->rel_res_true = rel_true;
     }
     return status;
+}
+
+// Times one of the Ritz step's matrix-core kernels on the first m columns of
+// the RBiCG store (W, Wt as operands, Wtmp as output): 40 X^T X, 41 X^T Y,
+// 42 X S (S from the small device scratch).  *flops: useful FP64 flops per launch.
+int time_ritz_kernel(rbs_ctx* c, int which, int m, int reps, double* avg_ms, double* flops) {
+    const int mmax = c->k_max + std::max(c->s_max, 0);
+    if (which > 42 || m < 1 || m > mmax || reps < 1 || c->s_max <= 0)
+        return fail(c, RBS_ERR_ARG, "Ritz kernels: which 40..42, 1 <= k <= k_max + s_max, s_max > 0");
+    hipStream_t s = c->stream;
+    const int64_t ld = c->ldw;
+    double* out = c->dsmall;   // >= 11 mmax^2 doubles: room for an m x m result and an m x m S
+    auto launch = [&]() {
+        if (which == 40)
+            rbs::launch_gemmt(s, c->n, c->W, ld, m, c->W, ld, m, nullptr, 0, 0, c->gpart, out);
+        else if (which == 41)
+            rbs::launch_gemmt(s, c->n, c->Wt, ld, m, c->W, ld, m, nullptr, 0, 0, c->gpart, out);
+        else
+            rbs::launch_gemm_ts(s, c->n, c->W, ld, m, out + (size_t)m * m, m, c->Wtmp, ld);
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    launch();   // warm-up
+    hipEventRecord(e0, s);
+    for (int i = 0; i < reps; ++i) launch();
+    hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(c, RBS_ERR_HIP, std::string("timing: ") + hipGetErrorString(e));
+    c->gen_valid = false;   // the store no longer holds a generated space
+    if (avg_ms) *avg_ms = ms / reps;
+    const double n = (double)c->n, mm = (double)m;
+    if (flops) *flops = which == 40 ? n * mm * (mm + 1.0) : 2.0 * n * mm * mm;
+    return RBS_OK;
 }
 
 }  // namespace
@@ -1522,6 +1577,7 @@ int rbicgstab_time_pass(rbs_ctx* c, int32_t which, int32_t k, int32_t reps, doub
                         double* bytes) {
     if (!c) return fail(nullptr, RBS_ERR_ARG, "ctx is NULL");
     if (!c->bound) return fail(c, RBS_ERR_ARG, "no matrix bound");
+    if (which >= 40) return time_ritz_kernel(c, which, k, reps, avg_ms, bytes);
     const bool multi = which >= 8;
     const int nr = multi ? (which - 8) / 4 + 1 : 1;
     if (which < 0 || which >= 8 + 4 * rbs::MULTI_MAX || (multi && (which - 8) % 4 == 3) || reps < 1 ||

@@ -590,95 +590,150 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_wave(int mx, int my, int
     if (lane == 0) *dst = s;
 }
 
-// Tall-skinny X^T Y on the matrix cores: a 128 x 128 output tile per block,
-// each of the 4 waves owns a 64 x 64 quarter as 4 x 4 tiles of
-// v_mfma_f64_16x16x4 (operand lanes: A(i, kk) and B(kk, j) from lane
+// Tall-skinny X^T Y on the matrix cores.  The output is cut into 128 x 128
+// tiles; when a dimension is not a multiple of 128, the last tile row / column
+// is only as wide as the remainder rounded up to 32.  The tiles fall in up to
+// four shape classes (interior, right edge, bottom edge, corner), each
+// computed by its own launch of a kernel instantiated for that shape, so
+// every launch is sized to fill the chip and no work goes into padding beyond
+// the 32-wide granularity.  A block computes one tile (32 WX) x (32 WY) over
+// one chunk of rows: its 4 waves own (16 WX) x (16 WY) quarters as WX x WY
+// tiles of v_mfma_f64_16x16x4 (operand lanes: A(i, kk) and B(kk, j) from lane
 // i + 16 kk / j + 16 kk; result element (i, j) of a 16 x 16 tile in lane
 // j + 16 (i % 4), register i / 4).  Rows are staged through LDS in slabs of
-// 16 (row-major in LDS, so an operand read is 16 consecutive doubles per
-// lane group; the row stride is padded so the two half-waves of a read hit
-// disjoint banks).  Symmetric products launch only tiles with tx <= ty.
+// 16 (row-major in LDS, the column index XOR-swizzled by the row within its
+// 16-column group so that the 16 rows a lane group stores fall in distinct
+// banks); a slab's operands are all loaded before they are staged.  Symmetric
+// products launch only the upper triangle of the interior class and no bottom
+// edge; the reduction mirrors.
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 128, MR = 16, MSTRIDE = MT + 16;
 
+// One shape class of a product: its tiles (ntx x nty of them, or the upper
+// triangle of an ntx x ntx grid when tri) start at element (x0, y0) in steps
+// of 128; each is computed in nchunks row chunks, chunk c of tile t writing
+// partial tile slot0 + c * ntiles + t of TX x TY doubles (row-major).
+struct GemmtClass {
+    int x0, y0, ntx, nty, tri, ntiles, nchunks, tx_dim, ty_dim;
+    int64_t rows_per_chunk, slot0;   // slot0 in doubles
+};
+
+template <int WX, int WY>
 __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* __restrict__ X,
                                                       int64_t ldx, int mx, const double* __restrict__ Y,
-                                                      int64_t ldy, int my, int tiles_y,
-                                                      int64_t rows_per_chunk, int symmetric,
+                                                      int64_t ldy, int my, GemmtClass cl,
                                                       double* __restrict__ partial) {
-    __shared__ double sx[MR * MSTRIDE];
-    __shared__ double sy[MR * MSTRIDE];
-    int tx, ty;
-    if (symmetric) {   // blockIdx.x enumerates the upper triangle row by row
-        int b = blockIdx.x;
-        tx = 0;
-        while (b >= tiles_y - tx) {
-            b -= tiles_y - tx;
-            ++tx;
+    constexpr int TX = 32 * WX, TY = 32 * WY;
+    constexpr int SX = TX + 16, SY = TY + 16;
+    __shared__ double sx[MR * SX];
+    __shared__ double sy[MR * SY];
+    int a, b;
+    if (cl.tri) {   // blockIdx.x enumerates the upper triangle row by row
+        int t = blockIdx.x;
+        a = 0;
+        while (t >= cl.ntx - a) {
+            t -= cl.ntx - a;
+            ++a;
         }
-        ty = tx + b;
+        b = a + t;
     } else {
-        tx = blockIdx.x / tiles_y;
-        ty = blockIdx.x % tiles_y;
+        a = blockIdx.x / cl.nty;
+        b = blockIdx.x % cl.nty;
     }
-    const int64_t c0 = (int64_t)blockIdx.y * rows_per_chunk;
-    const int64_t c1 = (c0 + rows_per_chunk < n) ? c0 + rows_per_chunk : n;
+    const int gx0 = cl.x0 + MT * a, gy0 = cl.y0 + MT * b;
+    const int64_t c0 = (int64_t)blockIdx.y * cl.rows_per_chunk;
+    const int64_t c1 = (c0 + cl.rows_per_chunk < n) ? c0 + cl.rows_per_chunk : n;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int wi = w >> 1, wj = w & 1;
     const int lr = threadIdx.x & 15, lc = threadIdx.x >> 4;   // load: row lr of columns lc + 16 q
-    d4 acc[4][4];
+    d4 acc[WX][WY];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int p = 0; p < WX; ++p)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < WY; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
     for (int64_t base = c0; base < c1; base += MR) {
         const int64_t row = base + lr;
         const bool rok = row < c1;
-        double px[MT / 16], py[MT / 16];   // this slab's operands: all loads first
+        double px[TX / 16], py[TY / 16];   // this slab's operands: all loads first
 #pragma unroll
-        for (int q = 0; q < MT / 16; ++q) {
-            const int c = lc + 16 * q;
-            const int gi = tx * MT + c, gj = ty * MT + c;
+        for (int q = 0; q < TX / 16; ++q) {
+            const int gi = gx0 + lc + 16 * q;
             px[q] = (rok && gi < mx) ? X[row + (int64_t)gi * ldx] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < TY / 16; ++q) {
+            const int gj = gy0 + lc + 16 * q;
             py[q] = (rok && gj < my) ? Y[row + (int64_t)gj * ldy] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < MT / 16; ++q) {
-            const int c = lc + 16 * q;
-            // column index XOR-swizzled by the row within its 16-column group:
-            // the 16 rows a lane group stores then fall in distinct banks
-            sx[lr * MSTRIDE + (c ^ lr)] = px[q];
-            sy[lr * MSTRIDE + (c ^ lr)] = py[q];
-        }
+        for (int q = 0; q < TX / 16; ++q) sx[lr * SX + ((lc + 16 * q) ^ lr)] = px[q];
+#pragma unroll
+        for (int q = 0; q < TY / 16; ++q) sy[lr * SY + ((lc + 16 * q) ^ lr)] = py[q];
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < MR / 4; ++ks) {
             const int r = ks * 4 + (lane >> 4);
-            double a[4], b[4];
+            double av[WX], bv[WY];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                a[t] = sx[r * MSTRIDE + ((wi * 64 + t * 16 + (lane & 15)) ^ r)];
-                b[t] = sy[r * MSTRIDE + ((wj * 64 + t * 16 + (lane & 15)) ^ r)];
-            }
+            for (int t = 0; t < WX; ++t) av[t] = sx[r * SX + ((wi * 16 * WX + t * 16 + (lane & 15)) ^ r)];
 #pragma unroll
-            for (int it = 0; it < 4; ++it)
+            for (int t = 0; t < WY; ++t) bv[t] = sy[r * SY + ((wj * 16 * WY + t * 16 + (lane & 15)) ^ r)];
 #pragma unroll
-                for (int jt = 0; jt < 4; ++jt)
-                    acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[it], b[jt], acc[it][jt], 0, 0, 0);
+            for (int it = 0; it < WX; ++it)
+#pragma unroll
+                for (int jt = 0; jt < WY; ++jt)
+                    acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[it], bv[jt], acc[it][jt], 0, 0, 0);
         }
         __syncthreads();
     }
-    double* out = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (MT * MT);
+    double* out = partial + cl.slot0 + ((int64_t)blockIdx.y * cl.ntiles + blockIdx.x) * (TX * TY);
 #pragma unroll
-    for (int it = 0; it < 4; ++it)
+    for (int it = 0; it < WX; ++it)
 #pragma unroll
-        for (int jt = 0; jt < 4; ++jt)
+        for (int jt = 0; jt < WY; ++jt)
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const int i = wi * 64 + it * 16 + (lane >> 4) + 4 * rr;
-                const int j = wj * 64 + jt * 16 + (lane & 15);
-                out[i * MT + j] = acc[it][jt][rr];
+                const int i = wi * 16 * WX + it * 16 + (lane >> 4) + 4 * rr;
+                const int j = wj * 16 * WY + jt * 16 + (lane & 15);
+                out[i * TY + j] = acc[it][jt][rr];
             }
+}
+
+// Sum the row-chunk partial tiles of the classes into out (mx x my,
+// column-major, ld = mx).  cls[0..3]: interior, right edge, bottom edge,
+// corner (a class with no tiles has ntiles = 0).  Symmetric products mirror
+// the lower triangle from the upper one.
+struct GemmtClasses {
+    GemmtClass c[4];
+    int lx, ly;   // full 128-tiles in x and y (the edge classes start there)
+};
+
+__global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_cls(int mx, int my, int symmetric, GemmtClasses cls,
+                                                            const double* __restrict__ partial,
+                                                            double* __restrict__ out) {
+    __shared__ GemmtClass sc[4];   // the classes in LDS: indexed per thread below
+    if (threadIdx.x < 4) sc[threadIdx.x] = cls.c[threadIdx.x];
+    __syncthreads();
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= (int64_t)mx * my) return;
+    int i = (int)(idx / my), j = (int)(idx % my);   // consecutive threads: consecutive j
+    double* dst = out + i + (int64_t)j * mx;
+    if (symmetric && i / MT > j / MT) {
+        const int t = i;
+        i = j;
+        j = t;
+    }
+    const int ta = i / MT, tb = j / MT;
+    const bool ex = ta >= cls.lx, ey = tb >= cls.ly;
+    const GemmtClass& cl = sc[(ex ? 2 : 0) + (ey ? 1 : 0)];
+    const int a = ex ? 0 : ta, b = ey ? 0 : tb;
+    const int t = cl.tri ? a * cl.ntx - a * (a - 1) / 2 + (b - a) : a * cl.nty + b;
+    const int off = (i - cl.x0 - MT * a) * cl.ty_dim + (j - cl.y0 - MT * b);
+    const int64_t tile = (int64_t)cl.tx_dim * cl.ty_dim;
+    const double* p = partial + cl.slot0 + (int64_t)t * tile + off;
+    double s = 0.0;
+    for (int c = 0; c < cl.nchunks; ++c) s += p[(int64_t)c * cl.ntiles * tile];
+    *dst = s;
 }
 
 // Y[:, 0:ko] = X[:, 0:m] S on the matrix cores, computed as Y^T = S^T X^T so
@@ -1909,20 +1964,51 @@ static void gemmt_shape(int64_t n, int mx, int my, int T, int rows_mult, int gri
     if (nchunks < 1) nchunks = 1;
 }
 
-// the matrix-core kernel pays off once the output spans more than one 64-wide tile
+// the matrix-core kernels pay off once the output spans more than one 64-wide tile
 constexpr int MFMA_MIN_DIM = 65;
-constexpr int MFMA_GRID = 512;
+constexpr int MFMA_GRID = 512;   // blocks per shape-class launch (two per CU)
 
 size_t gemmt_partial_doubles(int64_t n, int mx, int my) {
-    // chunks * tiles <= max(grid cap, tiles) for every shape with at most this
-    // many tiles, so one buffer of this size serves all smaller calls too
+    // each shape-class launch has at most max(MFMA_GRID, its tiles) blocks of
+    // at most 128 x 128 partials; the 64-tile path at most max(MAX_GRID, tiles)
+    // blocks of 64 x 64.  This bounds every smaller call too.
     (void)n;
     const int64_t t64 = (int64_t)((mx + GT - 1) / GT) * ((my + GT - 1) / GT);
     const int64_t t128 = (int64_t)((mx + MT - 1) / MT) * ((my + MT - 1) / MT);
     const int64_t a = (t64 > MAX_GRID ? t64 : MAX_GRID) * GT * GT;
-    const int64_t b = (t128 > MFMA_GRID ? t128 : MFMA_GRID) * MT * MT;
+    const int64_t b = 4 * (t128 > MFMA_GRID ? t128 : MFMA_GRID) * MT * MT;
     return (size_t)(a > b ? a : b);
 }
+
+namespace {
+
+template <int WX, int WY>
+void launch_gemmt_class(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y,
+                        int64_t ldy, int my, const GemmtClass& cl, double* partial) {
+    hipLaunchKernelGGL((k_gemmt_mfma<WX, WY>), dim3(cl.ntiles, cl.nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx,
+                       Y, ldy, my, cl, partial);
+}
+
+// The kernel instantiation for a tile of (32 wx) x (32 wy).
+void launch_gemmt_shape(int wx, int wy, hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx,
+                        const double* Y, int64_t ldy, int my, const GemmtClass& cl, double* partial) {
+#define RBS_GEMMT_Y(WXV)                                                                            \
+    switch (wy) {                                                                                   \
+        case 1: launch_gemmt_class<WXV, 1>(st, n, X, ldx, mx, Y, ldy, my, cl, partial); break;      \
+        case 2: launch_gemmt_class<WXV, 2>(st, n, X, ldx, mx, Y, ldy, my, cl, partial); break;      \
+        case 3: launch_gemmt_class<WXV, 3>(st, n, X, ldx, mx, Y, ldy, my, cl, partial); break;      \
+        default: launch_gemmt_class<WXV, 4>(st, n, X, ldx, mx, Y, ldy, my, cl, partial); break;     \
+    }
+    switch (wx) {
+        case 1: RBS_GEMMT_Y(1) break;
+        case 2: RBS_GEMMT_Y(2) break;
+        case 3: RBS_GEMMT_Y(3) break;
+        default: RBS_GEMMT_Y(4) break;
+    }
+#undef RBS_GEMMT_Y
+}
+
+}  // namespace
 
 void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y1,
                   int64_t ldy1, int my1, const double* Y2, int64_t ldy2, int my2, double* partial,
@@ -1931,24 +2017,54 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
     if (mx <= 0 || my <= 0) return;
     if (my2 > 0 && my1 > 0 && (mx >= MFMA_MIN_DIM || my >= MFMA_MIN_DIM)) {
         // X^T [Y1 Y2] as two products into the two column ranges of out (the
-        // matrix-core kernel reads one Y block; the second launch reuses the
+        // matrix-core kernel reads one Y block; the second product reuses the
         // partial buffer after the first reduction, in stream order)
         launch_gemmt(st, n, X, ldx, mx, Y1, ldy1, my1, nullptr, 0, 0, partial, out);
         launch_gemmt(st, n, X, ldx, mx, Y2, ldy2, my2, nullptr, 0, 0, partial, out + (int64_t)mx * my1);
         return;
     }
-    int tiles_y, ntiles, launched, nchunks;
-    int64_t rpc;
     const bool sym = X == Y1 && my2 == 0 && mx == my1 && ldx == ldy1;
     const int64_t total = (int64_t)mx * my;
     const unsigned rgrid = (unsigned)((total + BLOCK - 1) / BLOCK);
     if (mx >= MFMA_MIN_DIM || my >= MFMA_MIN_DIM) {
-        gemmt_shape(n, mx, my, MT, MR, MFMA_GRID, sym, tiles_y, ntiles, launched, nchunks, rpc);
-        hipLaunchKernelGGL(k_gemmt_mfma, dim3(launched, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1,
-                           ldy1, my1, tiles_y, rpc, sym ? 1 : 0, partial);
-        hipLaunchKernelGGL(k_gemmt_reduce<MT>, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, tiles_y, launched,
-                           nchunks, sym ? 1 : 0, sym ? 1 : 0, partial, out);
+        GemmtClasses cls;
+        cls.lx = mx / MT;
+        cls.ly = my / MT;
+        const int rx = mx - MT * cls.lx, ry = my - MT * cls.ly;   // remainders
+        const int wxe = (rx + 31) / 32, wye = (ry + 31) / 32;      // edge widths in 32s
+        int64_t slot = 0;
+        for (int q = 0; q < 4; ++q) {
+            const bool ex = (q & 2) != 0, ey = (q & 1) != 0;
+            GemmtClass& cl = cls.c[q];
+            cl.x0 = MT * (ex ? cls.lx : 0);
+            cl.y0 = MT * (ey ? cls.ly : 0);
+            cl.ntx = ex ? (rx > 0 ? 1 : 0) : cls.lx;
+            cl.nty = ey ? (ry > 0 ? 1 : 0) : cls.ly;
+            cl.tri = (sym && q == 0) ? 1 : 0;
+            const int wx = ex ? wxe : 4, wy = ey ? wye : 4;
+            cl.tx_dim = 32 * wx;
+            cl.ty_dim = 32 * wy;
+            cl.ntiles = cl.tri ? cl.ntx * (cl.ntx + 1) / 2 : cl.ntx * cl.nty;
+            if (sym && q == 2) cl.ntiles = 0;   // the bottom edge mirrors the right edge
+            cl.nchunks = 0;
+            cl.rows_per_chunk = n;
+            cl.slot0 = slot;
+            if (cl.ntiles == 0) continue;
+            int64_t nc = MFMA_GRID / cl.ntiles;
+            const int64_t maxc = (n + 255) / 256;
+            nc = nc < 1 ? 1 : (nc > maxc ? maxc : nc);
+            int64_t rpc = (n + nc - 1) / nc;
+            rpc = (rpc + MR - 1) / MR * MR;
+            cl.rows_per_chunk = rpc;
+            cl.nchunks = (int)((n + rpc - 1) / rpc);
+            slot += (int64_t)cl.nchunks * cl.ntiles * cl.tx_dim * cl.ty_dim;
+            launch_gemmt_shape(wx, wy, st, n, X, ldx, mx, Y1, ldy1, my1, cl, partial);
+        }
+        hipLaunchKernelGGL(k_gemmt_reduce_cls, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, sym ? 1 : 0, cls,
+                           partial, out);
     } else {
+        int tiles_y, ntiles, launched, nchunks;
+        int64_t rpc;
         gemmt_shape(n, mx, my, GT, GS, MAX_GRID, false, tiles_y, ntiles, launched, nchunks, rpc);
         hipLaunchKernelGGL(k_gemmt_tile, dim3(ntiles, nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y1,
                            ldy1, my1, Y2, ldy2, my2, tiles_y, rpc, sym ? 1 : 0, partial);

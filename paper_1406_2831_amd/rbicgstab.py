@@ -57,7 +57,8 @@ class Stats(ctypes.Structure):
                 ("matvecs_A", ctypes.c_int32), ("matvecs_At", ctypes.c_int32),
                 ("k_used", ctypes.c_int32), ("ritz_updates", ctypes.c_int32),
                 ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
-                ("ms", ctypes.c_double), ("ir_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ms", ctypes.c_double), ("ir_steps", ctypes.c_int32), ("ritz_m", ctypes.c_int32),
+                ("ritz_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -207,7 +208,8 @@ def rbicgstab_get_blocks(handle, n: int, k_max: int, device="cuda"):
 
 
 def rbicgstab_time_pass(handle, which: int, k: int, reps: int):
-    """(mean ms per launch, algorithmic bytes per launch) of one fused pass."""
+    """(mean ms per launch, algorithmic bytes per launch) of one fused pass; for the
+    Ritz-step matrix-core kernels (which 40..42) the second value is useful flops."""
     lib = load_library()
     ms, by = ctypes.c_double(0), ctypes.c_double(0)
     _check(lib, handle, lib.rbicgstab_time_pass(handle, which, k, reps, ctypes.byref(ms),

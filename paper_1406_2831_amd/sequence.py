@@ -14,6 +14,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List, Optional
 
+import time
+
 import numpy as np
 import torch
 
@@ -29,7 +31,12 @@ class GpuSequenceResult:
     solver: List[str] = field(default_factory=list)
     rel_res_true: List[float] = field(default_factory=list)
     k_used: List[int] = field(default_factory=list)
+    ms: List[float] = field(default_factory=list)        # host wall time of each solve call
+                                                         # (a multi-RHS call: on its first system)
+    ritz_ms: List[float] = field(default_factory=list)   # of which Ritz steps (RBiCG solves)
+    ritz_m: List[int] = field(default_factory=list)      # stored vectors of the last Ritz step
     setup_matvecs: int = 0
+    setup_ms: float = 0.0      # matrix binds and recycle-space installs (host wall time)
 
     @property
     def total_matvecs(self) -> int:
@@ -83,7 +90,9 @@ class GpuSequence:
             si, j = seq.system(idx)
             if j == 0:
                 A, At = self.mats[si]
+                t0 = time.perf_counter()
                 ctx.setup(A, At)
+                out.setup_ms += (time.perf_counter() - t0) * 1e3
                 ma, mat = ctx.setup_matvecs()
                 out.setup_matvecs += ma + mat
             gen = mode != "bicgstab" and j == 0 and self.k > 0
@@ -94,8 +103,8 @@ class GpuSequence:
                 X.zero_()
                 _, sts = ctx.solve_multi(self.rhs_block[idx:end], X, self.shadow_block[idx:end],
                                          rtol=rtol, max_it=max_it, mode=mode)
-                for g, st in zip(grp, sts):
-                    results[g] = (st, mode)
+                for g, st in zip(grp, sts):   # one call: its time counted once
+                    results[g] = (st, mode, st.ms if g == grp[0] else 0.0)
                 idx = end
                 continue
             b, sh, x = self.rhs[idx], self.shadows[idx], self.xbuf[idx]
@@ -107,7 +116,9 @@ class GpuSequence:
             elif gen:
                 _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicg",
                                   stop=rbicg_stop)
+                t0 = time.perf_counter()
                 ctx.recycle("from_last_solve")
+                out.setup_ms += (time.perf_counter() - t0) * 1e3
                 ma, mat = ctx.setup_matvecs()
                 out.setup_matvecs += ma + mat
                 solver = "rbicg"
@@ -115,10 +126,10 @@ class GpuSequence:
                 _, st = ctx.solve(b, x, shadow=sh, rtol=rtol, max_it=max_it, mode="rbicgstab",
                                   precision=precision)
                 solver = "rbicgstab"
-            results[idx] = (st, solver)
+            results[idx] = (st, solver, st.ms)
             idx += 1
         for i in range(last):
-            st, solver = results[i]
+            st, solver, call_ms = results[i]
             if self.keep_x:
                 out.x.append(self.xbuf[i])
             out.status.append(st.status)
@@ -127,6 +138,9 @@ class GpuSequence:
             out.solver.append(solver)
             out.rel_res_true.append(st.rel_res_true)
             out.k_used.append(st.k_used)
+            out.ms.append(call_ms)
+            out.ritz_ms.append(st.ritz_ms if solver == "rbicg" else 0.0)
+            out.ritz_m.append(st.ritz_m if solver == "rbicg" else 0)
         return out
 
     def close(self):
