@@ -199,12 +199,12 @@ def batched_workload(args):
     cfg = batch.config()
     xs = [torch.zeros_like(b) for b in bs]
 
-    def run_batch(mode):
+    def run_batch(mode, precision="fp64"):
         for x in xs:
             x.zero_()
-        sts = batch.solve(bs, xs, shs, rtol=args.rtol, max_it=20000, mode=mode)
+        sts = batch.solve(bs, xs, shs, rtol=args.rtol, max_it=20000, mode=mode, precision=precision)
         if any(s.status != 0 or s.rel_res_true > args.rtol for s in sts):
-            print(f"batched {mode}: not every system converged", file=sys.stderr)
+            print(f"batched {mode} {precision}: not every system converged", file=sys.stderr)
             sys.exit(1)
         return sts
 
@@ -215,19 +215,27 @@ def batched_workload(args):
             out.append(ctx.solve(b, x, shadow=sh, rtol=args.rtol, max_it=20000, mode=mode)[1])
         return out
 
-    timed = {}
-    for key, fn, mode in (("rbicgstab_batched", run_batch, "rbicgstab"),
-                          ("bicgstab_batched", run_batch, "bicgstab"),
-                          ("rbicgstab_single", run_single, "rbicgstab"),
-                          ("bicgstab_single", run_single, "bicgstab")):
+    timed, errs = {}, {}
+    x64 = None
+    for key, fn, mode, prec in (("rbicgstab_batched", run_batch, "rbicgstab", "fp64"),
+                                ("bicgstab_batched", run_batch, "bicgstab", "fp64"),
+                                ("rbicgstab_batched_fp32_ir", run_batch, "rbicgstab", "fp32_ir"),
+                                ("bicgstab_batched_fp32_ir", run_batch, "bicgstab", "fp32_ir"),
+                                ("rbicgstab_single", run_single, "rbicgstab", "fp64"),
+                                ("bicgstab_single", run_single, "bicgstab", "fp64")):
+        call = (lambda: fn(mode, prec)) if fn is run_batch else (lambda: fn(mode))
         for _ in range(args.warmup):
-            fn(mode)
+            call()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            sts = fn(mode)
+            sts = call()
         torch.cuda.synchronize()
         timed[key] = ((time.perf_counter() - t0) / args.steps, [s.iters for s in sts])
+        if key == "rbicgstab_batched":
+            x64 = [x.clone() for x in xs]
+        elif prec == "fp32_ir":   # error of each FP32-storage result against the FP64 batch's
+            errs[key] = [float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr)) for x, xr in zip(xs, x64)]
     nsys = len(ctxs)
     # the three batched passes moved these algorithmic bytes in one tuned iteration
     byts = sum((80 * n + 8 * n * kk) + (12 * nz + 4 * (n + 1) + 32 * n + 16 * n * kk)
@@ -246,6 +254,9 @@ def batched_workload(args):
         "iters": {key: v[1] for key, v in timed.items()},
         "systems_per_s": {key: nsys / v[0] for key, v in timed.items()},
         "rbicg_iters_round1": gen_iters,
+        "fp32_ir": {"err_vs_fp64": errs, "max_err_vs_fp64": max(max(v) for v in errs.values()),
+                    "note": "FP32 storage under FP64 refinement; inner FP32 solves batched, "
+                            "launched directly (no graph replay)"},
         "roofline": {"bound": "hbm", "kernel": "k_batch_update + k_batch_spmv1 + k_batch_spmv2 (one iteration)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None,

@@ -293,7 +293,11 @@ int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const i
  *   (RBS_RBICGSTAB) or none (RBS_BICGSTAB), zero initial guess; bvec, x and
  *   shadows (may be NULL) are host arrays of nsys device pointers; stats is a
  *   host array of nsys (may be NULL).  Per-system restarts as in
- *   rbicgstab_solve.  Returns RBS_OK if every system converged.
+ *   rbicgstab_solve.  OR-ed with RBS_FP32_IR: FP32 storage under FP64
+ *   refinement as in rbicgstab_solve, the inner FP32 solves of all systems
+ *   still above rtol batched together (launched directly, without graph
+ *   replay); stats as for RBS_FP32_IR.  Returns RBS_OK if every system
+ *   converged.
  * rbicgstab_batch_config: the tile height, grid and (when tuned) the measured
  *   ms per batched iteration of the chosen configuration.
  */

@@ -1224,6 +1224,7 @@ struct rbs_batch {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     rbs::SolveBufs* d_sys = nullptr;
+    rbs::SolveBufsF* d_sysf = nullptr;   // FP32-storage descriptors (refinement mode)
     rbs::BatchTile* d_tiles = nullptr;
     int32_t* d_tile_begin = nullptr;
     double* d_partials = nullptr;
@@ -1261,6 +1262,7 @@ constexpr int BATCH_TILE_MIN = 64;   // rows of the smallest tile (one slice)
 size_t batch_carve(rbs_batch* b, char* base, int nsys, int max_tiles) {
     Carver cv{base};
     b->d_sys = cv.take<rbs::SolveBufs>(nsys);
+    b->d_sysf = cv.take<rbs::SolveBufsF>(nsys);
     b->d_tiles = cv.take<rbs::BatchTile>(max_tiles);
     b->d_tile_begin = cv.take<int32_t>(nsys + 1);
     b->d_partials = cv.take<double>((size_t)(rbs::KMAX + 3) * max_tiles);
@@ -1307,6 +1309,20 @@ int batch_tiles(rbs_batch* b, int rows) {
 rbs::BatchBufs batch_bufs(const rbs_batch* b) {
     rbs::BatchBufs B;
     B.sys = b->d_sys;
+    B.tiles = b->d_tiles;
+    B.tile_begin = b->d_tile_begin;
+    B.nsys = b->nsys;
+    B.ntiles = b->ntiles;
+    B.kmax = b->kmax;
+    B.partials = b->d_partials;
+    B.tickets = b->d_tickets;
+    B.gpart = b->d_gpart;
+    return B;
+}
+
+rbs::BatchBufsF batch_bufs_f32(const rbs_batch* b) {
+    rbs::BatchBufsF B;
+    B.sys = b->d_sysf;
     B.tiles = b->d_tiles;
     B.tile_begin = b->d_tile_begin;
     B.nsys = b->nsys;
@@ -1382,6 +1398,156 @@ int batch_tune(rbs_batch* b) {
     b->tuned_ms = best;
     b->grid = best_grid;
     return batch_tiles(b, best_rows);
+}
+
+// FP32 storage under FP64 refinement for a batch (the single-system scheme of
+// solve_ir, with the inner solves of all unconverged systems batched): per
+// outer step, each system's FP64 residual r = b - A x and its norm; systems
+// at rtol leave; the others solve A d = r / ||r|| together with the FP32
+// batched passes to max(INNER_RTOL, rtol / 2 / rel) and update x += ||r|| d in
+// FP64.  A system whose FP32 correction is unusable (non-finite, or a
+// breakdown before any progress) is finished alone by the single-system
+// refinement (counted in its stats.restarts).  The inner iterations launch
+// directly (no graph replay).
+int batch_solve_ir(rbs_batch* b, const int* ks, const double* const* bvec, double* const* x,
+                   const double* const* shadows, double rtol, int max_it, rbs_stats* out) {
+    const int ns = b->nsys;
+    hipStream_t s = b->stream;
+    std::vector<rbs::SolveBufsF> d(ns);
+    std::vector<int> active(ns, 1), status(ns, RBS_MAXIT), steps(ns, 0), inner_iters(ns, 0), mvA(ns, 0),
+        mvAt(ns, 0), fallback(ns, 0);
+    std::vector<double> rel(ns, NAN), rn(ns, 0.0), rel_inner(ns, NAN);
+    b->kmax = 0;
+    for (int j = 0; j < ns; ++j) {
+        rbs_ctx* c = b->ctx[j];
+        int rc = ensure_f32(c);
+        if (rc) return bfail(b, rc, std::string("system ") + std::to_string(j) + ": " + c->err);
+        BHIPCHK(b, hipStreamSynchronize(c->stream));
+        d[j] = solve_bufs_f32(c, ks[j], shadows != nullptr);
+        b->kmax = std::max(b->kmax, ks[j]);
+        rbs::launch_fill(s, x[j], c->n, 0.0);
+        if (shadows) rbs::launch_to_float(s, c->n, shadows[j], 1.0, c->shf);
+    }
+    BHIPCHK(b, hipMemcpyAsync(b->d_sysf, d.data(), d.size() * sizeof(rbs::SolveBufsF), hipMemcpyHostToDevice, s));
+    const rbs::BatchBufsF B = batch_bufs_f32(b);
+    auto poll = [&]() -> int {
+        rbs::launch_gather_states(s, B, b->d_states);
+        BHIPCHK(b, hipMemcpy2DAsync(b->h_states, sizeof(SolveState), b->d_states, sizeof(SolveState), 128, ns,
+                                    hipMemcpyDeviceToHost, s));
+        BHIPCHK(b, hipEventRecord(b->ev, s));
+        return RBS_OK;
+    };
+    for (int outer = 0;; ++outer) {
+        // FP64 residuals of the systems still iterating
+        int nact = 0;
+        for (int j = 0; j < ns; ++j) {
+            if (!active[j]) continue;
+            rbs_ctx* c = b->ctx[j];
+            rbs::launch_residual(s, c->A, bvec[j], x[j], c->r64, c->partials, c->dsums);
+            BHIPCHK(b, hipMemcpyAsync(c->hp->sums, c->dsums, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        BHIPCHK(b, hipStreamSynchronize(s));
+        for (int j = 0; j < ns; ++j) {
+            if (!active[j]) continue;
+            rbs_ctx* c = b->ctx[j];
+            ++mvA[j];
+            const double rr = c->hp->sums[0], bb = c->hp->sums[1];
+            rel[j] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+            rn[j] = std::sqrt(rr);
+            if (!std::isfinite(rel[j])) {
+                status[j] = RBS_ERR_NONFINITE;
+                active[j] = 0;
+            } else if (rel[j] <= rtol) {
+                status[j] = RBS_OK;
+                active[j] = 0;
+            } else if (outer == MAX_IR_STEPS || inner_iters[j] >= max_it) {
+                status[j] = RBS_MAXIT;
+                active[j] = 0;
+            }
+            if (active[j]) ++nact;
+        }
+        if (nact == 0) break;
+        // the corrections of the active systems, batched; the others' states stay done
+        for (int j = 0; j < ns; ++j) {
+            if (!active[j]) continue;
+            rbs_ctx* c = b->ctx[j];
+            rbs::launch_to_float(s, c->n, c->r64, 1.0 / rn[j], c->bf);
+            const double want = std::max(INNER_RTOL, 0.5 * rtol / rel[j]);
+            rbs::launch_solve_prologue(s, d[j], 0, want, max_it - inner_iters[j]);
+            ++mvAt[j];
+        }
+        int rc = poll();
+        if (rc) return rc;
+        int enq = 0;
+        while (true) {
+            rbs::launch_batch_iterations(s, B, b->grid, CHUNK);
+            enq += CHUNK;
+            hipError_t e = hipEventSynchronize(b->ev);
+            if (e != hipSuccess) return bfail(b, RBS_ERR_HIP, hipGetErrorString(e));
+            bool all = true;
+            for (int j = 0; j < ns; ++j)
+                if (active[j] && !b->h_states[j].done) all = false;
+            if (all || enq > max_it + 4 * CHUNK) break;
+            if ((rc = poll())) return rc;
+        }
+        BHIPCHK(b, hipStreamSynchronize(s));
+        for (int j = 0; j < ns; ++j) {
+            if (!active[j]) continue;
+            rbs_ctx* c = b->ctx[j];
+            rbs::launch_solve_epilogue(s, d[j]);
+            BHIPCHK(b, hipMemcpyAsync(&c->hp->solve, c->st, 128, hipMemcpyDeviceToHost, s));
+        }
+        BHIPCHK(b, hipStreamSynchronize(s));
+        for (int j = 0; j < ns; ++j) {
+            if (!active[j]) continue;
+            rbs_ctx* c = b->ctx[j];
+            const SolveState& h = c->hp->solve;
+            const int st_in = h.done ? h.status : RBS_MAXIT;
+            inner_iters[j] += h.iters_done;
+            mvA[j] += 2 * h.iters_done;
+            rel_inner[j] = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : std::sqrt(h.rr);
+            const bool usable = st_in >= 0 && (st_in == RBS_OK || st_in == RBS_MAXIT ||
+                                               (h.iters_done > 0 && std::isfinite(rel_inner[j])));
+            ++steps[j];
+            if (usable) {
+                rbs::launch_add_float(s, c->n, x[j], c->df, rn[j]);
+            } else {
+                // finish this system alone from its iterate (single-system refinement)
+                rbs_stats s2{};
+                BHIPCHK(b, hipStreamSynchronize(s));
+                const int st2 = solve_ir(c, ks[j], bvec[j], x[j], 1, shadows ? shadows[j] : nullptr, rtol,
+                                         std::max(1, max_it - inner_iters[j]), &s2);
+                if (st2 < 0 && st2 != RBS_ERR_NONFINITE) return bfail(b, st2, c->err);
+                inner_iters[j] += s2.iters;
+                mvA[j] += s2.matvecs_A;
+                mvAt[j] += s2.matvecs_At;
+                steps[j] += s2.ir_steps;
+                fallback[j] = 1 + s2.restarts;
+                status[j] = st2;
+                rel[j] = s2.rel_res_true;
+                active[j] = 0;
+            }
+        }
+        BHIPCHK(b, hipGetLastError());
+    }
+    if (out)
+        for (int j = 0; j < ns; ++j) {
+            rbs_stats& st = out[j];
+            st = rbs_stats{};
+            st.status = status[j];
+            st.iters = st.total_iters = inner_iters[j];
+            st.restarts = fallback[j];
+            st.matvecs_A = mvA[j];
+            st.matvecs_At = mvAt[j];
+            st.k_used = ks[j];
+            st.rel_res_recur = rel_inner[j];
+            st.rel_res_true = rel[j];
+            st.ir_steps = steps[j];
+        }
+    int worst = RBS_OK;
+    for (int j = 0; j < ns; ++j)
+        if (status[j] != RBS_OK && (worst == RBS_OK || status[j] < 0)) worst = status[j];
+    return worst;
 }
 
 }  // namespace
@@ -1792,17 +1958,32 @@ int rbicgstab_batch_solve(rbs_batch* b, const double* const* bvec, double* const
     if (!b) return bfail(nullptr, RBS_ERR_ARG, "batch is NULL");
     if (!bvec || !x) return bfail(b, RBS_ERR_ARG, "b and x must be host arrays of device pointers");
     if (!(rtol > 0) || max_it < 1) return bfail(b, RBS_ERR_ARG, "rtol must be > 0 and max_it >= 1");
-    if (flags != RBS_RBICGSTAB && flags != RBS_BICGSTAB)
-        return bfail(b, RBS_ERR_ARG, "batched solves take RBS_RBICGSTAB or RBS_BICGSTAB");
+    const bool ir = (flags & RBS_FP32_IR) != 0;
+    const int mode = flags & ~RBS_FP32_IR;
+    if (mode != RBS_RBICGSTAB && mode != RBS_BICGSTAB)
+        return bfail(b, RBS_ERR_ARG, "batched solves take RBS_RBICGSTAB or RBS_BICGSTAB, optionally | RBS_FP32_IR");
     for (int j = 0; j < b->nsys; ++j)
         if (!bvec[j] || !x[j] || !b->ctx[j]->bound) return bfail(b, RBS_ERR_ARG, "missing vector or unbound context");
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = b->stream;
+    if (ir) {
+        std::vector<int> ks(b->nsys);
+        for (int j = 0; j < b->nsys; ++j) {
+            ks[j] = mode == RBS_BICGSTAB ? 0 : b->ctx[j]->k;
+            BHIPCHK(b, hipStreamSynchronize(b->ctx[j]->stream));
+        }
+        const int rc = batch_solve_ir(b, ks.data(), bvec, x, shadows, rtol, max_it, stats);
+        if (stats && rc >= 0) {
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            for (int j = 0; j < b->nsys; ++j) stats[j].ms = ms;
+        }
+        return rc;
+    }
     // every system's installed space (or none, for BiCGSTAB), its own vectors
     std::vector<int> ksave(b->nsys);
     for (int j = 0; j < b->nsys; ++j) {
         ksave[j] = b->ctx[j]->k;
-        if (flags == RBS_BICGSTAB) b->ctx[j]->k = 0;
+        if (mode == RBS_BICGSTAB) b->ctx[j]->k = 0;
         BHIPCHK(b, hipStreamSynchronize(b->ctx[j]->stream));
     }
     int rc = batch_upload(b, bvec, x, shadows);

@@ -116,8 +116,11 @@ struct BatchTile {
     int32_t pad;
     int64_t r0, r1;
 };
-struct BatchBufs {
-    const SolveBufs* sys;       // device array: system j's buffers (its k may be 0)
+// T is the storage type of every system's vectors, blocks and matrix values
+// (double, or float for the FP32-storage inner solves of iterative refinement).
+template <typename T>
+struct BatchBufsT {
+    const SolveBufsT<T>* sys;   // device array: system j's buffers (its k may be 0)
     const BatchTile* tiles;     // device array
     const int32_t* tile_begin;  // device array (nsys + 1): system j owns tiles [tb[j], tb[j+1])
     int nsys, ntiles, kmax;
@@ -125,12 +128,16 @@ struct BatchBufs {
     double* gpart;              // device array: (KMAX + 3) x TICKET_GROUPS group sums per system
     unsigned* tickets;          // device array: TICKET_WORDS completion counters per system
 };
+using BatchBufs = BatchBufsT<double>;
+using BatchBufsF = BatchBufsT<float>;
 // count iterations of every unfinished system; grid = workgroups of each pass
-void launch_batch_iterations(hipStream_t st, const BatchBufs& B, int grid, int count);
+template <typename T>
+void launch_batch_iterations(hipStream_t st, const BatchBufsT<T>& B, int grid, int count);
 // timing support: the main kernel of one batched pass (0 update, 1 spmv1, 2 spmv2)
 void launch_batch_pass(hipStream_t st, const BatchBufs& B, int grid, int which);
 // out[j] = first 128 bytes (the scalar header) of system j's state
-void launch_gather_states(hipStream_t st, const BatchBufs& B, SolveState* out);
+template <typename T>
+void launch_gather_states(hipStream_t st, const BatchBufsT<T>& B, SolveState* out);
 
 // y (float) = x (double) rounded, scaled by `scale`
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y);

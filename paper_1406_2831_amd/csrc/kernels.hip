@@ -558,8 +558,18 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce(int mx, int my, int tile
     const int ti = i / T, tj = j / T;
     const int slot = tri ? ti * tiles_y - ti * (ti - 1) / 2 + (tj - ti) : ti * tiles_y + tj;
     const int off = (i % T) * T + (j % T);
+    const double* p = partial + (int64_t)slot * (T * T) + off;
+    const int64_t cstride = (int64_t)stride * (T * T);
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * stride + slot) * (T * T) + off];
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {   // eight loads in flight, summed in chunk order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * cstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nchunks; ++c) s += p[(int64_t)c * cstride];
     *dst = s;
 }
 
@@ -731,8 +741,17 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_cls(int mx, int my, int 
     const int off = (i - cl.x0 - MT * a) * cl.ty_dim + (j - cl.y0 - MT * b);
     const int64_t tile = (int64_t)cl.tx_dim * cl.ty_dim;
     const double* p = partial + cl.slot0 + (int64_t)t * tile + off;
+    const int64_t cstride = (int64_t)cl.ntiles * tile;
     double s = 0.0;
-    for (int c = 0; c < cl.nchunks; ++c) s += p[(int64_t)c * cl.ntiles * tile];
+    int c = 0;
+    for (; c + 8 <= cl.nchunks; c += 8) {   // eight loads in flight, summed in chunk order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * cstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < cl.nchunks; ++c) s += p[(int64_t)c * cstride];
     *dst = s;
 }
 
@@ -1193,8 +1212,8 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
 
 // tile t of system sys: its partial, then the system's completion (tiles
 // b0..b1 of the system are its participants; per-system group sums and counters)
-template <int M>
-__device__ __forceinline__ bool tile_done(double (&v)[M], const BatchBufs& B, int t, int sys,
+template <int M, typename T>
+__device__ __forceinline__ bool tile_done(double (&v)[M], const BatchBufsT<T>& B, int t, int sys,
                                           double* tot) {
     const int b0 = B.tile_begin[sys], b1 = B.tile_begin[sys + 1];
     Completion cp;
@@ -1205,22 +1224,22 @@ __device__ __forceinline__ bool tile_done(double (&v)[M], const BatchBufs& B, in
     return block_complete<M>(v, M, cp, t - b0, b1 - b0, tot);
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufs B, int fin) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufsT<T> B, int fin) {
     constexpr int M = K + 3;
     __shared__ double tot[M];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
-        const SolveBufs S = B.sys[tl.sys];
+        const SolveBufsT<T> S = B.sys[tl.sys];
         if (S.state->done) continue;
         double acc[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) acc[j] = 0.0;
         if (S.k > 0) {
-            update_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+            update_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
         } else {
             double a0[3] = {0.0, 0.0, 0.0};
-            update_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
+            update_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
             acc[0] = a0[0];
             acc[1] = a0[1];
             acc[2] = a0[2];
@@ -1232,22 +1251,22 @@ __global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufs B, int fin) {
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufs B, int fin) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufsT<T> B, int fin) {
     constexpr int M = K > 0 ? K : 1;
     __shared__ double tot[M];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
-        const SolveBufs S = B.sys[tl.sys];
+        const SolveBufsT<T> S = B.sys[tl.sys];
         if (S.state->done) continue;
         double acc[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) acc[j] = 0.0;
         if (S.k > 0) {
-            spmv1_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+            spmv1_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
         } else {
             double a0[1] = {0.0};
-            spmv1_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
+            spmv1_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
         }
         if constexpr (K > 0) {
             if (tile_done<M>(acc, B, t, tl.sys, tot)) {
@@ -1258,16 +1277,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufs B, int fin) {
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufs B, int fin) {
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufsT<T> B, int fin) {
     __shared__ double tot[5];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
-        const SolveBufs S = B.sys[tl.sys];
+        const SolveBufsT<T> S = B.sys[tl.sys];
         if (S.state->done) continue;
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (S.k > 0) spmv2_rows<double, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
-        else spmv2_rows<double, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+        if (S.k > 0) spmv2_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+        else spmv2_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
         if (tile_done<5>(acc, B, t, tl.sys, tot)) {
             if (fin && threadIdx.x == 0) spmv2_fin_scalars(S.state, tot, S.k);
         }
@@ -1275,7 +1294,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufs B, int fin) {
     }
 }
 
-__global__ void k_gather_states(BatchBufs B, SolveState* out) {
+template <typename T>
+__global__ void k_gather_states(BatchBufsT<T> B, SolveState* out) {
     // 128-byte scalar header of each state, 16 doubles per system
     const int j = blockIdx.x, i = threadIdx.x;
     if (i < 16) reinterpret_cast<double*>(out + j)[i] = reinterpret_cast<const double*>(B.sys[j].state)[i];
@@ -2157,45 +2177,51 @@ void launch_multi_iterations(hipStream_t st, const MultiBufs& B, int count) {
     }
 }
 
-template <int K>
+template <typename T, int K>
 struct BatchLaunch {
-    static void iter(hipStream_t st, const BatchBufs& B, int grid, int count) {
+    static void iter(hipStream_t st, const BatchBufsT<T>& B, int grid, int count) {
         for (int it = 0; it < count; ++it) {
-            hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B, 1);
-            hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B, 1);
-            hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B, 1);
+            hipLaunchKernelGGL((k_batch_update<T, K>), dim3(grid), dim3(BLOCK), 0, st, B, 1);
+            hipLaunchKernelGGL((k_batch_spmv1<T, K>), dim3(grid), dim3(BLOCK), 0, st, B, 1);
+            hipLaunchKernelGGL((k_batch_spmv2<T, K>), dim3(grid), dim3(BLOCK), 0, st, B, 1);
         }
     }
-    static void pass(hipStream_t st, const BatchBufs& B, int grid, int which) {
-        if (which == 0) hipLaunchKernelGGL(k_batch_update<K>, dim3(grid), dim3(BLOCK), 0, st, B, 0);
-        else if (which == 1) hipLaunchKernelGGL(k_batch_spmv1<K>, dim3(grid), dim3(BLOCK), 0, st, B, 0);
-        else hipLaunchKernelGGL(k_batch_spmv2<K>, dim3(grid), dim3(BLOCK), 0, st, B, 0);
+    static void pass(hipStream_t st, const BatchBufsT<T>& B, int grid, int which) {
+        if (which == 0) hipLaunchKernelGGL((k_batch_update<T, K>), dim3(grid), dim3(BLOCK), 0, st, B, 0);
+        else if (which == 1) hipLaunchKernelGGL((k_batch_spmv1<T, K>), dim3(grid), dim3(BLOCK), 0, st, B, 0);
+        else hipLaunchKernelGGL((k_batch_spmv2<T, K>), dim3(grid), dim3(BLOCK), 0, st, B, 0);
     }
 };
 
-void launch_batch_iterations(hipStream_t st, const BatchBufs& B, int grid, int count) {
+template <typename T>
+void launch_batch_iterations(hipStream_t st, const BatchBufsT<T>& B, int grid, int count) {
     const int k = B.kmax;
-    if (k == 0) BatchLaunch<0>::iter(st, B, grid, count);
-    else if (k <= 4) BatchLaunch<4>::iter(st, B, grid, count);
-    else if (k <= 8) BatchLaunch<8>::iter(st, B, grid, count);
-    else if (k <= 16) BatchLaunch<16>::iter(st, B, grid, count);
-    else if (k <= 32) BatchLaunch<32>::iter(st, B, grid, count);
-    else BatchLaunch<64>::iter(st, B, grid, count);
+    if (k == 0) BatchLaunch<T, 0>::iter(st, B, grid, count);
+    else if (k <= 4) BatchLaunch<T, 4>::iter(st, B, grid, count);
+    else if (k <= 8) BatchLaunch<T, 8>::iter(st, B, grid, count);
+    else if (k <= 16) BatchLaunch<T, 16>::iter(st, B, grid, count);
+    else if (k <= 32) BatchLaunch<T, 32>::iter(st, B, grid, count);
+    else BatchLaunch<T, 64>::iter(st, B, grid, count);
 }
+template void launch_batch_iterations<double>(hipStream_t, const BatchBufsT<double>&, int, int);
+template void launch_batch_iterations<float>(hipStream_t, const BatchBufsT<float>&, int, int);
 
 void launch_batch_pass(hipStream_t st, const BatchBufs& B, int grid, int which) {
     const int k = B.kmax;
-    if (k == 0) BatchLaunch<0>::pass(st, B, grid, which);
-    else if (k <= 4) BatchLaunch<4>::pass(st, B, grid, which);
-    else if (k <= 8) BatchLaunch<8>::pass(st, B, grid, which);
-    else if (k <= 16) BatchLaunch<16>::pass(st, B, grid, which);
-    else if (k <= 32) BatchLaunch<32>::pass(st, B, grid, which);
-    else BatchLaunch<64>::pass(st, B, grid, which);
+    if (k == 0) BatchLaunch<double, 0>::pass(st, B, grid, which);
+    else if (k <= 4) BatchLaunch<double, 4>::pass(st, B, grid, which);
+    else if (k <= 8) BatchLaunch<double, 8>::pass(st, B, grid, which);
+    else if (k <= 16) BatchLaunch<double, 16>::pass(st, B, grid, which);
+    else if (k <= 32) BatchLaunch<double, 32>::pass(st, B, grid, which);
+    else BatchLaunch<double, 64>::pass(st, B, grid, which);
 }
 
-void launch_gather_states(hipStream_t st, const BatchBufs& B, SolveState* out) {
-    hipLaunchKernelGGL(k_gather_states, dim3(B.nsys), dim3(64), 0, st, B, out);
+template <typename T>
+void launch_gather_states(hipStream_t st, const BatchBufsT<T>& B, SolveState* out) {
+    hipLaunchKernelGGL(k_gather_states<T>, dim3(B.nsys), dim3(64), 0, st, B, out);
 }
+template void launch_gather_states<double>(hipStream_t, const BatchBufsT<double>&, SolveState*);
+template void launch_gather_states<float>(hipStream_t, const BatchBufsT<float>&, SolveState*);
 
 void launch_to_float(hipStream_t st, int64_t n, const double* x, double scale, float* y) {
     hipLaunchKernelGGL(k_to_float, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, x, scale, y);

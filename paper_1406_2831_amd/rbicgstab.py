@@ -387,8 +387,10 @@ class Batch:
                                                           ctypes.byref(ms)))
         return {"tile_rows": rows.value, "grid": grid.value, "tuned_ms_per_iter": ms.value}
 
-    def solve(self, bs, xs, shadows=None, rtol=1e-8, max_it=10000, mode: str = "rbicgstab"):
-        """bs, xs (, shadows): lists of device tensors, one per system."""
+    def solve(self, bs, xs, shadows=None, rtol=1e-8, max_it=10000, mode: str = "rbicgstab",
+              precision: str = "fp64"):
+        """bs, xs (, shadows): lists of device tensors, one per system; precision
+        "fp64" or "fp32_ir" (FP32 storage under FP64 iterative refinement)."""
         lib = load_library()
         nsys = len(self.contexts)
         P = ctypes.c_void_p * nsys
@@ -397,6 +399,7 @@ class Batch:
         ps = P(*[t.data_ptr() for t in shadows]) if shadows is not None else None
         stats = (Stats * nsys)()
         flags = {"rbicgstab": RBS_RBICGSTAB, "bicgstab": RBS_BICGSTAB}[mode]
+        flags |= {"fp64": 0, "fp32_ir": RBS_FP32_IR}[precision]
         torch.cuda.current_stream().synchronize()
         rc = lib.rbicgstab_batch_solve(self.handle, pb, px, ps, rtol, max_it, flags, stats)
         self._check(rc)

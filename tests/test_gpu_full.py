@@ -237,6 +237,13 @@ def test_large_recycle_dimension_batched(rb, torch_mod, stencil27):
         assert st.status == 0 and st.rel_res_true <= 1e-10
         assert abs(st.iters - st1.iters) <= max(3, 0.05 * st1.iters)
         assert _rel(x.cpu().numpy(), refs[j]) <= 1e-6
+    # FP32 storage under FP64 refinement, batched
+    xs = [torch_mod.zeros_like(b) for b in bs]
+    sts = batch.solve(bs, xs, shs, rtol=1e-10, precision="fp32_ir")
+    for j, (x, st) in enumerate(zip(xs, sts)):
+        print(f"batched fp32-ir system {j}: inner iters {st.iters}, outer {st.ir_steps}", flush=True)
+        assert st.status == 0 and st.rel_res_true <= 1e-10 and st.ir_steps >= 2
+        assert _rel(x.cpu().numpy(), refs[j]) <= 1e-6
     batch.close()
     for c in ctxs:
         c.close()

@@ -510,6 +510,15 @@ def test_batched_uneven_systems(rb, torch_mod):
                     x1, st1 = _solve(ctxs[j], torch_mod, systems[j][2], shadow=systems[j][3], mode=mode,
                                      rtol=1e-10)
                     assert abs(st1.iters - st.iters) <= max(3, 0.05 * st1.iters), (mode, j)
+        if graph:   # FP32 storage under FP64 refinement, batched (a tuned batch, direct launches)
+            for mode in ("rbicgstab", "bicgstab"):
+                xs = [torch_mod.zeros_like(b) for b in bs]
+                sts = batch.solve(bs, xs, shs, rtol=1e-10, mode=mode, precision="fp32_ir")
+                print(f"fp32-ir {mode}: inner iters {[s.iters for s in sts]}, outer {[s.ir_steps for s in sts]}",
+                      flush=True)
+                for j, (x, st) in enumerate(zip(xs, sts)):
+                    assert st.status == 0 and st.rel_res_true <= 1e-10, (mode, j, st.as_dict())
+                    assert _rel(x.cpu().numpy(), refs[j]) <= 1e-6, (mode, j)
         batch.close()
     for c in ctxs:
         c.close()
