@@ -174,8 +174,8 @@ int rbicgstab_solve(rbs_ctx* ctx, const double* b, double* x, int32_t x_nonzero,
  *  stats    host array of nrhs (may be NULL); stats[j].ms is the whole call
  * Systems stop updating as they converge; one whose true residual misses rtol
  * is finished alone from its iterate (counted as a restart).  The fused
- * passes carry 4 systems (one wavefront each per workgroup); more are solved
- * in groups of 4.  Returns RBS_OK if every system converged, else the first
+ * passes carry up to 4 systems (a workgroup has one wavefront per system);
+ * more are solved in groups of 4.  Returns RBS_OK if every system converged, else the first
  * numerical outcome (> 0) or an error (< 0).
  */
 int rbicgstab_solve_multi(rbs_ctx* ctx, int32_t nrhs, const double* B, int64_t ldb, double* X,
@@ -278,8 +278,10 @@ int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const i
  * Batches of independent systems (each with its own matrix of any size, its
  * own recycle space and context) advanced together: every pass of an
  * iteration is one persistent launch whose workgroups walk a list of row
- * tiles of all unfinished systems, every finalize one launch with a workgroup
- * per system.  Iterations can be replayed from a captured HIP graph.
+ * tiles of all unfinished systems; the workgroup that finishes a system's last
+ * tile of a pass completes that system's reduction and scalar update inside
+ * the same launch (three launches per iteration).  Iterations can be replayed
+ * from a captured HIP graph.
  *
  * rbicgstab_batch_workspace_bytes: device workspace for nsys systems of sizes
  *   n[0..nsys) (host array); 0 for invalid arguments.
