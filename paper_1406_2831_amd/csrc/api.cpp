@@ -80,7 +80,7 @@ struct rbs_ctx {
     int64_t ldw = 0;
     double* partials = nullptr;
     unsigned* tickets = nullptr;   // completion counters of the fused passes (zero between launches)
-    double* gpart_cmp = nullptr;   // group sums of the fused passes' reductions
+    double* gpart_cmp = nullptr;   // group sums of the fused passes' reductions (one area per pass type)
     SolveState* st = nullptr;
     BicgState* bst = nullptr;
     double* dsums = nullptr;
@@ -190,7 +190,7 @@ size_t carve(rbs_ctx* c, char* base) {
     c->gpart = cv.take<double>(c->gpart_doubles);
     c->partials = cv.take<double>((size_t)1024 * rbs::PARTIAL_ROWS);
     c->tickets = cv.take<unsigned>(rbs::TICKET_WORDS);
-    c->gpart_cmp = cv.take<double>((size_t)rbs::PARTIAL_ROWS * rbs::TICKET_GROUPS);
+    c->gpart_cmp = cv.take<double>((size_t)3 * rbs::PARTIAL_ROWS * rbs::TICKET_GROUPS);
     c->st = cv.take<SolveState>(1);
     c->bst = cv.take<BicgState>(1);
     c->dsums = cv.take<double>(8);
@@ -362,12 +362,13 @@ int setup_blocks(rbs_ctx* c) {
     return RBS_OK;
 }
 
-// The context's in-pass reduction area (per-block partials, group sums, counters).
+// The context's split-reduction area (per-block partials, the group sums of
+// each pass type, counters).
 rbs::Completion completion(rbs_ctx* c) {
     rbs::Completion cp;
     cp.part = c->partials;
     cp.pstride = 1024;
-    cp.gpart = c->gpart_cmp;
+    for (int p = 0; p < 3; ++p) cp.gs[p] = c->gpart_cmp + (size_t)p * rbs::PARTIAL_ROWS * rbs::TICKET_GROUPS;
     cp.ctr = c->tickets;
     return cp;
 }
@@ -1234,7 +1235,7 @@ struct rbs_batch {
     int32_t* d_tile_begin = nullptr;
     double* d_partials = nullptr;
     unsigned* d_tickets = nullptr;       // per-system completion counters of the fused passes
-    double* d_gpart = nullptr;           // per-system group sums of the fused passes
+    double* d_gpart = nullptr;           // per-system group sums of the fused passes (per pass type)
     SolveState* d_states = nullptr;      // gathered state headers (polling)
     SolveState* h_states = nullptr;      // pinned host copy
     int max_tiles = 0, ntiles = 0, tile_rows = 0, grid = 0, kmax = 0;
@@ -1271,7 +1272,7 @@ size_t batch_carve(rbs_batch* b, char* base, int nsys, int max_tiles) {
     b->d_tiles = cv.take<rbs::BatchTile>(max_tiles);
     b->d_tile_begin = cv.take<int32_t>(nsys + 1);
     b->d_partials = cv.take<double>((size_t)(rbs::KMAX + 3) * max_tiles);
-    b->d_gpart = cv.take<double>((size_t)nsys * (rbs::KMAX + 3) * rbs::TICKET_GROUPS);
+    b->d_gpart = cv.take<double>((size_t)3 * nsys * (rbs::KMAX + 3) * rbs::TICKET_GROUPS);
     b->d_tickets = cv.take<unsigned>((size_t)nsys * rbs::TICKET_WORDS);
     b->d_states = cv.take<SolveState>(nsys);
     return round_up(cv.off, ALIGN);

@@ -36,9 +36,10 @@ using Sell = SellT<double>;
 // FP32 copy of a matrix: same slices and column indices, values rounded to float
 using SellF = SellT<float>;
 
-// Device-resident scalars of one solve.  Written by the last block of each
-// fused kernel (deterministic fixed-order reductions), read by the next
-// kernel: the host never sits inside the iteration.
+// Device-resident scalars of one solve.  Each fused kernel derives the
+// scalars of the previous kernel's reduction (deterministic fixed-order sums)
+// in every workgroup and workgroup 0 records them here: the host never sits
+// inside the iteration.
 struct SolveState {
     double alpha, beta, omega;
     double rho;            // (rt0, r_{i-1}) of the current iteration
@@ -54,7 +55,7 @@ struct SolveState {
     int32_t max_it;
     int32_t omega_zero;    // omega was exactly zero (breakdown unless converged)
     int32_t k;
-    int32_t pad1;
+    int32_t fresh;         // 1 until the first iteration's alpha is recorded
     double zeta[KMAX];     // zeta_i = Chat^T A p_i
     double gamma[KMAX];    // gamma_i = Chat^T A s_i
     double xc[KMAX];       // x_c of Algorithm 2
@@ -72,6 +73,8 @@ struct BicgState {
     int32_t store_base, store_cap;    // cycle-store column of r_{i-1}; capacity
     int32_t stored;                   // Lanczos vectors stored in the current cycle
     int32_t cur_slot;                 // column written by the current iteration (-1: none)
+    int32_t fresh;                    // 1 until the first iteration's rho is recorded
+    int32_t pad;
     double zeta[KMAX], zetat[KMAX], zc[KMAX];
     double sums[16];
 };

@@ -41,16 +41,16 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
 double launch_gemmt_interior(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y,
                              int64_t ldy, int my, double* partial);
 
-// Where one in-pass reduction keeps its partials and counters: participant
-// i's m values go to part[v * pstride + i]; group g's sums to
-// gpart[v * TICKET_GROUPS + g] (gpart holds PARTIAL_ROWS x TICKET_GROUPS
-// doubles); the counters (TICKET_WORDS unsigned, zero between launches) are
-// ctr[g * TICKET_STRIDE] for the groups and ctr[TICKET_GROUPS * TICKET_STRIDE]
-// for the top.
+// Where the split reductions of the fused passes keep their partials, group
+// sums and counters: participant i's m values go to part[v * pstride + i];
+// the group sums of a pass of type p (0 update, 1 spmv1, 2 spmv2; RBiCG: 0
+// update, 1 spmv) to gs[p][v * TICKET_GROUPS + g] (PARTIAL_ROWS x
+// TICKET_GROUPS doubles each), where the next pass reads them; the counters
+// (TICKET_WORDS unsigned, zero between launches) are ctr[g * TICKET_STRIDE].
 struct Completion {
     double* part;
     int64_t pstride;
-    double* gpart;
+    double* gs[3];
     unsigned* ctr;
 };
 
@@ -83,8 +83,9 @@ template <typename T>
 void launch_solve_epilogue(hipStream_t st, const SolveBufsT<T>& B);
 // Timing support: put the solve state in a non-terminating configuration
 // (done = 0, tolerance below zero, fixed bounded scalars) and launch one of
-// the fused passes (0 update, 1 spmv1, 2 spmv2) with its in-kernel reduction
-// but without the scalar update, or 3, a plain SpMV y = A x.
+// the fused passes (0 update, 1 spmv1, 2 spmv2) with both its reduction
+// levels (the previous pass's second, its own first) but with the state's
+// scalars and nothing recorded, or 3, a plain SpMV y = A x.
 void launch_time_prep(hipStream_t st, SolveState* state, int count = 1);
 template <typename T>
 void launch_pass(hipStream_t st, const SolveBufsT<T>& B, int which);
@@ -130,7 +131,8 @@ struct BatchBufsT {
     const int32_t* tile_begin;  // device array (nsys + 1): system j owns tiles [tb[j], tb[j+1])
     int nsys, ntiles, kmax;
     double* partials;
-    double* gpart;              // device array: (KMAX + 3) x TICKET_GROUPS group sums per system
+    double* gpart;              // device array: group sums, (KMAX + 3) x TICKET_GROUPS per system and
+                                // pass type p (0 update, 1 spmv1, 2 spmv2) at (p nsys + j) (KMAX + 3) TICKET_GROUPS
     unsigned* tickets;          // device array: TICKET_WORDS completion counters per system
 };
 using BatchBufs = BatchBufsT<double>;

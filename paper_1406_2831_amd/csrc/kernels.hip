@@ -172,24 +172,27 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
     }
 }
 
-// ---------------------------------------------------------------- in-pass completion
+// ---------------------------------------------------------------- split completion
 //
-// A reducing pass finishes its own reduction.  Every participant (a
-// workgroup, or a tile of a batched pass) stores its partial sums with
-// device-coherent stores (relaxed agent-scope atomics, which write through
-// the XCD's L2), waits until they are performed, and counts itself in one of
-// TICKET_GROUPS counters (participant i in group i mod G).  The last member
-// of a group sums the group's partials in participant order, stores the group
-// sum the same way and counts the group in a top counter; the last group's
-// member sums the group sums in group order and runs the scalar update.  The
-// order of every sum is fixed by the launch shape, so results are the same on
-// every run.  Counters sit on separate 128-byte lines and are reset by the
-// participant that read them last, so they are zero between launches.  Two
-// levels keep the same-address atomics per counter near the square root of
-// the participant count: 1024 workgroups on one counter serialise for
-// microseconds.  Only the partials cross workgroups inside a kernel; the
-// vectors and the scalar state a pass writes reach the next pass through the
-// kernel boundary.
+// A reducing pass finishes the first level of its reduction and the next
+// pass finishes the second.  Every participant (a workgroup, or a tile of a
+// batched pass) stores its partial sums with device-coherent stores (relaxed
+// agent-scope atomics, which write through the XCD's L2), waits until they
+// are performed, and counts itself in one of TICKET_GROUPS counters
+// (participant i in group i mod G, G = min(count, TICKET_GROUPS)).  The last
+// member of a group sums the group's partials in participant order and stores
+// the group sum.  The next pass (after the kernel boundary, which makes those
+// stores visible) adds the G group sums in group order in every one of its
+// workgroups, so all of them derive the same scalars bit for bit, and its
+// workgroup 0 records them in the state.  The order of every sum is fixed by
+// the launch shape, so results are the same on every run.  Counters sit on
+// separate 128-byte lines and are reset by the participant that read them
+// last, so they are zero between launches; two levels keep the same-address
+// atomics per counter near the square root of the participant count (1024
+// workgroups on one counter serialise for microseconds).  Finishing the
+// second level in the consumer takes the top counter, the reloads of the
+// group sums and the scalar update off the end of every pass: each of them is
+// a dependent round trip to memory.
 
 __device__ __forceinline__ void store_coherent(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -232,51 +235,131 @@ __device__ __forceinline__ void block_sum_any(double (&w)[M], int m, double* red
     __syncthreads();
 }
 
-// m sums over the participants held in sums[0..m) (LDS, this participant's
-// totals); returns true (to every thread) for the one participant that
-// finishes the reduction, with the totals in tot[0..m) (LDS).
-__device__ __forceinline__ bool complete(const Completion& cp, const double* sums, int m, int i, int count,
-                                         double* tot) {
+// Sum of row[j * stride] over the members j < n in member order.  The
+// addresses are clamped into the row and the surplus masked by a select, so
+// 32 loads go out together (no branch around each).
+template <bool COHERENT>
+__device__ __forceinline__ double ordered_sum(const double* row, int n, int64_t stride) {
+    double acc = 0.0;
+    for (int j0 = 0; j0 < n; j0 += 32) {
+        double t[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int j = j0 + u < n ? j0 + u : n - 1;
+            const double x = COHERENT ? load_coherent(row + j * stride) : row[j * stride];
+            t[u] = j0 + u < n ? x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc += t[u];
+    }
+    return acc;
+}
+
+// First level: participant i of count stores its m sums (sums[0..m), LDS);
+// the last member of its group writes the group's sums to gsum[v * G + g].
+__device__ __forceinline__ void complete_groups(const Completion& cp, double* gsum, const double* sums, int m,
+                                                int i, int count) {
     for (int v = threadIdx.x; v < m; v += blockDim.x) store_coherent(cp.part + (int64_t)v * cp.pstride + i, sums[v]);
     const int G = count < TICKET_GROUPS ? count : TICKET_GROUPS;
     const int g = i % G;
     const int gsize = (count - g + G - 1) / G;   // participants g, g + G, ...
-    if (!count_in(cp.ctr + g * TICKET_STRIDE, (unsigned)gsize)) return false;
-    for (int v = threadIdx.x; v < m; v += blockDim.x) {
-        const double* row = cp.part + (int64_t)v * cp.pstride;
-        double acc = 0.0;
-        for (int j0 = 0; j0 < gsize; j0 += 8) {   // loads of eight members in flight
-            double t[8];
+    if (!count_in(cp.ctr + g * TICKET_STRIDE, (unsigned)gsize)) return;
+    for (int v = threadIdx.x; v < m; v += blockDim.x)
+        gsum[v * TICKET_GROUPS + g] = ordered_sum<true>(cp.part + (int64_t)v * cp.pstride + g, gsize, G);
+}
+
+// Second level, in the next pass: tot[v] (LDS) = the sum of the G group sums
+// of value v in group order, v < m, for a reduction over `count`
+// participants.  group_loads leaves the barrier to the caller (which issues
+// its other reads first, so that they share the round trip); group_totals
+// returns to every thread after tot is complete.
+__device__ __forceinline__ void group_loads(const double* gsum, int m, int count, double* tot) {
+    const int G = count < TICKET_GROUPS ? count : TICKET_GROUPS;
+    for (int v = threadIdx.x; v < m; v += blockDim.x) tot[v] = ordered_sum<false>(gsum + v * TICKET_GROUPS, G, 1);
+}
+
+__device__ __forceinline__ void group_totals(const double* gsum, int m, int count, double* tot) {
+    group_loads(gsum, m, count, tot);
+    __syncthreads();
+}
+
+// The same second level split around the caller's own loads: group_raw_load
+// issues the raw group sums (value v's G sums are raw elements 32 v .. 32 v +
+// G, spread over the threads, R per thread), the caller then issues the
+// loads of its first rows, and group_raw_finish (every thread) stages the
+// raw sums through LDS (raw: 32 m doubles) and adds each value's in group
+// order, so the round trip of the group sums overlaps that of the rows.
+template <int R>
+struct GroupRaw {
+    double v[R];
+};
+
+template <int R>
+__device__ __forceinline__ GroupRaw<R> group_raw_load(const double* gsum, int m, int stride = BLOCK) {
+    GroupRaw<R> g;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = j0 + u < gsize ? load_coherent(row + g + (j0 + u) * G) : 0.0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc += t[u];
-        }
-        store_coherent(cp.gpart + v * TICKET_GROUPS + g, acc);
+    for (int q = 0; q < R; ++q) {
+        const int e = threadIdx.x + q * stride;
+        const double x = gsum[e < 32 * m ? e : 0];
+        g.v[q] = e < 32 * m ? x : 0.0;
     }
-    if (!count_in(cp.ctr + TICKET_GROUPS * TICKET_STRIDE, (unsigned)G)) return false;
+    return g;
+}
+
+template <int R>
+__device__ __forceinline__ void group_raw_finish(const GroupRaw<R>& g, int m, int count, double* raw, double* tot,
+                                                 int stride = BLOCK) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int e = threadIdx.x + q * stride;
+        if (e < 32 * m) raw[e] = g.v[q];
+    }
+    __syncthreads();
+    const int G = count < TICKET_GROUPS ? count : TICKET_GROUPS;
     for (int v = threadIdx.x; v < m; v += blockDim.x) {
-        const double* row = cp.gpart + v * TICKET_GROUPS;
-        double t[TICKET_GROUPS];
-#pragma unroll
-        for (int u = 0; u < TICKET_GROUPS; ++u) t[u] = u < G ? load_coherent(row + u) : 0.0;
         double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < TICKET_GROUPS; ++u) acc += t[u];
+        for (int u = 0; u < G; ++u) acc += raw[v * TICKET_GROUPS + u];
         tot[v] = acc;
     }
     __syncthreads();
-    return true;
 }
 
-// Workgroup sums of m (<= M) values, then complete(): participant i of count.
+// raw elements per thread for m values
+constexpr int raw_per_thread(int m) { return (32 * m + BLOCK - 1) / BLOCK; }
+
+// Up to MMAX values: staged raw sums when they fit RAW_MAX_VALUES (at most 10
+// raw loads per thread, 20 KB of LDS), otherwise thread-per-value sums
+// issued at the finish (still after the caller's row loads, so the round
+// trips overlap as well; only with more registers live).
+constexpr int RAW_MAX_VALUES = 80;
+
+template <int MMAX>
+struct GroupSums {
+    static constexpr bool kRaw = MMAX <= RAW_MAX_VALUES;
+    static constexpr int R = kRaw ? raw_per_thread(MMAX) : 1;
+    GroupRaw<R> g;
+    const double* gsum;
+    int m;
+    __device__ __forceinline__ void load(const double* gs, int mv) {
+        gsum = gs;
+        m = mv;
+        if constexpr (kRaw) g = group_raw_load<R>(gs, mv);
+    }
+    // raw: LDS of 32 MMAX doubles (kRaw only); tot: LDS of MMAX doubles
+    __device__ __forceinline__ void finish(int count, double* raw, double* tot) {
+        if constexpr (kRaw) group_raw_finish<R>(g, m, count, raw, tot);
+        else group_totals(gsum, m, count, tot);
+    }
+};
+
+// Workgroup sums of m (<= M) values, then the first level: participant i of count.
 template <int M>
-__device__ __forceinline__ bool block_complete(double (&v)[M], int m, const Completion& cp, int i, int count,
-                                               double* tot) {
+__device__ __forceinline__ void block_groups(double (&v)[M], int m, const Completion& cp, double* gsum, int i,
+                                             int count) {
     __shared__ double red[(BLOCK / WAVE) * M];
     __shared__ double sums[M];
     block_sum_any<M>(v, m, red, sums);
-    return complete(cp, sums, m, i, count, tot);
+    complete_groups(cp, gsum, sums, m, i, count);
 }
 
 // Row product of the sliced matrix.  Entries are fetched eight at a time
@@ -309,6 +392,15 @@ __device__ __forceinline__ T sell_row(const SellT<T>& A, int64_t row, const T* _
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// A value that is the same in every lane (a scalar read from LDS), moved to
+// scalar registers: the vector registers stay free for the loads in flight.
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Offset of block column j for a kernel compiled for K >= k columns.  Past
 // the live k columns the index is clamped to column k-1 (a cached re-read)
@@ -956,6 +1048,7 @@ __global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufsT<T> B, int nb) {
         st->alpha = st->beta = st->omega = 0.0;
         st->omega_zero = 0;
         st->iter = 1;
+        st->fresh = 1;
         st->rr = tot[0];
         st->rho = tot[1];
         if (!finite(tot[0]) || !finite(tot[1])) {
@@ -971,191 +1064,389 @@ __global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufsT<T> B, int nb) {
     }
 }
 
-// update pass (end of iteration i-1 and start of iteration i) over the rows
-// r0, r0 + step, ... < r1 of one system; the K + 3 sums accumulate into acc.
+// The row work of the three passes, split into the loads that do not depend
+// on the iteration's scalars and the arithmetic that does, so that a pass can
+// issue its first row's loads before the scalar step's round trip.  Block
+// columns are carried in registers up to bucket PREF_K; above it they are
+// read in the arithmetic part.
+constexpr int PREF_K = 16;
+template <int K>
+constexpr int pref_cols() { return K > 0 && K <= PREF_K ? K : 1; }
+
+// update: (end of iteration i-1 and start of iteration i) r = s - omega t,
+// x += alpha p + omega s, p = r + beta (p - omega q); sums ||r||^2,
+// (rt0, r), (rh, p), Gh^T p
+template <int K>
+struct UpdateRow {
+    double s, t, p, q, x, rt0, rh;
+    double gh[pref_cols<K>()];
+};
+
+template <typename T, int K>
+__device__ __forceinline__ UpdateRow<K> update_load(const SolveBufsT<T>& B, int64_t row) {
+    UpdateRow<K> d;
+    d.s = B.s[row];
+    d.t = B.t[row];
+    d.p = B.p[row];
+    d.q = B.q[row];
+    d.x = B.x[row];
+    d.rt0 = B.rt0[row];
+    d.rh = B.rh[row];
+    if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) d.gh[j] = B.Gh[row + col_off(j, B.k, B.ld)];
+    }
+    return d;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void update_finish(const SolveBufsT<T>& B, int64_t row, const UpdateRow<K>& d,
+                                              double alpha, double omega, double beta, double (&acc)[K + 3]) {
+    const double rv = d.s - omega * d.t;
+    B.x[row] = d.x + (alpha * d.p + omega * d.s);
+    const double pn = rv + beta * (d.p - omega * d.q);
+    B.r[row] = rv;
+    B.p[row] = pn;
+    acc[0] += rv * rv;
+    acc[1] += d.rt0 * rv;
+    acc[2] += d.rh * pn;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double g;
+        if constexpr (K <= PREF_K) g = d.gh[j];
+        else g = B.Gh[row + col_off(j, B.k, B.ld)];
+        acc[3 + j] += g * pn;
+    }
+}
+
+// rows r0, r0 + step, ... < r1 of one system; the K + 3 sums accumulate into acc.
 // k > 0 is required when K > 0 (the batched passes check it per system).
 template <typename T, int K>
 __device__ __forceinline__ void update_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
-                                            double (&acc)[K + 3]) {
-    const SolveState* st = B.state;
-    const int k = B.k;
-    const double alpha = st->alpha, omega = st->omega, beta = st->beta;
-    for (int64_t row = r0; row < r1; row += step) {
-        const double sv = B.s[row], tv = B.t[row], pv = B.p[row], qv = B.q[row];
-        const double rv = sv - omega * tv;
-        B.x[row] += alpha * pv + omega * sv;
-        const double pn = rv + beta * (pv - omega * qv);
-        B.r[row] = rv;
-        B.p[row] = pn;
-        acc[0] += rv * rv;
-        acc[1] += B.rt0[row] * rv;
-        acc[2] += B.rh[row] * pn;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[3 + j] += B.Gh[row + col_off(j, k, B.ld)] * pn;
-    }
+                                            double alpha, double omega, double beta, double (&acc)[K + 3]) {
+    alpha = uniform(alpha);
+    omega = uniform(omega);
+    beta = uniform(beta);
+    for (int64_t row = r0; row < r1; row += step) update_finish<T, K>(B, row, update_load<T, K>(B, row), alpha,
+                                                                      omega, beta, acc);
 }
 
-__device__ void update_fin_scalars(SolveState* st, const double* tot, int k);
-__device__ void spmv2_fin_scalars(SolveState* st, const double* tot, int k);
+// spmv1: q = A p - C zeta ; s = r - alpha q ; sums Gh^T s
+template <int K>
+struct Spmv1Row {
+    double ap, r;
+    double c[pref_cols<K>()], gh[pref_cols<K>()];
+};
 
-// fin = 0 (timing only): the last workgroup reduces but leaves the state alone
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B, int fin) {
-    constexpr int M = K + 3;
-    SolveState* st = B.state;
-    if (st->done) return;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M];
+__device__ __forceinline__ Spmv1Row<K> spmv1_load(const SolveBufsT<T>& B, int64_t row) {
+    Spmv1Row<K> d;
+    d.ap = sell_row(B.A, row, B.p);
+    d.r = B.r[row];
+    if constexpr (K > 0 && K <= PREF_K) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    update_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
-    __shared__ double tot[M];
-    if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
-    if (fin && threadIdx.x == 0) update_fin_scalars(st, tot, B.k);
-}
-
-// Scalar part of the update finalize for one system: convergence / breakdown
-// tests on ||r||^2 and (rt0, r), then alpha from (rh, p) - w^T zeta.
-// tot = [||r||^2, (rt0, r), (rh, p), Gh^T p (k values)].
-__device__ void update_fin_scalars(SolveState* st, const double* tot, int k) {
-    const int i = st->iter;
-    const double rr = tot[0], rho = tot[1];
-    st->rr = rr;
-    if (!finite(rr) || !finite(rho)) {
-        st->done = 1;
-        st->status = S_NONFINITE;
-        st->iters_done = i - 1;
-    } else if (rr <= st->tol2) {
-        st->done = 1;
-        st->status = S_OK;
-        st->iters_done = i - 1;
-    } else if (st->omega_zero) {
-        st->done = 1;
-        st->status = S_BD_OMEGA;
-        st->iters_done = i - 1;
-    } else if (i > st->max_it) {
-        st->done = 1;
-        st->status = S_MAXIT;
-        st->iters_done = i - 1;
-    } else if (rho == 0.0) {
-        st->done = 1;
-        st->status = S_BD_RHO;
-        st->iters_done = i - 1;
-    } else {
-        double den = tot[2];
-        for (int j = 0; j < k; ++j) {
-            st->zeta[j] = tot[3 + j];
-            den -= st->w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
-        }
-        if (den == 0.0 || !finite(den)) {
-            st->done = 1;
-            st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
-            st->iters_done = i - 1;
-        } else {
-            st->rho = rho;
-            st->alpha = rho / den;
+        for (int j = 0; j < K; ++j) {
+            const int64_t o = row + col_off(j, B.k, B.ld);
+            d.c[j] = B.C[o];
+            d.gh[j] = B.Gh[o];
         }
     }
+    return d;
 }
 
-// spmv1: q = A p - C zeta ; s = r - alpha q ; partials Gh^T s (rows as update_rows)
 template <typename T, int K>
-__device__ __forceinline__ void spmv1_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
-                                           double (&acc)[K > 0 ? K : 1]) {
-    constexpr int M = K > 0 ? K : 1;
-    const SolveState* st = B.state;
-    const int k = B.k;
-    const double alpha = st->alpha;
-    double zeta[M];
+__device__ __forceinline__ void spmv1_finish(const SolveBufsT<T>& B, int64_t row, const Spmv1Row<K>& d,
+                                             double alpha, const double* zeta, double (&acc)[K > 0 ? K : 1]) {
+    double qv = d.ap;
 #pragma unroll
-    for (int j = 0; j < M; ++j) zeta[j] = (j < k) ? st->zeta[j] : 0.0;
-    for (int64_t row = r0; row < r1; row += step) {
-        double qv = sell_row(B.A, row, B.p);
-#pragma unroll
-        for (int j = 0; j < K; ++j) qv -= B.C[row + col_off(j, k, B.ld)] * zeta[j];
-        const double sv = B.r[row] - alpha * qv;
-        B.q[row] = qv;
-        B.s[row] = sv;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] += B.Gh[row + col_off(j, k, B.ld)] * sv;
+    for (int j = 0; j < K; ++j) {
+        double c;
+        if constexpr (K <= PREF_K) c = d.c[j];
+        else c = B.C[row + col_off(j, B.k, B.ld)];
+        qv -= c * zeta[j];
     }
-}
-
-template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B, int fin) {
-    constexpr int M = K > 0 ? K : 1;
-    SolveState* st = B.state;
-    if (st->done) return;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[M];
+    const double sv = d.r - alpha * qv;
+    B.q[row] = qv;
+    B.s[row] = sv;
 #pragma unroll
-    for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    spmv1_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
-    if constexpr (K > 0) {
-        __shared__ double tot[M];
-        if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
-        if (fin && threadIdx.x < B.k) st->gamma[threadIdx.x] = tot[threadIdx.x];
+    for (int j = 0; j < K; ++j) {
+        double g;
+        if constexpr (K <= PREF_K) g = d.gh[j];
+        else g = B.Gh[row + col_off(j, B.k, B.ld)];
+        acc[j] += g * sv;
     }
 }
 
 // spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
+template <int K>
+struct Spmv2Row {
+    double as, s, rt;
+    double c[pref_cols<K>()];
+};
+
 template <typename T, int K>
-__device__ __forceinline__ void spmv2_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
-                                           double (&acc)[5]) {
-    const SolveState* st = B.state;
-    const int k = B.k;
-    double gam[K > 0 ? K : 1];
+__device__ __forceinline__ Spmv2Row<K> spmv2_load(const SolveBufsT<T>& B, int64_t row) {
+    Spmv2Row<K> d;
+    d.as = sell_row(B.A, row, B.s);
+    d.s = B.s[row];
+    d.rt = B.rt0[row];
+    if constexpr (K > 0 && K <= PREF_K) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) gam[j] = (j < k) ? st->gamma[j] : 0.0;
-    for (int64_t row = r0; row < r1; row += step) {
-        double tv = sell_row(B.A, row, B.s);
-#pragma unroll
-        for (int j = 0; j < K; ++j) tv -= B.C[row + col_off(j, k, B.ld)] * gam[j];
-        B.t[row] = tv;
-        const double sv = B.s[row], rt = B.rt0[row];
-        acc[0] += sv * tv;
-        acc[1] += tv * tv;
-        acc[2] += rt * sv;
-        acc[3] += rt * tv;
-        acc[4] += sv * sv;
+        for (int j = 0; j < K; ++j) d.c[j] = B.C[row + col_off(j, B.k, B.ld)];
     }
+    return d;
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B, int fin) {
-    SolveState* st = B.state;
-    if (st->done) return;
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    spmv2_rows<T, K>(B, r0 + threadIdx.x, r1, BLOCK, acc);
-    __shared__ double tot[5];
-    if (!block_complete<5>(acc, 5, B.cp, blockIdx.x, gridDim.x, tot)) return;
-    if (fin && threadIdx.x == 0) spmv2_fin_scalars(st, tot, B.k);
+__device__ __forceinline__ void spmv2_finish(const SolveBufsT<T>& B, int64_t row, const Spmv2Row<K>& d,
+                                             const double* gam, double (&acc)[5]) {
+    double tv = d.as;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double c;
+        if constexpr (K <= PREF_K) c = d.c[j];
+        else c = B.C[row + col_off(j, B.k, B.ld)];
+        tv -= c * gam[j];
+    }
+    B.t[row] = tv;
+    acc[0] += d.s * tv;
+    acc[1] += tv * tv;
+    acc[2] += d.rt * d.s;
+    acc[3] += d.rt * tv;
+    acc[4] += d.s * d.s;
 }
 
-// Scalar part of the second finalize for one system: omega, x_c, beta.
-// tot = [(s,t), (t,t), (rt0,s), (rt0,t), (s,s)].
-__device__ void spmv2_fin_scalars(SolveState* st, const double* tot, int k) {
+// ---- the scalar steps of Algorithm 2, from the previous pass's totals
+
+// Closing iteration i from spmv2's totals tot = [(s,t), (t,t), (rt0,s),
+// (rt0,t), (s,s)]: omega, whether it is exactly zero (a breakdown unless s
+// already meets the tolerance), and beta from (rt0, r_i) = (rt0, s) -
+// omega (rt0, t), with alpha_i and rho_i of the state.
+struct OmegaStep {
+    double omega, beta;
+    int omega_zero;
+};
+
+__device__ __forceinline__ OmegaStep omega_step(const double* tot, double alpha, double rho, double tol2) {
     const double st_ = tot[0], tt = tot[1], rts = tot[2], rtt = tot[3];
-    const double alpha = st->alpha;
-    double omega;
+    OmegaStep o;
     if (tt == 0.0) {
         // (t, t) = 0: accept the half step x + alpha p if ||s|| <= tol
         // (the next update pass sees r = s and tests it), else breakdown
-        omega = 0.0;
-        st->omega_zero = tot[4] <= st->tol2 ? 0 : 1;
+        o.omega = 0.0;
+        o.omega_zero = tot[4] <= tol2 ? 0 : 1;
     } else {
-        omega = st_ / tt;
-        st->omega_zero = omega == 0.0 ? 1 : 0;
+        o.omega = st_ / tt;
+        o.omega_zero = o.omega == 0.0 ? 1 : 0;
     }
-    st->omega = omega;
-    for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + omega * st->gamma[j];
-    const double rho_new = rts - omega * rtt;   // (rt0, r_i) = (rt0, s) - omega (rt0, t)
-    st->beta = omega != 0.0 ? (rho_new / st->rho) * (alpha / omega) : 0.0;
+    const double rho_new = rts - o.omega * rtt;
+    o.beta = o.omega != 0.0 ? (rho_new / rho) * (alpha / o.omega) : 0.0;
+    return o;
+}
+
+// workgroup 0's record of omega_step: omega, beta, x_c += alpha zeta + omega gamma, i + 1
+__device__ __forceinline__ void record_omega(SolveState* st, const OmegaStep& o, int k) {
+    st->omega = o.omega;
+    st->omega_zero = o.omega_zero;
+    st->beta = o.beta;
+    const double alpha = st->alpha;
+    for (int j = 0; j < k; ++j) st->xc[j] += alpha * st->zeta[j] + o.omega * st->gamma[j];
     st->iter += 1;
+}
+
+// The state fields the start of an iteration tests.
+struct IterCheck {
+    double tol2;
+    int iter, max_it, omega_zero;
+};
+
+__device__ __forceinline__ IterCheck iter_check(const SolveState* st) {
+    IterCheck c;
+    c.tol2 = st->tol2;
+    c.iter = st->iter;
+    c.max_it = st->max_it;
+    c.omega_zero = st->omega_zero;
+    return c;
+}
+
+// Starting iteration i from the update pass's totals tot = [||r||^2,
+// (rt0, r), (rh, p), Gh^T p (k values)] and w = C^T rt0: the convergence and
+// breakdown tests, then alpha = (rt0, r) / ((rh, p) - w^T zeta).  Returns the
+// status that ends the solve, or -1 to go on (alpha in *alpha).
+__device__ __forceinline__ int alpha_step(const IterCheck& c, const double* tot, const double* w, int k,
+                                          double* alpha) {
+    const double rr = tot[0], rho = tot[1];
+    if (!finite(rr) || !finite(rho)) return S_NONFINITE;
+    if (rr <= c.tol2) return S_OK;
+    if (c.omega_zero) return S_BD_OMEGA;
+    if (c.iter > c.max_it) return S_MAXIT;
+    if (rho == 0.0) return S_BD_RHO;
+    double den = tot[2];
+    for (int j = 0; j < k; ++j) den -= w[j] * tot[3 + j];   // (rt0, q_i) = (rh, p_i) - (C^T rt0)^T zeta_i
+    if (den == 0.0) return S_BD_ALPHA;
+    if (!finite(den)) return S_NONFINITE;
+    *alpha = rho / den;
+    return -1;
+}
+
+// workgroup 0's record of alpha_step
+__device__ __forceinline__ void record_alpha(SolveState* st, const double* tot, int k, int status,
+                                             double alpha) {
+    st->rr = tot[0];
+    if (status >= S_OK || status == S_NONFINITE) {
+        st->done = 1;
+        st->status = status;
+        st->iters_done = st->iter - 1;
+        return;
+    }
+    st->rho = tot[1];
+    st->alpha = alpha;
+    for (int j = 0; j < k; ++j) st->zeta[j] = tot[3 + j];
+    st->fresh = 0;
+}
+
+// update pass: closes iteration i - 1 (omega, beta from spmv2's group sums;
+// the prologue's zeros on the first iteration) and forms r, x, p; first level
+// of ||r||^2, (rt0, r), (rh, p), Gh^T p.  fin = 0 (timing): the scalars come
+// from the state and nothing is recorded.  The state fields, the done flag,
+// the group sums and the first row's operands are all read before the
+// scalar step waits for any of them.
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B, int fin) {
+    constexpr int M = K + 3;
+    SolveState* st = B.state;
+    const int done = st->done, fresh = st->fresh;
+    const double alpha0 = st->alpha, omega0 = st->omega, beta0 = st->beta, rho = st->rho, tol2 = st->tol2;
+    __shared__ double raw[32 * 5];
+    __shared__ double tot[5];
+    const GroupRaw<1> g = group_raw_load<1>(B.cp.gs[2], 5);   // (unused on the first iteration)
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + threadIdx.x;
+    UpdateRow<K> d0;
+    if (row0 < r1) d0 = update_load<T, K>(B, row0);
+    if (done) return;
+    double omega = omega0, beta = beta0;   // first iteration: the prologue's zeros; timing: the state's
+    if (!fresh) {
+        group_raw_finish<1>(g, 5, gridDim.x, raw, tot);
+        const OmegaStep o = omega_step(tot, alpha0, rho, tol2);
+        if (fin) {
+            omega = o.omega;
+            beta = o.beta;
+            if (blockIdx.x == 0 && threadIdx.x == 0) record_omega(st, o, B.k);
+        }
+    }
+    const double alpha = uniform(alpha0);
+    omega = uniform(omega);
+    beta = uniform(beta);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    if (row0 < r1) update_finish<T, K>(B, row0, d0, alpha, omega, beta, acc);
+    update_rows<T, K>(B, row0 + BLOCK, r1, BLOCK, alpha, omega, beta, acc);
+    block_groups<M>(acc, M, B.cp, B.cp.gs[0], blockIdx.x, gridDim.x);
+}
+
+// spmv1 rows r0, r0 + step, ... < r1 (as update_rows)
+template <typename T, int K>
+__device__ __forceinline__ void spmv1_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step, double alpha,
+                                           const double* zeta_s, double (&acc)[K > 0 ? K : 1]) {
+    constexpr int M = K > 0 ? K : 1;
+    const int k = B.k;
+    double zeta[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) zeta[j] = uniform((j < k) ? zeta_s[j] : 0.0);
+    alpha = uniform(alpha);
+    for (int64_t row = r0; row < r1; row += step)
+        spmv1_finish<T, K>(B, row, spmv1_load<T, K>(B, row), alpha, zeta, acc);
+}
+
+// spmv1: starts iteration i (the tests, alpha and zeta from the update
+// pass's group sums); q = A p - C zeta ; s = r - alpha q ; first level of
+// Gh^T s.  The first row's product and operands are read before the scalar
+// step waits for the group sums.
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B, int fin) {
+    constexpr int M = K > 0 ? K : 1;
+    constexpr int MU = K + 3;
+    constexpr int R = raw_per_thread(MU);
+    SolveState* st = B.state;
+    const int done = st->done;
+    const IterCheck chk = iter_check(st);
+    __shared__ double raw[32 * MU];
+    __shared__ double tot[MU];
+    __shared__ double sw[M];
+    const GroupRaw<R> g = group_raw_load<R>(B.cp.gs[0], MU);
+    const double wv = st->w[threadIdx.x < KMAX ? threadIdx.x : 0];
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + threadIdx.x;
+    Spmv1Row<K> d0;
+    if (row0 < r1) d0 = spmv1_load<T, K>(B, row0);
+    if (done) return;
+    if (threadIdx.x < B.k) sw[threadIdx.x] = wv;
+    group_raw_finish<R>(g, MU, gridDim.x, raw, tot);
+    double alpha = 0.0;
+    const int status = alpha_step(chk, tot, sw, B.k, &alpha);
+    if (fin && blockIdx.x == 0 && threadIdx.x == 0) record_alpha(st, tot, B.k, status, alpha);
+    if (fin && status != -1) return;   // the solve ends here
+    if (!fin) alpha = st->alpha;
+    const double* zs = fin ? tot + 3 : st->zeta;
+    double zeta[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) zeta[j] = uniform(j < B.k ? zs[j] : 0.0);
+    alpha = uniform(alpha);
+    double acc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc[j] = 0.0;
+    if (row0 < r1) spmv1_finish<T, K>(B, row0, d0, alpha, zeta, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK)
+        spmv1_finish<T, K>(B, row, spmv1_load<T, K>(B, row), alpha, zeta, acc);
+    if constexpr (K > 0) block_groups<M>(acc, M, B.cp, B.cp.gs[1], blockIdx.x, gridDim.x);
+}
+
+// spmv2 rows r0, r0 + step, ... < r1 (as update_rows)
+template <typename T, int K>
+__device__ __forceinline__ void spmv2_rows(const SolveBufsT<T>& B, int64_t r0, int64_t r1, int step,
+                                           const double* gamma_s, double (&acc)[5]) {
+    const int k = B.k;
+    double gam[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) gam[j] = uniform((j < k) ? gamma_s[j] : 0.0);
+    for (int64_t row = r0; row < r1; row += step) spmv2_finish<T, K>(B, row, spmv2_load<T, K>(B, row), gam, acc);
+}
+
+// spmv2: gamma from spmv1's group sums; t = A s - C gamma ; first level of
+// (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
+template <typename T, int K>
+__global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B, int fin) {
+    constexpr int KM = K > 0 ? K : 1;
+    constexpr int R = raw_per_thread(KM);
+    SolveState* st = B.state;
+    const int done = st->done;
+    __shared__ double raw[32 * KM];
+    __shared__ double gtot[KM];
+    GroupRaw<R> g;
+    if constexpr (K > 0) g = group_raw_load<R>(B.cp.gs[1], K);
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + threadIdx.x;
+    Spmv2Row<K> d0;
+    if (row0 < r1) d0 = spmv2_load<T, K>(B, row0);
+    if (done) return;
+    double gam[KM];
+    if constexpr (K > 0) {
+        group_raw_finish<R>(g, K, gridDim.x, raw, gtot);
+        if (fin && blockIdx.x == 0 && threadIdx.x < B.k) st->gamma[threadIdx.x] = gtot[threadIdx.x];
+        const double* gs = fin ? gtot : st->gamma;
+#pragma unroll
+        for (int j = 0; j < K; ++j) gam[j] = uniform(j < B.k ? gs[j] : 0.0);
+    }
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (row0 < r1) spmv2_finish<T, K>(B, row0, d0, gam, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK)
+        spmv2_finish<T, K>(B, row, spmv2_load<T, K>(B, row), gam, acc);
+    block_groups<5>(acc, 5, B.cp, B.cp.gs[2], blockIdx.x, gridDim.x);
 }
 
 // epilogue: x_out = x - U x_c (the final correction of RBiCGSTAB, Section 4)
@@ -1204,92 +1495,140 @@ __global__ __launch_bounds__(BLOCK) void k_true_res_fin(const double* partials, 
 // Persistent kernels over the tiles of a batch of independent systems: the
 // per-row work is the single-system pass's (update_rows / spmv1_rows /
 // spmv2_rows); a system without recycle space (k = 0) runs the K = 0 body.
-// Each tile's partial goes to column t of the value-major tile partials; the
-// workgroup that completes a system's last tile (a ticket per system) sums
-// that system's tile partials in tile order and updates its scalars, so a
-// system's reduction is done as soon as its own tiles are, while the other
-// workgroups go on with other systems' tiles.
+// Each tile's partial goes to column t of the value-major tile partials and
+// counts in on its system's group counters; a tile first derives its
+// system's scalars from the previous pass's group sums of that system, and
+// the workgroup that takes the system's first tile records them.  A system's
+// reduction thus needs only its own tiles, while the workgroups go on with
+// other systems' tiles.
 
-// tile t of system sys: its partial, then the system's completion (tiles
-// b0..b1 of the system are its participants; per-system group sums and counters)
+// group sums of pass type p for system sys
+template <typename T>
+__device__ __forceinline__ double* batch_gsum(const BatchBufsT<T>& B, int p, int sys) {
+    return B.gpart + ((int64_t)p * B.nsys + sys) * (KMAX + 3) * TICKET_GROUPS;
+}
+
+// tile t of system sys: its partial, then the first level over the system's
+// tiles (tiles b0..b1 of the system are its participants)
 template <int M, typename T>
-__device__ __forceinline__ bool tile_done(double (&v)[M], const BatchBufsT<T>& B, int t, int sys,
-                                          double* tot) {
+__device__ __forceinline__ void tile_groups(double (&v)[M], const BatchBufsT<T>& B, int p, int t, int sys) {
     const int b0 = B.tile_begin[sys], b1 = B.tile_begin[sys + 1];
     Completion cp;
     cp.part = B.partials + b0;
     cp.pstride = B.ntiles;
-    cp.gpart = B.gpart + (int64_t)sys * (KMAX + 3) * TICKET_GROUPS;
     cp.ctr = B.tickets + (int64_t)sys * (TICKET_GROUPS + 1) * TICKET_STRIDE;
-    return block_complete<M>(v, M, cp, t - b0, b1 - b0, tot);
+    block_groups<M>(v, M, cp, batch_gsum(B, p, sys), t - b0, b1 - b0);
+}
+
+template <typename T>
+__device__ __forceinline__ int batch_tiles(const BatchBufsT<T>& B, int sys) {
+    return B.tile_begin[sys + 1] - B.tile_begin[sys];
 }
 
 template <typename T, int K>
 __global__ __launch_bounds__(BLOCK) void k_batch_update(BatchBufsT<T> B, int fin) {
     constexpr int M = K + 3;
-    __shared__ double tot[M];
+    __shared__ double tot[5];
+    __shared__ double sc[3];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
         const SolveBufsT<T> S = B.sys[tl.sys];
-        if (S.state->done) continue;
+        SolveState* st = S.state;
+        if (st->done) continue;
+        if (!st->fresh) {
+            group_totals(batch_gsum(B, 2, tl.sys), 5, batch_tiles(B, tl.sys), tot);
+            if (threadIdx.x == 0) {
+                const OmegaStep o = omega_step(tot, st->alpha, st->rho, st->tol2);
+                if (fin) {
+                    sc[1] = o.omega;
+                    sc[2] = o.beta;
+                    if (t == B.tile_begin[tl.sys]) record_omega(st, o, S.k);
+                } else {
+                    sc[1] = st->omega;
+                    sc[2] = st->beta;
+                }
+            }
+        } else if (threadIdx.x == 0) {
+            sc[1] = st->omega;
+            sc[2] = st->beta;
+        }
+        if (threadIdx.x == 0) sc[0] = st->alpha;
+        __syncthreads();
         double acc[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) acc[j] = 0.0;
         if (S.k > 0) {
-            update_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
+            update_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, sc[0], sc[1], sc[2], acc);
         } else {
             double a0[3] = {0.0, 0.0, 0.0};
-            update_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
+            update_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, sc[0], sc[1], sc[2], a0);
             acc[0] = a0[0];
             acc[1] = a0[1];
             acc[2] = a0[2];
         }
-        if (tile_done<M>(acc, B, t, tl.sys, tot)) {
-            if (fin && threadIdx.x == 0) update_fin_scalars(S.state, tot, S.k);
-        }
-        __syncthreads();   // tot and the ticket flag are reused by the next tile
+        tile_groups<M>(acc, B, 0, t, tl.sys);
+        __syncthreads();   // the LDS scalars are reused by the next tile
     }
 }
 
 template <typename T, int K>
 __global__ __launch_bounds__(BLOCK) void k_batch_spmv1(BatchBufsT<T> B, int fin) {
     constexpr int M = K > 0 ? K : 1;
-    __shared__ double tot[M];
+    __shared__ double tot[K + 3];
+    __shared__ double sal;
+    __shared__ int sgo;
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
         const SolveBufsT<T> S = B.sys[tl.sys];
-        if (S.state->done) continue;
-        double acc[M];
+        SolveState* st = S.state;
+        if (st->done) continue;
+        group_totals(batch_gsum(B, 0, tl.sys), K + 3, batch_tiles(B, tl.sys), tot);
+        if (threadIdx.x == 0) {
+            double alpha = 0.0;
+            const int status = alpha_step(iter_check(st), tot, st->w, S.k, &alpha);
+            if (fin && t == B.tile_begin[tl.sys]) record_alpha(st, tot, S.k, status, alpha);
+            sgo = (status < 0 || !fin) ? 1 : 0;
+            sal = fin ? alpha : st->alpha;
+        }
+        __syncthreads();
+        if (sgo) {
+            const double* zeta = fin ? tot + 3 : st->zeta;
+            double acc[M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) acc[j] = 0.0;
-        if (S.k > 0) {
-            spmv1_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
-        } else {
-            double a0[1] = {0.0};
-            spmv1_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, a0);
-        }
-        if constexpr (K > 0) {
-            if (tile_done<M>(acc, B, t, tl.sys, tot)) {
-                if (fin && threadIdx.x < S.k) S.state->gamma[threadIdx.x] = tot[threadIdx.x];
+            for (int j = 0; j < M; ++j) acc[j] = 0.0;
+            if (S.k > 0) {
+                spmv1_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, sal, zeta, acc);
+            } else {
+                double a0[1] = {0.0};
+                spmv1_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, sal, zeta, a0);
             }
-            __syncthreads();
+            if constexpr (K > 0) tile_groups<M>(acc, B, 1, t, tl.sys);
         }
+        __syncthreads();
     }
 }
 
 template <typename T, int K>
 __global__ __launch_bounds__(BLOCK) void k_batch_spmv2(BatchBufsT<T> B, int fin) {
-    __shared__ double tot[5];
+    __shared__ double gam[K > 0 ? K : 1];
     for (int t = blockIdx.x; t < B.ntiles; t += gridDim.x) {
         const BatchTile tl = B.tiles[t];
         const SolveBufsT<T> S = B.sys[tl.sys];
-        if (S.state->done) continue;
+        SolveState* st = S.state;
+        if (st->done) continue;
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (S.k > 0) spmv2_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
-        else spmv2_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, acc);
-        if (tile_done<5>(acc, B, t, tl.sys, tot)) {
-            if (fin && threadIdx.x == 0) spmv2_fin_scalars(S.state, tot, S.k);
+        if constexpr (K > 0) {
+            if (S.k > 0) {
+                group_totals(batch_gsum(B, 1, tl.sys), K, batch_tiles(B, tl.sys), gam);
+                if (fin && t == B.tile_begin[tl.sys] && threadIdx.x < S.k) st->gamma[threadIdx.x] = gam[threadIdx.x];
+                spmv2_rows<T, K>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, fin ? gam : st->gamma, acc);
+            } else {
+                spmv2_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, st->gamma, acc);
+            }
+        } else {
+            spmv2_rows<T, 0>(S, tl.r0 + threadIdx.x, tl.r1, BLOCK, st->gamma, acc);
         }
+        tile_groups<5>(acc, B, 2, t, tl.sys);
         __syncthreads();
     }
 }
@@ -1308,140 +1647,332 @@ __global__ void k_gather_states(BatchBufsT<T> B, SolveState* out) {
 // (C, Gh) at about the same time (one HBM fetch, the other waves hit the CU's
 // cache) while each keeps the register footprint of the single-system kernel.
 // Wave sums go to the value-major partials system-major (system j's M values
-// at rows j M ..); the last workgroup to finish reduces every active system's
-// values in block order and updates its scalars, with the arithmetic, and its
-// order, of the single-system passes.
+// at rows j M ..); the split completion runs over all systems' values at
+// once, and thread j of every workgroup derives system j's scalars from them
+// with the arithmetic, and the order, of the single-system passes.
 constexpr int MULTI_W = BLOCK / WAVE;   // systems per launch (one wave each)
 
-__device__ __forceinline__ bool multi_active_any(const MultiBufs& B) {
-    bool any = false;
-    for (int j = 0; j < MULTI_W; ++j) any = any || (j < B.nr && !B.state[j].done);
-    return any;
-}
-
 // Wave j's M sums are values j M .. of the workgroup's partial; then the
-// completion over the workgroups (totals of all systems in tot).
+// first level over the workgroups into the group sums of pass type p.
 template <int M>
-__device__ __forceinline__ bool multi_complete(double (&v)[M], int j, const MultiBufs& B, double* tot) {
+__device__ __forceinline__ void multi_groups(double (&v)[M], int j, const MultiBufs& B, int p) {
     __shared__ double sums[MULTI_W * M];
     wave_sums<M>(v, sums + j * M);
     __syncthreads();
-    return complete(B.cp, sums, B.nr * M, blockIdx.x, gridDim.x, tot);
+    complete_groups(B.cp, B.cp.gs[p], sums, B.nr * M, blockIdx.x, gridDim.x);
 }
+
+// Raw group sums per thread of a multi-RHS workgroup (one wave per system):
+// 32 M values' sums per system over 64 lanes per system.
+template <int M>
+constexpr int multi_raw() { return (32 * M + WAVE - 1) / WAVE; }
 
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
     constexpr int M = K + 3;
-    if (!multi_active_any(B)) return;
+    constexpr int RU = multi_raw<5>();
+    // the group sums, every system's state fields and the first row's
+    // operands are all read before the scalar step waits for any of them
+    __shared__ double raw[MULTI_W * 5 * 32];
+    __shared__ double tot[MULTI_W * 5];
+    __shared__ double sc[MULTI_W][5];   // alpha, omega, beta, rho, tol2
+    __shared__ int sf[MULTI_W][2];      // done, fresh
+    const GroupRaw<RU> g = group_raw_load<RU>(B.cp.gs[2], B.nr * 5, blockDim.x);
+    const int tq = threadIdx.x < B.nr ? threadIdx.x : 0;
+    const SolveState* sq = &B.state[tq];
+    const int q_done = sq->done, q_fresh = sq->fresh;
+    const double q_alpha = sq->alpha, q_omega = sq->omega, q_beta = sq->beta, q_rho = sq->rho, q_tol2 = sq->tol2;
     // the system index is uniform over a wave: keep it (and the scalars read
     // with it) in scalar registers, which leaves the vector registers to the
     // loads in flight
     const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
-    const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
     const int64_t ld = B.ld, so = (int64_t)j * ld;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + lane;
+    double d0[7];
+    double gh0[pref_cols<K>()];
+    if (row0 < r1) {
+        const int64_t o = row0 + so;
+        d0[0] = B.s[o];
+        d0[1] = B.t[o];
+        d0[2] = B.p[o];
+        d0[3] = B.q[o];
+        d0[4] = B.x[o];
+        d0[5] = B.rt0[o];
+        d0[6] = B.rh[o];
+        if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) gh0[jj] = B.Gh[row0 + col_off(jj, k, ld)];
+        }
+    }
+    if (threadIdx.x < B.nr) {
+        sf[threadIdx.x][0] = q_done;
+        sf[threadIdx.x][1] = q_fresh;
+        sc[threadIdx.x][0] = q_alpha;
+        sc[threadIdx.x][1] = q_omega;
+        sc[threadIdx.x][2] = q_beta;
+        sc[threadIdx.x][3] = q_rho;
+        sc[threadIdx.x][4] = q_tol2;
+    }
+    group_raw_finish<RU>(g, B.nr * 5, gridDim.x, raw, tot, blockDim.x);
+    bool any = false;
+    for (int q = 0; q < B.nr; ++q) any = any || !sf[q][0];
+    if (!any) return;
+    if (threadIdx.x < B.nr && !sf[threadIdx.x][0] && !sf[threadIdx.x][1] && fin) {
+        // (otherwise: the prologue's zeros, the timing state, or a finished system)
+        const int q = threadIdx.x;
+        const OmegaStep o = omega_step(tot + q * 5, sc[q][0], sc[q][3], sc[q][4]);
+        sc[q][1] = o.omega;
+        sc[q][2] = o.beta;
+        if (blockIdx.x == 0) record_omega(&B.state[q], o, B.k);
+    }
+    __syncthreads();
+    const bool act = !sf[j][0];
     double acc[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) acc[q] = 0.0;
     if (act) {
-        const double alpha = B.state[j].alpha, omega = B.state[j].omega, beta = B.state[j].beta;
-        int64_t r0, r1;
-        block_rows(B.n, r0, r1);
-        for (int64_t row = r0 + lane; row < r1; row += WAVE) {
+        const double alpha = uniform(sc[j][0]), omega = uniform(sc[j][1]), beta = uniform(sc[j][2]);
+        auto finish = [&](int64_t row, const double* d, const double* gh) {
             const int64_t o = row + so;
-            const double sv = B.s[o], tv = B.t[o], pv = B.p[o], qv = B.q[o];
+            const double sv = d[0], tv = d[1], pv = d[2], qv = d[3];
             const double rv = sv - omega * tv;
-            B.x[o] += alpha * pv + omega * sv;
+            B.x[o] = d[4] + (alpha * pv + omega * sv);
             const double pn = rv + beta * (pv - omega * qv);
             B.r[o] = rv;
             B.p[o] = pn;
             acc[0] += rv * rv;
-            acc[1] += B.rt0[o] * rv;
-            acc[2] += B.rh[o] * pn;
+            acc[1] += d[5] * rv;
+            acc[2] += d[6] * pn;
 #pragma unroll
-            for (int jj = 0; jj < K; ++jj) acc[3 + jj] += B.Gh[row + col_off(jj, k, ld)] * pn;
+            for (int jj = 0; jj < K; ++jj) {
+                double gv;
+                if constexpr (K <= PREF_K) gv = gh[jj];
+                else gv = B.Gh[row + col_off(jj, k, ld)];
+                acc[3 + jj] += gv * pn;
+            }
+        };
+        if (row0 < r1) finish(row0, d0, gh0);
+        for (int64_t row = row0 + WAVE; row < r1; row += WAVE) {
+            const int64_t o = row + so;
+            double d[7] = {B.s[o], B.t[o], B.p[o], B.q[o], B.x[o], B.rt0[o], B.rh[o]};
+            double gh[pref_cols<K>()];
+            if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) gh[jj] = B.Gh[row + col_off(jj, k, ld)];
+            }
+            finish(row, d, gh);
         }
     }
-    __shared__ double tot[MULTI_W * M];
-    if (!multi_complete<M>(acc, j, B, tot)) return;
-    if (fin && threadIdx.x < B.nr && !B.state[threadIdx.x].done)
-        update_fin_scalars(&B.state[threadIdx.x], tot + threadIdx.x * M, B.k);
+    multi_groups<M>(acc, j, B, 0);
 }
 
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
     constexpr int M = K > 0 ? K : 1;
-    if (!multi_active_any(B)) return;
+    constexpr int MU = K + 3;
+    constexpr bool kRaw = MULTI_W * MU <= RAW_MAX_VALUES;
+    constexpr int RU = kRaw ? multi_raw<MU>() : 1;
+    // the group sums, w = C^T rt0, the state fields of every system and the
+    // first row's product and operands are all read before the tests wait
+    __shared__ double raw[kRaw ? MULTI_W * MU * 32 : 1];
+    __shared__ double tot[MULTI_W * MU];
+    __shared__ double sw[MULTI_W * M];
+    __shared__ IterCheck chk[MULTI_W];
+    __shared__ int sdone[MULTI_W];
+    __shared__ double sal[MULTI_W];
+    __shared__ int sgo[MULTI_W];
+    GroupRaw<RU> g;
+    if constexpr (kRaw) g = group_raw_load<RU>(B.cp.gs[0], B.nr * MU, blockDim.x);
+    // nr k <= 64 nr = blockDim.x: at most one w entry per thread
+    const int tw = threadIdx.x < B.nr * B.k ? threadIdx.x : 0;
+    const double wv = B.k > 0 ? B.state[tw / (B.k > 0 ? B.k : 1)].w[tw % (B.k > 0 ? B.k : 1)] : 0.0;
+    const int tq = threadIdx.x < B.nr ? threadIdx.x : 0;
+    const SolveState* sq = &B.state[tq];
+    const int q_done = sq->done;
+    const IterCheck q_chk = iter_check(sq);
+    const double q_alpha = sq->alpha;
     const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
-    const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
     const int64_t ld = B.ld, so = (int64_t)j * ld;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + lane;
+    double ap0 = 0.0, rv0 = 0.0;
+    double c0[pref_cols<K>()], gh0[pref_cols<K>()];
+    if (row0 < r1) {
+        ap0 = sell_row(B.A, row0, B.p + so);
+        rv0 = B.r[row0 + so];
+        if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) {
+                const int64_t o = row0 + col_off(jj, k, ld);
+                c0[jj] = B.C[o];
+                gh0[jj] = B.Gh[o];
+            }
+        }
+    }
+    if (threadIdx.x < B.nr * B.k) sw[(threadIdx.x / B.k) * M + threadIdx.x % B.k] = wv;
+    if (threadIdx.x < B.nr) {
+        sdone[threadIdx.x] = q_done;
+        chk[threadIdx.x] = q_chk;
+        sal[threadIdx.x] = q_alpha;
+    }
+    if constexpr (kRaw) group_raw_finish<RU>(g, B.nr * MU, gridDim.x, raw, tot, blockDim.x);
+    else group_totals(B.cp.gs[0], B.nr * MU, gridDim.x, tot);
+    bool any = false;
+    for (int q = 0; q < B.nr; ++q) any = any || !sdone[q];
+    if (!any) return;
+    if (threadIdx.x < B.nr) {
+        const int q = threadIdx.x;
+        int go = 0;
+        if (!sdone[q]) {
+            double alpha = 0.0;
+            const int status = alpha_step(chk[q], tot + q * MU, sw + q * M, B.k, &alpha);
+            if (fin) {
+                if (blockIdx.x == 0) record_alpha(&B.state[q], tot + q * MU, B.k, status, alpha);
+                go = status == -1 ? 1 : 0;
+                sal[q] = alpha;
+            } else {   // timing: the state's scalars
+                go = 1;
+            }
+        }
+        sgo[q] = go;
+    }
+    __syncthreads();
+    const bool act = sgo[j];
     double acc[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) acc[q] = 0.0;
     if (act) {
-        const double alpha = B.state[j].alpha;
+        const double alpha = uniform(sal[j]);
+        const double* zs = fin ? tot + j * MU + 3 : B.state[j].zeta;
         double zeta[M];
 #pragma unroll
-        for (int q = 0; q < M; ++q) zeta[q] = q < k ? B.state[j].zeta[q] : 0.0;
-        int64_t r0, r1;
-        block_rows(B.n, r0, r1);
-        for (int64_t row = r0 + lane; row < r1; row += WAVE) {
+        for (int q = 0; q < M; ++q) zeta[q] = uniform(q < k ? zs[q] : 0.0);
+        auto finish = [&](int64_t row, double ap, double rv, const double* c, const double* gh) {
             const int64_t o = row + so;
-            double qv = sell_row(B.A, row, B.p + so);
+            double qv = ap;
 #pragma unroll
-            for (int jj = 0; jj < K; ++jj) qv -= B.C[row + col_off(jj, k, ld)] * zeta[jj];
-            const double sv = B.r[o] - alpha * qv;
+            for (int jj = 0; jj < K; ++jj) {
+                double cv;
+                if constexpr (K <= PREF_K) cv = c[jj];
+                else cv = B.C[row + col_off(jj, k, ld)];
+                qv -= cv * zeta[jj];
+            }
+            const double sv = rv - alpha * qv;
             B.q[o] = qv;
             B.s[o] = sv;
 #pragma unroll
-            for (int jj = 0; jj < K; ++jj) acc[jj] += B.Gh[row + col_off(jj, k, ld)] * sv;
+            for (int jj = 0; jj < K; ++jj) {
+                double gv;
+                if constexpr (K <= PREF_K) gv = gh[jj];
+                else gv = B.Gh[row + col_off(jj, k, ld)];
+                acc[jj] += gv * sv;
+            }
+        };
+        if (row0 < r1) finish(row0, ap0, rv0, c0, gh0);
+        for (int64_t row = row0 + WAVE; row < r1; row += WAVE) {
+            const double ap = sell_row(B.A, row, B.p + so);
+            const double rv = B.r[row + so];
+            double c[pref_cols<K>()], gh[pref_cols<K>()];
+            if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) {
+                    const int64_t o = row + col_off(jj, k, ld);
+                    c[jj] = B.C[o];
+                    gh[jj] = B.Gh[o];
+                }
+            }
+            finish(row, ap, rv, c, gh);
         }
     }
-    if constexpr (K > 0) {
-        __shared__ double tot[MULTI_W * M];
-        if (!multi_complete<M>(acc, j, B, tot)) return;
-        if (fin)
-            for (int t = threadIdx.x; t < B.nr * k; t += blockDim.x) {
-                const int sy = t / k, q = t % k;
-                if (!B.state[sy].done) B.state[sy].gamma[q] = tot[sy * M + q];
-            }
-    }
+    if constexpr (K > 0) multi_groups<M>(acc, j, B, 1);
 }
 
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B, int fin) {
     constexpr int KM = K > 0 ? K : 1;
-    if (!multi_active_any(B)) return;
+    constexpr bool kRaw = MULTI_W * KM <= RAW_MAX_VALUES;
+    constexpr int RU = kRaw ? multi_raw<KM>() : 1;
+    __shared__ double raw[kRaw && K > 0 ? MULTI_W * KM * 32 : 1];
+    __shared__ double gtot[MULTI_W * KM];
+    __shared__ int sdone[MULTI_W];
+    GroupRaw<RU> g;
+    if constexpr (K > 0 && kRaw) g = group_raw_load<RU>(B.cp.gs[1], B.nr * K, blockDim.x);
+    const int q_done = B.state[threadIdx.x < B.nr ? threadIdx.x : 0].done;
     const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), lane = threadIdx.x & (WAVE - 1);
-    const bool act = j < B.nr && !B.state[j].done;
     const int k = B.k;
     const int64_t ld = B.ld, so = (int64_t)j * ld;
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + lane;
+    double as0 = 0.0, s0 = 0.0, rt0v = 0.0;
+    double c0[pref_cols<K>()];
+    if (row0 < r1) {
+        as0 = sell_row(B.A, row0, B.s + so);
+        s0 = B.s[row0 + so];
+        rt0v = B.rt0[row0 + so];
+        if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) c0[jj] = B.C[row0 + col_off(jj, k, ld)];
+        }
+    }
+    if (threadIdx.x < B.nr) sdone[threadIdx.x] = q_done;
+    if constexpr (K > 0) {
+        if constexpr (kRaw) group_raw_finish<RU>(g, B.nr * K, gridDim.x, raw, gtot, blockDim.x);
+        else group_totals(B.cp.gs[1], B.nr * K, gridDim.x, gtot);
+    } else {
+        __syncthreads();
+    }
+    bool any = false;
+    for (int q = 0; q < B.nr; ++q) any = any || !sdone[q];
+    if (!any) return;
+    if constexpr (K > 0) {
+        if (fin && blockIdx.x == 0)
+            for (int t = threadIdx.x; t < B.nr * B.k; t += blockDim.x) {
+                const int sy = t / B.k, q = t % B.k;
+                if (!sdone[sy]) B.state[sy].gamma[q] = gtot[sy * K + q];
+            }
+    }
+    const bool act = !sdone[j];
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
+        const double* gs = fin ? gtot + j * KM : B.state[j].gamma;
         double gam[KM];
 #pragma unroll
-        for (int q = 0; q < KM; ++q) gam[q] = q < k ? B.state[j].gamma[q] : 0.0;
-        int64_t r0, r1;
-        block_rows(B.n, r0, r1);
-        for (int64_t row = r0 + lane; row < r1; row += WAVE) {
-            const int64_t o = row + so;
-            double tv = sell_row(B.A, row, B.s + so);
+        for (int q = 0; q < KM; ++q) gam[q] = uniform(q < k ? gs[q] : 0.0);
+        auto finish = [&](int64_t row, double as, double sv, double rt, const double* c) {
+            double tv = as;
 #pragma unroll
-            for (int jj = 0; jj < K; ++jj) tv -= B.C[row + col_off(jj, k, ld)] * gam[jj];
-            B.t[o] = tv;
-            const double sv = B.s[o], rt = B.rt0[o];
+            for (int jj = 0; jj < K; ++jj) {
+                double cv;
+                if constexpr (K <= PREF_K) cv = c[jj];
+                else cv = B.C[row + col_off(jj, k, ld)];
+                tv -= cv * gam[jj];
+            }
+            B.t[row + so] = tv;
             acc[0] += sv * tv;
             acc[1] += tv * tv;
             acc[2] += rt * sv;
             acc[3] += rt * tv;
             acc[4] += sv * sv;
+        };
+        if (row0 < r1) finish(row0, as0, s0, rt0v, c0);
+        for (int64_t row = row0 + WAVE; row < r1; row += WAVE) {
+            const double as = sell_row(B.A, row, B.s + so);
+            const int64_t o = row + so;
+            double c[pref_cols<K>()];
+            if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) c[jj] = B.C[row + col_off(jj, k, ld)];
+            }
+            finish(row, as, B.s[o], B.rt0[o], c);
         }
     }
-    __shared__ double tot[MULTI_W * 5];
-    if (!multi_complete<5>(acc, j, B, tot)) return;
-    if (fin && threadIdx.x < B.nr && !B.state[threadIdx.x].done)
-        spmv2_fin_scalars(&B.state[threadIdx.x], tot + threadIdx.x * 5, B.k);
+    multi_groups<5>(acc, j, B, 2);
 }
 
 // ---------------------------------------------------------------- iterative refinement support
@@ -1646,6 +2177,7 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
         for (int j = 0; j < k; ++j) st->zc[j] = 0.0;
         st->alpha = st->beta = 0.0;
         st->iter = 1;
+        st->fresh = 1;
         st->stored = 0;
         st->rr = tot[0];
         st->rho = tot[1];
@@ -1668,143 +2200,248 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
 // zetat = Ccheck^T A^T pt = GhT^T pt are sums over the new p, pt, so they are
 // reduced in the pass that forms p and pt, and the projected products
 // q = A p - C zeta, qt = A^T pt - Ct zetat come out of the SpMV pass directly.
+// Each pass finishes the previous pass's reduction (split completion) and
+// takes the scalar step that needs it; workgroup 0 records it.
 //
-// BQ1: r -= alpha q; rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt;
-//      store r, rt into the cycle store; sums ||r||^2, (rt, r), ||rt||^2, Gh^T p, GhT^T pt
+// BQ1: alpha, beta of iteration i - 1 from BQ2's group sums; r -= alpha q;
+//      rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt; store
+//      r, rt into the cycle store; first level of ||r||^2, (rt, r), ||rt||^2,
+//      Gh^T p, GhT^T pt
+template <int K>
+struct BupdateRow {
+    double r, q, rt, qt, p, pt, x;
+    double gh[pref_cols<K>()], ght[pref_cols<K>()];
+};
+
+template <int K>
+__device__ __forceinline__ BupdateRow<K> bupdate_load(const BicgBufs& B, int64_t row) {
+    BupdateRow<K> d;
+    d.r = B.r[row];
+    d.q = B.q[row];
+    d.rt = B.rt[row];
+    d.qt = B.qt[row];
+    d.p = B.p[row];
+    d.pt = B.pt[row];
+    d.x = B.x[row];
+    if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t o = row + col_off(j, B.k, B.ld);
+            d.gh[j] = B.Gh[o];
+            d.ght[j] = B.GhT[o];
+        }
+    }
+    return d;
+}
+
+template <int K>
+__device__ __forceinline__ void bupdate_finish(const BicgBufs& B, int64_t row, const BupdateRow<K>& d, double alpha,
+                                               double beta, bool store, double* wcol, double* wtcol,
+                                               double (&acc)[3 + 2 * K]) {
+    const double rv = d.r - alpha * d.q;
+    const double rtv = d.rt - alpha * d.qt;
+    const double pn = rv + beta * d.p, ptn = rtv + beta * d.pt;
+    const double xv = d.x + alpha * d.p;
+    acc[0] += rv * rv;
+    acc[1] += rtv * rv;
+    acc[2] += rtv * rtv;
+    // (above the prefetch bucket) the block-column loads come before this
+    // row's stores, so that the compiler can issue them together (no store
+    // they might alias in between)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double g, gt;
+        if constexpr (K <= PREF_K) {
+            g = d.gh[j];
+            gt = d.ght[j];
+        } else {
+            const int64_t o = row + col_off(j, B.k, B.ld);
+            g = B.Gh[o];
+            gt = B.GhT[o];
+        }
+        acc[3 + j] += g * pn;
+        acc[3 + K + j] += gt * ptn;
+    }
+    B.x[row] = xv;
+    B.r[row] = rv;
+    B.rt[row] = rtv;
+    B.p[row] = pn;
+    B.pt[row] = ptn;
+    if (store) {
+        wcol[row] = rv;
+        wtcol[row] = rtv;
+    }
+}
+
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
     constexpr int M = 3 + 2 * K;
     BicgState* st = B.state;
-    if (st->done) return;
-    const double alpha = st->alpha, beta = st->beta;
-    const int k = B.k;
-    const int slot = st->stored;
-    const bool store = slot < st->store_cap;
-    double* wcol = B.W + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
-    double* wtcol = B.Wt + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
+    // the state fields, the done flag, the group sums and the first row's
+    // operands are all read before the scalar step waits for any of them
+    const int done = st->done, fresh = st->fresh, slot = st->stored, cap = st->store_cap;
+    const double rho = st->rho;
+    double alpha = st->alpha, beta = st->beta;   // first iteration: the prologue's zeros
+    __shared__ double raw[32 * 4];
+    __shared__ double tot[4];
+    const GroupRaw<1> g = group_raw_load<1>(B.cp.gs[1], 4);   // (unused on the first iteration)
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + threadIdx.x;
+    BupdateRow<K> d0;
+    if (row0 < r1) d0 = bupdate_load<K>(B, row0);
+    if (done) return;
+    if (!fresh) {
+        group_raw_finish<1>(g, 4, gridDim.x, raw, tot);
+        const double den = tot[0];
+        if (den == 0.0 || !finite(den)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->done = 1;
+                st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
+                st->iters_done = st->iter - 1;
+            }
+            return;
+        }
+        // alpha = rho / (pt, q); beta from (rt - a qt, r - a q) expanded
+        alpha = rho / den;
+        const double rho_new = rho - alpha * tot[2] - alpha * tot[1] + alpha * alpha * tot[3];
+        beta = rho_new / rho;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->alpha = alpha;
+            st->beta = beta;
+            for (int j = 0; j < B.k; ++j) st->zc[j] += alpha * st->zeta[j];
+            st->iter += 1;
+        }
+    }
+    alpha = uniform(alpha);
+    beta = uniform(beta);
+    const bool store = slot < cap;
+    double* wcol = B.W + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
+    double* wtcol = B.Wt + (int64_t)(B.col0 + (store ? slot : 0)) * B.ldw;
     double acc[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
-        const double rv = B.r[row] - alpha * B.q[row];
-        const double rtv = B.rt[row] - alpha * B.qt[row];
-        const double pv = B.p[row], ptv = B.pt[row];
-        const double pn = rv + beta * pv, ptn = rtv + beta * ptv;
-        const double xv = B.x[row] + alpha * pv;
-        acc[0] += rv * rv;
-        acc[1] += rtv * rv;
-        acc[2] += rtv * rtv;
-        // the block-column loads come before this row's stores, so that the
-        // compiler can issue them together (no store they might alias in between)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t o = row + col_off(j, k, B.ld);
-            acc[3 + j] += B.Gh[o] * pn;
-            acc[3 + K + j] += B.GhT[o] * ptn;
-        }
-        B.x[row] = xv;
-        B.r[row] = rv;
-        B.rt[row] = rtv;
-        B.p[row] = pn;
-        B.pt[row] = ptn;
-        if (store) {
-            wcol[row] = rv;
-            wtcol[row] = rtv;
-        }
-    }
-    __shared__ double tot[M];
-    if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
-    if (threadIdx.x < k) {
-        st->zeta[threadIdx.x] = tot[3 + threadIdx.x];
-        st->zetat[threadIdx.x] = tot[3 + K + threadIdx.x];
-    }
-    if (threadIdx.x == 0) {
-        const int i = st->iter;
-        const int slot = st->stored;
-        const bool store = slot < st->store_cap;
-        const double rr = tot[0], rho = tot[1], rtrt = tot[2];
-        st->rr = rr;
-        st->rtrt = rtrt;
-        // Section 3: RBiCG stops when both the primary and the dual residual meet
-        // the tolerance (tol2_dual is +inf when only the primary one is asked for)
-        if (!finite(rr) || !finite(rho) || !finite(rtrt)) {
-            st->done = 1;
-            st->status = S_NONFINITE;
-            st->iters_done = i - 1;
-        } else if (rr <= st->tol2 && rtrt <= st->tol2_dual) {
-            st->done = 1;
-            st->status = S_OK;
-            st->iters_done = i - 1;
-        } else if (i > st->max_it) {
-            st->done = 1;
-            st->status = S_MAXIT;
-            st->iters_done = i - 1;
-        } else if (rho == 0.0) {
-            st->done = 1;
-            st->status = S_BD_RHO;
-            st->iters_done = i - 1;
-        } else {
-            st->rho = rho;
-            st->cur_slot = store ? slot : -1;
-            if (store) st->stored = slot + 1;
-        }
-    }
+    if (row0 < r1) bupdate_finish<K>(B, row0, d0, alpha, beta, store, wcol, wtcol, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK)
+        bupdate_finish<K>(B, row, bupdate_load<K>(B, row), alpha, beta, store, wcol, wtcol, acc);
+    block_groups<M>(acc, M, B.cp, B.cp.gs[0], blockIdx.x, gridDim.x);
 }
 
-// BQ2: q = A p - C zeta ; qt = A^T pt - Ct zetat ; sums (pt, q), (rt, q), (qt, r),
-//      (qt, q) for alpha = rho / (pt, q) and beta from (rt - a qt, r - a q) expanded
+// BQ2: the stopping tests and rho of iteration i from BQ1's group sums (Section
+//      3: RBiCG stops when both the primary and the dual residual meet the
+//      tolerance; tol2_dual is +inf when only the primary one is asked for);
+//      q = A p - C zeta ; qt = A^T pt - Ct zetat ; first level of (pt, q),
+//      (rt, q), (qt, r), (qt, q) for alpha = rho / (pt, q) and beta
+template <int K>
+struct BspmvRow {
+    double ap, atpt, pt, r, rt;
+    double c[pref_cols<K>()], ct[pref_cols<K>()];
+};
+
+template <int K>
+__device__ __forceinline__ BspmvRow<K> bspmv_load(const BicgBufs& B, int64_t row) {
+    BspmvRow<K> d;
+    d.ap = sell_row(B.A, row, B.p);
+    d.atpt = sell_row(B.At, row, B.pt);
+    d.pt = B.pt[row];
+    d.r = B.r[row];
+    d.rt = B.rt[row];
+    if constexpr (K > 0 && K <= PREF_K) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t o = row + col_off(j, B.k, B.ld);
+            d.c[j] = B.C[o];
+            d.ct[j] = B.Ct[o];
+        }
+    }
+    return d;
+}
+
+template <int K>
+__device__ __forceinline__ void bspmv_finish(const BicgBufs& B, int64_t row, const BspmvRow<K>& d, const double* zeta,
+                                             const double* zetat, double (&acc)[4]) {
+    double qv = d.ap, qtv = d.atpt;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double c, ct;
+        if constexpr (K <= PREF_K) {
+            c = d.c[j];
+            ct = d.ct[j];
+        } else {
+            const int64_t o = row + col_off(j, B.k, B.ld);
+            c = B.C[o];
+            ct = B.Ct[o];
+        }
+        qv -= c * zeta[j];
+        qtv -= ct * zetat[j];
+    }
+    B.q[row] = qv;
+    B.qt[row] = qtv;
+    acc[0] += d.pt * qv;
+    acc[1] += d.rt * qv;
+    acc[2] += qtv * d.r;
+    acc[3] += qtv * qv;
+}
+
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_bspmvq(BicgBufs B) {
     constexpr int M = 4;
+    constexpr int MU = 3 + 2 * K;
+    using Sums = GroupSums<MU>;
     BicgState* st = B.state;
-    if (st->done) return;
+    // the state fields, the done flag, the group sums and the first row's
+    // products and operands are all read before the tests wait for any of them
+    const int done = st->done, iter = st->iter, max_it = st->max_it;
+    const double tol2 = st->tol2, tol2_dual = st->tol2_dual;
+    __shared__ double raw[Sums::kRaw ? 32 * MU : 1];
+    __shared__ double tot[MU];
+    Sums gsums;
+    gsums.load(B.cp.gs[0], MU);
+    int64_t r0, r1;
+    block_rows(B.n, r0, r1);
+    const int64_t row0 = r0 + threadIdx.x;
+    BspmvRow<K> d0;
+    if (row0 < r1) d0 = bspmv_load<K>(B, row0);
+    if (done) return;
+    gsums.finish(gridDim.x, raw, tot);
+    const double rr = tot[0], rho = tot[1], rtrt = tot[2];
+    int status = -1;
+    if (!finite(rr) || !finite(rho) || !finite(rtrt)) status = S_NONFINITE;
+    else if (rr <= tol2 && rtrt <= tol2_dual) status = S_OK;
+    else if (iter > max_it) status = S_MAXIT;
+    else if (rho == 0.0) status = S_BD_RHO;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr = rr;
+        st->rtrt = rtrt;
+        if (status != -1) {
+            st->done = 1;
+            st->status = status;
+            st->iters_done = iter - 1;
+        } else {
+            const int slot = st->stored;
+            const bool store = slot < st->store_cap;
+            st->rho = rho;
+            for (int j = 0; j < B.k; ++j) {
+                st->zeta[j] = tot[3 + j];
+                st->zetat[j] = tot[3 + K + j];
+            }
+            st->cur_slot = store ? slot : -1;
+            if (store) st->stored = slot + 1;
+            st->fresh = 0;
+        }
+    }
+    if (status != -1) return;
     const int k = B.k;
     double zeta[K > 0 ? K : 1], zetat[K > 0 ? K : 1];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        zeta[j] = j < k ? st->zeta[j] : 0.0;
-        zetat[j] = j < k ? st->zetat[j] : 0.0;
+        zeta[j] = uniform(j < k ? tot[3 + j] : 0.0);
+        zetat[j] = uniform(j < k ? tot[3 + K + j] : 0.0);
     }
-    int64_t r0, r1;
-    block_rows(B.n, r0, r1);
     double acc[M] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
-        double qv = sell_row(B.A, row, B.p);
-        double qtv = sell_row(B.At, row, B.pt);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t o = row + col_off(j, k, B.ld);
-            qv -= B.C[o] * zeta[j];
-            qtv -= B.Ct[o] * zetat[j];
-        }
-        B.q[row] = qv;
-        B.qt[row] = qtv;
-        const double rv = B.r[row], rtv = B.rt[row];
-        acc[0] += B.pt[row] * qv;
-        acc[1] += rtv * qv;
-        acc[2] += qtv * rv;
-        acc[3] += qtv * qv;
-    }
-    __shared__ double tot[M];
-    if (!block_complete<M>(acc, M, B.cp, blockIdx.x, gridDim.x, tot)) return;
-    if (threadIdx.x == 0) {
-        const double den = tot[0];
-        if (den == 0.0 || !finite(den)) {
-            st->done = 1;
-            st->status = den == 0.0 ? S_BD_ALPHA : S_NONFINITE;
-            st->iters_done = st->iter - 1;
-        } else {
-            const double rho = st->rho;
-            const double a = rho / den;
-            const double rho_new = rho - a * tot[2] - a * tot[1] + a * a * tot[3];
-            st->alpha = a;
-            st->beta = rho_new / rho;
-            for (int j = 0; j < k; ++j) st->zc[j] += a * st->zeta[j];
-            st->iter += 1;
-        }
-    }
+    if (row0 < r1) bspmv_finish<K>(B, row0, d0, zeta, zetat, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK) bspmv_finish<K>(B, row, bspmv_load<K>(B, row), zeta, zetat, acc);
+    block_groups<M>(acc, M, B.cp, B.cp.gs[1], blockIdx.x, gridDim.x);
 }
 
 template <int K>
@@ -1836,6 +2473,7 @@ __global__ void k_time_prep(SolveState* st) {
     st->beta = 0.1;
     st->omega = 0.2;
     st->rho = 1.0;
+    st->fresh = 0;
 }
 
 // compile-time recycle-dimension buckets
