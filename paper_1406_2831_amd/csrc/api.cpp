@@ -852,14 +852,13 @@ struct OrthJob {
     // the context's buffer pointers: a transform writes the spare buffer
     // (c->Wtmp), which then takes the basis' place (no copy back)
     double** X = nullptr;
-    double** AX = nullptr;
     int m0 = 0, m = 0, pass = 0;
-    int mpass[2] = {0, 0}, rpass[2] = {0, 0};
-    double *dG = nullptr, *dS[2] = {nullptr, nullptr}, *dStot = nullptr;   // device scratch
+    double *dG = nullptr, *dS[2] = {nullptr, nullptr};   // device scratch
     double *hG = nullptr, *hS = nullptr;                                   // pinned host
     hipEvent_t ev = nullptr;
     bool done = false;
     int rank = 0;
+    double wait_ms = 0.0, factor_ms = 0.0;   // host time waiting for the Gram matrices / factoring (trace)
 };
 
 // Gram matrix X^T X of the job's current columns to the host (asynchronous).
@@ -872,11 +871,14 @@ int orth_gram(rbs_ctx* c, OrthJob& j) {
 }
 
 // Waits for the job's Gram matrix, factors it on the host and enqueues the
-// transform (and the next Gram product, or the AX transform after the last pass).
+// transform (and the next Gram product after the first pass).
 int orth_advance(rbs_ctx* c, OrthJob& j) {
     hipStream_t s = c->stream;
     const int64_t ld = c->ldw;
+    const auto tw = std::chrono::steady_clock::now();
     HIPCHK(c, hipEventSynchronize(j.ev));
+    const auto tf = std::chrono::steady_clock::now();
+    j.wait_ms += std::chrono::duration<double, std::milli>(tf - tw).count();
     const int m = j.m;
     std::vector<double> S;
     const double eps = std::numeric_limits<double>::epsilon();
@@ -888,20 +890,14 @@ int orth_advance(rbs_ctx* c, OrthJob& j) {
         j.rank = 0;
         return RBS_OK;
     }
+    j.factor_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
     std::memcpy(j.hS, S.data(), S.size() * sizeof(double));
     HIPCHK(c, hipMemcpyAsync(j.dS[j.pass], j.hS, S.size() * sizeof(double), hipMemcpyHostToDevice, s));
     rbs::launch_gemm_ts(s, c->n, *j.X, ld, m, j.dS[j.pass], r, c->Wtmp, ld);
     std::swap(*j.X, c->Wtmp);   // stream order: later writes to the old buffer follow this read
-    j.mpass[j.pass] = m;
-    j.rpass[j.pass] = r;
     j.m = r;
     ++j.pass;
     if (j.pass < 2) return orth_gram(c, j);
-    if (j.AX) {   // AX needs only the product of the two transforms: one pass over it
-        rbs::launch_gemm_ts(s, j.m0, j.dS[0], j.m0, j.mpass[1], j.dS[1], j.rpass[1], j.dStot, j.m0);
-        rbs::launch_gemm_ts(s, c->n, *j.AX, ld, j.m0, j.dStot, j.m, c->Wtmp, ld);
-        std::swap(*j.AX, c->Wtmp);
-    }
     j.done = true;
     j.rank = j.m;
     return RBS_OK;
@@ -921,8 +917,8 @@ int ritz_host_buffers(rbs_ctx* c) {
 }
 
 // Cycle-end recycle-space update from the gen_k current columns and ns new
-// Lanczos vectors held in W / Wt / AW.  W and Wt are first replaced by
-// orthonormal bases of their ranges (AW follows W's transform), so the
+// Lanczos vectors held in W / Wt.  W and Wt are first replaced by
+// orthonormal bases of their ranges (A Q is then formed by explicit products), so the
 // small problems solved on the host are well conditioned: harmonic Ritz
 // vectors of A on range(W) (right) and the left vectors of the two-sided
 // projection on (Wt, W).  The new space replaces the first columns.
@@ -945,12 +941,7 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     const int64_t ld = c->ldw;
     int rc = ritz_host_buffers(c);
     if (rc) return rc;
-    // A W by explicit products (the Lanczos recurrences give it only up to a
-    // cancellation that grows with ||p|| / ||r||, which perturbs the Ritz
-    // vectors of clustered values)
-    rbs::launch_spmm(s, c->A, c->W, ld, c->AW, ld, m);
-    c->ritz_mv += m;
-    // device scratch: W job Gram | S0 | S1 | S0 S1, Wt job Gram | S0 | S1,
+    // device scratch: W job Gram | S0 | S1 | (unused), Wt job Gram | S0 | S1,
     // then Q^T AQ | (AQ)^T AQ and Qt^T [Q AQ]; pinned host: the two jobs' Gram
     // and factor, the right pencil's inputs, the left pencil's inputs
     const size_t mm = (size_t)(c->k_max + std::max(c->s_max, 0)) * (c->k_max + std::max(c->s_max, 0));
@@ -958,13 +949,11 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     double* h = c->hritz;
     OrthJob jw, jt;
     jw.X = &c->W;
-    jw.AX = &c->AW;
     jt.X = &c->Wt;
     jw.m0 = jw.m = jt.m0 = jt.m = m;
     jw.dG = d;
     jw.dS[0] = d + mm;
     jw.dS[1] = d + 2 * mm;
-    jw.dStot = d + 3 * mm;
     jt.dG = d + 4 * mm;
     jt.dS[0] = d + 5 * mm;
     jt.dS[1] = d + 6 * mm;
@@ -991,13 +980,20 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     bool right_started = false;
     int r = 0;
     std::atomic<int> worker_rc{RBS_OK};
-    double t_right_ms = 0.0;
+    double t_right_ms = 0.0, right_ms = 0.0;
     while (!jw.done || !jt.done) {
         if (!jw.done) {
             if ((rc = orth_advance(c, jw))) return rc;
             if (jw.done) {
                 r = jw.rank;
                 if (r == 0) break;
+                // A Q by explicit products of the orthonormal basis (the
+                // Lanczos recurrences give A W only up to a cancellation that
+                // grows with ||p|| / ||r||, which perturbs the Ritz vectors of
+                // clustered values; a transform of A W by the two factors
+                // would cost as much as the products)
+                rbs::launch_spmm(s, c->A, c->W, ld, c->AW, ld, r);
+                c->ritz_mv += r;
                 // right (harmonic) pencil inputs; its host eigenproblem runs on a
                 // worker thread as soon as they arrive
                 rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
@@ -1014,7 +1010,10 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
                         worker_rc = RBS_ERR_HIP;
                         return;
                     }
+                    const auto t0 = std::chrono::steady_clock::now();
                     right = rbs::dense::ritz_right_harmonic(r, hF2 + (size_t)r * r, hF2, kmax);
+                    right_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                                   .count();
                 });
                 right_started = true;
             }
@@ -1034,6 +1033,8 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     HIPCHK(c, hipStreamSynchronize(s));
     const auto t_left = std::chrono::steady_clock::now();
     left = rbs::dense::ritz_left_two_sided(r, rt, hFG, hFG + (size_t)rt * r, c->k_max);
+    const double left_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_left).count();
     worker.join();
     if (worker_rc != RBS_OK) return fail(c, worker_rc, "Ritz step: waiting for the Gram products failed");
     rbs::dense::RitzResult res = rbs::dense::ritz_combine(r, rt, right, left);
@@ -1042,9 +1043,11 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
         auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
         std::fprintf(stderr,
                      "[rbs] ritz m=%d r=%d rt=%d k=%d: right pencil inputs queued at %.2f ms, both bases "
-                     "and left inputs %.2f ms, left pencil + join %.2f ms, total %.2f ms\n",
+                     "and left inputs %.2f ms, left pencil + join %.2f ms, total %.2f ms; host waits %.2f ms, "
+                     "host factors %.2f ms, left pencil alone %.2f ms, right pencil %.2f ms\n",
                      m, r, rt, res.kout, t_right_ms, ms(t_start, t_left), ms(t_left, t_end),
-                     ms(t_start, t_end));
+                     ms(t_start, t_end), jw.wait_ms + jt.wait_ms, jw.factor_ms + jt.factor_ms, left_ms,
+                     right_ms);
     }
     if (!res.ok || res.kout == 0) {
         c->gen_k = 0;
