@@ -542,7 +542,7 @@ def main():
 
     # the kernel with the largest share of device time in the timed pipeline is the
     # Ritz step's Gram product kernel, whose interior 128 x 128 tile class
-    # (instantiation k_gemmt_mfma<4, 4>) does most of its work (rocprofv3 kernel
+    # (kernel k_gemmt_mfma_dl) does most of its work (rocprofv3 kernel
     # statistics in profiles/): per Ritz step five symmetric X^T X (upper-triangle
     # tiles) and three X^T Y; each is timed live as that class's launch alone
     # (2 n 128^2 flops per tile) at the median m of the timed run's Ritz steps on
@@ -591,10 +591,10 @@ def main():
         "spmv_gbs": passes["spmv"]["gbs"],
         "passes": dict(passes, k=k_last, multi_nrhs=nr),
         "ritz_kernels": ritz_kernels,
-        "roofline": {"bound": "mfma", "kernel": "k_gemmt_mfma<4, 4> (interior 128 x 128 tiles)",
+        "roofline": {"bound": "mfma", "kernel": "k_gemmt_mfma_dl (interior 128 x 128 tiles)",
                      "achieved": gram_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": gram_tflops / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": counter_traffic(f"k_gemmt_mfma<4,4> m={m_ritz}"),
+                     "traffic": counter_traffic(f"k_gemmt_mfma_dl m={m_ritz}"),
                      "flops_per_launch": (5 * f_sym + 3 * f_gen) / 8,
                      "us_per_launch": (5 * t_sym + 3 * t_gen) / 8 * 1e3,
                      "mix": "interior-tile launches of 5 X^T X + 3 X^T Y per Ritz step"},

@@ -1189,7 +1189,7 @@ int time_ritz_kernel(rbs_ctx* c, int which, int m, int reps, double* avg_ms, dou
     const int64_t ld = c->ldw;
     double* out = c->dsmall;   // >= 11 mmax^2 doubles: room for an m x m result and an m x m S
     // the Gram products are timed as their interior 128 x 128 tile class alone:
-    // the matrix-core kernel instantiation k_gemmt_mfma<4, 4>, which does most
+    // the matrix-core kernel k_gemmt_mfma_dl, which does most
     // of their work (the edge classes and the reduction are separate launches)
     double fl = 0.0;
     auto launch = [&]() {

@@ -36,7 +36,7 @@ void launch_gemmt(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m
                   const double* Y1, int64_t ldy1, int my1, const double* Y2, int64_t ldy2,
                   int my2, double* partial, double* out);
 // Timing support: the launch of X^T Y's interior 128 x 128 tile class alone
-// (the matrix-core kernel k_gemmt_mfma<4, 4>; no reduction); returns its FP64
+// (the matrix-core kernel k_gemmt_mfma_dl; no reduction); returns its FP64
 // flops (0 and no launch when the product has no full 128 x 128 tile).
 double launch_gemmt_interior(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y,
                              int64_t ldy, int my, double* partial);

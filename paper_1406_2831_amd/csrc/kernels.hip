@@ -801,6 +801,130 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
             }
 }
 
+// The interior class (128 x 128 tiles) with the operand slabs loaded
+// straight from global memory into LDS (global_load_lds_dwordx4: each lane
+// moves 16 bytes, no registers), double-buffered: the loads of slab s + 1 are
+// in flight while the matrix cores work on slab s, at two workgroups per CU.
+// A lane's 16 bytes are rows 2h, 2h + 1 of one column, and one wave
+// instruction fills a 1 KB group: 8 columns x 8 row pairs, i.e. 8 whole
+// 128-byte lines of the column-major operand.  Group g (columns 8 g .. 8 g +
+// 7) sits at 1024 g bytes; inside it, unit (column c, row pair h) sits at
+// position 8 (h xor (g mod 2)) + c mod 8.  The operand read of a k-step (rows
+// 4 ks + kk of 16 consecutive columns, two groups) then puts the two groups'
+// lanes on different banks.  Rows past the last whole slab of the chunk go
+// through registers with masked loads.
+constexpr int DL_GROUP = 128;   // doubles of one 8-column group of a slab
+
+__device__ __forceinline__ int dl_offset(int r, int c) {   // doubles
+    const int g = c >> 3;
+    return g * DL_GROUP + (((r >> 1) ^ (g & 1)) * 8 + (c & 7)) * 2 + (r & 1);
+}
+
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemmt_mfma_dl(
+    int64_t n, const double* __restrict__ X, int64_t ldx, int mx, const double* __restrict__ Y, int64_t ldy, int my,
+    GemmtClass cl, double* __restrict__ partial) {
+    __shared__ __attribute__((aligned(16))) double lds[2][2][16 * MT];   // buffer, operand, slab
+    int a, b;
+    if (cl.tri) {
+        int t = blockIdx.x;
+        a = 0;
+        while (t >= cl.ntx - a) {
+            t -= cl.ntx - a;
+            ++a;
+        }
+        b = a + t;
+    } else {
+        a = blockIdx.x / cl.nty;
+        b = blockIdx.x % cl.nty;
+    }
+    const int gx0 = cl.x0 + MT * a, gy0 = cl.y0 + MT * b;
+    const int64_t c0 = (int64_t)blockIdx.y * cl.rows_per_chunk;
+    const int64_t c1 = (c0 + cl.rows_per_chunk < n) ? c0 + cl.rows_per_chunk : n;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int wi = w >> 1, wj = w & 1;
+    d4 acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+    // wave w loads groups 4 w .. 4 w + 3 of both operands; lane l of the
+    // instruction for group g fills position l: row pair (l / 8) xor (g mod 2)
+    // of column 8 g + l mod 8 (the parity of g is that of the group index q)
+    const int cl8 = lane & 7, hp = lane >> 3;
+    auto issue = [&](int64_t base, int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int g = 4 * w + q;
+            const int h = hp ^ (q & 1);
+            const int64_t roff = base + 2 * h;
+            const int c = 8 * g + cl8;
+            __builtin_amdgcn_global_load_lds(X + roff + (int64_t)(gx0 + c) * ldx,
+                                             (__attribute__((address_space(3))) void*)&lds[buf][0][g * DL_GROUP], 16,
+                                             0, 0);
+            __builtin_amdgcn_global_load_lds(Y + roff + (int64_t)(gy0 + c) * ldy,
+                                             (__attribute__((address_space(3))) void*)&lds[buf][1][g * DL_GROUP], 16,
+                                             0, 0);
+        }
+    };
+    const int i16 = lane & 15, kq = lane >> 4;
+    auto compute = [&](int buf) {
+        const double* sx = lds[buf][0];
+        const double* sy = lds[buf][1];
+#pragma unroll
+        for (int ks = 0; ks < MR / 4; ++ks) {
+            const int r = ks * 4 + kq;
+            double av[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) av[t] = sx[dl_offset(r, wi * 64 + t * 16 + i16)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[t] = sy[dl_offset(r, wj * 64 + t * 16 + i16)];
+#pragma unroll
+            for (int it = 0; it < 4; ++it)
+#pragma unroll
+                for (int jt = 0; jt < 4; ++jt)
+                    acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[it], bv[jt], acc[it][jt], 0, 0, 0);
+        }
+    };
+    const int64_t nfull = c1 > c0 ? (c1 - c0) / MR : 0;
+    if (nfull > 0) issue(c0, 0);
+    for (int64_t sl = 0; sl < nfull; ++sl) {
+        if (sl + 1 < nfull) {
+            issue(c0 + (sl + 1) * MR, (int)((sl + 1) & 1));
+            __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8): this wave's loads of slab sl have landed
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        }
+        __syncthreads();
+        compute((int)(sl & 1));
+        __syncthreads();
+    }
+    const int64_t tail = c0 + nfull * MR;
+    if (tail < c1) {   // the last rows of the matrix: masked loads through registers into buffer 0
+        const int lr = threadIdx.x & 15, lc = threadIdx.x >> 4;   // row lr of columns lc + 16 q
+        const int64_t row = tail + lr;
+        const bool rok = row < c1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = lc + 16 * q;
+            lds[0][0][dl_offset(lr, c)] = rok ? X[row + (int64_t)(gx0 + c) * ldx] : 0.0;
+            lds[0][1][dl_offset(lr, c)] = rok ? Y[row + (int64_t)(gy0 + c) * ldy] : 0.0;
+        }
+        __syncthreads();
+        compute(0);
+    }
+    double* out = partial + cl.slot0 + ((int64_t)blockIdx.y * cl.ntiles + blockIdx.x) * (MT * MT);
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i = wi * 64 + it * 16 + (lane >> 4) + 4 * rr;
+                const int j = wj * 64 + jt * 16 + (lane & 15);
+                out[i * MT + j] = acc[it][jt][rr];
+            }
+}
+
 // Sum the row-chunk partial tiles of the classes into out (mx x my,
 // column-major, ld = mx).  cls[0..3]: interior, right edge, bottom edge,
 // corner (a class with no tiles has ntiles = 0).  Symmetric products mirror
@@ -2643,6 +2767,15 @@ namespace {
 template <int WX, int WY>
 void launch_gemmt_class(hipStream_t st, int64_t n, const double* X, int64_t ldx, int mx, const double* Y,
                         int64_t ldy, int my, const GemmtClass& cl, double* partial) {
+    // interior tiles through direct LDS loads when both operands allow 16-byte
+    // loads of row pairs (even leading dimensions, 16-byte aligned bases; the
+    // row chunks are multiples of 16 rows)
+    if (WX == 4 && WY == 4 && ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)X & 15) == 0 &&
+        ((uintptr_t)Y & 15) == 0 && cl.rows_per_chunk % MR == 0) {
+        hipLaunchKernelGGL(k_gemmt_mfma_dl, dim3(cl.ntiles, cl.nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y, ldy,
+                           my, cl, partial);
+        return;
+    }
     hipLaunchKernelGGL((k_gemmt_mfma<WX, WY>), dim3(cl.ntiles, cl.nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx,
                        Y, ldy, my, cl, partial);
 }
