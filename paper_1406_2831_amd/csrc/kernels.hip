@@ -976,8 +976,8 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_cls(int mx, int my, int 
 // X[row j, k kk]) and the result (D: lane j + 16 (i % 4), register i / 4) both
 // cover 16 consecutive rows of one column.  A wave owns 64 rows x 64 columns
 // of Y (4 x 4 tiles), a block of four waves 256 rows; S is staged through LDS
-// in chunks of 16 values of k shared by the four waves, and the X operands of
-// the next chunk are loaded before the current chunk's products.  Work items
+// in chunks of 16 values of k shared by the four waves, and the X operands and
+// S values of the next chunk are loaded before the current chunk's products.  Work items
 // (row tile, column tile) are dealt to the XCDs in contiguous ranges so that
 // the column tiles of one row tile share that XCD's L2.
 constexpr int TS_ROWS = 256, TS_COLS = 64, TS_KC = 16, TS_STRIDE = TS_COLS + 16;
@@ -1013,20 +1013,29 @@ __global__ __launch_bounds__(BLOCK) void k_gemm_ts_mfma(int64_t n, const double*
                 xn[ks][rb] = (kk < m && row < n) ? X[row + (int64_t)kk * ldx] : 0.0;
             }
     };
-    load_x(0);
-    for (int k0 = 0; k0 < m; k0 += TS_KC) {
-        __syncthreads();   // the previous chunk's LDS reads are done
+    double sn[TS_COLS / 16];   // this thread's S values of the next chunk
+    auto load_s = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < TS_COLS / 16; ++q) {
             const int c = sc + 16 * q, kk = k0 + sk;
-            sS[sk * TS_STRIDE + c] = (kk < m && c0 + c < ko) ? S[kk + (int64_t)(c0 + c) * m] : 0.0;
+            sn[q] = (kk < m && c0 + c < ko) ? S[kk + (int64_t)(c0 + c) * m] : 0.0;
         }
+    };
+    load_x(0);
+    load_s(0);
+    for (int k0 = 0; k0 < m; k0 += TS_KC) {
+        __syncthreads();   // the previous chunk's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < TS_COLS / 16; ++q) sS[sk * TS_STRIDE + sc + 16 * q] = sn[q];
         double xb[4][4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) xb[ks][rb] = xn[ks][rb];
-        if (k0 + TS_KC < m) load_x(k0 + TS_KC);
+        if (k0 + TS_KC < m) {   // the next chunk's operands load while this one is multiplied
+            load_x(k0 + TS_KC);
+            load_s(k0 + TS_KC);
+        }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
