@@ -594,7 +594,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_gemmt_mfma_dl (interior 128 x 128 tiles)",
                      "achieved": gram_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": gram_tflops / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": counter_traffic(f"k_gemmt_mfma_dl m={m_ritz}"),
+                     "traffic": counter_traffic(f"k_gemmt_mfma_dl tiles={m_ritz // 128} n={n}"),
                      "flops_per_launch": (5 * f_sym + 3 * f_gen) / 8,
                      "us_per_launch": (5 * t_sym + 3 * t_gen) / 8 * 1e3,
                      "mix": "interior-tile launches of 5 X^T X + 3 X^T Y per Ritz step"},

@@ -262,6 +262,26 @@ int rbicgstab_adjoint_grads_noalloc(int64_t n, int64_t nnz, const int32_t* rowpt
                                     hipStream_t stream);
 
 /*
+ * The Gram product of the recycle-space update (Section 3's two-sided
+ * Rayleigh-Ritz step needs W^T W, Wt^T W, W^T A W and the like): out = X^T Y
+ * for tall X (n x mx) and Y (n x my), device, column-major with leading
+ * dimensions ldx, ldy >= n; out device, mx x my column-major (ld = mx).
+ * Passing the same pointer, width and leading dimension for X and Y computes
+ * the symmetric product (upper-triangle tiles, mirrored).  The workspace
+ * (device, 256-byte aligned, rbicgstab_gram_workspace_bytes(n, mx, my) bytes)
+ * holds the row-chunk partial tiles; the caller owns it and every array.  The
+ * work is enqueued on `stream` without waiting for it.  These are the
+ * library's own Gram kernels (matrix-core tiles, row chunks summed in a fixed
+ * order), as the Ritz step runs them.
+ * Errors: RBS_ERR_ARG for bad sizes or NULL pointers, RBS_ERR_WORKSPACE for a
+ * small or misaligned workspace, RBS_ERR_HIP for a failed launch
+ * (rbicgstab_last_error(NULL) describes them).
+ */
+size_t rbicgstab_gram_workspace_bytes(int64_t n, int32_t mx, int32_t my);
+int rbicgstab_gram(int64_t n, const double* X, int64_t ldx, int32_t mx, const double* Y, int64_t ldy,
+                   int32_t my, double* out, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Values of A(sigma) = K + sigma M on a fixed pattern (Section 6.1's
  * parametrised family): val = kval, then val[diag_pos[i]] += sigma mdiag[i].
  * With perm_t non-NULL also valT[e] = val[perm_t[e]] (the values of A^T in

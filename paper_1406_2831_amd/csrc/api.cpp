@@ -1843,6 +1843,23 @@ int rbicgstab_adjoint_grads_noalloc(int64_t n, int64_t nnz, const int32_t* rowpt
     return RBS_OK;
 }
 
+size_t rbicgstab_gram_workspace_bytes(int64_t n, int32_t mx, int32_t my) {
+    if (n < 1 || mx < 1 || my < 1) return 0;
+    return rbs::gemmt_partial_doubles(n, mx, my) * sizeof(double);
+}
+
+int rbicgstab_gram(int64_t n, const double* X, int64_t ldx, int32_t mx, const double* Y, int64_t ldy,
+                   int32_t my, double* out, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (n < 1 || n >= (int64_t(1) << 31) || mx < 1 || my < 1 || ldx < n || ldy < n || !X || !Y || !out)
+        return fail(nullptr, RBS_ERR_ARG, "1 <= n < 2^31, mx, my >= 1, ldx, ldy >= n; X, Y, out required");
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0 || ws_bytes < rbicgstab_gram_workspace_bytes(n, mx, my))
+        return fail(nullptr, RBS_ERR_WORKSPACE, "the Gram workspace is too small or not 256-byte aligned");
+    rbs::launch_gemmt(stream, n, X, ldx, mx, Y, ldy, my, nullptr, 0, 0, static_cast<double*>(workspace), out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, RBS_ERR_HIP, hipGetErrorString(e));
+    return RBS_OK;
+}
+
 int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const int64_t* diag_pos,
                              const double* mdiag, double sigma, const int64_t* perm_t, double* val,
                              double* valT, hipStream_t stream) {

@@ -46,7 +46,8 @@ EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "r
            "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_solve_multi",
            "rbicgstab_destroy", "rbicgstab_last_error", "rbicgstab_batch_workspace_bytes",
            "rbicgstab_batch_create", "rbicgstab_batch_solve", "rbicgstab_batch_config",
-           "rbicgstab_batch_destroy", "rbicgstab_batch_last_error", "rbicgstab_adjoint_grads_noalloc")
+           "rbicgstab_batch_destroy", "rbicgstab_batch_last_error", "rbicgstab_adjoint_grads_noalloc",
+           "rbicgstab_gram_workspace_bytes", "rbicgstab_gram")
 RBS_BATCH_TUNE = 1
 RBS_BATCH_GRAPH = 2
 
@@ -110,6 +111,10 @@ def load_library(path: str = LIB_PATH):
     lib.rbicgstab_adjoint_grads.restype = ctypes.c_int
     lib.rbicgstab_adjoint_grads_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rbicgstab_adjoint_grads_noalloc.restype = ctypes.c_int
+    lib.rbicgstab_gram_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.rbicgstab_gram_workspace_bytes.restype = sz
+    lib.rbicgstab_gram.argtypes = [i64, vp, i64, i32, vp, i64, i32, vp, vp, sz, vp]
+    lib.rbicgstab_gram.restype = ctypes.c_int
     lib.rbicgstab_shifted_values.argtypes = [i64, i64, vp, vp, vp, f64, vp, vp, vp, vp]
     lib.rbicgstab_shifted_values.restype = ctypes.c_int
     lib.rbicgstab_setup_matvecs.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -237,6 +242,27 @@ def rbicgstab_adjoint_grads_noalloc(rowptr: torch.Tensor, colidx: torch.Tensor, 
     _check(lib, None, lib.rbicgstab_adjoint_grads_noalloc(lam.numel(), colidx.numel(), _ptr(rowptr),
                                                           _ptr(colidx), _ptr(lam), _ptr(x), _ptr(mdiag),
                                                           _ptr(grad_val), _ptr(grad_sigma), _stream(stream)))
+
+
+def rbicgstab_gram(X: torch.Tensor, Y: torch.Tensor, stream=None) -> torch.Tensor:
+    """X^T Y with the library's Gram kernels.  X (mx, n) and Y (my, n) are device
+    tensors whose rows are the columns of the n x mx and n x my column-major
+    operands (leading dimension n); passing the same tensor twice gives the
+    symmetric product.  Returns the (my, mx) tensor whose rows are the columns
+    of X^T Y, i.e. its transpose Y^T X in row-major terms (synchronised)."""
+    lib = load_library()
+    mx, n = X.shape
+    my = Y.shape[0]
+    out = torch.empty((my, mx), dtype=torch.float64, device=X.device)
+    ws = torch.empty(max(1, lib.rbicgstab_gram_workspace_bytes(n, mx, my) // 8 + 32), dtype=torch.float64,
+                     device=X.device)
+    base = ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    nbytes = ws.numel() * 8 - (aligned - base)
+    _check(lib, None, lib.rbicgstab_gram(n, _ptr(X), n, mx, _ptr(Y), n, my, _ptr(out),
+                                         ctypes.c_void_p(aligned), nbytes, _stream(stream)))
+    torch.cuda.synchronize(X.device)
+    return out
 
 
 def rbicgstab_shifted_values(kval: torch.Tensor, diag_pos: torch.Tensor, mdiag: torch.Tensor,
