@@ -26,9 +26,11 @@ void launch_spmv(hipStream_t st, const SellF& A, const float* x, float* y);
 // Y[:, j] = A X[:, j], j < m (column-major, leading dimension ld)
 void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
                  int64_t ldy, int m);
-// Y[:, 0:ko] = X[:, 0:m] S   (S device, m x ko column-major with leading dim m)
+// Y[:, 0:ko] = X[:, 0:m] S   (S device, m x ko column-major with leading dim m);
+// upper: S is upper triangular (rows past a column's index are zero and are
+// skipped by the matrix-core path)
 void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m,
-                    const double* S, int ko, double* Y, int64_t ldy);
+                    const double* S, int ko, double* Y, int64_t ldy, bool upper = false);
 // out (mx x (my1+my2), column-major, ld = mx) = X^T [Y1 Y2]; partial buffer
 // must hold tile partials (see gemmt_partial_doubles).
 size_t gemmt_partial_doubles(int64_t n, int mx, int my);

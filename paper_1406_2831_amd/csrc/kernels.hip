@@ -368,12 +368,23 @@ __device__ __forceinline__ void block_groups(double (&v)[M], int m, const Comple
 // flight instead of one dependent chain per entry.
 constexpr int SPMV_BATCH = 8;
 
+// A row of a sliced-ELL matrix: its slice's start and width (the loads the
+// product's other loads depend on), then the product with x.
+struct SellSlice {
+    int32_t beg, end;
+};
+
 template <typename T>
-__device__ __forceinline__ T sell_row(const SellT<T>& A, int64_t row, const T* __restrict__ x) {
+__device__ __forceinline__ SellSlice sell_slice(const SellT<T>& A, int64_t row) {
     const int64_t s = row / WAVE;
+    return SellSlice{A.slice_ptr[s], A.slice_ptr[s + 1]};
+}
+
+template <typename T>
+__device__ __forceinline__ T sell_product(const SellT<T>& A, int64_t row, SellSlice sl, const T* __restrict__ x) {
     const int lane = (int)(row & (WAVE - 1));
-    const int32_t beg = A.slice_ptr[s];
-    const int w = (A.slice_ptr[s + 1] - beg) / WAVE;
+    const int32_t beg = sl.beg;
+    const int w = (sl.end - beg) / WAVE;
     T acc = 0;
     for (int j0 = 0; j0 < w; j0 += SPMV_BATCH) {
         int32_t c[SPMV_BATCH];
@@ -389,6 +400,11 @@ __device__ __forceinline__ T sell_row(const SellT<T>& A, int64_t row, const T* _
         for (int u = 0; u < SPMV_BATCH; ++u) acc += v[u] * x[c[u]];
     }
     return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T sell_row(const SellT<T>& A, int64_t row, const T* __restrict__ x) {
+    return sell_product(A, row, sell_slice(A, row), x);
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
@@ -985,7 +1001,7 @@ constexpr int TS_ROWS = 256, TS_COLS = 64, TS_KC = 16, TS_STRIDE = TS_COLS + 16;
 __global__ __launch_bounds__(BLOCK) void k_gemm_ts_mfma(int64_t n, const double* __restrict__ X,
                                                         int64_t ldx, int m, const double* __restrict__ S,
                                                         int ko, double* __restrict__ Y, int64_t ldy,
-                                                        int row_tiles, int col_tiles) {
+                                                        int row_tiles, int col_tiles, int upper) {
     __shared__ double sS[TS_KC * TS_STRIDE];
     const int total = row_tiles * col_tiles;
     int item = blockIdx.x;
@@ -1021,9 +1037,12 @@ __global__ __launch_bounds__(BLOCK) void k_gemm_ts_mfma(int64_t n, const double*
             sn[q] = (kk < m && c0 + c < ko) ? S[kk + (int64_t)(c0 + c) * m] : 0.0;
         }
     };
+    // upper-triangular S: column c takes rows 0..c only, so this column tile
+    // stops at its last column
+    const int kend = upper && c0 + TS_COLS < m ? c0 + TS_COLS : m;
     load_x(0);
     load_s(0);
-    for (int k0 = 0; k0 < m; k0 += TS_KC) {
+    for (int k0 = 0; k0 < kend; k0 += TS_KC) {
         __syncthreads();   // the previous chunk's LDS reads are done
 #pragma unroll
         for (int q = 0; q < TS_COLS / 16; ++q) sS[sk * TS_STRIDE + sc + 16 * q] = sn[q];
@@ -1032,7 +1051,7 @@ __global__ __launch_bounds__(BLOCK) void k_gemm_ts_mfma(int64_t n, const double*
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) xb[ks][rb] = xn[ks][rb];
-        if (k0 + TS_KC < m) {   // the next chunk's operands load while this one is multiplied
+        if (k0 + TS_KC < kend) {   // the next chunk's operands load while this one is multiplied
             load_x(k0 + TS_KC);
             load_s(k0 + TS_KC);
         }
@@ -1199,25 +1218,34 @@ __global__ __launch_bounds__(BLOCK) void k_pro2_fin(SolveBufsT<T> B, int nb) {
 
 // The row work of the three passes, split into the loads that do not depend
 // on the iteration's scalars and the arithmetic that does, so that a pass can
-// issue its first row's loads before the scalar step's round trip.  Block
-// columns are carried in registers up to bucket PREF_K; above it they are
-// read in the arithmetic part.
-constexpr int PREF_K = 16;
+// issue its first row's loads before the scalar step's round trip.  Operands
+// are held in their storage type (converted to FP64 where they are used).
+// Block columns are carried in registers (all of a row's loads in flight
+// together) up to bucket 16 and at buckets 28-32; at 20-24 they are read in
+// the arithmetic part, which measured faster there, and at 28-32 that form
+// was compiled into one load in flight at a time.  The multi-RHS passes
+// (several systems per workgroup) and the RBiCG passes (two block sets) carry
+// them up to PREF_K_WIDE.
 template <int K>
-constexpr int pref_cols() { return K > 0 && K <= PREF_K ? K : 1; }
+constexpr bool prefetched() { return K > 0 && (K <= 16 || (K >= 28 && K <= 32)); }
+constexpr int PREF_K_WIDE = 16;
+template <int K>
+constexpr int pref_cols() { return prefetched<K>() ? K : 1; }
+template <int K>
+constexpr int pref_cols_wide() { return K > 0 && K <= PREF_K_WIDE ? K : 1; }
 
 // update: (end of iteration i-1 and start of iteration i) r = s - omega t,
 // x += alpha p + omega s, p = r + beta (p - omega q); sums ||r||^2,
 // (rt0, r), (rh, p), Gh^T p
-template <int K>
+template <typename T, int K>
 struct UpdateRow {
-    double s, t, p, q, x, rt0, rh;
-    double gh[pref_cols<K>()];
+    T s, t, p, q, x, rt0, rh;
+    T gh[pref_cols<K>()];
 };
 
 template <typename T, int K>
-__device__ __forceinline__ UpdateRow<K> update_load(const SolveBufsT<T>& B, int64_t row) {
-    UpdateRow<K> d;
+__device__ __forceinline__ UpdateRow<T, K> update_load(const SolveBufsT<T>& B, int64_t row) {
+    UpdateRow<T, K> d;
     d.s = B.s[row];
     d.t = B.t[row];
     d.p = B.p[row];
@@ -1225,7 +1253,7 @@ __device__ __forceinline__ UpdateRow<K> update_load(const SolveBufsT<T>& B, int6
     d.x = B.x[row];
     d.rt0 = B.rt0[row];
     d.rh = B.rh[row];
-    if constexpr (K > 0 && K <= PREF_K) {
+    if constexpr (prefetched<K>()) {
 #pragma unroll
         for (int j = 0; j < K; ++j) d.gh[j] = B.Gh[row + col_off(j, B.k, B.ld)];
     }
@@ -1233,20 +1261,21 @@ __device__ __forceinline__ UpdateRow<K> update_load(const SolveBufsT<T>& B, int6
 }
 
 template <typename T, int K>
-__device__ __forceinline__ void update_finish(const SolveBufsT<T>& B, int64_t row, const UpdateRow<K>& d,
+__device__ __forceinline__ void update_finish(const SolveBufsT<T>& B, int64_t row, const UpdateRow<T, K>& d,
                                               double alpha, double omega, double beta, double (&acc)[K + 3]) {
-    const double rv = d.s - omega * d.t;
-    B.x[row] = d.x + (alpha * d.p + omega * d.s);
-    const double pn = rv + beta * (d.p - omega * d.q);
+    const double s = d.s, t = d.t, p = d.p, q = d.q;
+    const double rv = s - omega * t;
+    B.x[row] = (double)d.x + (alpha * p + omega * s);
+    const double pn = rv + beta * (p - omega * q);
     B.r[row] = rv;
     B.p[row] = pn;
     acc[0] += rv * rv;
-    acc[1] += d.rt0 * rv;
-    acc[2] += d.rh * pn;
+    acc[1] += (double)d.rt0 * rv;
+    acc[2] += (double)d.rh * pn;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double g;
-        if constexpr (K <= PREF_K) g = d.gh[j];
+        if constexpr (prefetched<K>()) g = d.gh[j];
         else g = B.Gh[row + col_off(j, B.k, B.ld)];
         acc[3 + j] += g * pn;
     }
@@ -1265,18 +1294,20 @@ __device__ __forceinline__ void update_rows(const SolveBufsT<T>& B, int64_t r0, 
 }
 
 // spmv1: q = A p - C zeta ; s = r - alpha q ; sums Gh^T s
-template <int K>
+template <typename T, int K>
 struct Spmv1Row {
-    double ap, r;
-    double c[pref_cols<K>()], gh[pref_cols<K>()];
+    T ap, r;
+    T c[pref_cols<K>()], gh[pref_cols<K>()];
 };
 
 template <typename T, int K>
-__device__ __forceinline__ Spmv1Row<K> spmv1_load(const SolveBufsT<T>& B, int64_t row) {
-    Spmv1Row<K> d;
+__device__ __forceinline__ Spmv1Row<T, K> spmv1_load(const SolveBufsT<T>& B, int64_t row) {
+    // (the product first: with the block columns live across the product's
+    // loop this pass drops a wave per SIMD at bucket 16)
+    Spmv1Row<T, K> d;
     d.ap = sell_row(B.A, row, B.p);
     d.r = B.r[row];
-    if constexpr (K > 0 && K <= PREF_K) {
+    if constexpr (prefetched<K>()) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t o = row + col_off(j, B.k, B.ld);
@@ -1288,65 +1319,67 @@ __device__ __forceinline__ Spmv1Row<K> spmv1_load(const SolveBufsT<T>& B, int64_
 }
 
 template <typename T, int K>
-__device__ __forceinline__ void spmv1_finish(const SolveBufsT<T>& B, int64_t row, const Spmv1Row<K>& d,
+__device__ __forceinline__ void spmv1_finish(const SolveBufsT<T>& B, int64_t row, const Spmv1Row<T, K>& d,
                                              double alpha, const double* zeta, double (&acc)[K > 0 ? K : 1]) {
     double qv = d.ap;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double c;
-        if constexpr (K <= PREF_K) c = d.c[j];
+        if constexpr (prefetched<K>()) c = d.c[j];
         else c = B.C[row + col_off(j, B.k, B.ld)];
         qv -= c * zeta[j];
     }
-    const double sv = d.r - alpha * qv;
+    const double sv = (double)d.r - alpha * qv;
     B.q[row] = qv;
     B.s[row] = sv;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double g;
-        if constexpr (K <= PREF_K) g = d.gh[j];
+        if constexpr (prefetched<K>()) g = d.gh[j];
         else g = B.Gh[row + col_off(j, B.k, B.ld)];
         acc[j] += g * sv;
     }
 }
 
 // spmv2: t = A s - C gamma ; sums (s,t), (t,t), (rt0,s), (rt0,t), (s,s)
-template <int K>
+template <typename T, int K>
 struct Spmv2Row {
-    double as, s, rt;
-    double c[pref_cols<K>()];
+    T as, s, rt;
+    T c[pref_cols<K>()];
 };
 
 template <typename T, int K>
-__device__ __forceinline__ Spmv2Row<K> spmv2_load(const SolveBufsT<T>& B, int64_t row) {
-    Spmv2Row<K> d;
-    d.as = sell_row(B.A, row, B.s);
+__device__ __forceinline__ Spmv2Row<T, K> spmv2_load(const SolveBufsT<T>& B, int64_t row) {
+    Spmv2Row<T, K> d;   // block columns ahead of the product, as in spmv1_load
+    const SellSlice sl = sell_slice(B.A, row);
     d.s = B.s[row];
     d.rt = B.rt0[row];
-    if constexpr (K > 0 && K <= PREF_K) {
+    if constexpr (prefetched<K>()) {
 #pragma unroll
         for (int j = 0; j < K; ++j) d.c[j] = B.C[row + col_off(j, B.k, B.ld)];
     }
+    d.as = sell_product(B.A, row, sl, B.s);
     return d;
 }
 
 template <typename T, int K>
-__device__ __forceinline__ void spmv2_finish(const SolveBufsT<T>& B, int64_t row, const Spmv2Row<K>& d,
+__device__ __forceinline__ void spmv2_finish(const SolveBufsT<T>& B, int64_t row, const Spmv2Row<T, K>& d,
                                              const double* gam, double (&acc)[5]) {
+    const double s = d.s, rt = d.rt;
     double tv = d.as;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double c;
-        if constexpr (K <= PREF_K) c = d.c[j];
+        if constexpr (prefetched<K>()) c = d.c[j];
         else c = B.C[row + col_off(j, B.k, B.ld)];
         tv -= c * gam[j];
     }
     B.t[row] = tv;
-    acc[0] += d.s * tv;
+    acc[0] += s * tv;
     acc[1] += tv * tv;
-    acc[2] += d.rt * d.s;
-    acc[3] += d.rt * tv;
-    acc[4] += d.s * d.s;
+    acc[2] += rt * s;
+    acc[3] += rt * tv;
+    acc[4] += s * s;
 }
 
 // ---- the scalar steps of Algorithm 2, from the previous pass's totals
@@ -1456,7 +1489,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(SolveBufsT<T> B, int fin) {
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     const int64_t row0 = r0 + threadIdx.x;
-    UpdateRow<K> d0;
+    UpdateRow<T, K> d0;
     if (row0 < r1) d0 = update_load<T, K>(B, row0);
     if (done) return;
     double omega = omega0, beta = beta0;   // first iteration: the prologue's zeros; timing: the state's
@@ -1514,7 +1547,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B, int fin) {
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     const int64_t row0 = r0 + threadIdx.x;
-    Spmv1Row<K> d0;
+    Spmv1Row<T, K> d0;
     if (row0 < r1) d0 = spmv1_load<T, K>(B, row0);
     if (done) return;
     if (threadIdx.x < B.k) sw[threadIdx.x] = wv;
@@ -1564,7 +1597,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B, int fin) {
     int64_t r0, r1;
     block_rows(B.n, r0, r1);
     const int64_t row0 = r0 + threadIdx.x;
-    Spmv2Row<K> d0;
+    Spmv2Row<T, K> d0;
     if (row0 < r1) d0 = spmv2_load<T, K>(B, row0);
     if (done) return;
     double gam[KM];
@@ -1825,7 +1858,7 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
     block_rows(B.n, r0, r1);
     const int64_t row0 = r0 + lane;
     double d0[7];
-    double gh0[pref_cols<K>()];
+    double gh0[pref_cols_wide<K>()];
     if (row0 < r1) {
         const int64_t o = row0 + so;
         d0[0] = B.s[o];
@@ -1835,7 +1868,7 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
         d0[4] = B.x[o];
         d0[5] = B.rt0[o];
         d0[6] = B.rh[o];
-        if constexpr (K > 0 && K <= PREF_K) {
+        if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) gh0[jj] = B.Gh[row0 + col_off(jj, k, ld)];
         }
@@ -1882,7 +1915,7 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
                 double gv;
-                if constexpr (K <= PREF_K) gv = gh[jj];
+                if constexpr (K <= PREF_K_WIDE) gv = gh[jj];
                 else gv = B.Gh[row + col_off(jj, k, ld)];
                 acc[3 + jj] += gv * pn;
             }
@@ -1891,8 +1924,8 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
         for (int64_t row = row0 + WAVE; row < r1; row += WAVE) {
             const int64_t o = row + so;
             double d[7] = {B.s[o], B.t[o], B.p[o], B.q[o], B.x[o], B.rt0[o], B.rh[o]};
-            double gh[pref_cols<K>()];
-            if constexpr (K > 0 && K <= PREF_K) {
+            double gh[pref_cols_wide<K>()];
+            if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
                 for (int jj = 0; jj < K; ++jj) gh[jj] = B.Gh[row + col_off(jj, k, ld)];
             }
@@ -1934,11 +1967,11 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
     block_rows(B.n, r0, r1);
     const int64_t row0 = r0 + lane;
     double ap0 = 0.0, rv0 = 0.0;
-    double c0[pref_cols<K>()], gh0[pref_cols<K>()];
-    if (row0 < r1) {
-        ap0 = sell_row(B.A, row0, B.p + so);
+    double c0[pref_cols_wide<K>()], gh0[pref_cols_wide<K>()];
+    if (row0 < r1) {   // slice bounds and block columns ahead of the product
+        const SellSlice sl = sell_slice(B.A, row0);
         rv0 = B.r[row0 + so];
-        if constexpr (K > 0 && K <= PREF_K) {
+        if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
                 const int64_t o = row0 + col_off(jj, k, ld);
@@ -1946,6 +1979,7 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
                 gh0[jj] = B.Gh[o];
             }
         }
+        ap0 = sell_product(B.A, row0, sl, B.p + so);
     }
     if (threadIdx.x < B.nr * B.k) sw[(threadIdx.x / B.k) * M + threadIdx.x % B.k] = wv;
     if (threadIdx.x < B.nr) {
@@ -1991,7 +2025,7 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
                 double cv;
-                if constexpr (K <= PREF_K) cv = c[jj];
+                if constexpr (K <= PREF_K_WIDE) cv = c[jj];
                 else cv = B.C[row + col_off(jj, k, ld)];
                 qv -= cv * zeta[jj];
             }
@@ -2001,17 +2035,17 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
                 double gv;
-                if constexpr (K <= PREF_K) gv = gh[jj];
+                if constexpr (K <= PREF_K_WIDE) gv = gh[jj];
                 else gv = B.Gh[row + col_off(jj, k, ld)];
                 acc[jj] += gv * sv;
             }
         };
         if (row0 < r1) finish(row0, ap0, rv0, c0, gh0);
         for (int64_t row = row0 + WAVE; row < r1; row += WAVE) {
-            const double ap = sell_row(B.A, row, B.p + so);
+            const SellSlice sl = sell_slice(B.A, row);
             const double rv = B.r[row + so];
-            double c[pref_cols<K>()], gh[pref_cols<K>()];
-            if constexpr (K > 0 && K <= PREF_K) {
+            double c[pref_cols_wide<K>()], gh[pref_cols_wide<K>()];
+            if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
                 for (int jj = 0; jj < K; ++jj) {
                     const int64_t o = row + col_off(jj, k, ld);
@@ -2019,7 +2053,7 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
                     gh[jj] = B.Gh[o];
                 }
             }
-            finish(row, ap, rv, c, gh);
+            finish(row, sell_product(B.A, row, sl, B.p + so), rv, c, gh);
         }
     }
     if constexpr (K > 0) multi_groups<M>(acc, j, B, 1);
@@ -2043,15 +2077,16 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B, int fin) {
     block_rows(B.n, r0, r1);
     const int64_t row0 = r0 + lane;
     double as0 = 0.0, s0 = 0.0, rt0v = 0.0;
-    double c0[pref_cols<K>()];
-    if (row0 < r1) {
-        as0 = sell_row(B.A, row0, B.s + so);
+    double c0[pref_cols_wide<K>()];
+    if (row0 < r1) {   // slice bounds and block columns ahead of the product
+        const SellSlice sl = sell_slice(B.A, row0);
         s0 = B.s[row0 + so];
         rt0v = B.rt0[row0 + so];
-        if constexpr (K > 0 && K <= PREF_K) {
+        if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) c0[jj] = B.C[row0 + col_off(jj, k, ld)];
         }
+        as0 = sell_product(B.A, row0, sl, B.s + so);
     }
     if (threadIdx.x < B.nr) sdone[threadIdx.x] = q_done;
     if constexpr (K > 0) {
@@ -2082,7 +2117,7 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B, int fin) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
                 double cv;
-                if constexpr (K <= PREF_K) cv = c[jj];
+                if constexpr (K <= PREF_K_WIDE) cv = c[jj];
                 else cv = B.C[row + col_off(jj, k, ld)];
                 tv -= cv * gam[jj];
             }
@@ -2095,14 +2130,15 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv2(MultiBufs B, int fin) {
         };
         if (row0 < r1) finish(row0, as0, s0, rt0v, c0);
         for (int64_t row = row0 + WAVE; row < r1; row += WAVE) {
-            const double as = sell_row(B.A, row, B.s + so);
+            const SellSlice sl = sell_slice(B.A, row);
             const int64_t o = row + so;
-            double c[pref_cols<K>()];
-            if constexpr (K > 0 && K <= PREF_K) {
+            const double sv = B.s[o], rtv = B.rt0[o];
+            double c[pref_cols_wide<K>()];
+            if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
                 for (int jj = 0; jj < K; ++jj) c[jj] = B.C[row + col_off(jj, k, ld)];
             }
-            finish(row, as, B.s[o], B.rt0[o], c);
+            finish(row, sell_product(B.A, row, sl, B.s + so), sv, rtv, c);
         }
     }
     multi_groups<5>(acc, j, B, 2);
@@ -2343,7 +2379,7 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
 template <int K>
 struct BupdateRow {
     double r, q, rt, qt, p, pt, x;
-    double gh[pref_cols<K>()], ght[pref_cols<K>()];
+    double gh[pref_cols_wide<K>()], ght[pref_cols_wide<K>()];
 };
 
 template <int K>
@@ -2356,7 +2392,7 @@ __device__ __forceinline__ BupdateRow<K> bupdate_load(const BicgBufs& B, int64_t
     d.p = B.p[row];
     d.pt = B.pt[row];
     d.x = B.x[row];
-    if constexpr (K > 0 && K <= PREF_K) {
+    if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t o = row + col_off(j, B.k, B.ld);
@@ -2384,7 +2420,7 @@ __device__ __forceinline__ void bupdate_finish(const BicgBufs& B, int64_t row, c
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double g, gt;
-        if constexpr (K <= PREF_K) {
+        if constexpr (K <= PREF_K_WIDE) {
             g = d.gh[j];
             gt = d.ght[j];
         } else {
@@ -2468,18 +2504,19 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
 template <int K>
 struct BspmvRow {
     double ap, atpt, pt, r, rt;
-    double c[pref_cols<K>()], ct[pref_cols<K>()];
+    double c[pref_cols_wide<K>()], ct[pref_cols_wide<K>()];
 };
 
 template <int K>
 __device__ __forceinline__ BspmvRow<K> bspmv_load(const BicgBufs& B, int64_t row) {
+    // both products' slice bounds and the block columns ahead of the
+    // products' dependent loads
     BspmvRow<K> d;
-    d.ap = sell_row(B.A, row, B.p);
-    d.atpt = sell_row(B.At, row, B.pt);
+    const SellSlice sa = sell_slice(B.A, row), sat = sell_slice(B.At, row);
     d.pt = B.pt[row];
     d.r = B.r[row];
     d.rt = B.rt[row];
-    if constexpr (K > 0 && K <= PREF_K) {
+    if constexpr (K > 0 && K <= PREF_K_WIDE) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t o = row + col_off(j, B.k, B.ld);
@@ -2487,6 +2524,8 @@ __device__ __forceinline__ BspmvRow<K> bspmv_load(const BicgBufs& B, int64_t row
             d.ct[j] = B.Ct[o];
         }
     }
+    d.ap = sell_product(B.A, row, sa, B.p);
+    d.atpt = sell_product(B.At, row, sat, B.pt);
     return d;
 }
 
@@ -2497,7 +2536,7 @@ __device__ __forceinline__ void bspmv_finish(const BicgBufs& B, int64_t row, con
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double c, ct;
-        if constexpr (K <= PREF_K) {
+        if constexpr (K <= PREF_K_WIDE) {
             c = d.c[j];
             ct = d.ct[j];
         } else {
@@ -2720,7 +2759,7 @@ void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, do
 }
 
 void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m, const double* S,
-                    int ko, double* Y, int64_t ldy) {
+                    int ko, double* Y, int64_t ldy, bool upper) {
     if (ko <= 0 || n <= 0) return;
     if (ko > GC && m >= TS_KC) {   // wide products on the matrix cores
         const int64_t rt = (n + TS_ROWS - 1) / TS_ROWS;
@@ -2728,7 +2767,7 @@ void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int
         int64_t g = rt * ct;
         if (g >= 64) g = (g + 7) / 8 * 8;
         hipLaunchKernelGGL(k_gemm_ts_mfma, dim3((unsigned)g), dim3(BLOCK), 0, st, n, X, ldx, m, S, ko, Y,
-                           ldy, (int)rt, ct);
+                           ldy, (int)rt, ct, upper ? 1 : 0);
         return;
     }
     hipLaunchKernelGGL(k_gemm_ts, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, X, ldx, m, S, ko, Y, ldy);
