@@ -618,6 +618,7 @@ def main():
             "within_bound": max(errs) <= kappa * args.rtol}
     if not args.no_hbm128:
         out["hbm_resident_128"] = hbm_resident_passes(args)
+        out["hbm_stream_reference"] = stream_references()
     if args.calib_copy_mib > 0:
         # a plain device-to-device copy of known size (outside the timed region):
         # the reference the HBM counters of a profiled run are calibrated with
@@ -632,6 +633,25 @@ def main():
         out["cpu_baseline"] = cpu_baseline(seq, args.rtol, args.cpu_systems)
     gs.close()
     print(json.dumps(out), flush=True)
+
+
+def stream_references(n=1 << 27, reps=10):
+    """HBM rates of plain streams with the passes' work distribution (the library's
+    streaming reference kernels over two 1 GiB buffers, four times the last-level
+    cache): a read, a copy, and the update pass's seven-read / three-write mix, at
+    the passes' grid of 1024 workgroups and at 4096."""
+    import torch
+    from paper_1406_2831_amd.rbicgstab import rbicgstab_time_stream
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for grid in (1024, 4096):
+        for kind, name in ((0, "read"), (1, "copy"), (2, "mix_7r_3w")):
+            ms, by = rbicgstab_time_stream(kind, a, b, grid, reps)
+            gbs = by / (ms * 1e-3) / 1e9
+            res[f"{name}_grid{grid}"] = {"us": ms * 1e3, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    del a, b
+    return res
 
 
 def hbm_resident_passes(args, N=128, k=20):

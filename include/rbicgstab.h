@@ -200,8 +200,9 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  * Time one of the fused per-iteration passes of Algorithm 2 on the bound
  * matrix with recycle dimension k (0 <= k <= installed k): which = 0 the
  * update pass, 1 the first SpMV + projection pass, 2 the second SpMV +
- * projection pass (each including its in-kernel reduction by the last
- * workgroup, with the scalar update skipped), 3 a plain SpMV; which = 4..7 the same passes
+ * projection pass (each including the previous pass's second reduction level
+ * in every workgroup and its own first level, with the scalar step's results
+ * not recorded), 3 a plain SpMV; which = 4..7 the same passes
  * with the FP32 storage of RBS_FP32_IR (4-byte values and vector entries);
  * which = 8 + 4 (nr - 1) + pass (pass 0..2) the multi-RHS pass of
  * rbicgstab_solve_multi for nr systems (nr, k in its fused range).  The pass is launched `reps` times
@@ -222,6 +223,26 @@ int rbicgstab_get_blocks(rbs_ctx* ctx, double* U, double* Ut, double* C, double*
  */
 int rbicgstab_time_pass(rbs_ctx* ctx, int32_t which, int32_t k, int32_t reps, double* avg_ms,
                         double* bytes);
+
+/*
+ * Streaming reference rates for the fused passes' rooflines: plain streams
+ * over caller buffers with the passes' work distribution (a contiguous row
+ * range per workgroup, `grid` workgroups of 256 threads; the passes use
+ * min(n / 256, 1024)).  kind 0 reads a[0, n) (and writes one double per
+ * thread to b[0, 256 grid)); kind 1 copies a[0, n) to
+ * b[0, n); kind 2 reads seven streams of a and writes three of b, each
+ * len = floor(n / 8192) * 1024 doubles long and len + 512 doubles apart (the
+ * update pass's seven vector reads and three writes; a and b hold n doubles).
+ * a, b: device; the launch is repeated `reps` times on `stream` between two
+ * HIP events after one warm-up launch; *avg_ms receives the mean duration of
+ * one launch and *bytes the bytes it reads and writes.  For n well past the
+ * 256 MB last-level cache these are the HBM rates the pattern reaches with
+ * no arithmetic.  Errors: RBS_ERR_ARG (kind 0..2, 2^16 <= n < 2^40, grid a
+ * multiple of 8 in [8, 65536] with 256 grid <= n, reps >= 1, non-NULL
+ * buffers), RBS_ERR_HIP.
+ */
+int rbicgstab_time_stream(int32_t kind, int64_t n, const double* a, double* b, int32_t grid, int32_t reps,
+                          hipStream_t stream, double* avg_ms, double* bytes);
 
 /*
  * Adjoint gradients for the parametrised matrices A(sigma) = K + sigma M of

@@ -1870,6 +1870,40 @@ int rbicgstab_gram(int64_t n, const double* X, int64_t ldx, int32_t mx, const do
     return RBS_OK;
 }
 
+int rbicgstab_time_stream(int32_t kind, int64_t n, const double* a, double* b, int32_t grid, int32_t reps,
+                          hipStream_t stream, double* avg_ms, double* bytes) {
+    if (kind < 0 || kind > 2 || n < (int64_t(1) << 16) || n >= (int64_t(1) << 40) || !a || !b || grid < 8 ||
+        grid > 65536 || grid % 8 != 0 || (int64_t)grid * 256 > n || reps < 1)
+        return fail(nullptr, RBS_ERR_ARG,
+                    "kind 0..2, 2^16 <= n < 2^40, a and b required, grid a multiple of 8 in [8, 65536] with "
+                    "256 grid <= n, reps >= 1");
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return fail(nullptr, RBS_ERR_HIP, hipGetErrorString(e));
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(nullptr, RBS_ERR_HIP, hipGetErrorString(e));
+    }
+    rbs::launch_stream(stream, kind, a, b, n, grid);   // warm-up
+    hipEventRecord(e0, stream);
+    for (int i = 0; i < reps; ++i) rbs::launch_stream(stream, kind, a, b, n, grid);
+    hipEventRecord(e1, stream);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(nullptr, RBS_ERR_HIP, std::string("stream timing: ") + hipGetErrorString(e));
+    if (avg_ms) *avg_ms = ms / reps;
+    if (bytes) {
+        const double len = (double)(rbs::stream_mix_ld(n) - 512);
+        *bytes = kind == 0 ? 8.0 * n + 8.0 * grid * 256 : kind == 1 ? 16.0 * n : 80.0 * len;
+    }
+    return RBS_OK;
+}
+
 int rbicgstab_shifted_values(int64_t n, int64_t nnz, const double* kval, const int64_t* diag_pos,
                              const double* mdiag, double sigma, const int64_t* perm_t, double* val,
                              double* valT, hipStream_t stream) {

@@ -24,6 +24,12 @@ void launch_copy(hipStream_t st, double* y, const double* x, int64_t len);
 void launch_spmv(hipStream_t st, const Sell& A, const double* x, double* y);
 void launch_spmv(hipStream_t st, const SellF& A, const float* x, float* y);
 // Y[:, j] = A X[:, j], j < m (column-major, leading dimension ld)
+// Streaming references (kind 0 read of a[0, n) with one value per thread to
+// b, 1 copy a -> b, 2 seven read streams of a and three write streams of b,
+// stream_mix_ld(n) apart) with the passes' work distribution over `grid`
+// workgroups.
+int64_t stream_mix_ld(int64_t n);
+void launch_stream(hipStream_t st, int kind, const double* a, double* b, int64_t n, int grid);
 void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
                  int64_t ldy, int m);
 // Y[:, 0:ko] = X[:, 0:m] S   (S device, m x ko column-major with leading dim m);

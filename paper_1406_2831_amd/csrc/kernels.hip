@@ -513,15 +513,90 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellT<T> A, const T* __restrict_
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) y[row] = sell_row(A, row, x);
 }
 
+// ---------------------------------------------------------------- streaming references
+//
+// Plain streams with the passes' work distribution (a contiguous row range
+// per workgroup, rows strided by the workgroup size inside it), timed to give
+// the HBM rates such access reaches without any arithmetic: a read of one
+// array, a copy, and the update pass's mix of seven read and three write
+// streams ld apart.  Each thread has STREAM_U rows' loads in flight at once.
+constexpr int STREAM_U = 4;
+
+__global__ __launch_bounds__(BLOCK) void k_stream_read(const double* __restrict__ a, int64_t n,
+                                                       double* __restrict__ out) {
+    int64_t r0, r1;
+    block_rows(n, r0, r1);
+    double acc[STREAM_U] = {0.0, 0.0, 0.0, 0.0};
+    int64_t r = r0 + threadIdx.x;
+    for (; r + (STREAM_U - 1) * BLOCK < r1; r += STREAM_U * BLOCK) {
+        double v[STREAM_U];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) v[u] = a[r + u * BLOCK];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) acc[u] += v[u];
+    }
+    for (; r < r1; r += BLOCK) acc[0] += a[r];
+    out[(int64_t)blockIdx.x * BLOCK + threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_stream_copy(const double* __restrict__ a, double* __restrict__ b,
+                                                       int64_t n) {
+    int64_t r0, r1;
+    block_rows(n, r0, r1);
+    int64_t r = r0 + threadIdx.x;
+    for (; r + (STREAM_U - 1) * BLOCK < r1; r += STREAM_U * BLOCK) {
+        double v[STREAM_U];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) v[u] = a[r + u * BLOCK];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) b[r + u * BLOCK] = v[u];
+    }
+    for (; r < r1; r += BLOCK) b[r] = a[r];
+}
+
+__device__ __forceinline__ void stream_mix_row(const double (&v)[7], double* __restrict__ b, int64_t r,
+                                               int64_t ld) {
+    const double s = v[0] + v[1] + v[2] + v[3], t = v[4] + v[5] + v[6];
+    b[r] = s;
+    b[r + ld] = t;
+    b[r + 2 * ld] = s - t;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_stream_mix(const double* __restrict__ a, double* __restrict__ b,
+                                                      int64_t len, int64_t ld) {
+    int64_t r0, r1;
+    block_rows(len, r0, r1);
+    int64_t r = r0 + threadIdx.x;
+    for (; r + (STREAM_U - 1) * BLOCK < r1; r += STREAM_U * BLOCK) {
+        double v[STREAM_U][7];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u)
+#pragma unroll
+            for (int j = 0; j < 7; ++j) v[u][j] = a[r + u * BLOCK + j * ld];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u) stream_mix_row(v[u], b, r + u * BLOCK, ld);
+    }
+    for (; r < r1; r += BLOCK) {
+        double v[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) v[j] = a[r + j * ld];
+        stream_mix_row(v, b, r, ld);
+    }
+}
+
+// Y[:, 0:m] = A X[:, 0:m]: blockIdx.y takes columns 8 y .. 8 y + 7, so that
+// the column groups of a row range run in parallel (on the XCD that holds
+// those rows of A in its L2) instead of one after another in each thread.
 __global__ __launch_bounds__(BLOCK) void k_spmm(Sell A, const double* __restrict__ X, int64_t ldx,
                                                 double* __restrict__ Y, int64_t ldy, int m) {
     int64_t r0, r1;
     block_rows(A.n, r0, r1);
+    const int c0 = 8 * (int)blockIdx.y;
     for (int64_t row = r0 + threadIdx.x; row < r1; row += BLOCK) {
         const int64_t s = row / WAVE;
         const int lane = (int)(row & (WAVE - 1));
         const int32_t beg = A.slice_ptr[s], end = A.slice_ptr[s + 1];
-        for (int c0 = 0; c0 < m; c0 += 8) {
+        {
             double acc[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc[c] = 0.0;
@@ -974,9 +1049,19 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_cls(int mx, int my, int 
     const int64_t tile = (int64_t)cl.tx_dim * cl.ty_dim;
     const double* p = partial + cl.slot0 + (int64_t)t * tile + off;
     const int64_t cstride = (int64_t)cl.ntiles * tile;
+    // 32 loads in flight (a launch has about one wave per SIMD, so each
+    // thread's chain of round trips is the launch's time), summed in chunk
+    // order
     double s = 0.0;
     int c = 0;
-    for (; c + 8 <= cl.nchunks; c += 8) {   // eight loads in flight, summed in chunk order
+    for (; c + 32 <= cl.nchunks; c += 32) {
+        double v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = p[(int64_t)(c + u) * cstride];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) s += v[u];
+    }
+    for (; c + 8 <= cl.nchunks; c += 8) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * cstride];
@@ -2752,10 +2837,25 @@ void launch_spmv(hipStream_t st, const SellF& A, const float* x, float* y) {
     hipLaunchKernelGGL(k_spmv<float>, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, x, y);
 }
 
+int64_t stream_mix_ld(int64_t n) {
+    // seven streams of len rows, ld = 512 (mod 1024) apart, inside n doubles
+    const int64_t len = n / 8 / 1024 * 1024;
+    return len + 512;
+}
+
+void launch_stream(hipStream_t st, int kind, const double* a, double* b, int64_t n, int grid) {
+    if (kind == 0) hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(BLOCK), 0, st, a, n, b);
+    else if (kind == 1) hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(BLOCK), 0, st, a, b, n);
+    else {
+        const int64_t ld = stream_mix_ld(n);
+        hipLaunchKernelGGL(k_stream_mix, dim3(grid), dim3(BLOCK), 0, st, a, b, ld - 512, ld);
+    }
+}
+
 void launch_spmm(hipStream_t st, const Sell& A, const double* X, int64_t ldx, double* Y,
                  int64_t ldy, int m) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_spmm, dim3(stream_grid(A.n)), dim3(BLOCK), 0, st, A, X, ldx, Y, ldy, m);
+    hipLaunchKernelGGL(k_spmm, dim3(stream_grid(A.n), (m + 7) / 8), dim3(BLOCK), 0, st, A, X, ldx, Y, ldy, m);
 }
 
 void launch_gemm_ts(hipStream_t st, int64_t n, const double* X, int64_t ldx, int m, const double* S,

@@ -42,7 +42,7 @@ RBS_RECYCLE_FROM_LAST_SOLVE = 1
 RBS_RECYCLE_CLEAR = 2
 
 EXPORTS = ("rbicgstab_workspace_bytes", "rbicgstab_setup", "rbicgstab_solve", "recycle_update",
-           "rbicgstab_get_blocks", "rbicgstab_time_pass", "rbicgstab_setup_matvecs",
+           "rbicgstab_get_blocks", "rbicgstab_time_pass", "rbicgstab_time_stream", "rbicgstab_setup_matvecs",
            "rbicgstab_adjoint_grads", "rbicgstab_shifted_values", "rbicgstab_solve_multi",
            "rbicgstab_destroy", "rbicgstab_last_error", "rbicgstab_batch_workspace_bytes",
            "rbicgstab_batch_create", "rbicgstab_batch_solve", "rbicgstab_batch_config",
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.rbicgstab_get_blocks.restype = ctypes.c_int
     lib.rbicgstab_time_pass.argtypes = [vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
     lib.rbicgstab_time_pass.restype = ctypes.c_int
+    lib.rbicgstab_time_stream.argtypes = [i32, i64, vp, vp, i32, i32, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    lib.rbicgstab_time_stream.restype = ctypes.c_int
     lib.rbicgstab_adjoint_grads.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(f64)]
     lib.rbicgstab_adjoint_grads.restype = ctypes.c_int
     lib.rbicgstab_adjoint_grads_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -219,6 +221,16 @@ def rbicgstab_time_pass(handle, which: int, k: int, reps: int):
     ms, by = ctypes.c_double(0), ctypes.c_double(0)
     _check(lib, handle, lib.rbicgstab_time_pass(handle, which, k, reps, ctypes.byref(ms),
                                                 ctypes.byref(by)))
+    return ms.value, by.value
+
+
+def rbicgstab_time_stream(kind: int, a: torch.Tensor, b: torch.Tensor, grid: int, reps: int, stream=None):
+    """(mean ms per launch, bytes per launch) of a streaming reference kernel over the
+    float64 device tensors a and b (kind 0 read, 1 copy, 2 seven-read / three-write mix)."""
+    lib = load_library()
+    ms, by = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib, None, lib.rbicgstab_time_stream(kind, a.numel(), _ptr(a), _ptr(b), grid, reps,
+                                                _stream(stream), ctypes.byref(ms), ctypes.byref(by)))
     return ms.value, by.value
 
 
