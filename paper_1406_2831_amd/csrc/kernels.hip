@@ -915,9 +915,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     int64_t n, const double* __restrict__ X, int64_t ldx, int mx, const double* __restrict__ Y, int64_t ldy, int my,
     GemmtClass cl, double* __restrict__ partial) {
     __shared__ __attribute__((aligned(16))) double lds[2][2][16 * MT];   // buffer, operand, slab
+    // one-dimensional grid (a multiple of 8 workgroups): the workgroups of an
+    // XCD take a contiguous range of (row chunk, tile) items, tile fastest, so
+    // the tiles of a row chunk run together on one XCD and its L2 serves the
+    // operand slabs they share
+    const int item = logical_block();
+    if (item >= cl.ntiles * cl.nchunks) return;
+    const int tile = item % cl.ntiles, chunk = item / cl.ntiles;
     int a, b;
     if (cl.tri) {
-        int t = blockIdx.x;
+        int t = tile;
         a = 0;
         while (t >= cl.ntx - a) {
             t -= cl.ntx - a;
@@ -925,11 +932,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
         }
         b = a + t;
     } else {
-        a = blockIdx.x / cl.nty;
-        b = blockIdx.x % cl.nty;
+        a = tile / cl.nty;
+        b = tile % cl.nty;
     }
     const int gx0 = cl.x0 + MT * a, gy0 = cl.y0 + MT * b;
-    const int64_t c0 = (int64_t)blockIdx.y * cl.rows_per_chunk;
+    const int64_t c0 = (int64_t)chunk * cl.rows_per_chunk;
     const int64_t c1 = (c0 + cl.rows_per_chunk < n) ? c0 + cl.rows_per_chunk : n;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int wi = w >> 1, wj = w & 1;
@@ -1003,7 +1010,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
         __syncthreads();
         compute(0);
     }
-    double* out = partial + cl.slot0 + ((int64_t)blockIdx.y * cl.ntiles + blockIdx.x) * (MT * MT);
+    double* out = partial + cl.slot0 + ((int64_t)chunk * cl.ntiles + tile) * (MT * MT);
 #pragma unroll
     for (int it = 0; it < 4; ++it)
 #pragma unroll
@@ -2920,7 +2927,8 @@ void launch_gemmt_class(hipStream_t st, int64_t n, const double* X, int64_t ldx,
     // row chunks are multiples of 16 rows)
     if (WX == 4 && WY == 4 && ldx % 2 == 0 && ldy % 2 == 0 && ((uintptr_t)X & 15) == 0 &&
         ((uintptr_t)Y & 15) == 0 && cl.rows_per_chunk % MR == 0) {
-        hipLaunchKernelGGL(k_gemmt_mfma_dl, dim3(cl.ntiles, cl.nchunks), dim3(BLOCK), 0, st, n, X, ldx, mx, Y, ldy,
+        const int items = cl.ntiles * cl.nchunks;
+        hipLaunchKernelGGL(k_gemmt_mfma_dl, dim3((items + 7) / 8 * 8), dim3(BLOCK), 0, st, n, X, ldx, mx, Y, ldy,
                            my, cl, partial);
         return;
     }
