@@ -818,8 +818,8 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
                                                       double* __restrict__ partial) {
     constexpr int TX = 32 * WX, TY = 32 * WY;
     constexpr int SX = TX + 16, SY = TY + 16;
-    __shared__ double sx[MR * SX];
-    __shared__ double sy[MR * SY];
+    __shared__ double sx[2][MR * SX];   // double-buffered: one barrier per slab
+    __shared__ double sy[2][MR * SY];
     int a, b;
     if (cl.tri) {   // blockIdx.x enumerates the upper triangle row by row
         int t = blockIdx.x;
@@ -844,10 +844,10 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
     for (int p = 0; p < WX; ++p)
 #pragma unroll
         for (int q = 0; q < WY; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t base = c0; base < c1; base += MR) {
+    double px[TX / 16], py[TY / 16];   // a slab's operands, loaded one slab ahead
+    auto load = [&](int64_t base) {
         const int64_t row = base + lr;
         const bool rok = row < c1;
-        double px[TX / 16], py[TY / 16];   // this slab's operands: all loads first
 #pragma unroll
         for (int q = 0; q < TX / 16; ++q) {
             const int gi = gx0 + lc + 16 * q;
@@ -858,26 +858,34 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_mfma(int64_t n, const double* _
             const int gj = gy0 + lc + 16 * q;
             py[q] = (rok && gj < my) ? Y[row + (int64_t)gj * ldy] : 0.0;
         }
+    };
+    if (c0 < c1) load(c0);
+    int buf = 0;
+    for (int64_t base = c0; base < c1; base += MR, buf ^= 1) {
+        // this slab goes to the buffer of the slab before last: every wave
+        // finished that slab's products before it reached the last barrier
+        double* bx = sx[buf];
+        double* by = sy[buf];
 #pragma unroll
-        for (int q = 0; q < TX / 16; ++q) sx[lr * SX + ((lc + 16 * q) ^ lr)] = px[q];
+        for (int q = 0; q < TX / 16; ++q) bx[lr * SX + ((lc + 16 * q) ^ lr)] = px[q];
 #pragma unroll
-        for (int q = 0; q < TY / 16; ++q) sy[lr * SY + ((lc + 16 * q) ^ lr)] = py[q];
+        for (int q = 0; q < TY / 16; ++q) by[lr * SY + ((lc + 16 * q) ^ lr)] = py[q];
         __syncthreads();
+        if (base + MR < c1) load(base + MR);   // in flight while this slab is multiplied
 #pragma unroll
         for (int ks = 0; ks < MR / 4; ++ks) {
             const int r = ks * 4 + (lane >> 4);
             double av[WX], bv[WY];
 #pragma unroll
-            for (int t = 0; t < WX; ++t) av[t] = sx[r * SX + ((wi * 16 * WX + t * 16 + (lane & 15)) ^ r)];
+            for (int t = 0; t < WX; ++t) av[t] = bx[r * SX + ((wi * 16 * WX + t * 16 + (lane & 15)) ^ r)];
 #pragma unroll
-            for (int t = 0; t < WY; ++t) bv[t] = sy[r * SY + ((wj * 16 * WY + t * 16 + (lane & 15)) ^ r)];
+            for (int t = 0; t < WY; ++t) bv[t] = by[r * SY + ((wj * 16 * WY + t * 16 + (lane & 15)) ^ r)];
 #pragma unroll
             for (int it = 0; it < WX; ++it)
 #pragma unroll
                 for (int jt = 0; jt < WY; ++jt)
                     acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[it], bv[jt], acc[it][jt], 0, 0, 0);
         }
-        __syncthreads();
     }
     double* out = partial + cl.slot0 + ((int64_t)blockIdx.y * cl.ntiles + blockIdx.x) * (TX * TY);
 #pragma unroll
@@ -983,21 +991,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
                     acc[it][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[it], bv[jt], acc[it][jt], 0, 0, 0);
         }
     };
+    // One barrier per slab: after it, every wave's loads of slab sl have landed
+    // and every wave has finished the products of slab sl - 1, whose buffer
+    // then takes the loads of slab sl + 1 while slab sl is multiplied.
     const int64_t nfull = c1 > c0 ? (c1 - c0) / MR : 0;
     if (nfull > 0) issue(c0, 0);
     for (int64_t sl = 0; sl < nfull; ++sl) {
-        if (sl + 1 < nfull) {
-            issue(c0 + (sl + 1) * MR, (int)((sl + 1) & 1));
-            __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8): this wave's loads of slab sl have landed
-        } else {
-            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of slab sl have landed
         __syncthreads();
+        if (sl + 1 < nfull) issue(c0 + (sl + 1) * MR, (int)((sl + 1) & 1));
         compute((int)(sl & 1));
-        __syncthreads();
     }
     const int64_t tail = c0 + nfull * MR;
     if (tail < c1) {   // the last rows of the matrix: masked loads through registers into buffer 0
+        __syncthreads();   // every wave is done with the last slab's buffer
         const int lr = threadIdx.x & 15, lc = threadIdx.x >> 4;   // row lr of columns lc + 16 q
         const int64_t row = tail + lr;
         const bool rok = row < c1;
