@@ -52,6 +52,9 @@ def _check(rb, torch_mod, n, mx, my, sym, seed):
     (4099, 128, 128, False),    # interior only
     (4099, 40, 60, False),      # below the matrix-core sizes: the 64-tile kernel
     (262144, 282, 282, True),   # the benchmark's store size
+    (20007, 323, 323, True),    # 96-wide edges (the first shift's store size)
+    (20007, 323, 250, False),   # 96-wide bottom edge, 128-wide right edge
+    (4099, 228, 300, False),    # 128-wide bottom edge (100 valid), 64-wide right edge (44 valid)
 ])
 def test_gram_matches_numpy(rb, torch_mod, n, mx, my, sym):
     _check(rb, torch_mod, n, mx, my, sym, seed=n + mx + my)
