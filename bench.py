@@ -168,7 +168,7 @@ def adjoint_workload(args):
 
 def batched_workload(args):
     """32 shifted 3D 7-point systems of uneven size (n from 40k to 500k, velocities
-    U[-1,1]^3, sigma log-spaced in [1e-2, 1e1]), k = 16.  Round 1 (untimed) builds
+    U[-1,1]^3, sigma log-spaced in [1e-2, 1e1]), k = 16.  A first, untimed pass builds
     each system's recycle space by RBiCG; the timed step solves all 32 systems with
     their spaces in one batch (persistent tile-walking passes, tuned tiles, graph
     replay).  Also timed: the same solves one system at a time, and BiCGSTAB batched."""
