@@ -679,9 +679,11 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_tile(int64_t n, const double* _
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int64_t base = c0; base < c1; base += GS) {
-        // load: thread covers row (tid % 32) of 8 columns (tid / 32 + 8 q)
-        const int lr = threadIdx.x % GS, lc = threadIdx.x / GS;
+    // load: thread covers row (tid % 32) of 8 columns (tid / 32 + 8 q); the
+    // next slab's values load while the current slab is multiplied
+    const int lr = threadIdx.x % GS, lc = threadIdx.x / GS;
+    double px[GT / 8], py[GT / 8];
+    auto load = [&](int64_t base) {
         const int64_t row = base + lr;
 #pragma unroll
         for (int q = 0; q < GT / 8; ++q) {
@@ -692,10 +694,19 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_tile(int64_t n, const double* _
             const int gj = ty * GT + c;
             if (row < c1 && gj < my) vy = gj < my1 ? Y1[row + (int64_t)gj * ldy1]
                                                   : Y2[row + (int64_t)(gj - my1) * ldy2];
-            sx[lr][c] = vx;
-            sy[lr][c] = vy;
+            px[q] = vx;
+            py[q] = vy;
+        }
+    };
+    if (c0 < c1) load(c0);
+    for (int64_t base = c0; base < c1; base += GS) {
+#pragma unroll
+        for (int q = 0; q < GT / 8; ++q) {
+            sx[lr][lc + 8 * q] = px[q];
+            sy[lr][lc + 8 * q] = py[q];
         }
         __syncthreads();
+        if (base + GS < c1) load(base + GS);
 #pragma unroll 4
         for (int rr = 0; rr < GS; ++rr) {
             double a[4], b[4];
@@ -1032,8 +1043,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
 
 // Sum the row-chunk partial tiles of the classes into out (mx x my,
 // column-major, ld = mx).  cls[0..3]: interior, right edge, bottom edge,
-// corner (a class with no tiles has ntiles = 0).  Symmetric products mirror
-// the lower triangle from the upper one.
+// corner (a class with no tiles has ntiles = 0).  One thread per computed
+// tile element (consecutive threads: consecutive elements of a partial tile
+// row, so every chunk's load is coalesced); symmetric products also write
+// the mirror of the elements of off-diagonal interior tiles and of the right
+// edge (the lower triangle, which no tile computes).
 struct GemmtClasses {
     GemmtClass c[4];
     int lx, ly;   // full 128-tiles in x and y (the edge classes start there)
@@ -1045,45 +1059,61 @@ __global__ __launch_bounds__(BLOCK) void k_gemmt_reduce_cls(int mx, int my, int 
     __shared__ GemmtClass sc[4];   // the classes in LDS: indexed per thread below
     if (threadIdx.x < 4) sc[threadIdx.x] = cls.c[threadIdx.x];
     __syncthreads();
-    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= (int64_t)mx * my) return;
-    int i = (int)(idx / my), j = (int)(idx % my);   // consecutive threads: consecutive j
-    double* dst = out + i + (int64_t)j * mx;
-    if (symmetric && i / MT > j / MT) {
-        const int t = i;
-        i = j;
-        j = t;
+    int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int q = 0;
+    for (; q < 4; ++q) {   // the class of this element
+        const int64_t cnt = (int64_t)sc[q].ntiles * sc[q].tx_dim * sc[q].ty_dim;
+        if (idx < cnt) break;
+        idx -= cnt;
     }
-    const int ta = i / MT, tb = j / MT;
-    const bool ex = ta >= cls.lx, ey = tb >= cls.ly;
-    const GemmtClass& cl = sc[(ex ? 2 : 0) + (ey ? 1 : 0)];
-    const int a = ex ? 0 : ta, b = ey ? 0 : tb;
-    const int t = cl.tri ? a * cl.ntx - a * (a - 1) / 2 + (b - a) : a * cl.nty + b;
-    const int off = (i - cl.x0 - MT * a) * cl.ty_dim + (j - cl.y0 - MT * b);
+    if (q == 4) return;
+    const GemmtClass& cl = sc[q];
     const int64_t tile = (int64_t)cl.tx_dim * cl.ty_dim;
+    const int t = (int)(idx / tile);
+    const int off = (int)(idx % tile);
+    const int r = off / cl.ty_dim, c = off % cl.ty_dim;
+    int a, b;
+    if (cl.tri) {   // the upper triangle, row by row
+        int u = t;
+        a = 0;
+        while (u >= cl.ntx - a) {
+            u -= cl.ntx - a;
+            ++a;
+        }
+        b = a + u;
+    } else {
+        a = t / cl.nty;
+        b = t % cl.nty;
+    }
+    const int i = cl.x0 + MT * a + r, j = cl.y0 + MT * b + c;
+    if (i >= mx || j >= my) return;
     const double* p = partial + cl.slot0 + (int64_t)t * tile + off;
     const int64_t cstride = (int64_t)cl.ntiles * tile;
     // 32 loads in flight (a launch has about one wave per SIMD, so each
     // thread's chain of round trips is the launch's time), summed in chunk
     // order
     double s = 0.0;
-    int c = 0;
-    for (; c + 32 <= cl.nchunks; c += 32) {
+    int k = 0;
+    for (; k + 32 <= cl.nchunks; k += 32) {
         double v[32];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) v[u] = p[(int64_t)(c + u) * cstride];
+        for (int u = 0; u < 32; ++u) v[u] = p[(int64_t)(k + u) * cstride];
+        // keep the sums after all 32 loads (otherwise the scheduler interleaves
+        // them with a window of about five loads in flight)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < 32; ++u) s += v[u];
     }
-    for (; c + 8 <= cl.nchunks; c += 8) {
+    for (; k + 8 <= cl.nchunks; k += 8) {
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * cstride];
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * cstride];
 #pragma unroll
         for (int u = 0; u < 8; ++u) s += v[u];
     }
-    for (; c < cl.nchunks; ++c) s += p[(int64_t)c * cstride];
-    *dst = s;
+    for (; k < cl.nchunks; ++k) s += p[(int64_t)k * cstride];
+    out[i + (int64_t)j * mx] = s;
+    if (symmetric && (q == 1 || (q == 0 && a != b))) out[j + (int64_t)i * mx] = s;
 }
 
 // Y[:, 0:ko] = X[:, 0:m] S on the matrix cores, computed as Y^T = S^T X^T so
@@ -3043,8 +3073,10 @@ static double launch_gemmt_classes(hipStream_t st, int64_t n, const double* X, i
             launch_gemmt_shape(wx, wy, st, n, X, ldx, mx, Y1, ldy1, my1, cl, partial);
         }
         if (interior_only) return 0.0;
-        hipLaunchKernelGGL(k_gemmt_reduce_cls, dim3(rgrid), dim3(BLOCK), 0, st, mx, my, sym ? 1 : 0, cls,
-                           partial, out);
+        int64_t elems = 0;   // the computed tile elements, one reduction thread each
+        for (int q = 0; q < 4; ++q) elems += (int64_t)cls.c[q].ntiles * cls.c[q].tx_dim * cls.c[q].ty_dim;
+        hipLaunchKernelGGL(k_gemmt_reduce_cls, dim3((unsigned)((elems + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
+                           mx, my, sym ? 1 : 0, cls, partial, out);
     } else {
         if (interior_only) return 0.0;
         int tiles_y, ntiles, launched, nchunks;
