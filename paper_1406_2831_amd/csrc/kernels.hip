@@ -597,15 +597,22 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Sell A, const double* __restrict
         const int lane = (int)(row & (WAVE - 1));
         const int32_t beg = A.slice_ptr[s], end = A.slice_ptr[s + 1];
         {
+            // columns past m are clamped to m - 1 (read, never stored), so the
+            // eight gathers of an entry carry no branch and go out together
+            int64_t xo[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) xo[c] = (int64_t)(c0 + c < m ? c0 + c : m - 1) * ldx;
             double acc[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc[c] = 0.0;
             for (int32_t e = beg + lane; e < end; e += WAVE) {
                 const double v = A.val[e];
                 const int64_t col = A.col[e];
+                double xv[8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (c0 + c < m) acc[c] += v * X[col + (int64_t)(c0 + c) * ldx];
+                for (int c = 0; c < 8; ++c) xv[c] = X[col + xo[c]];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += v * xv[c];
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c)
