@@ -1399,6 +1399,14 @@ __device__ __forceinline__ UpdateRow<T, K> update_load(const SolveBufsT<T>& B, i
 template <typename T, int K>
 __device__ __forceinline__ void update_finish(const SolveBufsT<T>& B, int64_t row, const UpdateRow<T, K>& d,
                                               double alpha, double omega, double beta, double (&acc)[K + 3]) {
+    // (block columns not carried from the load part: all of them before the
+    // row's stores and arithmetic, in one round trip)
+    T gl[(prefetched<K>() || K == 0) ? 1 : K];
+    if constexpr (!prefetched<K>() && K > 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) gl[j] = B.Gh[row + col_off(j, B.k, B.ld)];
+        __builtin_amdgcn_sched_barrier(0);
+    }
     const double s = d.s, t = d.t, p = d.p, q = d.q;
     const double rv = s - omega * t;
     B.x[row] = (double)d.x + (alpha * p + omega * s);
@@ -1412,7 +1420,7 @@ __device__ __forceinline__ void update_finish(const SolveBufsT<T>& B, int64_t ro
     for (int j = 0; j < K; ++j) {
         double g;
         if constexpr (prefetched<K>()) g = d.gh[j];
-        else g = B.Gh[row + col_off(j, B.k, B.ld)];
+        else g = gl[j];
         acc[3 + j] += g * pn;
     }
 }
@@ -1425,8 +1433,13 @@ __device__ __forceinline__ void update_rows(const SolveBufsT<T>& B, int64_t r0, 
     alpha = uniform(alpha);
     omega = uniform(omega);
     beta = uniform(beta);
-    for (int64_t row = r0; row < r1; row += step) update_finish<T, K>(B, row, update_load<T, K>(B, row), alpha,
-                                                                      omega, beta, acc);
+    for (int64_t row = r0; row < r1; row += step) {
+        const UpdateRow<T, K> d = update_load<T, K>(B, row);
+        // the row's loads all go out before its arithmetic (the scheduler
+        // otherwise splits them into several round trips)
+        __builtin_amdgcn_sched_barrier(0);
+        update_finish<T, K>(B, row, d, alpha, omega, beta, acc);
+    }
 }
 
 // spmv1: q = A p - C zeta ; s = r - alpha q ; sums Gh^T s
@@ -1457,12 +1470,25 @@ __device__ __forceinline__ Spmv1Row<T, K> spmv1_load(const SolveBufsT<T>& B, int
 template <typename T, int K>
 __device__ __forceinline__ void spmv1_finish(const SolveBufsT<T>& B, int64_t row, const Spmv1Row<T, K>& d,
                                              double alpha, const double* zeta, double (&acc)[K > 0 ? K : 1]) {
+    // (block columns not carried from the load part: all of them before the
+    // row's stores and arithmetic, in one round trip)
+    constexpr int KL = (prefetched<K>() || K == 0) ? 1 : K;
+    T cl[KL], gl[KL];
+    if constexpr (!prefetched<K>() && K > 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t o = row + col_off(j, B.k, B.ld);
+            cl[j] = B.C[o];
+            gl[j] = B.Gh[o];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
     double qv = d.ap;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double c;
         if constexpr (prefetched<K>()) c = d.c[j];
-        else c = B.C[row + col_off(j, B.k, B.ld)];
+        else c = cl[j];
         qv -= c * zeta[j];
     }
     const double sv = (double)d.r - alpha * qv;
@@ -1472,7 +1498,7 @@ __device__ __forceinline__ void spmv1_finish(const SolveBufsT<T>& B, int64_t row
     for (int j = 0; j < K; ++j) {
         double g;
         if constexpr (prefetched<K>()) g = d.gh[j];
-        else g = B.Gh[row + col_off(j, B.k, B.ld)];
+        else g = gl[j];
         acc[j] += g * sv;
     }
 }
@@ -1501,13 +1527,20 @@ __device__ __forceinline__ Spmv2Row<T, K> spmv2_load(const SolveBufsT<T>& B, int
 template <typename T, int K>
 __device__ __forceinline__ void spmv2_finish(const SolveBufsT<T>& B, int64_t row, const Spmv2Row<T, K>& d,
                                              const double* gam, double (&acc)[5]) {
+    constexpr int KL = (prefetched<K>() || K == 0) ? 1 : K;
+    T cl[KL];
+    if constexpr (!prefetched<K>() && K > 0) {   // as in spmv1_finish
+#pragma unroll
+        for (int j = 0; j < K; ++j) cl[j] = B.C[row + col_off(j, B.k, B.ld)];
+        __builtin_amdgcn_sched_barrier(0);
+    }
     const double s = d.s, rt = d.rt;
     double tv = d.as;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         double c;
         if constexpr (prefetched<K>()) c = d.c[j];
-        else c = B.C[row + col_off(j, B.k, B.ld)];
+        else c = cl[j];
         tv -= c * gam[j];
     }
     B.t[row] = tv;
@@ -1659,8 +1692,11 @@ __device__ __forceinline__ void spmv1_rows(const SolveBufsT<T>& B, int64_t r0, i
 #pragma unroll
     for (int j = 0; j < M; ++j) zeta[j] = uniform((j < k) ? zeta_s[j] : 0.0);
     alpha = uniform(alpha);
-    for (int64_t row = r0; row < r1; row += step)
-        spmv1_finish<T, K>(B, row, spmv1_load<T, K>(B, row), alpha, zeta, acc);
+    for (int64_t row = r0; row < r1; row += step) {
+        const Spmv1Row<T, K> d = spmv1_load<T, K>(B, row);
+        __builtin_amdgcn_sched_barrier(0);   // the row's loads before its arithmetic
+        spmv1_finish<T, K>(B, row, d, alpha, zeta, acc);
+    }
 }
 
 // spmv1: starts iteration i (the tests, alpha and zeta from the update
@@ -1702,8 +1738,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmv1(SolveBufsT<T> B, int fin) {
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
     if (row0 < r1) spmv1_finish<T, K>(B, row0, d0, alpha, zeta, acc);
-    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK)
-        spmv1_finish<T, K>(B, row, spmv1_load<T, K>(B, row), alpha, zeta, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK) {
+        const Spmv1Row<T, K> d = spmv1_load<T, K>(B, row);
+        __builtin_amdgcn_sched_barrier(0);   // the row's loads before its arithmetic
+        spmv1_finish<T, K>(B, row, d, alpha, zeta, acc);
+    }
     if constexpr (K > 0) block_groups<M>(acc, M, B.cp, B.cp.gs[1], blockIdx.x, gridDim.x);
 }
 
@@ -1715,7 +1754,11 @@ __device__ __forceinline__ void spmv2_rows(const SolveBufsT<T>& B, int64_t r0, i
     double gam[K > 0 ? K : 1];
 #pragma unroll
     for (int j = 0; j < K; ++j) gam[j] = uniform((j < k) ? gamma_s[j] : 0.0);
-    for (int64_t row = r0; row < r1; row += step) spmv2_finish<T, K>(B, row, spmv2_load<T, K>(B, row), gam, acc);
+    for (int64_t row = r0; row < r1; row += step) {
+        const Spmv2Row<T, K> d = spmv2_load<T, K>(B, row);
+        __builtin_amdgcn_sched_barrier(0);   // the row's loads before its arithmetic
+        spmv2_finish<T, K>(B, row, d, gam, acc);
+    }
 }
 
 // spmv2: gamma from spmv1's group sums; t = A s - C gamma ; first level of
@@ -1746,8 +1789,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmv2(SolveBufsT<T> B, int fin) {
     }
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (row0 < r1) spmv2_finish<T, K>(B, row0, d0, gam, acc);
-    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK)
-        spmv2_finish<T, K>(B, row, spmv2_load<T, K>(B, row), gam, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK) {
+        const Spmv2Row<T, K> d = spmv2_load<T, K>(B, row);
+        __builtin_amdgcn_sched_barrier(0);   // the row's loads before its arithmetic
+        spmv2_finish<T, K>(B, row, d, gam, acc);
+    }
     block_groups<5>(acc, 5, B.cp, B.cp.gs[2], blockIdx.x, gridDim.x);
 }
 
@@ -2065,6 +2111,10 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
 #pragma unroll
                 for (int jj = 0; jj < K; ++jj) gh[jj] = B.Gh[row + col_off(jj, k, ld)];
             }
+            // the row's loads all go out before its arithmetic (the scheduler
+            // otherwise split them into three round trips); above the bucket
+            // whose block columns are carried here, finish loads them itself
+            if constexpr (K <= PREF_K_WIDE) __builtin_amdgcn_sched_barrier(0);
             finish(row, d, gh);
         }
     }
