@@ -2562,10 +2562,19 @@ __global__ __launch_bounds__(BLOCK) void k_bpro2_fin(BicgBufs B, int nb) {
 //      rt -= alpha qt; x += alpha p; p = r + beta p; pt = rt + beta pt; store
 //      r, rt into the cycle store; first level of ||r||^2, (rt, r), ||rt||^2,
 //      Gh^T p, GhT^T pt
+// The RBiCG update pass carries the row's two block sets in registers up to
+// bucket 8; above it they are read in chunks of 8 columns in the arithmetic part.
+// With the per-row column addresses of the row loop this holds bucket 8 within
+// 128 registers (four waves per SIMD: with 1024 workgroups every wave of a launch
+// is then resident at once) and bucket 16 within 192 (two waves per SIMD).
+template <int K>
+constexpr bool bupdate_pref() { return K > 0 && K <= 8; }
+constexpr int BUPDATE_CHUNK = 8;
+
 template <int K>
 struct BupdateRow {
     double r, q, rt, qt, p, pt, x;
-    double gh[pref_cols_wide<K>()], ght[pref_cols_wide<K>()];
+    double gh[bupdate_pref<K>() ? K : 1], ght[bupdate_pref<K>() ? K : 1];
 };
 
 template <int K>
@@ -2578,7 +2587,7 @@ __device__ __forceinline__ BupdateRow<K> bupdate_load(const BicgBufs& B, int64_t
     d.p = B.p[row];
     d.pt = B.pt[row];
     d.x = B.x[row];
-    if constexpr (K > 0 && K <= PREF_K_WIDE) {
+    if constexpr (bupdate_pref<K>()) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t o = row + col_off(j, B.k, B.ld);
@@ -2600,22 +2609,33 @@ __device__ __forceinline__ void bupdate_finish(const BicgBufs& B, int64_t row, c
     acc[0] += rv * rv;
     acc[1] += rtv * rv;
     acc[2] += rtv * rtv;
-    // (above the prefetch bucket) the block-column loads come before this
-    // row's stores, so that the compiler can issue them together (no store
-    // they might alias in between)
+    if constexpr (bupdate_pref<K>()) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        double g, gt;
-        if constexpr (K <= PREF_K_WIDE) {
-            g = d.gh[j];
-            gt = d.ght[j];
-        } else {
-            const int64_t o = row + col_off(j, B.k, B.ld);
-            g = B.Gh[o];
-            gt = B.GhT[o];
+        for (int j = 0; j < K; ++j) {
+            acc[3 + j] += d.gh[j] * pn;
+            acc[3 + K + j] += d.ght[j] * ptn;
         }
-        acc[3 + j] += g * pn;
-        acc[3 + K + j] += gt * ptn;
+    } else {
+        // above bucket 8: the block columns in chunks of 8, each chunk's loads
+        // together (before this row's stores, which they might alias)
+#pragma unroll
+        for (int j0 = 0; j0 < K; j0 += BUPDATE_CHUNK) {
+            double gl[BUPDATE_CHUNK], gtl[BUPDATE_CHUNK];
+#pragma unroll
+            for (int u = 0; u < BUPDATE_CHUNK; ++u) {
+                const int64_t o = row + col_off(j0 + u < K ? j0 + u : K - 1, B.k, B.ld);
+                gl[u] = B.Gh[o];
+                gtl[u] = B.GhT[o];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < BUPDATE_CHUNK; ++u) {
+                if (j0 + u < K) {
+                    acc[3 + j0 + u] += gl[u] * pn;
+                    acc[3 + K + j0 + u] += gtl[u] * ptn;
+                }
+            }
+        }
     }
     B.x[row] = xv;
     B.r[row] = rv;
@@ -2677,8 +2697,19 @@ __global__ __launch_bounds__(BLOCK) void k_bupdate(BicgBufs B) {
 #pragma unroll
     for (int j = 0; j < M; ++j) acc[j] = 0.0;
     if (row0 < r1) bupdate_finish<K>(B, row0, d0, alpha, beta, store, wcol, wtcol, acc);
-    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK)
-        bupdate_finish<K>(B, row, bupdate_load<K>(B, row), alpha, beta, store, wcol, wtcol, acc);
+    for (int64_t row = row0 + BLOCK; row < r1; row += BLOCK) {
+        // the leading dimension passes through an empty asm statement, so the
+        // 2K + 7 column addresses are formed per row instead of being hoisted
+        // out of the loop into registers held across it (which cost this pass
+        // a wave per SIMD at buckets 8-16)
+        int64_t ldv = B.ld;
+        asm volatile("" : "+s"(ldv));
+        BicgBufs Bl = B;
+        Bl.ld = ldv;
+        const BupdateRow<K> d = bupdate_load<K>(Bl, row);
+        __builtin_amdgcn_sched_barrier(0);   // the row's loads before its arithmetic
+        bupdate_finish<K>(Bl, row, d, alpha, beta, store, wcol, wtcol, acc);
+    }
     block_groups<M>(acc, M, B.cp, B.cp.gs[0], blockIdx.x, gridDim.x);
 }
 
