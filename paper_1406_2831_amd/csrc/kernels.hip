@@ -584,6 +584,8 @@ __global__ __launch_bounds__(BLOCK) void k_stream_mix(const double* __restrict__
     }
 }
 
+constexpr int SPMM_BATCH = 4;
+
 // Y[:, 0:m] = A X[:, 0:m]: blockIdx.y takes columns 8 y .. 8 y + 7, so that
 // the column groups of a row range run in parallel (on the XCD that holds
 // those rows of A in its L2) instead of one after another in each thread.
@@ -605,14 +607,30 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Sell A, const double* __restrict
             double acc[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-            for (int32_t e = beg + lane; e < end; e += WAVE) {
-                const double v = A.val[e];
-                const int64_t col = A.col[e];
-                double xv[8];
+            // the slice's entries in batches of SPMM_BATCH: a batch's indices
+            // and values first, then all of its 8 x SPMM_BATCH gathers together
+            // (entries past the slice width repeat the last one with value 0)
+            const int w = (end - beg) / WAVE;
+            for (int j0 = 0; j0 < w; j0 += SPMM_BATCH) {
+                int64_t col[SPMM_BATCH];
+                double v[SPMM_BATCH];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) xv[c] = X[col + xo[c]];
+                for (int u = 0; u < SPMM_BATCH; ++u) {
+                    const int j = j0 + u < w ? j0 + u : w - 1;
+                    const int32_t e = beg + j * WAVE + lane;
+                    col[u] = A.col[e];
+                    v[u] = j0 + u < w ? A.val[e] : 0.0;
+                }
+                double xv[SPMM_BATCH][8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] += v * xv[c];
+                for (int u = 0; u < SPMM_BATCH; ++u)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) xv[u][c] = X[col[u] + xo[c]];
+                __builtin_amdgcn_sched_barrier(0);   // the gathers before the FMAs
+#pragma unroll
+                for (int u = 0; u < SPMM_BATCH; ++u)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[c] += v[u] * xv[u][c];
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c)
@@ -623,7 +641,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Sell A, const double* __restrict
 
 // Y[:, 0:ko] = X[:, 0:m] S, S (m x ko) column-major.  One thread per row
 // accumulates 32 output columns; S is staged through LDS in 64-row tiles.
-constexpr int GC = 32, GR = 64;
+constexpr int GC = 32, GR = 64, TS_BATCH = 8;
 
 __global__ __launch_bounds__(BLOCK) void k_gemm_ts(int64_t n, const double* __restrict__ X, int64_t ldx,
                                                    int m, const double* __restrict__ S, int ko,
@@ -647,8 +665,22 @@ __global__ __launch_bounds__(BLOCK) void k_gemm_ts(int64_t n, const double* __re
                 __syncthreads();
                 if (act) {
                     const int iend = (m - i0) < GR ? (m - i0) : GR;
-                    for (int i = 0; i < iend; ++i) {
-                        const double xv = X[row + (int64_t)(i0 + i) * ldx];
+                    const double* xr = X + row + (int64_t)i0 * ldx;
+                    int i = 0;
+                    // eight of the row's elements requested together, then
+                    // their products (the same order of accumulation)
+                    for (; i + TS_BATCH <= iend; i += TS_BATCH) {
+                        double xv[TS_BATCH];
+#pragma unroll
+                        for (int u = 0; u < TS_BATCH; ++u) xv[u] = xr[(int64_t)(i + u) * ldx];
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int u = 0; u < TS_BATCH; ++u)
+#pragma unroll
+                            for (int c = 0; c < GC; ++c) acc[c] += xv[u] * sS[i + u][c];
+                    }
+                    for (; i < iend; ++i) {
+                        const double xv = xr[(int64_t)i * ldx];
 #pragma unroll
                         for (int c = 0; c < GC; ++c) acc[c] += xv * sS[i][c];
                     }
