@@ -2153,6 +2153,8 @@ __global__ __launch_bounds__(BLOCK) void k_mupdate(MultiBufs B, int fin) {
     multi_groups<M>(acc, j, B, 0);
 }
 
+constexpr int MSPMV1_LOCAL_K = 24;
+
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
     constexpr int M = K > 0 ? K : 1;
@@ -2239,11 +2241,26 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
         for (int q = 0; q < M; ++q) zeta[q] = uniform(q < k ? zs[q] : 0.0);
         auto finish = [&](int64_t row, double ap, double rv, const double* c, const double* gh) {
             const int64_t o = row + so;
+            // buckets 20 and 24 read the row's block columns here, all of them
+            // before the arithmetic and the stores (which they might alias):
+            // one round trip instead of one before and one after the stores
+            constexpr bool kLocal = K > PREF_K_WIDE && K <= MSPMV1_LOCAL_K;
+            double cl[kLocal ? K : 1], gl[kLocal ? K : 1];
+            if constexpr (kLocal) {
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) {
+                    const int64_t oc = row + col_off(jj, k, ld);
+                    cl[jj] = B.C[oc];
+                    gl[jj] = B.Gh[oc];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
             double qv = ap;
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
                 double cv;
                 if constexpr (K <= PREF_K_WIDE) cv = c[jj];
+                else if constexpr (kLocal) cv = cl[jj];
                 else cv = B.C[row + col_off(jj, k, ld)];
                 qv -= cv * zeta[jj];
             }
@@ -2254,6 +2271,7 @@ __global__ __launch_bounds__(BLOCK) void k_mspmv1(MultiBufs B, int fin) {
             for (int jj = 0; jj < K; ++jj) {
                 double gv;
                 if constexpr (K <= PREF_K_WIDE) gv = gh[jj];
+                else if constexpr (kLocal) gv = gl[jj];
                 else gv = B.Gh[row + col_off(jj, k, ld)];
                 acc[jj] += gv * sv;
             }

@@ -195,10 +195,11 @@ def test_large_recycle_dimension_single_and_fp32(rb, torch_mod, stencil27, k):
     ctx.close()
 
 
-@pytest.mark.parametrize("k", [30, 64])
+@pytest.mark.parametrize("k", [20, 22, 30, 64])
 def test_large_recycle_dimension_multi_rhs(rb, torch_mod, stencil27, k):
-    """Three right-hand sides solved together at buckets 32 and 64 (64: the largest
-    fused reduction, 3 x 67 sums per workgroup) vs one-at-a-time solves."""
+    """Three right-hand sides solved together at buckets 20, 24 (block columns read
+    in the row's arithmetic part), 32 and 64 (64: the largest fused reduction,
+    3 x 67 sums per workgroup) vs one-at-a-time solves."""
     seq, A, At, As, Ats, U, Ut, refs = stencil27
     _say(f"27-point N=24, k={k}: multi-RHS")
     ctx = _context(rb, A, At, 64)
