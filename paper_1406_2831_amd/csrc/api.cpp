@@ -100,7 +100,7 @@ struct rbs_ctx {
     // inputs (allocated at the first Ritz step), and its events
     double* hritz = nullptr;
     size_t hritz_doubles = 0;
-    hipEvent_t rev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t rev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::string err;
 };
 
@@ -978,6 +978,7 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     jw.ev = c->rev[0];
     jt.ev = c->rev[1];
     hipEvent_t ev_right = c->rev[2];
+    hipEvent_t ev_left = c->rev[3];
     if ((rc = orth_gram(c, jw)) || (rc = orth_gram(c, jt))) return rc;
     rbs::dense::PencilResult right, left;
     std::thread worker;
@@ -987,7 +988,6 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
             if (t.joinable()) t.join();
         }
     } joiner{worker};
-    bool right_started = false;
     int r = 0;
     std::atomic<int> worker_rc{RBS_OK};
     double t_right_ms = 0.0, right_ms = 0.0;
@@ -1004,43 +1004,41 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
                 // would cost as much as the products)
                 rbs::launch_spmm(s, c->A, c->W, ld, c->AW, ld, r);
                 c->ritz_mv += r;
-                // right (harmonic) pencil inputs; its host eigenproblem runs on a
-                // worker thread as soon as they arrive
-                rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
-                rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart,
-                                  dF2 + (size_t)r * r);
-                HIPCHK(c, hipMemcpyAsync(hF2, dF2, (size_t)2 * r * r * sizeof(double),
-                                         hipMemcpyDeviceToHost, s));
-                HIPCHK(c, hipEventRecord(ev_right, s));
-                t_right_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
-                                                                       t_start).count();
-                const int kmax = c->k_max;
-                worker = std::thread([&, r, kmax]() {
-                    if (hipEventSynchronize(ev_right) != hipSuccess) {
-                        worker_rc = RBS_ERR_HIP;
-                        return;
-                    }
-                    const auto t0 = std::chrono::steady_clock::now();
-                    right = rbs::dense::ritz_right_harmonic(r, hF2 + (size_t)r * r, hF2, kmax);
-                    right_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
-                                   .count();
-                });
-                right_started = true;
             }
         }
         if (!jt.done && (rc = orth_advance(c, jt))) return rc;
     }
-    (void)right_started;
     if (r == 0 || jt.rank == 0) {
-        if (worker.joinable()) worker.join();
         HIPCHK(c, hipStreamSynchronize(s));
         c->gen_k = 0;
         return RBS_OK;
     }
     const int rt = jt.rank;
+    // the left pencil's inputs first: its host eigenproblem is the one the
+    // device waits for, so it starts as soon as both bases are done; the right
+    // (harmonic) pencil's inputs follow, and its eigenproblem runs on a worker
+    // thread beside the left one
     rbs::launch_gemmt(s, c->n, c->Wt, ld, rt, c->W, ld, r, c->AW, ld, r, c->gpart, dFG);
     HIPCHK(c, hipMemcpyAsync(hFG, dFG, (size_t)2 * rt * r * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipEventRecord(ev_left, s));
+    rbs::launch_gemmt(s, c->n, c->W, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2);
+    rbs::launch_gemmt(s, c->n, c->AW, ld, r, c->AW, ld, r, nullptr, 0, 0, c->gpart, dF2 + (size_t)r * r);
+    HIPCHK(c, hipMemcpyAsync(hF2, dF2, (size_t)2 * r * r * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(ev_right, s));
+    t_right_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    {
+        const int kmax = c->k_max;
+        worker = std::thread([&, r, kmax]() {
+            if (hipEventSynchronize(ev_right) != hipSuccess) {
+                worker_rc = RBS_ERR_HIP;
+                return;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            right = rbs::dense::ritz_right_harmonic(r, hF2 + (size_t)r * r, hF2, kmax);
+            right_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        });
+    }
+    HIPCHK(c, hipEventSynchronize(ev_left));
     const auto t_left = std::chrono::steady_clock::now();
     left = rbs::dense::ritz_left_two_sided(r, rt, hFG, hFG + (size_t)rt * r, c->k_max);
     const double left_ms =
