@@ -951,8 +951,9 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     const int64_t ld = c->ldw;
     int rc = ritz_host_buffers(c);
     if (rc) return rc;
-    // device scratch: W job Gram | S0 | S1 | (unused), Wt job Gram | S0 | S1,
-    // then Q^T AQ | (AQ)^T AQ and Qt^T [Q AQ]; pinned host: the two jobs' Gram
+    // device scratch: W job Gram | S0 | S1 | the left space's coefficients,
+    // Wt job Gram | S0 | S1, then Q^T AQ | (AQ)^T AQ and Qt^T [Q AQ] (the
+    // right space's coefficients reuse the first slot); pinned host: the two jobs' Gram
     // and factor, the right pencil's inputs, the left pencil's inputs
     const size_t mm = (size_t)(c->k_max + std::max(c->s_max, 0)) * (c->k_max + std::max(c->s_max, 0));
     double* d = c->dsmall;
@@ -1043,6 +1044,19 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
     left = rbs::dense::ritz_left_two_sided(r, rt, hFG, hFG + (size_t)rt * r, c->k_max);
     const double left_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_left).count();
+    // the left space's transform goes out while the right pencil finishes: its
+    // columns are the ones the combined result keeps (unit_cols, column by
+    // column), and up to 32 columns one kernel computes each column alone, so
+    // the leading ones do not depend on how many are formed
+    const int me = std::min(r, rt);
+    const int kl = left.ok && me > 0 ? (int)(left.cols.size() / me) : 0;
+    const bool t2_early = kl > 0 && kl <= 32;
+    if (t2_early) {
+        const std::vector<double> yt = rbs::dense::unit_cols(left, me, rt, kl);
+        double* dYt_early = d + 3 * mm;
+        if ((rc = to_device(c, dYt_early, yt.data(), yt.size() * sizeof(double)))) return rc;
+        rbs::launch_gemm_ts(s, c->n, c->Wt, ld, rt, dYt_early, kl, c->T2, c->ld);
+    }
     worker.join();
     if (worker_rc != RBS_OK) return fail(c, worker_rc, "Ritz step: waiting for the Gram products failed");
     rbs::dense::RitzResult res = rbs::dense::ritz_combine(r, rt, right, left);
@@ -1061,15 +1075,15 @@ int ritz_cycle_work(rbs_ctx* c, int ns) {
         c->gen_k = 0;
         return RBS_OK;
     }
-    const int ko = res.kout;
+    const int ko = res.kout;   // <= kl: the early transform covers it
     std::vector<double> up(res.Y);
-    up.insert(up.end(), res.Yt.begin(), res.Yt.end());
+    if (!t2_early) up.insert(up.end(), res.Yt.begin(), res.Yt.end());
     double* dY = c->dsmall;
     double* dYt = dY + (size_t)r * ko;
     if ((rc = to_device(c, dY, up.data(), up.size() * sizeof(double)))) return rc;
     const int64_t lb = c->ld;
     rbs::launch_gemm_ts(s, c->n, c->W, ld, r, dY, ko, c->T1, lb);
-    rbs::launch_gemm_ts(s, c->n, c->Wt, ld, rt, dYt, ko, c->T2, lb);
+    if (!t2_early) rbs::launch_gemm_ts(s, c->n, c->Wt, ld, rt, dYt, ko, c->T2, lb);
     if ((rc = copy_cols(c, c->W, ld, c->T1, lb, ko))) return rc;
     if ((rc = copy_cols(c, c->Wt, ld, c->T2, lb, ko))) return rc;
     HIPCHK(c, hipGetLastError());

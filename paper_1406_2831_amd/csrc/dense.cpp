@@ -662,6 +662,18 @@ PencilResult ritz_left_two_sided(int r, int rt, const double* F, const double* G
     return out;
 }
 
+std::vector<double> unit_cols(const PencilResult& p, int rows, int ld, int kc) {
+    std::vector<double> out((size_t)ld * kc, 0.0);
+    for (int c = 0; c < kc; ++c) {   // orthonormal bases: unit coefficient vectors
+        const double* v = p.cols.data() + (size_t)c * rows;
+        double a = 0.0;
+        for (int i = 0; i < rows; ++i) a += v[i] * v[i];
+        a = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
+        for (int i = 0; i < rows; ++i) out[i + (size_t)c * ld] = v[i] * a;
+    }
+    return out;
+}
+
 RitzResult ritz_combine(int r, int rt, const PencilResult& right, const PencilResult& left) {
     RitzResult out;
     if (!right.ok || !left.ok) return out;
@@ -670,17 +682,8 @@ RitzResult ritz_combine(int r, int rt, const PencilResult& right, const PencilRe
     const int kl = me > 0 ? (int)(left.cols.size() / me) : 0;
     const int kout = std::min(kr, kl);
     out.m_eff = me;
-    out.Y.assign((size_t)r * kout, 0.0);
-    out.Yt.assign((size_t)rt * kout, 0.0);
-    for (int c = 0; c < kout; ++c) {   // orthonormal bases: unit coefficient vectors
-        double a = 0.0, b = 0.0;
-        for (int i = 0; i < r; ++i) a += right.cols[i + (size_t)c * r] * right.cols[i + (size_t)c * r];
-        for (int i = 0; i < me; ++i) b += left.cols[i + (size_t)c * me] * left.cols[i + (size_t)c * me];
-        a = a > 0 ? 1.0 / std::sqrt(a) : 0.0;
-        b = b > 0 ? 1.0 / std::sqrt(b) : 0.0;
-        for (int i = 0; i < r; ++i) out.Y[i + (size_t)c * r] = right.cols[i + (size_t)c * r] * a;
-        for (int i = 0; i < me; ++i) out.Yt[i + (size_t)c * rt] = left.cols[i + (size_t)c * me] * b;
-    }
+    out.Y = unit_cols(right, r, r, kout);
+    out.Yt = unit_cols(left, me, rt, kout);
     if (kout > 0) out.theta.assign(right.theta.begin(), right.theta.begin() + kout);
     out.kout = kout;
     out.ok = true;

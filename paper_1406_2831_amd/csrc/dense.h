@@ -67,6 +67,11 @@ struct PencilResult {
 PencilResult ritz_right_harmonic(int r, const double* G2, const double* F2, int k);
 PencilResult ritz_left_two_sided(int r, int rt, const double* F, const double* G, int k);
 RitzResult ritz_combine(int r, int rt, const PencilResult& right, const PencilResult& left);
+// The first kc columns of a pencil's result (rows entries each) scaled to unit
+// norm, in a column-major ld x kc block whose rows past `rows` are zero: the
+// coefficients of the new space in an orthonormal basis.  ritz_combine builds
+// both of its blocks with it.
+std::vector<double> unit_cols(const PencilResult& p, int rows, int ld, int kc);
 
 // Orthonormalising factor of a tall block X from its Gram matrix X^T X
 // (m x m): columns scaled to unit norm (D), pivoted Cholesky of D G D
