@@ -53,6 +53,30 @@ int shim_orth_factor_chol(int m, const double* G, double shift, double* S) {
     return r;
 }
 
+// The left space's coefficients formed from the two-sided pencil alone (as the
+// library does while the harmonic pencil is still being solved) against the
+// combined result's: the largest difference over the kept columns (exactly 0
+// expected), the left pencil's column count in *kl_out; returns the kept count.
+int shim_left_coefficients_early(int r, int rt, const double* F, const double* G, const double* G2,
+                                 const double* F2, int k, int* kl_out, double* maxdiff) {
+    const PencilResult right = ritz_right_harmonic(r, G2, F2, k);
+    const PencilResult left = ritz_left_two_sided(r, rt, F, G, k);
+    const RitzResult res = ritz_combine(r, rt, right, left);
+    if (!res.ok) return -1;
+    const int me = r < rt ? r : rt;
+    const int kl = me > 0 ? (int)(left.cols.size() / me) : 0;
+    *kl_out = kl;
+    const std::vector<double> early = unit_cols(left, me, rt, kl);
+    double d = 0.0;
+    for (int c = 0; c < res.kout; ++c)
+        for (int i = 0; i < rt; ++i) {
+            const double e = early[i + (size_t)c * rt] - res.Yt[i + (size_t)c * rt];
+            d = e < 0 ? (-e > d ? -e : d) : (e > d ? e : d);
+        }
+    *maxdiff = d;
+    return res.kout;
+}
+
 int shim_recycle_ritz_orth(int r, int rt, const double* F, const double* G, const double* G2,
                            const double* F2, int k, double* Y, double* Yt) {
     RitzResult res = recycle_ritz_orth(r, rt, F, G, G2, F2, k);

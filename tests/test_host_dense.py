@@ -36,6 +36,8 @@ def shim(tmp_path_factory):
     lib.shim_orth_factor.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
     lib.shim_orth_factor_chol.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
     lib.shim_recycle_ritz_orth.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P]
+    lib.shim_left_coefficients_early.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int), P]
     return lib
 
 
@@ -157,6 +159,44 @@ def test_shifted_cholesky_qr_keeps_ill_conditioned_directions(shim):
     S = np.zeros(m * m)
     G = _fortran(X.T @ X).ravel(order="F")
     assert shim.shim_orth_factor(m, _p(G), 1e-12, _p(S)) < m - 1
+
+
+def _ritz_inputs(shim):
+    """The reduced pencils of one RBiCG cycle of a small convection-diffusion
+    system, in the library's orthonormal coordinates."""
+    seq = w.seq_3d(N=12, nshift=1, nrhs=1, k=10)
+    A, At = (m.to_scipy() for m in seq.matrix(0))
+    n = A.shape[0]
+    st = {}
+
+    def cyc(V, Vt):
+        st["V"], st["Vt"] = V, Vt
+
+    o.rbicg(A, At, o.empty_blocks(n), seq.rhs[0], rtol=1e-10, s=100000, on_cycle=cyc)
+    W, Wt = st["V"], st["Vt"]
+    scale = np.logspace(0, -9, W.shape[1])
+    W, Wt = W * scale, Wt * scale[::-1]
+    Q, AQ = _orth(shim, W, A @ W)
+    Qt, _ = _orth(shim, Wt)
+    F = _fortran(Qt.T @ Q).ravel(order="F")
+    G = _fortran(Qt.T @ AQ).ravel(order="F")
+    F2 = _fortran(Q.T @ AQ).ravel(order="F")
+    G2 = _fortran(AQ.T @ AQ).ravel(order="F")
+    return Q.shape[1], Qt.shape[1], F, G, F2, G2
+
+
+def test_left_coefficients_formed_early_match(shim):
+    """The left space's transform is launched before the harmonic pencil is done,
+    with as many columns as the two-sided pencil gave: its leading columns must be
+    exactly the combined result's (unit columns, built column by column)."""
+    r, rt, F, G, F2, G2 = _ritz_inputs(shim)
+    for k in (4, 10):
+        kl = ctypes.c_int(0)
+        diff = np.zeros(1)
+        kout = shim.shim_left_coefficients_early(r, rt, _p(F), _p(G), _p(G2), _p(F2), k,
+                                                 ctypes.byref(kl), _p(diff))
+        assert 0 < kout <= kl.value
+        assert diff[0] == 0.0
 
 
 def test_recycle_ritz_vs_oracle(shim):
